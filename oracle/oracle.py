@@ -1,0 +1,110 @@
+"""ctypes binding of the FP64 restricted-loop oracle ``libmlcc3_oracle.so`` (TEST INFRASTRUCTURE).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libmlcc3_oracle.so")
+_lib = None
+
+
+def build(verbose=False):
+    """Compile the oracle with gcc (plain C, OpenMP, no BLAS)."""
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wno-unused-variable", "-o", _SO + ".tmp",
+           os.path.join(_HERE, "mlcc3_oracle.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_o", ctypes.c_int), ("n_v", ctypes.c_int), ("N_O", ctypes.c_int),
+                ("N_V", ctypes.c_int), ("n_chol", ctypes.c_int)] + \
+               [(k, ctypes.POINTER(ctypes.c_double)) for k in
+                ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_triples.restype = ctypes.c_int64
+        L.orc_num_triples.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """Holds the problem arrays (kept alive for the C side)."""
+
+    def __init__(self, prob):
+        d = prob.dims
+        self.d = d
+        self._keep = {k: _c(getattr(prob, k)) for k in
+                      ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")}
+        self.P = _Problem(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol,
+                          *[_ptr(self._keep[k]) for k in
+                            ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")])
+
+    def _outs(self):
+        d = self.d
+        return (np.zeros((d.N_V, d.N_O)), np.zeros((d.n_v, d.N_V, d.n_o, d.n_o)),
+                np.zeros((d.n_v, d.n_v, d.n_o, d.N_O)))
+
+    def num_triples(self):
+        return lib().orc_num_triples(self.d.n_o)
+
+    def ground_residual(self, tb=0, te=-1):
+        o = self._outs()
+        lib().orc_ground_residual(ctypes.byref(self.P), ctypes.c_int64(tb), ctypes.c_int64(te),
+                                  *[_ptr(x) for x in o])
+        return {"x1": o[0], "x2_vVoo": o[1], "x2_vvoO": o[2]}
+
+    def _vec_call(self, fn, omega, vec, tb, te):
+        v = [_c(vec[k]) for k in ("x1", "x2_vVoo", "x2_vvoO")]
+        o = self._outs()
+        fn(ctypes.byref(self.P), ctypes.c_double(omega), *[_ptr(x) for x in v],
+           ctypes.c_int64(tb), ctypes.c_int64(te), *[_ptr(x) for x in o])
+        return {"x1": o[0], "x2_vVoo": o[1], "x2_vvoO": o[2]}
+
+    def right_transform(self, omega, vec, tb=0, te=-1):
+        return self._vec_call(lib().orc_right_transform, omega, vec, tb, te)
+
+    def left_transform(self, omega, vec, tb=0, te=-1):
+        return self._vec_call(lib().orc_left_transform, omega, vec, tb, te)
+
+    def triples_block(self, kind, i, j, k, omega=0.0, vec=None):
+        d = self.d
+        out = np.zeros((d.n_v, d.n_v, d.n_v))
+        if vec is None:
+            v = [np.zeros(1)] * 3
+        else:
+            v = [_c(vec[kk]) for kk in ("x1", "x2_vVoo", "x2_vvoO")]
+        lib().orc_triples_block(ctypes.byref(self.P), ctypes.c_int(kind), ctypes.c_double(omega),
+                                *[_ptr(x) for x in v], i, j, k, _ptr(out))
+        return out
+
+
+def num_threads():
+    return lib().orc_num_threads()
