@@ -1,0 +1,137 @@
+/* libmlcc3: MI355X (gfx950) implementation of the CC3 triples hot path of
+ * equation-of-motion MLCC3 (Paul, Folkestad, Myhre, Koch: "Oscillator strengths
+ * from equation-of-motion multilevel CC3", Implementation section and the
+ * Supporting Information equations).
+ *
+ * The library computes, on one GPU, the triples contributions of the active
+ * orbital space to
+ *   - the ground-state residual Omega (SI: contributions to the contravariant
+ *     ground-state residual; eq. tau3 for the triples amplitudes),
+ *   - the right Jacobian transformation rho = J R (SI: Jacobian transformation
+ *     of a trial vector R; eqs. R3, ups_v, ups_o),
+ *   - the left (transpose) transformation sigma = L^T J (SI: transformation with
+ *     the transpose of the Jacobian).
+ * For every unique active occupied triple i>=j>=k the triples amplitudes are
+ * built from the doubles and the T1-transformed Cholesky integrals, summed over
+ * the six pair permutations P^{abc}_{ijk}, divided by the orbital-energy
+ * denominators, converted to contravariant form and contracted back.
+ *
+ * Conventions (all arrays FP64, C row-major, last index fastest):
+ *   orbitals: occupied (N_O) then virtual (N_V); the first n_o occupied and the
+ *   first n_v virtual orbitals are active.  Capital indices run over the full
+ *   spaces, lower-case ones over the active spaces.
+ *   eps_o [N_O], eps_v [N_V]          orbital energies (canonical reference)
+ *   L_OO  [n_chol][N_O][N_O]           bare MO Cholesky vectors, g_pqrs = sum_J L^J_pq L^J_rs,
+ *   L_OV  [n_chol][N_O][N_V]           symmetric in pq (L_VO is the transpose of L_OV)
+ *   L_vV  [n_chol][n_v][N_V]           active-virtual rows of the virtual-virtual block
+ *   t1    [N_V][N_O]                   t^A_I
+ *   t2_vVoo [n_v][N_V][n_o][n_o]       t^{aD}_{ij}   (two blocks of the symmetric doubles,
+ *   t2_vvoO [n_v][n_v][n_o][N_O]       t^{ab}_{iL}    Implementation section after eq. tau3)
+ *   vector blocks x1 [N_V][N_O], x2_vVoo, x2_vvoO as the t-blocks; inputs must be
+ *   pair-symmetric (X^{AB}_{IJ} = X^{BA}_{JI}) and agree where the blocks overlap.
+ *
+ * Outputs are the triples contribution only (the caller adds its CCSD part) and
+ * are overwritten.  Output doubles are covariant values of the full symmetric
+ * doubles array on the two blocks; singles are [N_V][N_O] and zero outside the
+ * active block.  The contravariant -> covariant map is
+ * X^{AB}_{IJ} = (2 X~^{AB}_{IJ} + X~^{BA}_{IJ}) / 3 (Implementation section);
+ * rho_2 additionally carries Delta^{-1}, Delta_{ai,bj} = 1 + delta_ij delta_ab (SI).
+ *
+ * Pointers in mlcc3_ground / mlcc3_vec / mlcc3_out are DEVICE pointers on the
+ * device the workspace was created for; omega arrays are HOST arrays.  The
+ * caller owns all buffers; the library never frees or retains them beyond the
+ * call.  Work is enqueued on `stream` (a hipStream_t, NULL = default stream)
+ * and the call returns after enqueue; outputs are valid once the stream has
+ * synchronised.  Inputs are read-only; outputs must not alias inputs.  One
+ * workspace must not be used by two calls at the same time.
+ *
+ * Return value: MLCC3_OK or a negative status (mlcc3_status_string).  No C++
+ * exception crosses this interface and the library never aborts the process.
+ */
+#ifndef MLCC3_H
+#define MLCC3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MLCC3_OK = 0,
+  MLCC3_EINVAL = -1,       /* bad sizes, NULL pointers, nvec < 1, bad options          */
+  MLCC3_ESINGULAR = -2,    /* |eps^{abc}_{ijk} - omega| < opts.guard for an active triple */
+  MLCC3_ENOMEM = -3,       /* device allocation failed                                  */
+  MLCC3_EHIP = -4,         /* HIP runtime error (text in mlcc3_status_string / last_error) */
+  MLCC3_ENONFINITE = -5,   /* NaN/Inf found in an input (only with opts.check_finite)   */
+  MLCC3_EUNSUPPORTED = -7  /* requested precision or device not supported               */
+};
+
+enum { MLCC3_FP64 = 0, MLCC3_FP32 = 1, MLCC3_BF16X3 = 2 };
+
+typedef struct {
+  int32_t n_o, n_v, N_O, N_V, n_chol; /* 0 <= n_o <= N_O, 0 <= n_v <= N_V, n_chol >= 1 */
+  const double *eps_o, *eps_v;
+  const double *L_OO, *L_OV, *L_vV;
+  const double *t1, *t2_vVoo, *t2_vvoO;
+} mlcc3_ground;
+
+typedef struct { const double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_vec;
+typedef struct { double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_out;
+
+typedef struct {
+  int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3: arithmetic of the
+                             d-contraction GEMMs; denominators and accumulation stay FP64 */
+  int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
+                             since the last call on this workspace; reuse its prepared blocks */
+  int64_t triple_begin;   /* half-open range over the canonical list of unique occupied     */
+  int64_t triple_end;     /* triples (i>=j>=k, not all equal; i outer, k inner); end < 0 = all.
+                             Outputs are the partial sums over that range.                 */
+  double guard;           /* minimum |eps^{abc}_{ijk} - omega| (0 disables the check)       */
+  int32_t check_finite;   /* nonzero: scan inputs for NaN/Inf first                          */
+} mlcc3_opts;
+
+typedef struct mlcc3_ws_s *mlcc3_ws;
+
+/* Workspace: device scratch and the cached ground-state blocks, bound to `device`. */
+int mlcc3_ws_create(mlcc3_ws *ws, int device);
+int mlcc3_ws_destroy(mlcc3_ws ws);
+/* Bytes of device memory currently held by the workspace. */
+int64_t mlcc3_ws_bytes(mlcc3_ws ws);
+
+void mlcc3_opts_default(mlcc3_opts *o);
+
+/* Number of unique active occupied triples i>=j>=k, not all equal: C(n_o+2,3) - n_o. */
+int64_t mlcc3_num_triples(int32_t n_o);
+
+/* Triples contribution to the ground-state residual (SI ground-state residual
+ * equations): Omega^a_i = sum tau~ g_jbkc, Omega^{ab}_{ij} from P sum tau~ F_kc,
+ * Omega^{ab}_{iL} = -P sum tau~ g_jLkc, Omega^{aD}_{ij} = P sum tau~ g_Dbkc. */
+int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *opts,
+                          mlcc3_out *omega_T, void *stream);
+
+/* Triples contribution to rho_m = J(omega_m) R_m for nvec trial vectors (eq. R3 and
+ * the SI right-transformation terms).  R and rho are host arrays of nvec descriptors
+ * holding device pointers; omega[nvec] is a host array. */
+int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
+                          const mlcc3_vec *R, mlcc3_out *rho, const mlcc3_opts *opts, void *stream);
+
+/* Triples contribution to sigma_m = L_m^T J(omega_m) (SI transpose transformation:
+ * L3, sigma^D_L, sigma^D_l, sigma^d_L, sigma^{aD}_{ij}, sigma^{ab}_{iL}). */
+int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
+                         const mlcc3_vec *L, mlcc3_out *sigma, const mlcc3_opts *opts, void *stream);
+
+/* Algorithmic FLOPs of one call (which: 0 ground residual, 1 right, 2 left) for nvec
+ * vectors over the full triple list: U = 2 N_V n_v^3 (n_o^3 - n_o); ground 2U,
+ * right/left (1 + 3 nvec) U (Implementation section cost model with the exact
+ * number of ordered triples). */
+double mlcc3_flops(const mlcc3_ground *g, int32_t which, int32_t nvec);
+
+const char *mlcc3_status_string(int status);
+/* Text of the last error on the calling thread ("" if none). */
+const char *mlcc3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLCC3_H */

@@ -1,0 +1,184 @@
+// FP64 MFMA GEMM for gfx950 (CDNA4) with strided two-level operand maps.
+//
+// C[m,n] = alpha * sum_seg scale_seg * sum_k A_seg(m,k) B_seg(k,n) + beta * C[m,n]
+//
+// 256 threads = 4 waves (64 lanes) in a 2x2 arrangement; each wave owns a
+// (16*TM) x (16*TN) sub-tile built from v_mfma_f64_16x16x4_f64 tiles, so the block tile
+// is (32*TM) x (32*TN).  K advances in slabs of 16 staged through LDS with a
+// register prefetch of the next slab (two LDS buffers, one barrier per slab).
+// Global loads are coalesced along whichever operand index is unit-stride.
+#include "mlcc3_internal.h"
+
+namespace mlcc3 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ long long ioff(const Idx2 &f, int x) {
+  if (f.d <= 0) return (long long)x * f.s0;
+  const int q = x / f.d;
+  return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
+}
+
+constexpr int BK = 16;
+
+template <int TM, int TN, bool AKF, bool BNF>
+__global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int PA = BM + 2, PB = BN + 2;
+  constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+  __shared__ double As[2][BK][PA];
+  __shared__ double Bs[2][BK][PB];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; i++)
+#pragma unroll
+    for (int j = 0; j < TN; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[NA], rb[NB];
+
+  for (int s = 0; s < g.nseg; s++) {
+    const Seg &sg = g.seg[s];
+    const int K = sg.K;
+    if (K <= 0) continue;
+    const double *Ap = sg.A.p + (long long)z * sg.A.batch;
+    const double *Bp = sg.B.p + (long long)z * sg.B.batch;
+    const double scale = sg.scale;
+    // hoisted offsets of the fixed (non-K) index of each staged element
+    long long aoff[NA], boff[NB];
+    bool aok[NA], bok[NB];
+#pragma unroll
+    for (int u = 0; u < NA; u++) {
+      const int m = AKF ? (m0 + tid / BK + u * (256 / BK)) : (m0 + tid % BM);
+      aok[u] = m < g.M;
+      aoff[u] = aok[u] ? ioff(sg.A.row, m) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; u++) {
+      const int n = BNF ? (n0 + tid % BN) : (n0 + tid / BK + u * (256 / BK));
+      bok[u] = n < g.N;
+      bok[u] = bok[u];
+      boff[u] = bok[u] ? ioff(sg.B.col, n) : 0;
+    }
+    auto load = [&](int kt) {
+      const int kb = kt * BK;
+      if (AKF) {
+        const int k = kb + tid % BK;
+        const bool kin = k < K;
+        const long long ko = kin ? ioff(sg.A.col, k) : 0;
+#pragma unroll
+        for (int u = 0; u < NA; u++) ra[u] = (kin && aok[u]) ? Ap[aoff[u] + ko] : 0.0;
+      } else {
+#pragma unroll
+        for (int u = 0; u < NA; u++) {
+          const int k = kb + tid / BM + u * (256 / BM);
+          ra[u] = (k < K && aok[u]) ? Ap[aoff[u] + ioff(sg.A.col, k)] : 0.0;
+        }
+      }
+      if (BNF) {
+#pragma unroll
+        for (int u = 0; u < NB; u++) {
+          const int k = kb + tid / BN + u * (256 / BN);
+          rb[u] = (k < K && bok[u]) ? Bp[ioff(sg.B.row, k) + boff[u]] : 0.0;
+        }
+      } else {
+        const int k = kb + tid % BK;
+        const bool kin = k < K;
+        const long long ko = kin ? ioff(sg.B.row, k) : 0;
+#pragma unroll
+        for (int u = 0; u < NB; u++) rb[u] = (kin && bok[u]) ? Bp[ko + boff[u]] : 0.0;
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < NA; u++) {
+        if (AKF) As[buf][tid % BK][tid / BK + u * (256 / BK)] = ra[u] * scale;
+        else As[buf][tid / BM + u * (256 / BM)][tid % BM] = ra[u] * scale;
+      }
+#pragma unroll
+      for (int u = 0; u < NB; u++) {
+        if (BNF) Bs[buf][tid / BN + u * (256 / BN)][tid % BN] = rb[u];
+        else Bs[buf][tid % BK][tid / BK + u * (256 / BK)] = rb[u];
+      }
+    };
+
+    const int nkt = (K + BK - 1) / BK;
+    __syncthreads();  // previous segment's readers are done with both buffers
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nkt; kt++) {
+      const int cur = kt & 1;
+      if (kt + 1 < nkt) load(kt + 1);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; i++) a[i] = As[cur][kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; j++) b[j] = Bs[cur][kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+          for (int j = 0; j < TN; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      if (kt + 1 < nkt) store(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: lane holds rows 4*(lane/16)+v, column lane%16 of each 16x16 tile
+  double *Cp = g.C + (long long)z * g.cbatch;
+#pragma unroll
+  for (int j = 0; j < TN; j++) {
+    const int n = n0 + wn0 + 16 * j + (lane & 15);
+    if (n >= g.N) continue;
+    const long long co = ioff(g.ccol, n);
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int m = m0 + wm0 + 16 * i + 4 * (lane >> 4) + v;
+        if (m >= g.M) continue;
+        const long long o = ioff(g.crow, m) + co;
+        double r = g.alpha * acc[i][j][v];
+        if (g.beta != 0.0) r += g.beta * Cp[o];
+        Cp[o] = r;
+      }
+  }
+}
+
+template <int TM, int TN>
+static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf) {
+  dim3 grid((g.N + 32 * TN - 1) / (32 * TN), (g.M + 32 * TM - 1) / (32 * TM), g.nbatch);
+  if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true>), grid, dim3(256), 0, s, g);
+  else if (akf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, false>), grid, dim3(256), 0, s, g);
+  else if (bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, false>), grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+static bool unit(const Idx2 &f) { return f.d <= 0 && f.s0 == 1; }
+
+bool g_dry = false;
+
+hipError_t gemm_f64(const Gemm &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g_dry) return hipSuccess;
+  if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
+  const bool akf = unit(g.seg[0].A.col);
+  const bool bnf = unit(g.seg[0].B.col);
+  const int tm = g.M <= 32 ? 1 : 4;
+  const int tn = g.N <= 32 ? 1 : 4;
+  if (tm == 4 && tn == 4) return launch_tiles<4, 4>(g, s, akf, bnf);
+  if (tm == 4 && tn == 1) return launch_tiles<4, 1>(g, s, akf, bnf);
+  if (tm == 1 && tn == 4) return launch_tiles<1, 4>(g, s, akf, bnf);
+  return launch_tiles<1, 1>(g, s, akf, bnf);
+}
+
+}  // namespace mlcc3

@@ -1,0 +1,807 @@
+// C-ABI of libmlcc3: validation, workspace, and the orchestration of the
+// triples path on one stream.  See include/mlcc3.h for the contract.
+//
+// Data flow of one call (all on the caller's stream):
+//   ground prep   Lhat = (1-T)L(1+T); integral blocks ghat = sum_J Lhat Lhat (MFMA GEMMs)
+//   W             d-contraction for every ordered occupied triple (MFMA GEMM, K = N_V or 2 N_V)
+//                 minus the occupied (N_O-sized) term (MFMA GEMM, accumulating)
+//   permute       X~ = contravariant of -(eps - omega)^{-1} P W, written for every ordering
+//   back          Y^{aD}_{ij} (K = n_o n_v^2), Y^{ab}_{iL} (K = n_o^2 n_v) GEMMs, small terms
+//   out           Delta^{-1}, pair symmetrisation, contravariant -> covariant, block gather
+#include <algorithm>
+#include <cstdlib>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mlcc3.h"
+#include "mlcc3_internal.h"
+#include "triples_kernels.h"
+
+using namespace mlcc3;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Status {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) throw Status{MLCC3_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define HIPRT(x)            \
+  do {                      \
+    if (!g_dry) HIPCHK(x);  \
+  } while (0)
+
+// Host-side bounds self-check: every GEMM operand range is checked against the extents of
+// the buffers registered for the current call (workspace buffers and the caller's arrays).
+struct Extent {
+  uintptr_t lo, hi;
+  std::string name;
+};
+thread_local std::vector<Extent> t_ext;
+
+void reg(const void *p, long long count, const char *name) {
+  if (!p || count <= 0) return;
+  t_ext.push_back({(uintptr_t)p, (uintptr_t)p + (uintptr_t)count * sizeof(double), name});
+}
+
+}  // namespace
+
+struct mlcc3_ws_s {
+  int device = 0;
+  std::map<std::string, std::pair<void *, size_t>> bufs;
+  long long total = 0;
+  bool prepared = false;
+  mlcc3_ground key{};
+  int nu = 0;
+  uintptr_t fake_next = (uintptr_t)1 << 44;  // dry-run address space
+};
+
+namespace {
+
+double *buf(mlcc3_ws ws, const std::string &name, size_t count, hipStream_t s) {
+  auto &b = ws->bufs[name];
+  size_t bytes = std::max<size_t>(count * sizeof(double), 256);
+  if (b.second >= bytes) {
+    reg(b.first, (long long)(b.second / sizeof(double)), "ws");
+    return (double *)b.first;
+  }
+  if (g_dry) {
+    b = {(void *)ws->fake_next, bytes};
+    ws->fake_next += (bytes + 4095) & ~(uintptr_t)4095;
+    ws->total += bytes;
+    reg(b.first, (long long)(bytes / sizeof(double)), "ws");
+    return (double *)b.first;
+  }
+  if (b.first) {
+    HIPRT(hipStreamSynchronize(s));
+    HIPRT(hipFree(b.first));
+    ws->total -= b.second;
+    b = {nullptr, 0};
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Status{MLCC3_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes for '" + name + "' failed"};
+  }
+  b = {p, bytes};
+  ws->total += bytes;
+  reg(p, (long long)(bytes / sizeof(double)), "ws");
+  return (double *)p;
+}
+
+struct Dims {
+  int no, nv, NO, NV, nc;
+  long long nv2, nv3, nord;
+};
+
+Dims dims_of(const mlcc3_ground *g) {
+  Dims d{g->n_o, g->n_v, g->N_O, g->N_V, g->n_chol, 0, 0, 0};
+  d.nv2 = (long long)d.nv * d.nv;
+  d.nv3 = d.nv2 * d.nv;
+  d.nord = (long long)d.no * d.no * d.no;
+  return d;
+}
+
+void check(bool ok, const char *what) {
+  if (!ok) throw Status{MLCC3_EINVAL, what};
+}
+
+void validate_ground(const mlcc3_ground *g) {
+  check(g != nullptr, "ground is NULL");
+  check(g->n_chol >= 1, "n_chol must be >= 1");
+  check(g->N_O >= 1 && g->N_V >= 1, "N_O and N_V must be >= 1");
+  check(g->n_o >= 0 && g->n_o <= g->N_O, "need 0 <= n_o <= N_O");
+  check(g->n_v >= 0 && g->n_v <= g->N_V, "need 0 <= n_v <= N_V");
+  check(g->eps_o && g->eps_v && g->L_OO && g->L_OV && g->t1 && g->t2_vVoo && g->t2_vvoO,
+        "NULL pointer in the ground-state inputs");
+  check(g->n_v == 0 || g->L_vV, "L_vV is NULL");
+  check((long long)g->n_o * g->n_o * g->n_o * g->n_v * g->n_v * g->n_v < (1LL << 40), "active space too large");
+}
+
+void validate_vecs(int nvec, const double *omega, const mlcc3_vec *v, const mlcc3_out *o) {
+  check(nvec >= 1, "nvec must be >= 1");
+  check(omega && v && o, "NULL omega / vector / output array");
+  for (int m = 0; m < nvec; m++) {
+    check(v[m].x1 && v[m].x2_vVoo && v[m].x2_vvoO, "NULL pointer in an input vector");
+    check(o[m].x1 && o[m].x2_vVoo && o[m].x2_vvoO, "NULL pointer in an output vector");
+    check(std::isfinite(omega[m]), "omega must be finite");
+  }
+}
+
+void validate_out(const mlcc3_out *o) {
+  check(o && o->x1 && o->x2_vVoo && o->x2_vvoO, "NULL output pointer");
+}
+
+struct Range {
+  long long tb, te;
+};
+
+Range range_of(const mlcc3_opts &o, long long nt) {
+  long long tb = o.triple_begin, te = o.triple_end;
+  if (te < 0 || te > nt) te = nt;
+  check(tb >= 0 && tb <= te, "need 0 <= triple_begin <= triple_end");
+  return {tb, te};
+}
+
+// minimal |eps^{abc}_{ijk} - omega| over active triples with distinct occupied indices
+// not all equal (the i=j=k blocks never enter)
+void guard_check(const mlcc3_ground *g, const double *omega, int nvec, double guard, hipStream_t s) {
+  if (!(guard > 0.0) || g->n_o < 2 || g->n_v < 1 || g_dry) return;
+  std::vector<double> eo(g->n_o), ev(g->n_v);
+  HIPCHK(hipMemcpyAsync(eo.data(), g->eps_o, sizeof(double) * g->n_o, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ev.data(), g->eps_v, sizeof(double) * g->n_v, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> vs;
+  vs.reserve((size_t)g->n_v * g->n_v * g->n_v);
+  for (int a = 0; a < g->n_v; a++)
+    for (int b = 0; b <= a; b++)
+      for (int c = 0; c <= b; c++) vs.push_back(ev[a] + ev[b] + ev[c]);
+  std::sort(vs.begin(), vs.end());
+  for (int i = 0; i < g->n_o; i++)
+    for (int j = 0; j <= i; j++)
+      for (int k = 0; k <= j; k++) {
+        if (i == j && j == k) continue;
+        const double e = eo[i] + eo[j] + eo[k];
+        for (int m = 0; m < nvec; m++) {
+          const double target = e + omega[m];
+          auto it = std::lower_bound(vs.begin(), vs.end(), target);
+          double best = 1e300;
+          if (it != vs.end()) best = std::min(best, std::fabs(*it - target));
+          if (it != vs.begin()) best = std::min(best, std::fabs(*(it - 1) - target));
+          if (best < guard)
+            throw Status{MLCC3_ESINGULAR, "omega within guard of an orbital-energy denominator"};
+        }
+      }
+}
+
+__global__ void k_nonfinite(const double *x, long long n, int *flag) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; id < n; id += (long long)gridDim.x * blockDim.x)
+    if (!isfinite(x[id])) flag[0] = 1;  // every writer stores the same value
+}
+
+void finite_check(mlcc3_ws ws, std::vector<std::pair<const double *, long long>> arrs, hipStream_t s) {
+  if (g_dry) return;
+  int *flag = (int *)buf(ws, "finite_flag", 1, s);
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
+  for (auto &a : arrs)
+    if (a.second > 0) hipLaunchKernelGGL(k_nonfinite, dim3(1024), dim3(256), 0, s, a.first, a.second, flag);
+  HIPRT(hipGetLastError());
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h) throw Status{MLCC3_ENONFINITE, "NaN or Inf in an input array"};
+}
+
+void ground_finite(mlcc3_ws ws, const mlcc3_ground *g, hipStream_t s) {
+  const Dims d = dims_of(g);
+  finite_check(ws,
+               {{g->eps_o, d.NO},
+                {g->eps_v, d.NV},
+                {g->L_OO, (long long)d.nc * d.NO * d.NO},
+                {g->L_OV, (long long)d.nc * d.NO * d.NV},
+                {g->L_vV, (long long)d.nc * d.nv * d.NV},
+                {g->t1, (long long)d.NV * d.NO},
+                {g->t2_vVoo, (long long)d.nv * d.NV * d.no * d.no},
+                {g->t2_vvoO, (long long)d.nv * d.nv * d.no * d.NO}},
+               s);
+}
+
+void vec_finite(mlcc3_ws ws, const Dims &d, const mlcc3_vec &v, hipStream_t s) {
+  finite_check(ws,
+               {{v.x1, (long long)d.NV * d.NO},
+                {v.x2_vVoo, (long long)d.nv * d.NV * d.no * d.no},
+                {v.x2_vvoO, (long long)d.nv * d.nv * d.no * d.NO}},
+               s);
+}
+
+long long max_off(const Idx2 &f, int X) {
+  if (X <= 0) return 0;
+  if (f.d <= 0) return (long long)(X - 1) * f.s0;
+  const long long q = (X - 1) / f.d, r = (X - 1) % f.d;
+  long long best = q * f.s1 + r * f.s0;
+  if (q > 0) best = std::max(best, (q - 1) * f.s1 + (long long)(f.d - 1) * f.s0);
+  return best;
+}
+
+void check_range(const double *p, const Idx2 &row, int R, const Idx2 &col, int Cc, long long batch, int nb,
+                 const char *what) {
+  const uintptr_t lo = (uintptr_t)p;
+  const uintptr_t hi = lo + (uintptr_t)(max_off(row, R) + max_off(col, Cc) + batch * (nb - 1) + 1) * sizeof(double);
+  for (const Extent &e : t_ext)
+    if (e.lo <= lo && hi <= e.hi) return;
+  throw Status{MLCC3_EHIP, std::string("internal bounds check failed for GEMM operand ") + what};
+}
+
+void gemm(const Gemm &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return;
+  for (int i = 0; i < g.nseg; i++) {
+    const Seg &sg = g.seg[i];
+    if (sg.K <= 0) continue;
+    check_range(sg.A.p, sg.A.row, g.M, sg.A.col, sg.K, sg.A.batch, g.nbatch, "A");
+    check_range(sg.B.p, sg.B.row, sg.K, sg.B.col, g.N, sg.B.batch, g.nbatch, "B");
+  }
+  check_range(g.C, g.crow, g.M, g.ccol, g.N, g.cbatch, g.nbatch, "C");
+  HIPCHK(gemm_f64(g, s));
+}
+
+void reg_ground(const mlcc3_ground *g) {
+  const long long no = g->n_o, nv = g->n_v, NO = g->N_O, NV = g->N_V, nc = g->n_chol;
+  reg(g->eps_o, NO, "eps_o");
+  reg(g->eps_v, NV, "eps_v");
+  reg(g->L_OO, nc * NO * NO, "L_OO");
+  reg(g->L_OV, nc * NO * NV, "L_OV");
+  reg(g->L_vV, nc * nv * NV, "L_vV");
+  reg(g->t1, NV * NO, "t1");
+  reg(g->t2_vVoo, nv * NV * no * no, "t2_vVoo");
+  reg(g->t2_vvoO, nv * nv * no * NO, "t2_vvoO");
+}
+
+void reg_vec(const mlcc3_ground *g, const double *x1, const double *a, const double *b) {
+  const long long no = g->n_o, nv = g->n_v, NO = g->N_O, NV = g->N_V;
+  reg(x1, NV * NO, "x1");
+  reg(a, nv * NV * no * no, "x2_vVoo");
+  reg(b, nv * nv * no * NO, "x2_vvoO");
+}
+
+Seg seg(const double *A, Idx2 arow, Idx2 acol, long long abatch, const double *B, Idx2 brow, Idx2 bcol,
+        long long bbatch, int K, double scale = 1.0) {
+  Seg sg;
+  sg.A.p = A; sg.A.row = arow; sg.A.col = acol; sg.A.batch = abatch;
+  sg.B.p = B; sg.B.row = brow; sg.B.col = bcol; sg.B.batch = bbatch;
+  sg.K = K;
+  sg.scale = scale;
+  return sg;
+}
+
+// ------------------------------------------------------ Cholesky assemblies
+// vVvo-kind: C[k][D][b][c] = sum_J A^J_bD B^J_ck  (A: [nc][nv][NV], B: [nc][nv][NO])
+Gemm asm_vVvo(const Dims &d, double *C) {
+  Gemm g;
+  g.M = d.nv * d.NV;  // m = b*NV + D
+  g.N = d.nv * d.no;  // n = c*no + k
+  g.crow = split(d.NV, d.nv, d.nv2);
+  g.ccol = split(d.no, 1, (long long)d.NV * d.nv2);
+  g.C = C;
+  return g;
+}
+Seg asm_vVvo_seg(const Dims &d, const double *A, const double *B) {
+  return seg(A, plain(1), plain((long long)d.nv * d.NV), 0, B, plain((long long)d.nv * d.NO), split(d.no, d.NO, 1),
+             0, d.nc);
+}
+// oovo-kind: C[L][j][k][c] = sum_J A^J_Lj B^J_ck  (A: [nc][NO][NO], B: [nc][nv][NO])
+Gemm asm_oovo(const Dims &d, double *C) {
+  Gemm g;
+  g.M = d.NO * d.no;  // m = L*no + j
+  g.N = d.nv * d.no;  // n = c*no + k
+  g.crow = plain((long long)d.no * d.nv);
+  g.ccol = split(d.no, 1, d.nv);
+  g.C = C;
+  return g;
+}
+Seg asm_oovo_seg(const Dims &d, const double *A, const double *B) {
+  return seg(A, split(d.no, d.NO, 1), plain((long long)d.NO * d.NO), 0, B, plain((long long)d.nv * d.NO),
+             split(d.no, d.NO, 1), 0, d.nc);
+}
+
+// -------------------------------------------------------------- ground prep
+bool same_ground(const mlcc3_ground &a, const mlcc3_ground &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t s) {
+  if (reuse && ws->prepared && same_ground(ws->key, *g)) return;
+  ws->prepared = false;
+  const Dims d = dims_of(g);
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
+  double *LhOO = buf(ws, "LhOO", (size_t)nc * NO * NO, s);
+  double *LhvV = buf(ws, "LhvV", (size_t)nc * nv * NV, s);
+  double *LhVv = buf(ws, "LhVv", (size_t)nc * NV * nv, s);
+  double *LhvO = buf(ws, "LhvO", (size_t)nc * nv * NO, s);
+  launch_lhat(g->L_OO, g->L_OV, g->L_vV, g->t1, nc, NO, NV, nv, LhOO, LhvV, LhVv, LhvO, s);
+  HIPRT(hipGetLastError());
+  const long long LOVs = (long long)NO * NV;
+  // G1[k][D][b][c] = ghat_bDck
+  double *G1 = buf(ws, "G1", (size_t)no * NV * d.nv2, s);
+  {
+    Gemm gg = asm_vVvo(d, G1);
+    gg.nseg = 1;
+    gg.seg[0] = asm_vVvo_seg(d, LhvV, LhvO);
+    gemm(gg, s);
+  }
+  // G2[L][j][k][c] = ghat_Ljck
+  double *G2 = buf(ws, "G2", (size_t)NO * no * no * nv, s);
+  {
+    Gemm gg = asm_oovo(d, G2);
+    gg.nseg = 1;
+    gg.seg[0] = asm_oovo_seg(d, LhOO, LhvO);
+    gemm(gg, s);
+  }
+  // Gb1[k][b][c][D] = ghat_Dbkc = sum_J Lhat_Db L_kc
+  double *Gb1 = buf(ws, "Gb1", (size_t)no * d.nv2 * NV, s);
+  {
+    Gemm gg;
+    gg.M = NV * nv;  // m = D*nv + b
+    gg.N = no * nv;  // n = k*nv + c
+    gg.crow = split(nv, 1, (long long)nv * NV);
+    gg.ccol = split(nv, d.nv2 * NV, NV);
+    gg.C = Gb1;
+    gg.nseg = 1;
+    gg.seg[0] = seg(LhVv, plain(1), plain((long long)NV * nv), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
+    gemm(gg, s);
+  }
+  // Gb3[j][k][c][L] = ghat_jLkc = sum_J Lhat_jL L_kc
+  double *Gb3 = buf(ws, "Gb3", (size_t)no * no * nv * NO, s);
+  {
+    Gemm gg;
+    gg.M = no * NO;  // m = j*NO + L
+    gg.N = no * nv;  // n = k*nv + c
+    gg.crow = split(NO, (long long)no * nv * NO, 1);
+    gg.ccol = plain(NO);
+    gg.C = Gb3;
+    gg.nseg = 1;
+    gg.seg[0] = seg(LhOO, plain(1), plain((long long)NO * NO), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
+    gemm(gg, s);
+  }
+  // gov[j][k][b][c] = g_jbkc (bare)
+  double *gov = buf(ws, "gov", (size_t)no * no * d.nv2, s);
+  {
+    Gemm gg;
+    gg.M = no * nv;  // m = j*nv + b
+    gg.N = no * nv;  // n = k*nv + c
+    gg.crow = split(nv, (long long)no * d.nv2, nv);
+    gg.ccol = split(nv, d.nv2, 1);
+    gg.C = gov;
+    gg.nseg = 1;
+    gg.seg[0] = seg(g->L_OV, split(nv, NV, 1), plain(LOVs), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
+    gemm(gg, s);
+  }
+  // gLb[k][b][c][L] = g_Lbkc (bare)
+  double *gLb = buf(ws, "gLb", (size_t)no * d.nv2 * NO, s);
+  {
+    Gemm gg;
+    gg.M = NO * nv;  // m = L*nv + b
+    gg.N = no * nv;  // n = k*nv + c
+    gg.crow = split(nv, 1, (long long)nv * NO);
+    gg.ccol = split(nv, d.nv2 * NO, NO);
+    gg.C = gLb;
+    gg.nseg = 1;
+    gg.seg[0] = seg(g->L_OV, split(nv, NV, 1), plain(LOVs), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
+    gemm(gg, s);
+  }
+  // gDo[j][k][c][D] = g_jDkc (bare)
+  double *gDo = buf(ws, "gDo", (size_t)no * no * nv * NV, s);
+  {
+    Gemm gg;
+    gg.M = no * NV;  // m = j*NV + D
+    gg.N = no * nv;  // n = k*nv + c
+    gg.crow = split(NV, (long long)no * nv * NV, 1);
+    gg.ccol = plain(NV);
+    gg.C = gDo;
+    gg.nseg = 1;
+    gg.seg[0] = seg(g->L_OV, plain(1), plain(LOVs), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
+    gemm(gg, s);
+  }
+  // F_kc
+  double *F = buf(ws, "F", (size_t)no * nv, s);
+  launch_fock_like(g->L_OV, g->t1, nc, NO, NV, no, nv, buf(ws, "fock_s", nc, s),
+                   buf(ws, "fock_y", (size_t)nc * no * NO, s), F, s);
+  // tA[p][q][a][D] = t^{aD}_{pq}
+  launch_pack_vVoo(g->t2_vVoo, no, nv, NV, 0, buf(ws, "tA", (size_t)no * no * nv * NV, s), s);
+  HIPRT(hipGetLastError());
+  // unique triples (including i=j=k, which the permutation kernel zeroes)
+  std::vector<UniqueTriple> ut;
+  long long canon = 0;
+  for (int i = 0; i < no; i++)
+    for (int j = 0; j <= i; j++)
+      for (int k = 0; k <= j; k++) {
+        UniqueTriple u;
+        u.i = i; u.j = j; u.k = k;
+        const bool alleq = (i == j && j == k);
+        u.canon = alleq ? -1 : canon++;
+        static const int P[6][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {0, 2, 1}, {2, 0, 1}, {1, 2, 0}};
+        const int o[3] = {i, j, k};
+        int mask = 0;
+        for (int sidx = 0; sidx < 6; sidx++) {
+          bool dup = false;
+          for (int t = 0; t < sidx; t++)
+            if (o[P[t][0]] == o[P[sidx][0]] && o[P[t][1]] == o[P[sidx][1]] && o[P[t][2]] == o[P[sidx][2]]) dup = true;
+          if (!dup) mask |= 1 << sidx;
+        }
+        u.mask = mask;
+        ut.push_back(u);
+      }
+  ws->nu = (int)ut.size();
+  void *dut = buf(ws, "utriples", ut.size() * sizeof(UniqueTriple) / sizeof(double) + 1, s);
+  HIPRT(hipMemcpyAsync(dut, ut.data(), ut.size() * sizeof(UniqueTriple), hipMemcpyHostToDevice, s));
+  HIPRT(hipStreamSynchronize(s));  // the host vector goes out of scope
+  ws->key = *g;
+  ws->prepared = true;
+}
+
+double *B(mlcc3_ws ws, const char *name) {
+  auto it = ws->bufs.find(name);
+  if (it == ws->bufs.end()) throw Status{MLCC3_EHIP, std::string("internal: missing buffer ") + name};
+  return (double *)it->second.first;
+}
+
+// ------------------------------------------------------------ W and X~ builders
+// W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G[r][D][(b,c)]  (+ second segment)
+void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, const double *xA2, const double *G2,
+             hipStream_t s) {
+  Gemm g;
+  g.M = d.no * d.no * d.nv;
+  g.N = (int)d.nv2;
+  g.nbatch = d.no;
+  g.C = W;
+  g.crow = split(d.nv, (long long)d.no * d.nv3, d.nv2);
+  g.ccol = plain(1);
+  g.cbatch = d.nv3;
+  g.nseg = xA2 ? 2 : 1;
+  g.seg[0] = seg(xA1, plain(d.NV), plain(1), 0, G1, plain(d.nv2), plain(1), (long long)d.NV * d.nv2, d.NV);
+  if (xA2) g.seg[1] = seg(xA2, plain(d.NV), plain(1), 0, G2, plain(d.nv2), plain(1), (long long)d.NV * d.nv2, d.NV);
+  gemm(g, s);
+}
+
+// W[p][q][r][a][b][c] -= sum_L x^{ab}_{pL} Go[L][(q,r,c)]  (+ second segment)
+void w_oterm(const Dims &d, double *W, const double *xB1, const double *Go1, const double *xB2, const double *Go2,
+             hipStream_t s) {
+  Gemm g;
+  g.M = (int)d.nv2;
+  g.N = d.no * d.no * d.nv;
+  g.nbatch = d.no;
+  g.C = W;
+  g.crow = plain(d.nv);
+  g.ccol = split(d.nv, d.nv3, 1);
+  g.cbatch = (long long)d.no * d.no * d.nv3;
+  g.alpha = -1.0;
+  g.beta = 1.0;
+  g.nseg = xB2 ? 2 : 1;
+  const long long ldB = (long long)d.no * d.no * d.nv;
+  g.seg[0] = seg(xB1, plain((long long)d.no * d.NO), plain(1), d.NO, Go1, plain(ldB), plain(1), 0, d.NO);
+  if (xB2) g.seg[1] = seg(xB2, plain((long long)d.no * d.NO), plain(1), d.NO, Go2, plain(ldB), plain(1), 0, d.NO);
+  gemm(g, s);
+}
+
+void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
+             double omega, Range r, const LocalTerms &lt, hipStream_t s) {
+  launch_permute_denom(W, Xt, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, omega, r.tb,
+                       r.te, lt, s);
+  HIPRT(hipGetLastError());
+}
+
+// tau~ for all ordered triples into "XT"
+void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s) {
+  double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
+  double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
+  w_dterm(d, W, B(ws, "tA"), B(ws, "G1"), nullptr, nullptr, s);
+  w_oterm(d, W, g->t2_vvoO, B(ws, "G2"), nullptr, nullptr, s);
+  permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, s);
+}
+
+// Y[(i,j,a)][D] = sum_{k,bc} X~[i][j][k][a][b][c] G[k][b][c][D]   (+ optional second segment)
+Gemm back_vV(const Dims &d, const double *X, const double *G, int N, double *Y) {
+  Gemm g;
+  g.M = d.no * d.no * d.nv;
+  g.N = N;
+  g.C = Y;
+  g.crow = plain(N);
+  g.ccol = plain(1);
+  g.nseg = 1;
+  g.seg[0] = seg(X, split(d.nv, (long long)d.no * d.nv3, d.nv2), split((int)d.nv2, d.nv3, 1), 0, G, plain(N),
+                 plain(1), 0, (int)(d.no * d.nv2));
+  return g;
+}
+
+// Y[i][(a,b)][L] = alpha * sum_{(j,k,c)} X~[i][j][k][a][b][c] G[(j,k,c)][L]   (+ second segment)
+Gemm back_vO(const Dims &d, const double *X1, const double *G1, const double *X2, const double *G2, double *Y,
+             double alpha) {
+  Gemm g;
+  g.M = (int)d.nv2;
+  g.N = d.NO;
+  g.nbatch = d.no;
+  g.C = Y;
+  g.crow = plain(d.NO);
+  g.ccol = plain(1);
+  g.cbatch = d.nv2 * d.NO;
+  g.alpha = alpha;
+  g.nseg = X2 ? 2 : 1;
+  const int K = d.no * d.no * d.nv;
+  const long long xb = (long long)d.no * d.no * d.nv3;
+  g.seg[0] = seg(X1, plain(d.nv), split(d.nv, d.nv3, 1), xb, G1, plain(d.NO), plain(1), 0, K);
+  if (X2) g.seg[1] = seg(X2, plain(d.nv), split(d.nv, d.nv3, 1), xb, G2, plain(d.NO), plain(1), 0, K);
+  return g;
+}
+
+void zero_out(const Dims &d, const mlcc3_out *o, hipStream_t s) {
+  HIPRT(hipMemsetAsync(o->x1, 0, sizeof(double) * d.NV * d.NO, s));
+  HIPRT(hipMemsetAsync(o->x2_vVoo, 0, sizeof(double) * d.nv * d.NV * d.no * d.no, s));
+  HIPRT(hipMemsetAsync(o->x2_vvoO, 0, sizeof(double) * d.nv * d.nv * d.no * d.NO, s));
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (g_dry) return;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    HIPCHK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <class F>
+int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    const char *dr = std::getenv("MLCC3_DRYRUN");
+    g_dry = dr && dr[0] == '1';
+    t_ext.clear();
+    f();
+    return MLCC3_OK;
+  } catch (const Status &st) {
+    g_last_error = st.msg;
+    return st.code;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return MLCC3_EHIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return MLCC3_EHIP;
+  }
+}
+
+mlcc3_opts opts_or_default(const mlcc3_opts *o) {
+  mlcc3_opts r;
+  mlcc3_opts_default(&r);
+  if (o) r = *o;
+  check(r.precision == MLCC3_FP64 || r.precision == MLCC3_FP32 || r.precision == MLCC3_BF16X3, "bad precision");
+  if (r.precision != MLCC3_FP64) throw Status{MLCC3_EUNSUPPORTED, "only MLCC3_FP64 is implemented"};
+  return r;
+}
+
+// ρ/Ω small terms and the output gather shared by the ground residual and the right transform
+void finish_right_like(mlcc3_ws ws, const Dims &d, const double *X, const double *T, const double *U,
+                       const double *YvV, const double *YvO, int delta, const mlcc3_out *out, hipStream_t s) {
+  double *part1 = buf(ws, "part1", (size_t)d.no * d.no * d.nv, s);
+  double *Yvv = buf(ws, "Yvv", (size_t)d.no * d.no * d.nv2, s);
+  launch_small_right(X, T, B(ws, "gov"), B(ws, "F"), U, d.no, d.nv, part1, Yvv, s);
+  launch_singles_out(part1, d.no, d.nv, d.NO, d.NV, out->x1, s);
+  DoublesRaw y;
+  y.YvV = YvV; y.YvO = YvO; y.Yvv = Yvv;
+  y.no = d.no; y.nv = d.nv; y.NO = d.NO; y.NV = d.NV; y.delta = delta;
+  launch_doubles_out(y, out->x2_vVoo, out->x2_vvoO, s);
+  HIPRT(hipGetLastError());
+}
+
+}  // namespace
+
+// =================================================================== C-ABI
+extern "C" {
+
+void mlcc3_opts_default(mlcc3_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = MLCC3_FP64;
+  o->triple_begin = 0;
+  o->triple_end = -1;
+}
+
+int64_t mlcc3_num_triples(int32_t n_o) {
+  const long long n = n_o < 0 ? 0 : n_o;
+  return n * (n + 1) * (n + 2) / 6 - n;
+}
+
+int mlcc3_ws_create(mlcc3_ws *ws, int device) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    int n = 1;
+    HIPRT(hipGetDeviceCount(&n));
+    check(device >= 0 && device < n, "bad device ordinal");
+    *ws = new mlcc3_ws_s();
+    (*ws)->device = device;
+  });
+}
+
+int mlcc3_ws_destroy(mlcc3_ws ws) {
+  return guarded([&] {
+    if (!ws) return;
+    if (!g_dry) {
+      DeviceGuard dg(ws->device);
+      HIPCHK(hipDeviceSynchronize());
+      for (auto &kv : ws->bufs)
+        if (kv.second.first) (void)hipFree(kv.second.first);
+    }
+    delete ws;
+  });
+}
+
+int64_t mlcc3_ws_bytes(mlcc3_ws ws) { return ws ? ws->total : 0; }
+
+double mlcc3_flops(const mlcc3_ground *g, int32_t which, int32_t nvec) {
+  if (!g) return 0.0;
+  const double no = g->n_o, nv = g->n_v, NV = g->N_V;
+  const double U = 2.0 * NV * nv * nv * nv * (no * no * no - no);
+  if (which == 0) return 2.0 * U;
+  return (1.0 + 3.0 * std::max(nvec, 1)) * U;
+}
+
+int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *opts, mlcc3_out *out,
+                          void *stream) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    validate_ground(g);
+    validate_out(out);
+    reg_ground(g);
+    reg_vec(g, out->x1, out->x2_vVoo, out->x2_vvoO);
+    const mlcc3_opts o = opts_or_default(opts);
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(ws->device);
+    const Dims d = dims_of(g);
+    const Range r = range_of(o, mlcc3_num_triples(d.no));
+    if (o.check_finite) ground_finite(ws, g, s);
+    if (d.no < 2 || d.nv < 2 || r.tb == r.te) {  // CCSD reduction: triples terms vanish
+      zero_out(d, out, s);
+      return;
+    }
+    prepare_ground(ws, g, o.reuse_ground != 0, s);
+    tau_path(ws, g, d, r, s);
+    double *XT = B(ws, "XT");
+    double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
+    double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
+    gemm(back_vV(d, XT, B(ws, "Gb1"), d.NV, YvV), s);
+    gemm(back_vO(d, XT, B(ws, "Gb3"), nullptr, nullptr, YvO, -1.0), s);
+    finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
+  });
+}
+
+int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
+                          const mlcc3_vec *R, mlcc3_out *rho, const mlcc3_opts *opts, void *stream) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    validate_ground(g);
+    validate_vecs(nvec, omega, R, rho);
+    reg_ground(g);
+    for (int m = 0; m < nvec; m++) {
+      reg_vec(g, R[m].x1, R[m].x2_vVoo, R[m].x2_vvoO);
+      reg_vec(g, rho[m].x1, rho[m].x2_vVoo, rho[m].x2_vvoO);
+    }
+    const mlcc3_opts o = opts_or_default(opts);
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(ws->device);
+    const Dims d = dims_of(g);
+    const Range r = range_of(o, mlcc3_num_triples(d.no));
+    if (o.check_finite) {
+      ground_finite(ws, g, s);
+      for (int m = 0; m < nvec; m++) vec_finite(ws, d, R[m], s);
+    }
+    guard_check(g, omega, nvec, o.guard, s);
+    if (d.no < 2 || d.nv < 2 || r.tb == r.te) {
+      for (int m = 0; m < nvec; m++) zero_out(d, &rho[m], s);
+      return;
+    }
+    prepare_ground(ws, g, o.reuse_ground != 0, s);
+    const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
+    // tau~ and Xtau[(i,j,a)][L] = sum tau~ g_Lbkc (shared by all vectors)
+    tau_path(ws, g, d, r, s);
+    double *XT = B(ws, "XT");
+    double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
+    gemm(back_vV(d, XT, B(ws, "gLb"), NO, Xtau), s);
+    double *W = B(ws, "W");
+    double *XR = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
+    for (int m = 0; m < nvec; m++) {
+      // vector prep: Rbar blocks, one-index transformed integrals Upsilon, Upsilon_kc, Xi
+      double *RA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
+      double *RB = buf(ws, "RB", (size_t)nv * nv * no * NO, s);
+      launch_pack_vVoo(R[m].x2_vVoo, no, nv, NV, 1, RA, s);
+      launch_rbar_vvoO(R[m].x2_vvoO, no, nv, NO, RB, s);
+      double *dOO = buf(ws, "dOO", (size_t)nc * NO * NO, s);
+      double *dvV = buf(ws, "dvV", (size_t)nc * nv * NV, s);
+      double *dvO = buf(ws, "dvO", (size_t)nc * nv * NO, s);
+      launch_dlhat(g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R[m].x1, nc, NO, NV, nv, dOO, dvV, dvO, s);
+      HIPRT(hipGetLastError());
+      double *U1 = buf(ws, "U1", (size_t)no * NV * d.nv2, s);
+      {
+        Gemm gg = asm_vVvo(d, U1);
+        gg.nseg = 2;
+        gg.seg[0] = asm_vVvo_seg(d, dvV, B(ws, "LhvO"));
+        gg.seg[1] = asm_vVvo_seg(d, B(ws, "LhvV"), dvO);
+        gemm(gg, s);
+      }
+      double *Uo = buf(ws, "Uo", (size_t)NO * no * no * nv, s);
+      {
+        Gemm gg = asm_oovo(d, Uo);
+        gg.nseg = 2;
+        gg.seg[0] = asm_oovo_seg(d, dOO, B(ws, "LhvO"));
+        gg.seg[1] = asm_oovo_seg(d, B(ws, "LhOO"), dvO);
+        gemm(gg, s);
+      }
+      double *Ukc = buf(ws, "Ukc", (size_t)no * nv, s);
+      launch_fock_like(g->L_OV, R[m].x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), Ukc, s);
+      // Xi[(j,k,c)][L] = sum_D g_jDkc R^D_L
+      double *Xi = buf(ws, "Xi", (size_t)no * no * nv * NO, s);
+      {
+        Gemm gg;
+        gg.M = no * no * nv;
+        gg.N = NO;
+        gg.C = Xi;
+        gg.crow = plain(NO);
+        gg.ccol = plain(1);
+        gg.nseg = 1;
+        gg.seg[0] = seg(B(ws, "gDo"), plain(NV), plain(1), 0, R[m].x1, plain(NO), plain(1), 0, NV);
+        gemm(gg, s);
+      }
+      // R3 before P: W(Rbar; ghat) + W(t; Upsilon)
+      w_dterm(d, W, RA, B(ws, "G1"), B(ws, "tA"), U1, s);
+      w_oterm(d, W, RB, B(ws, "G2"), g->t2_vvoO, Uo, s);
+      permute(ws, d, W, XR, g->eps_o, g->eps_v, omega[m], r, LocalTerms{}, s);
+      // back-contractions
+      double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+      double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+      {
+        Gemm gg = back_vV(d, XR, B(ws, "Gb1"), NV, YvV);
+        gg.nseg = 2;  // - sum_L Xtau[(i,j,a)][L] R^D_L
+        gg.seg[1] = seg(Xtau, plain(NO), plain(1), 0, R[m].x1, plain(1), plain(NO), 0, NO, -1.0);
+        gemm(gg, s);
+      }
+      gemm(back_vO(d, XR, B(ws, "Gb3"), XT, Xi, YvO, -1.0), s);
+      finish_right_like(ws, d, XR, XT, Ukc, YvV, YvO, 1, &rho[m], s);
+    }
+  });
+}
+
+int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
+                         const mlcc3_vec *L, mlcc3_out *sigma, const mlcc3_opts *opts, void *stream) {
+  return guarded([&] {
+    (void)ws; (void)g; (void)nvec; (void)omega; (void)L; (void)sigma; (void)opts; (void)stream;
+    throw Status{MLCC3_EUNSUPPORTED, "left transform not built yet"};
+  });
+}
+
+const char *mlcc3_status_string(int status) {
+  switch (status) {
+    case MLCC3_OK: return "ok";
+    case MLCC3_EINVAL: return "invalid argument";
+    case MLCC3_ESINGULAR: return "omega too close to an orbital-energy denominator";
+    case MLCC3_ENOMEM: return "device allocation failed";
+    case MLCC3_EHIP: return "HIP runtime error";
+    case MLCC3_ENONFINITE: return "non-finite input";
+    case MLCC3_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+const char *mlcc3_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Launchers of the element-wise / reduction kernels of the triples path.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mlcc3 {
+
+// One unique active occupied triple i>=j>=k; mask bit s set when the pair
+// permutation s gives an ordering not produced by an earlier s; canon is the index
+// in the canonical list of triples that are not all equal (-1 for i=j=k).
+struct UniqueTriple {
+  int i, j, k, mask;
+  long long canon;
+};
+
+// Extra local terms of the left triples (SI L3): L^a_i g_jbkc + L^{ab}_{ij} F_kc.
+struct LocalTerms {
+  const double *L1 = nullptr;   // [N_V][N_O]
+  const double *gov = nullptr;  // g_jbkc as [j][k][b][c]
+  const double *LV = nullptr;   // L^{ab}_{ij} as [i][j][a][b]
+  const double *F = nullptr;    // F_kc as [k][c]
+  int NO = 0;
+};
+
+// Raw (pre-symmetrisation) doubles blocks; delta=1 applies Delta^{-1}.
+struct DoublesRaw {
+  const double *YvV = nullptr;  // [i][j][a][D]
+  const double *YvO = nullptr;  // [i][a][b][L]
+  const double *Yvv = nullptr;  // [i][j][a][b]
+  int no = 0, nv = 0, NO = 0, NV = 0, delta = 0;
+};
+
+void launch_lhat(const double *LOO, const double *LOV, const double *LvV, const double *t1, int nc, int NO,
+                 int NV, int nv, double *LhOO, double *LhvV, double *LhVv, double *LhvO, hipStream_t s);
+void launch_dlhat(const double *LOV, const double *LhvV, const double *LhOO, const double *R1, int nc, int NO,
+                  int NV, int nv, double *dOO, double *dvV, double *dvO, hipStream_t s);
+void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV, int no, int nv,
+                      double *tmp_s, double *tmp_y, double *out, hipStream_t s);
+void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA, hipStream_t s);
+void launch_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB, hipStream_t s);
+void launch_pack_vvoo(const double *x, int no, int nv, int NV, double *xV, hipStream_t s);
+void launch_permute_denom(const double *W, double *Xt, const UniqueTriple *ut, int nu, int no, int nv,
+                          const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
+                          const LocalTerms &lt, hipStream_t s);
+void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
+                        int no, int nv, double *part1, double *Yvv, hipStream_t s);
+void launch_singles_out(const double *part1, int no, int nv, int NO, int NV, double *x1, hipStream_t s);
+void launch_doubles_out(const DoublesRaw &y, double *out_a, double *out_b, hipStream_t s);
+
+}  // namespace mlcc3

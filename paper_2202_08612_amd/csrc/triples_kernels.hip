@@ -1,0 +1,384 @@
+// Element-wise and reduction kernels of the MLCC3 triples path (gfx950).
+//
+// Layout of the ordered-triple buffers used throughout: X[p][q][r][a][b][c]
+// (every ordered active occupied triple (p,q,r), including p=q=r, holds one
+// contiguous n_v^3 block).
+#include "mlcc3_internal.h"
+#include "triples_kernels.h"
+
+namespace mlcc3 {
+
+static inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------- T1 transform
+// Lhat = (1 - T) L (1 + T) with T[N_O+A, I] = t^A_I (T1-transformed Hamiltonian);
+// blocks: OO, active-virtual rows (a,B), active-virtual columns (D,b), (c,K).
+__global__ void k_lhat_oo(const double *LOO, const double *LOV, const double *t1, int nc, int NO,
+                          int NV, double *LhOO) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * NO * NO) return;
+  const int K = id % NO, I = (id / NO) % NO;
+  const long long J = id / ((long long)NO * NO);
+  const double *lov = LOV + (J * NO + I) * NV;
+  double s = LOO[id];
+  for (int B = 0; B < NV; B++) s += lov[B] * t1[(long long)B * NO + K];
+  LhOO[id] = s;
+}
+
+__global__ void k_lhat_vV(const double *LvV, const double *LOV, const double *t1, int nc, int NO,
+                          int NV, int nv, double *LhvV) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * nv * NV) return;
+  const int B = id % NV, a = (id / NV) % nv;
+  const long long J = id / ((long long)nv * NV);
+  double s = LvV[id];
+  for (int I = 0; I < NO; I++) s -= t1[(long long)a * NO + I] * LOV[(J * NO + I) * NV + B];
+  LhvV[id] = s;
+}
+
+__global__ void k_lhat_Vv(const double *LvV, const double *LOV, const double *t1, int nc, int NO,
+                          int NV, int nv, double *LhVv) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * NV * nv) return;
+  const int b = id % nv, D = (id / nv) % NV;
+  const long long J = id / ((long long)nv * NV);
+  double s = LvV[(J * nv + b) * NV + D];  // L_Db = L_bD
+  for (int I = 0; I < NO; I++) s -= t1[(long long)D * NO + I] * LOV[(J * NO + I) * NV + b];
+  LhVv[id] = s;
+}
+
+// Lhat_cK = L_cK + sum_B L_cB t^B_K - sum_I t^c_I Lhat_IK   (Lhat_IK = L_IK + sum_B L_IB t^B_K)
+__global__ void k_lhat_vO(const double *LvV, const double *LOV, const double *t1, const double *LhOO,
+                          int nc, int NO, int NV, int nv, double *LhvO) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * nv * NO) return;
+  const int K = id % NO, c = (id / NO) % nv;
+  const long long J = id / ((long long)nv * NO);
+  double s = LOV[(J * NO + K) * NV + c];
+  const double *lv = LvV + (J * nv + c) * NV;
+  for (int B = 0; B < NV; B++) s += lv[B] * t1[(long long)B * NO + K];
+  for (int I = 0; I < NO; I++) s -= t1[(long long)c * NO + I] * LhOO[(J * NO + I) * NO + K];
+  LhvO[id] = s;
+}
+
+// one-index transformation with a singles vector R: dLhat = Lhat R - R Lhat
+__global__ void k_dl_oo(const double *LOV, const double *R1, int nc, int NO, int NV, double *dOO) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * NO * NO) return;
+  const int K = id % NO, I = (id / NO) % NO;
+  const long long J = id / ((long long)NO * NO);
+  const double *lov = LOV + (J * NO + I) * NV;
+  double s = 0.0;
+  for (int A = 0; A < NV; A++) s += lov[A] * R1[(long long)A * NO + K];
+  dOO[id] = s;
+}
+
+__global__ void k_dl_vV(const double *LOV, const double *R1, int nc, int NO, int NV, int nv, double *dvV) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * nv * NV) return;
+  const int B = id % NV, a = (id / NV) % nv;
+  const long long J = id / ((long long)nv * NV);
+  double s = 0.0;
+  for (int I = 0; I < NO; I++) s -= R1[(long long)a * NO + I] * LOV[(J * NO + I) * NV + B];
+  dvV[id] = s;
+}
+
+__global__ void k_dl_vO(const double *LhvV, const double *LhOO, const double *R1, int nc, int NO, int NV,
+                        int nv, double *dvO) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * nv * NO) return;
+  const int K = id % NO, c = (id / NO) % nv;
+  const long long J = id / ((long long)nv * NO);
+  const double *lv = LhvV + (J * nv + c) * NV;
+  double s = 0.0;
+  for (int B = 0; B < NV; B++) s += lv[B] * R1[(long long)B * NO + K];
+  for (int I = 0; I < NO; I++) s -= R1[(long long)c * NO + I] * LhOO[(J * NO + I) * NO + K];
+  dvO[id] = s;
+}
+
+// --------------------------------------------- X_kc = sum_LD (2 g_kcLD - g_kDLc) x^D_L
+// with bare (ov|ov) = sum_J L_kc L_LD:  s_J = sum_LD L^J_LD x^D_L,
+// y^J_kL = sum_D L^J_kD x^D_L,  X_kc = sum_J (2 L^J_kc s_J - sum_L y^J_kL L^J_Lc)
+__global__ void k_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *s) {
+  const int J = blockIdx.x;
+  __shared__ double red[256];
+  double acc = 0.0;
+  const double *l = LOV + (long long)J * NO * NV;
+  for (int e = threadIdx.x; e < NO * NV; e += blockDim.x) {
+    const int L = e / NV, D = e % NV;
+    acc += l[e] * x[(long long)D * NO + L];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s[J] = red[0];
+}
+
+__global__ void k_fock_y(const double *LOV, const double *x, int nc, int NO, int NV, int no, double *y) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * no * NO) return;
+  const int L = id % NO, k = (id / NO) % no;
+  const long long J = id / ((long long)no * NO);
+  const double *l = LOV + (J * NO + k) * NV;
+  double s = 0.0;
+  for (int D = 0; D < NV; D++) s += l[D] * x[(long long)D * NO + L];
+  y[id] = s;
+}
+
+__global__ void k_fock_out(const double *LOV, const double *s, const double *y, int nc, int NO, int NV,
+                           int no, int nv, double *out) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= no * nv) return;
+  const int c = id % nv, k = id / nv;
+  double acc = 0.0;
+  for (int J = 0; J < nc; J++) {
+    const double *l = LOV + (long long)J * NO * NV;
+    double e = 2.0 * l[(long long)k * NV + c] * s[J];
+    const double *yy = y + ((long long)J * no + k) * NO;
+    for (int L = 0; L < NO; L++) e -= yy[L] * l[(long long)L * NV + c];
+    acc += e;
+  }
+  out[id] = acc;
+}
+
+// ------------------------------------------------------------------ repacks
+// xA[p][q][a][D] = f * x^{aD}_{pq},  f = 1 + delta_{aD} delta_{pq} when rbar
+__global__ void k_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)no * no * nv * NV) return;
+  const int D = id % NV, a = (id / NV) % nv;
+  const int q = (id / ((long long)NV * nv)) % no, p = id / ((long long)NV * nv * no);
+  double v = x[(((long long)a * NV + D) * no + p) * no + q];
+  if (rbar && a == D && p == q) v *= 2.0;
+  xA[id] = v;
+}
+
+// xB[a][b][p][L] = (1 + delta_{ab} delta_{pL}) x^{ab}_{pL}
+__global__ void k_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nv * nv * no * NO) return;
+  const int L = id % NO, p = (id / NO) % no, b = (id / ((long long)NO * no)) % nv,
+            a = id / ((long long)NO * no * nv);
+  double v = x[id];
+  if (a == b && p == L) v *= 2.0;
+  xB[id] = v;
+}
+
+// xV[p][q][a][b] = x^{ab}_{pq} (all-active block)
+__global__ void k_pack_vvoo(const double *x, int no, int nv, int NV, double *xV) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)no * no * nv * nv) return;
+  const int b = id % nv, a = (id / nv) % nv, q = (id / ((long long)nv * nv)) % no,
+            p = id / ((long long)nv * nv * no);
+  xV[id] = x[(((long long)a * NV + b) * no + p) * no + q];
+}
+
+// ------------------------------------------ permutation / denominator / contravariant
+// One block per (unique triple u, first virtual a).  For v=(a,b,c):
+//   S(v') = sum over the six pair permutations s of W_{o.s}[v'.s]        (P, eq. tau3)
+//   X~(v) = -(4S(abc) - 2S(bac) - 2S(cba) - 2S(acb) + S(cab) + S(bca)) / (eps - omega)
+// and X~ is written to every distinct ordering o.s of the triple at v.s (X~ is
+// pair-symmetric).  All-equal triples and triples outside the requested range get 0.
+__device__ __constant__ int c_perm[6][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {0, 2, 1}, {2, 0, 1}, {1, 2, 0}};
+
+__global__ __launch_bounds__(256) void k_permute_denom(const double *__restrict__ W, double *__restrict__ Xt,
+                                                       const UniqueTriple *ut, int no, int nv,
+                                                       const double *eps_o, const double *eps_v,
+                                                       double omega, long long tb, long long te,
+                                                       LocalTerms lt) {
+  const UniqueTriple u = ut[blockIdx.x];
+  const int a = blockIdx.y;
+  const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
+  const int o[3] = {u.i, u.j, u.k};
+  const bool active = !(u.i == u.j && u.j == u.k) && u.canon >= tb && u.canon < te;
+  long long base[6];
+  for (int s = 0; s < 6; s++)
+    base[s] = ((long long)(o[c_perm[s][0]] * no + o[c_perm[s][1]]) * no + o[c_perm[s][2]]) * nv3;
+  const double eocc = eps_o[u.i] + eps_o[u.j] + eps_o[u.k];
+  for (int bc = threadIdx.x; bc < nv2; bc += blockDim.x) {
+    const int b = bc / nv, c = bc % nv;
+    const int v[3] = {a, b, c};
+    double val = 0.0;
+    if (active) {
+      // virtual permutations tau of v with contravariant coefficients
+      const int tv[6][3] = {{a, b, c}, {b, a, c}, {c, b, a}, {a, c, b}, {c, a, b}, {b, c, a}};
+      const double coef[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
+      double acc = 0.0;
+      for (int t = 0; t < 6; t++) {
+        double S = 0.0;
+        for (int s = 0; s < 6; s++) {
+          const int x = tv[t][c_perm[s][0]], y = tv[t][c_perm[s][1]], z = tv[t][c_perm[s][2]];
+          S += W[base[s] + (x * nv + y) * (long long)nv + z];
+          if (lt.L1) {
+            const int p = o[c_perm[s][0]], q = o[c_perm[s][1]], r = o[c_perm[s][2]];
+            S += lt.L1[(long long)x * lt.NO + p] * lt.gov[(((long long)q * no + r) * nv + y) * nv + z] +
+                 lt.LV[(((long long)p * no + q) * nv + x) * nv + y] * lt.F[(long long)r * nv + z];
+          }
+        }
+        acc += coef[t] * S;
+      }
+      const double den = eps_v[a] + eps_v[b] + eps_v[c] - eocc - omega;
+      val = -acc / den;
+    }
+    for (int s = 0; s < 6; s++) {
+      if (!((u.mask >> s) & 1)) continue;
+      Xt[base[s] + (v[c_perm[s][0]] * nv + v[c_perm[s][1]]) * (long long)nv + v[c_perm[s][2]]] = val;
+    }
+  }
+}
+
+// -------------------------------------------------------------- wave helpers
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ρ-type small contractions over ordered blocks, one wave per (p,q,a):
+//   part1[p][q][a]   = sum_{r,b,c} X~^{abc}_{pqr} g_qbrc
+//   Yvv[p][q][a][b]  = sum_{r,c} (X~^{abc}_{pqr} F_rc + T~^{abc}_{pqr} U_rc)
+__global__ __launch_bounds__(64) void k_small_right(const double *__restrict__ X, const double *__restrict__ T,
+                                                    const double *gov, const double *F, const double *U,
+                                                    int no, int nv, double *part1, double *Yvv) {
+  const int id = blockIdx.x;
+  const int a = id % nv, q = (id / nv) % no, p = id / (nv * no);
+  const int lane = threadIdx.x;
+  const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
+  extern __shared__ double ysum[];
+  for (int b = lane; b < nv; b += 64) ysum[b] = 0.0;
+  __syncthreads();
+  double racc = 0.0;
+  for (int r = 0; r < no; r++) {
+    const long long base = (((long long)p * no + q) * no + r) * nv3 + (long long)a * nv2;
+    const double *g = gov + ((long long)q * no + r) * nv2;
+    for (int b = 0; b < nv; b++) {
+      double yb = 0.0;
+      for (int c = lane; c < nv; c += 64) {
+        const double x = X[base + (long long)b * nv + c];
+        racc += x * g[(long long)b * nv + c];
+        yb += x * F[(long long)r * nv + c];
+        if (T) yb += T[base + (long long)b * nv + c] * U[(long long)r * nv + c];
+      }
+      yb = wave_sum(yb);
+      if (lane == 0) ysum[b] += yb;
+    }
+  }
+  racc = wave_sum(racc);
+  __syncthreads();
+  if (lane == 0) part1[((long long)p * no + q) * nv + a] = racc;
+  for (int b = lane; b < nv; b += 64) Yvv[(((long long)p * no + q) * nv + a) * nv + b] = ysum[b];
+}
+
+// x1[A][I] = sum_q part1[I][q][A] on the active block, 0 elsewhere
+__global__ void k_singles_out(const double *part1, int no, int nv, int NO, int NV, double *x1) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= NV * NO) return;
+  const int I = id % NO, A = id / NO;
+  double s = 0.0;
+  if (A < nv && I < no)
+    for (int q = 0; q < no; q++) s += part1[((long long)I * no + q) * nv + A];
+  x1[id] = s;
+}
+
+// raw full-space doubles Y^{AB}_{IJ} from the blocks YvV[i][j][a][D], YvO[i][a][b][L], Yvv[i][j][a][b]
+__device__ __forceinline__ double yfull(const DoublesRaw &y, int A, int B, int I, int J) {
+  double s = 0.0;
+  const int no = y.no, nv = y.nv, NO = y.NO, NV = y.NV;
+  if (A < nv && I < no && J < no) {
+    s += y.YvV[(((long long)I * no + J) * nv + A) * NV + B];
+    if (B < nv && y.Yvv) s += y.Yvv[(((long long)I * no + J) * nv + A) * nv + B];
+  }
+  if (A < nv && B < nv && I < no && y.YvO) s += y.YvO[(((long long)I * nv + A) * nv + B) * NO + J];
+  return s;
+}
+__device__ __forceinline__ double xcontra(const DoublesRaw &y, int A, int B, int I, int J) {
+  double s = yfull(y, A, B, I, J) + yfull(y, B, A, J, I);
+  if (y.delta && A == B && I == J) s *= 0.5;
+  return s;
+}
+__device__ __forceinline__ double xcov(const DoublesRaw &y, int A, int B, int I, int J) {
+  return (2.0 * xcontra(y, A, B, I, J) + xcontra(y, B, A, I, J)) * (1.0 / 3.0);
+}
+
+// covariant output blocks: out_a[a][D][i][j], out_b[a][b][i][L]
+__global__ void k_doubles_out(DoublesRaw y, double *out_a, double *out_b) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int no = y.no, nv = y.nv, NO = y.NO, NV = y.NV;
+  const long long na = (long long)nv * NV * no * no, nb = (long long)nv * nv * no * NO;
+  if (id < na) {
+    const int j = id % no, i = (id / no) % no, D = (id / ((long long)no * no)) % NV,
+              a = id / ((long long)no * no * NV);
+    out_a[id] = xcov(y, a, D, i, j);
+  } else if (id < na + nb) {
+    const long long e = id - na;
+    const int L = e % NO, i = (e / NO) % no, b = (e / ((long long)NO * no)) % nv,
+              a = e / ((long long)NO * no * nv);
+    out_b[e] = xcov(y, a, b, i, L);
+  }
+}
+
+// ------------------------------------------------------------- host launchers
+#define L1D(kern, n, ...) \
+  do { if (!g_dry && (n) > 0) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(256), 0, s, __VA_ARGS__); } while (0)
+
+void launch_lhat(const double *LOO, const double *LOV, const double *LvV, const double *t1, int nc, int NO,
+                 int NV, int nv, double *LhOO, double *LhvV, double *LhVv, double *LhvO, hipStream_t s) {
+  L1D(k_lhat_oo, (long long)nc * NO * NO, LOO, LOV, t1, nc, NO, NV, LhOO);
+  if (nv > 0) {
+    L1D(k_lhat_vV, (long long)nc * nv * NV, LvV, LOV, t1, nc, NO, NV, nv, LhvV);
+    L1D(k_lhat_Vv, (long long)nc * NV * nv, LvV, LOV, t1, nc, NO, NV, nv, LhVv);
+    L1D(k_lhat_vO, (long long)nc * nv * NO, LvV, LOV, t1, LhOO, nc, NO, NV, nv, LhvO);
+  }
+}
+
+void launch_dlhat(const double *LOV, const double *LhvV, const double *LhOO, const double *R1, int nc, int NO,
+                  int NV, int nv, double *dOO, double *dvV, double *dvO, hipStream_t s) {
+  L1D(k_dl_oo, (long long)nc * NO * NO, LOV, R1, nc, NO, NV, dOO);
+  L1D(k_dl_vV, (long long)nc * nv * NV, LOV, R1, nc, NO, NV, nv, dvV);
+  L1D(k_dl_vO, (long long)nc * nv * NO, LhvV, LhOO, R1, nc, NO, NV, nv, dvO);
+}
+
+void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV, int no, int nv,
+                      double *tmp_s, double *tmp_y, double *out, hipStream_t s) {
+  if (!g_dry) hipLaunchKernelGGL(k_fock_s, dim3(nc), dim3(256), 0, s, LOV, x, nc, NO, NV, tmp_s);
+  L1D(k_fock_y, (long long)nc * no * NO, LOV, x, nc, NO, NV, no, tmp_y);
+  L1D(k_fock_out, (long long)no * nv, LOV, tmp_s, tmp_y, nc, NO, NV, no, nv, out);
+}
+
+void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA, hipStream_t s) {
+  L1D(k_pack_vVoo, (long long)no * no * nv * NV, x, no, nv, NV, rbar, xA);
+}
+void launch_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB, hipStream_t s) {
+  L1D(k_rbar_vvoO, (long long)nv * nv * no * NO, x, no, nv, NO, xB);
+}
+void launch_pack_vvoo(const double *x, int no, int nv, int NV, double *xV, hipStream_t s) {
+  L1D(k_pack_vvoo, (long long)no * no * nv * nv, x, no, nv, NV, xV);
+}
+
+void launch_permute_denom(const double *W, double *Xt, const UniqueTriple *ut, int nu, int no, int nv,
+                          const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
+                          const LocalTerms &lt, hipStream_t s) {
+  if (nu <= 0 || nv <= 0 || g_dry) return;
+  hipLaunchKernelGGL(k_permute_denom, dim3(nu, nv), dim3(256), 0, s, W, Xt, ut, no, nv, eps_o, eps_v, omega,
+                     tb, te, lt);
+}
+
+void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
+                        int no, int nv, double *part1, double *Yvv, hipStream_t s) {
+  if (no <= 0 || nv <= 0 || g_dry) return;
+  hipLaunchKernelGGL(k_small_right, dim3(no * no * nv), dim3(64), nv * sizeof(double), s, X, T, gov, F, U,
+                     no, nv, part1, Yvv);
+}
+
+void launch_singles_out(const double *part1, int no, int nv, int NO, int NV, double *x1, hipStream_t s) {
+  L1D(k_singles_out, (long long)NV * NO, part1, no, nv, NO, NV, x1);
+}
+
+void launch_doubles_out(const DoublesRaw &y, double *out_a, double *out_b, hipStream_t s) {
+  const long long n = (long long)y.nv * y.NV * y.no * y.no + (long long)y.nv * y.nv * y.no * y.NO;
+  L1D(k_doubles_out, n, y, out_a, out_b);
+}
+
+}  // namespace mlcc3

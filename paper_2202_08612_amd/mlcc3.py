@@ -1,0 +1,200 @@
+"""Thin ctypes binding of ``libmlcc3.so`` (the C-ABI in ``include/mlcc3.h``).
+
+Argument marshalling only: every step of the triples path runs in the HIP
+library.  torch provides device memory and the current stream.  Importing this
+module raises if the library has not been built (``python -m
+paper_2202_08612_amd.build``); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlcc3.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2202_08612_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ESINGULAR, ENOMEM, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -7
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Ground(ctypes.Structure):
+    _fields_ = [("n_o", ctypes.c_int32), ("n_v", ctypes.c_int32), ("N_O", ctypes.c_int32),
+                ("N_V", ctypes.c_int32), ("n_chol", ctypes.c_int32)] + \
+               [(k, ctypes.c_void_p) for k in ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1",
+                                                "t2_vVoo", "t2_vvoO")]
+
+
+class _Vec(ctypes.Structure):
+    _fields_ = [("x1", ctypes.c_void_p), ("x2_vVoo", ctypes.c_void_p), ("x2_vvoO", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("reuse_ground", ctypes.c_int32),
+                ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
+                ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32)]
+
+
+_lib.mlcc3_ws_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+_lib.mlcc3_ws_destroy.argtypes = [ctypes.c_void_p]
+_lib.mlcc3_ws_bytes.argtypes = [ctypes.c_void_p]
+_lib.mlcc3_ws_bytes.restype = ctypes.c_int64
+_lib.mlcc3_num_triples.argtypes = [ctypes.c_int32]
+_lib.mlcc3_num_triples.restype = ctypes.c_int64
+_lib.mlcc3_opts_default.argtypes = [ctypes.POINTER(_Opts)]
+_lib.mlcc3_ground_residual.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.POINTER(_Opts),
+                                       ctypes.POINTER(_Vec), ctypes.c_void_p]
+for _fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
+    getattr(_lib, _fn).argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.c_int32, _dp,
+                                   ctypes.POINTER(_Vec), ctypes.POINTER(_Vec), ctypes.POINTER(_Opts),
+                                   ctypes.c_void_p]
+_lib.mlcc3_flops.argtypes = [ctypes.POINTER(_Ground), ctypes.c_int32, ctypes.c_int32]
+_lib.mlcc3_flops.restype = ctypes.c_double
+_lib.mlcc3_status_string.argtypes = [ctypes.c_int]
+_lib.mlcc3_status_string.restype = ctypes.c_char_p
+_lib.mlcc3_last_error.restype = ctypes.c_char_p
+
+EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_opts_default",
+            "mlcc3_num_triples", "mlcc3_ground_residual", "mlcc3_right_transform",
+            "mlcc3_left_transform", "mlcc3_flops", "mlcc3_status_string", "mlcc3_last_error"]
+
+
+class MLCC3Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        msg = _lib.mlcc3_last_error().decode() or _lib.mlcc3_status_string(rc).decode()
+        raise MLCC3Error(rc, msg)
+
+
+def num_triples(n_o):
+    return int(_lib.mlcc3_num_triples(n_o))
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Workspace:
+    """Device scratch and cached ground-state blocks on one GPU."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        _check(_lib.mlcc3_ws_create(ctypes.byref(h), self.device.index or 0))
+        self.h = h
+
+    def bytes(self):
+        return int(_lib.mlcc3_ws_bytes(self.h))
+
+    def close(self):
+        if self.h:
+            _check(_lib.mlcc3_ws_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+GROUND_KEYS = ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")
+VEC_KEYS = ("x1", "x2_vVoo", "x2_vvoO")
+
+
+def _dev(x, device):
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+    return t.contiguous()
+
+
+class Ground:
+    """Ground-state inputs resident on the device (see include/mlcc3.h for layouts)."""
+
+    def __init__(self, prob, device="cuda"):
+        d = prob.dims
+        self.dims = d
+        self.t = {k: _dev(getattr(prob, k), device) for k in GROUND_KEYS}
+        self.c = _Ground(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol,
+                         *[self.t[k].data_ptr() for k in GROUND_KEYS])
+
+    def flops(self, which, nvec=1):
+        return float(_lib.mlcc3_flops(ctypes.byref(self.c), which, nvec))
+
+
+def vec_to_device(vec, device="cuda"):
+    return {k: _dev(vec[k], device) for k in VEC_KEYS}
+
+
+def empty_out(d, device="cuda"):
+    return {"x1": torch.empty((d.N_V, d.N_O), dtype=torch.float64, device=device),
+            "x2_vVoo": torch.empty((d.n_v, d.N_V, d.n_o, d.n_o), dtype=torch.float64, device=device),
+            "x2_vvoO": torch.empty((d.n_v, d.n_v, d.n_o, d.N_O), dtype=torch.float64, device=device)}
+
+
+def _vecs(lst):
+    arr = (_Vec * len(lst))()
+    for m, v in enumerate(lst):
+        for k in VEC_KEYS:
+            assert v[k].is_contiguous() and v[k].dtype == torch.float64
+        arr[m] = _Vec(v["x1"].data_ptr(), v["x2_vVoo"].data_ptr(), v["x2_vvoO"].data_ptr())
+    return arr
+
+
+def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0, check_finite=False):
+    o = _Opts()
+    _lib.mlcc3_opts_default(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.reuse_ground = 1 if reuse_ground else 0
+    if triple_range is not None:
+        o.triple_begin, o.triple_end = int(triple_range[0]), int(triple_range[1])
+    o.guard = float(guard)
+    o.check_finite = 1 if check_finite else 0
+    return o
+
+
+def ground_residual(ws, ground, out=None, **kw):
+    out = empty_out(ground.dims, ws.device) if out is None else out
+    o = make_opts(**kw)
+    arr = _vecs([out])
+    _check(_lib.mlcc3_ground_residual(ws.h, ctypes.byref(ground.c), ctypes.byref(o), arr, _stream(ws.device)))
+    return out
+
+
+def _transform(fn, ws, ground, omegas, vecs, outs=None, **kw):
+    n = len(vecs)
+    outs = [empty_out(ground.dims, ws.device) for _ in range(n)] if outs is None else outs
+    om = (ctypes.c_double * n)(*[float(w) for w in omegas])
+    o = make_opts(**kw)
+    _check(fn(ws.h, ctypes.byref(ground.c), n, om, _vecs(vecs), _vecs(outs), ctypes.byref(o),
+              _stream(ws.device)))
+    return outs
+
+
+def right_transform(ws, ground, omegas, vecs, outs=None, **kw):
+    return _transform(_lib.mlcc3_right_transform, ws, ground, omegas, vecs, outs, **kw)
+
+
+def left_transform(ws, ground, omegas, vecs, outs=None, **kw):
+    return _transform(_lib.mlcc3_left_transform, ws, ground, omegas, vecs, outs, **kw)
+
+
+def to_numpy(out):
+    return {k: v.detach().cpu().numpy() for k, v in out.items()}

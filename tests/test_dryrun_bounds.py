@@ -1,0 +1,74 @@
+"""Host-side launch validation without a GPU (MLCC3_DRYRUN=1).
+
+Every entry point runs its full orchestration with fake device addresses: no kernel
+is launched, but each GEMM descriptor is checked against the extents of the buffers it
+may touch (workspace buffers and the caller's arrays, sized from the problem
+dimensions).  A violation would return MLCC3_EHIP with "bounds" in the message.
+"""
+import ctypes
+import os
+
+import pytest
+
+from paper_2202_08612_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SO = os.path.join(ROOT, "paper_2202_08612_amd", "libmlcc3.so")
+
+
+class G(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("n_o", "n_v", "N_O", "N_V", "n_chol")] + \
+               [(k, ctypes.c_void_p) for k in ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1",
+                                                "t2_vVoo", "t2_vvoO")]
+
+
+class V(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x1", "x2_vVoo", "x2_vvoO")]
+
+
+class O(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("reuse_ground", ctypes.c_int32),
+                ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
+                ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(SO):
+        pytest.skip("libmlcc3.so not built")
+    os.environ["MLCC3_DRYRUN"] = "1"
+    L = ctypes.CDLL(SO)
+    L.mlcc3_last_error.restype = ctypes.c_char_p
+    yield L
+    os.environ.pop("MLCC3_DRYRUN", None)
+
+
+def _fake(n):
+    base = 1 << 40
+    return [base + (i << 38) for i in range(n)]
+
+
+CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1)]
+
+
+@pytest.mark.parametrize("d", CASES, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
+def test_all_launches_in_bounds(lib, d):
+    ws = ctypes.c_void_p()
+    assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+    p = _fake(64)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:8])
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    out = (V * 1)(V(*p[8:11]))
+    rc = lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None)
+    assert rc == 0, lib.mlcc3_last_error()
+    nvec = 3
+    vin = (V * nvec)(*[V(*p[11 + 3 * m: 14 + 3 * m]) for m in range(nvec)])
+    vout = (V * nvec)(*[V(*p[30 + 3 * m: 33 + 3 * m]) for m in range(nvec)])
+    om = (ctypes.c_double * nvec)(0.4, 0.5, 0.6)
+    for fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
+        rc = getattr(lib, fn)(ws, ctypes.byref(g), nvec, om, vin, vout, ctypes.byref(o), None)
+        if rc == -7 and "not built" in lib.mlcc3_last_error().decode():
+            continue
+        assert rc == 0, (fn, lib.mlcc3_last_error())
+    assert lib.mlcc3_ws_destroy(ws) == 0

@@ -1,0 +1,139 @@
+"""HIP path vs the FP64 oracle, element by element, through the C-ABI (FP64: <= 1e-10 relative).
+
+Sizes span several GEMM tiles and ragged tails; the full config-1 shape is checked
+on subsets of the triple list (partial sums are part of the ABI) and by properties
+that hold at any size (range additivity, adjoint identity, linearity).
+"""
+import numpy as np
+import pytest
+
+from paper_2202_08612_amd import inputs as I
+from tests.helpers import maxrel, pair_form_blocks, rel
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+SMALL = [I.Dims(3, 4, 4, 6, 10), I.Dims(4, 5, 5, 7, 12), I.CONFIGS[0]["dims"], I.Dims(4, 6, 4, 6, 9),
+         I.Dims(2, 3, 4, 5, 8), I.Dims(5, 17, 7, 37, 23), I.Dims(6, 9, 6, 140, 33)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2202_08612_amd import mlcc3
+    return mlcc3
+
+
+@pytest.fixture(scope="module")
+def ws(lib):
+    w = lib.Workspace(0)
+    yield w
+    w.close()
+
+
+def _check(gpu, ref, tol=TOL):
+    for k in ("x1", "x2_vVoo", "x2_vvoO"):
+        g = gpu[k].detach().cpu().numpy() if hasattr(gpu[k], "detach") else gpu[k]
+        assert np.all(np.isfinite(g)), k
+        assert rel(g, ref[k]) <= tol, (k, rel(g, ref[k]))
+        assert maxrel(g, ref[k]) <= tol, (k, maxrel(g, ref[k]))
+
+
+def _setup(lib, d, seed):
+    from oracle.oracle import Oracle
+    p = I.make_problem(d, seed)
+    return p, Oracle(p), lib.Ground(p)
+
+
+@pytest.mark.parametrize("d", SMALL, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
+def test_ground_residual(lib, ws, d):
+    p, orc, g = _setup(lib, d, 1234)
+    _check(lib.ground_residual(ws, g), orc.ground_residual())
+
+
+@pytest.mark.parametrize("d", SMALL, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
+def test_right_transform(lib, ws, d):
+    p, orc, g = _setup(lib, d, 99)
+    R = I.right_vectors(p, 2)
+    om = I.omegas(False, 2)
+    out = lib.right_transform(ws, g, om, [lib.vec_to_device(r) for r in R])
+    for m in range(2):
+        _check(out[m], orc.right_transform(om[m], R[m]))
+
+
+def test_triple_range_and_reuse(lib, ws):
+    d = I.Dims(5, 7, 6, 15, 11)
+    p, orc, g = _setup(lib, d, 5)
+    R = I.right_vectors(p, 1)[0]
+    nt = lib.num_triples(d.n_o)
+    for (a, b) in ((0, 1), (3, 9), (9, nt), (4, 4)):
+        out = lib.right_transform(ws, g, [0.45], [lib.vec_to_device(R)], triple_range=(a, b),
+                                  reuse_ground=True)[0]
+        _check(out, orc.right_transform(0.45, R, a, b))
+
+
+def test_ccsd_reductions_give_zero(lib, ws):
+    for d in (I.Dims(1, 5, 4, 9, 7), I.Dims(4, 1, 5, 9, 7), I.Dims(0, 3, 3, 5, 4)):
+        p = I.make_problem(d, 3)
+        g = lib.Ground(p)
+        out = lib.ground_residual(ws, g)
+        assert all(float(v.abs().max()) == 0.0 for v in out.values())
+        R = lib.vec_to_device(I.right_vectors(p, 1)[0])
+        out = lib.right_transform(ws, g, [0.5], [R])[0]
+        assert all(float(v.abs().max()) == 0.0 for v in out.values())
+
+
+@pytest.mark.parametrize("cfg", [1])
+@pytest.mark.parametrize("rng", [(0, 5), (140, 143), (347, 352)])
+def test_full_shape_subsets(lib, ws, cfg, rng):
+    """Full config shapes (N_V, N_O, rank), a subset of the triple list (degenerate ones included)."""
+    from oracle.oracle import Oracle
+    p = I.make_config(cfg)
+    orc = Oracle(p)
+    g = lib.Ground(p)
+    R = I.right_vectors(p, 1)[0]
+    om = I.omegas(cfg, 1)[0]
+    _check(lib.ground_residual(ws, g, triple_range=rng), orc.ground_residual(*rng))
+    out = lib.right_transform(ws, g, [om], [lib.vec_to_device(R)], triple_range=rng, reuse_ground=True)[0]
+    _check(out, orc.right_transform(om, R, *rng))
+
+
+def test_full_shape_range_additivity(lib, ws):
+    """Config 1, every triple: the full call equals the sum of disjoint ranges."""
+    import torch
+    p = I.make_config(1)
+    g = lib.Ground(p)
+    R = lib.vec_to_device(I.right_vectors(p, 1)[0])
+    nt = lib.num_triples(p.dims.n_o)
+    full = lib.right_transform(ws, g, [0.4], [R])[0]
+    parts = [lib.right_transform(ws, g, [0.4], [R], triple_range=r, reuse_ground=True)[0]
+             for r in ((0, 100), (100, 251), (251, nt))]
+    for k in full:
+        tot = sum(x[k] for x in parts)
+        assert float((tot - full[k]).norm() / full[k].norm()) < 1e-13
+        assert torch.isfinite(full[k]).all()
+
+
+def test_errors(lib, ws):
+    d = I.Dims(3, 4, 4, 6, 10)
+    p = I.make_problem(d, 1)
+    g = lib.Ground(p)
+    R = lib.vec_to_device(I.right_vectors(p, 1)[0])
+    with pytest.raises(lib.MLCC3Error) as e:
+        lib.right_transform(ws, g, [0.4], [R], triple_range=(5, 2))
+    assert e.value.code == lib.EINVAL
+    # omega placed on a denominator: rejected by the guard check
+    eo, ev = p.eps_o, p.eps_v
+    w = ev[0] + ev[1] + ev[2] - eo[0] - eo[1] - eo[2]
+    with pytest.raises(lib.MLCC3Error) as e:
+        lib.right_transform(ws, g, [w], [R], guard=1e-3)
+    assert e.value.code == lib.ESINGULAR
+    bad = I.make_problem(d, 1)
+    bad.t1 = bad.t1.copy()
+    bad.t1[0, 0] = np.nan
+    with pytest.raises(lib.MLCC3Error) as e:
+        lib.ground_residual(ws, lib.Ground(bad), check_finite=True)
+    assert e.value.code == lib.ENONFINITE
+    # the workspace is still usable afterwards
+    _ = lib.ground_residual(ws, g)
