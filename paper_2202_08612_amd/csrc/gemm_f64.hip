@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
     }
   }
 
-  // epilogue: lane holds rows 4*(lane/16)+v, column lane%16 of each 16x16 tile
+  // epilogue: on gfx950 lane l, register v of a 16x16 f64 tile holds row l/16 + 4v, column l%16
   double *Cp = g.C + (long long)z * g.cbatch;
 #pragma unroll
   for (int j = 0; j < TN; j++) {
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
     for (int i = 0; i < TM; i++)
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int m = m0 + wm0 + 16 * i + 4 * (lane >> 4) + v;
+        const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
         if (m >= g.M) continue;
         const long long o = ioff(g.crow, m) + co;
         double r = g.alpha * acc[i][j][v];

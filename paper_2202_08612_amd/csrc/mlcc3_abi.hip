@@ -124,24 +124,27 @@ void validate_ground(const mlcc3_ground *g) {
   check(g->N_O >= 1 && g->N_V >= 1, "N_O and N_V must be >= 1");
   check(g->n_o >= 0 && g->n_o <= g->N_O, "need 0 <= n_o <= N_O");
   check(g->n_v >= 0 && g->n_v <= g->N_V, "need 0 <= n_v <= N_V");
-  check(g->eps_o && g->eps_v && g->L_OO && g->L_OV && g->t1 && g->t2_vVoo && g->t2_vvoO,
-        "NULL pointer in the ground-state inputs");
+  const bool act = g->n_o > 0 && g->n_v > 0;  // the t2 blocks are empty otherwise
+  check(g->eps_o && g->eps_v && g->L_OO && g->L_OV && g->t1, "NULL pointer in the ground-state inputs");
+  check(!act || (g->t2_vVoo && g->t2_vvoO), "NULL t2 block");
   check(g->n_v == 0 || g->L_vV, "L_vV is NULL");
   check((long long)g->n_o * g->n_o * g->n_o * g->n_v * g->n_v * g->n_v < (1LL << 40), "active space too large");
 }
 
-void validate_vecs(int nvec, const double *omega, const mlcc3_vec *v, const mlcc3_out *o) {
+void validate_vecs(const mlcc3_ground *g, int nvec, const double *omega, const mlcc3_vec *v, const mlcc3_out *o) {
   check(nvec >= 1, "nvec must be >= 1");
   check(omega && v && o, "NULL omega / vector / output array");
+  const bool act = g->n_o > 0 && g->n_v > 0;
   for (int m = 0; m < nvec; m++) {
-    check(v[m].x1 && v[m].x2_vVoo && v[m].x2_vvoO, "NULL pointer in an input vector");
-    check(o[m].x1 && o[m].x2_vVoo && o[m].x2_vvoO, "NULL pointer in an output vector");
+    check(v[m].x1 && (!act || (v[m].x2_vVoo && v[m].x2_vvoO)), "NULL pointer in an input vector");
+    check(o[m].x1 && (!act || (o[m].x2_vVoo && o[m].x2_vvoO)), "NULL pointer in an output vector");
     check(std::isfinite(omega[m]), "omega must be finite");
   }
 }
 
-void validate_out(const mlcc3_out *o) {
-  check(o && o->x1 && o->x2_vVoo && o->x2_vvoO, "NULL output pointer");
+void validate_out(const mlcc3_ground *g, const mlcc3_out *o) {
+  const bool act = g->n_o > 0 && g->n_v > 0;
+  check(o && o->x1 && (!act || (o->x2_vVoo && o->x2_vvoO)), "NULL output pointer");
 }
 
 struct Range {
@@ -452,6 +455,7 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
 double *B(mlcc3_ws ws, const char *name) {
   auto it = ws->bufs.find(name);
   if (it == ws->bufs.end()) throw Status{MLCC3_EHIP, std::string("internal: missing buffer ") + name};
+  reg(it->second.first, (long long)(it->second.second / sizeof(double)), "ws");
   return (double *)it->second.first;
 }
 
@@ -544,9 +548,10 @@ Gemm back_vO(const Dims &d, const double *X1, const double *G1, const double *X2
 }
 
 void zero_out(const Dims &d, const mlcc3_out *o, hipStream_t s) {
+  const size_t na = sizeof(double) * d.nv * d.NV * d.no * d.no, nb = sizeof(double) * d.nv * d.nv * d.no * d.NO;
   HIPRT(hipMemsetAsync(o->x1, 0, sizeof(double) * d.NV * d.NO, s));
-  HIPRT(hipMemsetAsync(o->x2_vVoo, 0, sizeof(double) * d.nv * d.NV * d.no * d.no, s));
-  HIPRT(hipMemsetAsync(o->x2_vvoO, 0, sizeof(double) * d.nv * d.nv * d.no * d.NO, s));
+  if (na) HIPRT(hipMemsetAsync(o->x2_vVoo, 0, na, s));
+  if (nb) HIPRT(hipMemsetAsync(o->x2_vvoO, 0, nb, s));
 }
 
 struct DeviceGuard {
@@ -662,7 +667,7 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
   return guarded([&] {
     check(ws != nullptr, "ws is NULL");
     validate_ground(g);
-    validate_out(out);
+    validate_out(g, out);
     reg_ground(g);
     reg_vec(g, out->x1, out->x2_vVoo, out->x2_vvoO);
     const mlcc3_opts o = opts_or_default(opts);
@@ -691,7 +696,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
   return guarded([&] {
     check(ws != nullptr, "ws is NULL");
     validate_ground(g);
-    validate_vecs(nvec, omega, R, rho);
+    validate_vecs(g, nvec, omega, R, rho);
     reg_ground(g);
     for (int m = 0; m < nvec; m++) {
       reg_vec(g, R[m].x1, R[m].x2_vVoo, R[m].x2_vvoO);

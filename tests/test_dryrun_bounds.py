@@ -72,3 +72,23 @@ def test_all_launches_in_bounds(lib, d):
             continue
         assert rc == 0, (fn, lib.mlcc3_last_error())
     assert lib.mlcc3_ws_destroy(ws) == 0
+
+
+def test_empty_active_space_accepts_null_blocks(lib):
+    """n_o = 0: the doubles blocks are empty and may be NULL; the call returns zeros (OK)."""
+    d = I.Dims(0, 3, 3, 5, 4)
+    ws = ctypes.c_void_p()
+    assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+    p = _fake(16)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:6], None, None)
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    out = (V * 1)(V(p[8], None, None))
+    assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == 0
+    vin = (V * 1)(V(p[9], None, None))
+    vout = (V * 1)(V(p[10], None, None))
+    om = (ctypes.c_double * 1)(0.4)
+    assert lib.mlcc3_right_transform(ws, ctypes.byref(g), 1, om, vin, vout, ctypes.byref(o), None) == 0
+    g.t1 = None
+    assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == -1
+    assert lib.mlcc3_ws_destroy(ws) == 0

@@ -78,10 +78,10 @@ def test_ccsd_reductions_give_zero(lib, ws):
         p = I.make_problem(d, 3)
         g = lib.Ground(p)
         out = lib.ground_residual(ws, g)
-        assert all(float(v.abs().max()) == 0.0 for v in out.values())
+        assert all(v.numel() == 0 or float(v.abs().max()) == 0.0 for v in out.values())
         R = lib.vec_to_device(I.right_vectors(p, 1)[0])
         out = lib.right_transform(ws, g, [0.5], [R])[0]
-        assert all(float(v.abs().max()) == 0.0 for v in out.values())
+        assert all(v.numel() == 0 or float(v.abs().max()) == 0.0 for v in out.values())
 
 
 @pytest.mark.parametrize("cfg", [1])
