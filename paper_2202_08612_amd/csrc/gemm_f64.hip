@@ -133,24 +133,49 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
     }
   }
 
-  // epilogue: on gfx950 lane l, register v of a 16x16 f64 tile holds row l/16 + 4v, column l%16
+  // epilogue: on gfx950 lane l, register v of a 16x16 f64 tile holds row l/16 + 4v, column l%16.
+  // All old C values are loaded before the first store so the loads are not serialised
+  // behind stores to the same array.
   double *Cp = g.C + (long long)z * g.cbatch;
+  long long ro[TM][4], co[TN];
+  bool rok[TM][4], cok[TN];
 #pragma unroll
   for (int j = 0; j < TN; j++) {
     const int n = n0 + wn0 + 16 * j + (lane & 15);
-    if (n >= g.N) continue;
-    const long long co = ioff(g.ccol, n);
+    cok[j] = n < g.N;
+    co[j] = cok[j] ? ioff(g.ccol, n) : 0;
+  }
 #pragma unroll
-    for (int i = 0; i < TM; i++)
+  for (int i = 0; i < TM; i++)
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
-        if (m >= g.M) continue;
-        const long long o = ioff(g.crow, m) + co;
-        double r = g.alpha * acc[i][j][v];
-        if (g.beta != 0.0) r += g.beta * Cp[o];
-        Cp[o] = r;
-      }
+    for (int v = 0; v < 4; v++) {
+      const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
+      rok[i][v] = m < g.M;
+      ro[i][v] = rok[i][v] ? ioff(g.crow, m) : 0;
+    }
+  if (g.beta != 0.0) {
+    double old[TM][TN][4];
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) old[i][j][v] = (cok[j] && rok[i][v]) ? Cp[ro[i][v] + co[j]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+          if (cok[j] && rok[i][v]) Cp[ro[i][v] + co[j]] = g.alpha * acc[i][j][v] + g.beta * old[i][j][v];
+  } else {
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+          if (cok[j] && rok[i][v]) Cp[ro[i][v] + co[j]] = g.alpha * acc[i][j][v];
   }
 }
 
@@ -164,21 +189,35 @@ static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf)
   return hipGetLastError();
 }
 
-static bool unit(const Idx2 &f) { return f.d <= 0 && f.s0 == 1; }
+// unit stride inside each run of the index (two-level maps with s0 = 1 are contiguous in runs of d)
+static bool unit(const Idx2 &f) { return f.s0 == 1; }
 
 bool g_dry = false;
+
+static int pick(int n) { return n <= 32 ? 1 : (n <= 64 ? 2 : 4); }
 
 hipError_t gemm_f64(const Gemm &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g_dry) return hipSuccess;
   if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
   const bool akf = unit(g.seg[0].A.col);
   const bool bnf = unit(g.seg[0].B.col);
-  const int tm = g.M <= 32 ? 1 : 4;
-  const int tn = g.N <= 32 ? 1 : 4;
-  if (tm == 4 && tn == 4) return launch_tiles<4, 4>(g, s, akf, bnf);
-  if (tm == 4 && tn == 1) return launch_tiles<4, 1>(g, s, akf, bnf);
-  if (tm == 1 && tn == 4) return launch_tiles<1, 4>(g, s, akf, bnf);
-  return launch_tiles<1, 1>(g, s, akf, bnf);
+  int tm = pick(g.M), tn = pick(g.N);
+  long long ktot = 0;
+  for (int i = 0; i < g.nseg; i++) ktot += g.seg[i].K;
+  // short K is bound by the C traffic: smaller tiles give more waves per SIMD
+  if (ktot <= 64) { tm = tm > 2 ? 2 : tm; tn = tn > 2 ? 2 : tn; }
+  auto blocks = [&](int a, int b) {
+    return (long long)((g.M + 32 * a - 1) / (32 * a)) * ((g.N + 32 * b - 1) / (32 * b)) * g.nbatch;
+  };
+  while (blocks(tm, tn) < 512 && (tm > 2 || tn > 2)) {
+    if (tm >= tn) tm /= 2; else tn /= 2;
+  }
+#define MLCC3_TILE(a, b) \
+  if (tm == a && tn == b) return launch_tiles<a, b>(g, s, akf, bnf);
+  MLCC3_TILE(4, 4) MLCC3_TILE(4, 2) MLCC3_TILE(4, 1) MLCC3_TILE(2, 4) MLCC3_TILE(2, 2) MLCC3_TILE(2, 1)
+  MLCC3_TILE(1, 4) MLCC3_TILE(1, 2) MLCC3_TILE(1, 1)
+#undef MLCC3_TILE
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mlcc3

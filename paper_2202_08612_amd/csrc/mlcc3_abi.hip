@@ -418,7 +418,7 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   // F_kc
   double *F = buf(ws, "F", (size_t)no * nv, s);
   launch_fock_like(g->L_OV, g->t1, nc, NO, NV, no, nv, buf(ws, "fock_s", nc, s),
-                   buf(ws, "fock_y", (size_t)nc * no * NO, s), F, s);
+                   buf(ws, "fock_y", (size_t)nc * no * NO, s), buf(ws, "fock_z", (size_t)nc * no * nv, s), F, s);
   // tA[p][q][a][D] = t^{aD}_{pq}
   launch_pack_vVoo(g->t2_vVoo, no, nv, NV, 0, buf(ws, "tA", (size_t)no * no * nv * NV, s), s);
   HIPRT(hipGetLastError());
@@ -460,9 +460,23 @@ double *B(mlcc3_ws ws, const char *name) {
 }
 
 // ------------------------------------------------------------ W and X~ builders
-// W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G[r][D][(b,c)]  (+ second segment)
-void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, const double *xA2, const double *G2,
-             hipStream_t s) {
+// B operand of the d-contraction for batch r: element (D, (b,c)) of G_r
+struct BMap {
+  const double *p;
+  Idx2 row, col;
+  long long batch;
+};
+// G stored [r][D][b][c]
+BMap bm_rDbc(const Dims &d, const double *G) { return {G, plain(d.nv2), plain(1), (long long)d.NV * d.nv2}; }
+// G stored [r][b][c][D]
+BMap bm_rbcD(const Dims &d, const double *G) { return {G, plain(1), plain(d.NV), (long long)d.NV * d.nv2}; }
+// occupied-term B operand (L, (q,r,c)): stored [L][q][r][c]
+BMap bm_Lqrc(const Dims &d, const double *G) { return {G, plain((long long)d.no * d.no * d.nv), plain(1), 0}; }
+// stored [q][r][c][L]
+BMap bm_qrcL(const Dims &d, const double *G) { return {G, plain(1), plain(d.NO), 0}; }
+
+// W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G_r(D,(b,c))  (+ second segment)
+void w_dterm(const Dims &d, double *W, const double *xA1, BMap G1, const double *xA2, BMap G2, hipStream_t s) {
   Gemm g;
   g.M = d.no * d.no * d.nv;
   g.N = (int)d.nv2;
@@ -472,14 +486,13 @@ void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, cons
   g.ccol = plain(1);
   g.cbatch = d.nv3;
   g.nseg = xA2 ? 2 : 1;
-  g.seg[0] = seg(xA1, plain(d.NV), plain(1), 0, G1, plain(d.nv2), plain(1), (long long)d.NV * d.nv2, d.NV);
-  if (xA2) g.seg[1] = seg(xA2, plain(d.NV), plain(1), 0, G2, plain(d.nv2), plain(1), (long long)d.NV * d.nv2, d.NV);
+  g.seg[0] = seg(xA1, plain(d.NV), plain(1), 0, G1.p, G1.row, G1.col, G1.batch, d.NV);
+  if (xA2) g.seg[1] = seg(xA2, plain(d.NV), plain(1), 0, G2.p, G2.row, G2.col, G2.batch, d.NV);
   gemm(g, s);
 }
 
-// W[p][q][r][a][b][c] -= sum_L x^{ab}_{pL} Go[L][(q,r,c)]  (+ second segment)
-void w_oterm(const Dims &d, double *W, const double *xB1, const double *Go1, const double *xB2, const double *Go2,
-             hipStream_t s) {
+// W[p][q][r][a][b][c] -= sum_L x^{ab}_{pL} G(L,(q,r,c))  (+ second segment); x stored [a][b][p][L]
+void w_oterm(const Dims &d, double *W, const double *xB1, BMap G1, const double *xB2, BMap G2, hipStream_t s) {
   Gemm g;
   g.M = (int)d.nv2;
   g.N = d.no * d.no * d.nv;
@@ -491,16 +504,16 @@ void w_oterm(const Dims &d, double *W, const double *xB1, const double *Go1, con
   g.alpha = -1.0;
   g.beta = 1.0;
   g.nseg = xB2 ? 2 : 1;
-  const long long ldB = (long long)d.no * d.no * d.nv;
-  g.seg[0] = seg(xB1, plain((long long)d.no * d.NO), plain(1), d.NO, Go1, plain(ldB), plain(1), 0, d.NO);
-  if (xB2) g.seg[1] = seg(xB2, plain((long long)d.no * d.NO), plain(1), d.NO, Go2, plain(ldB), plain(1), 0, d.NO);
+  g.seg[0] = seg(xB1, plain((long long)d.no * d.NO), plain(1), d.NO, G1.p, G1.row, G1.col, G1.batch, d.NO);
+  if (xB2) g.seg[1] = seg(xB2, plain((long long)d.no * d.NO), plain(1), d.NO, G2.p, G2.row, G2.col, G2.batch, d.NO);
   gemm(g, s);
 }
 
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
              double omega, Range r, const LocalTerms &lt, hipStream_t s) {
-  launch_permute_denom(W, Xt, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, omega, r.tb,
-                       r.te, lt, s);
+  double *Xu = buf(ws, "Xu", (size_t)ws->nu * d.nv3, s);
+  launch_permute_denom(W, Xu, Xt, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, omega,
+                       r.tb, r.te, lt, s);
   HIPRT(hipGetLastError());
 }
 
@@ -508,28 +521,36 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
 void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s) {
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
-  w_dterm(d, W, B(ws, "tA"), B(ws, "G1"), nullptr, nullptr, s);
-  w_oterm(d, W, g->t2_vvoO, B(ws, "G2"), nullptr, nullptr, s);
+  w_dterm(d, W, B(ws, "tA"), bm_rDbc(d, B(ws, "G1")), nullptr, BMap{}, s);
+  w_oterm(d, W, g->t2_vvoO, bm_Lqrc(d, B(ws, "G2")), nullptr, BMap{}, s);
   permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, s);
 }
 
-// Y[(i,j,a)][D] = sum_{k,bc} X~[i][j][k][a][b][c] G[k][b][c][D]   (+ optional second segment)
-Gemm back_vV(const Dims &d, const double *X, const double *G, int N, double *Y) {
+// Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
+// writes one partial product per k into P[k][(i,j,a)][n] and a fixed-order sum reduces them.
+void back_vV(mlcc3_ws ws, const Dims &d, const double *X, BMap G, int N, double *Y, hipStream_t s) {
+  const long long MN = (long long)d.no * d.no * d.nv * N;
+  double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
   Gemm g;
   g.M = d.no * d.no * d.nv;
   g.N = N;
-  g.C = Y;
+  g.nbatch = d.no;
+  g.C = P;
   g.crow = plain(N);
   g.ccol = plain(1);
+  g.cbatch = MN;
   g.nseg = 1;
-  g.seg[0] = seg(X, split(d.nv, (long long)d.no * d.nv3, d.nv2), split((int)d.nv2, d.nv3, 1), 0, G, plain(N),
-                 plain(1), 0, (int)(d.no * d.nv2));
-  return g;
+  g.seg[0] = seg(X, split(d.nv, (long long)d.no * d.nv3, d.nv2), plain(1), d.nv3, G.p, G.row, G.col, G.batch,
+                 (int)d.nv2);
+  gemm(g, s);
+  launch_sum_rows(P, d.no, MN, Y, s);
+  HIPRT(hipGetLastError());
 }
+// G stored [k][b][c][n] with n-extent N
+BMap bm_kbcN(const Dims &d, const double *G, int N) { return {G, plain(N), plain(1), d.nv2 * N}; }
 
-// Y[i][(a,b)][L] = alpha * sum_{(j,k,c)} X~[i][j][k][a][b][c] G[(j,k,c)][L]   (+ second segment)
-Gemm back_vO(const Dims &d, const double *X1, const double *G1, const double *X2, const double *G2, double *Y,
-             double alpha) {
+// Y[i][(a,b)][L] = alpha * sum_{(j,k,c)} X~[i][j][k][a][b][c] G((j,k,c),L)   (+ second segment)
+Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2, double *Y, double alpha) {
   Gemm g;
   g.M = (int)d.nv2;
   g.N = d.NO;
@@ -542,8 +563,42 @@ Gemm back_vO(const Dims &d, const double *X1, const double *G1, const double *X2
   g.nseg = X2 ? 2 : 1;
   const int K = d.no * d.no * d.nv;
   const long long xb = (long long)d.no * d.no * d.nv3;
-  g.seg[0] = seg(X1, plain(d.nv), split(d.nv, d.nv3, 1), xb, G1, plain(d.NO), plain(1), 0, K);
-  if (X2) g.seg[1] = seg(X2, plain(d.nv), split(d.nv, d.nv3, 1), xb, G2, plain(d.NO), plain(1), 0, K);
+  g.seg[0] = seg(X1, plain(d.nv), split(d.nv, d.nv3, 1), xb, G1.p, G1.row, G1.col, G1.batch, K);
+  if (X2) g.seg[1] = seg(X2, plain(d.nv), split(d.nv, d.nv3, 1), xb, G2.p, G2.row, G2.col, G2.batch, K);
+  return g;
+}
+// G stored [j][k][c][L]
+BMap bm_jkcL(const Dims &d, const double *G) { return {G, plain(d.NO), plain(1), 0}; }
+
+// Y[(q,r,c)][M] = sum_{p,(a,b)} X~[p][q][r][a][b][c] x[a][b][p][M], split over p
+void back_qrc(mlcc3_ws ws, const Dims &d, const double *X, const double *x, double *Y, hipStream_t s) {
+  const long long MN = (long long)d.no * d.no * d.nv * d.NO;
+  double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
+  Gemm g;
+  g.M = d.no * d.no * d.nv;
+  g.N = d.NO;
+  g.nbatch = d.no;
+  g.C = P;
+  g.crow = plain(d.NO);
+  g.ccol = plain(1);
+  g.cbatch = MN;
+  g.nseg = 1;
+  g.seg[0] = seg(X, split(d.nv, d.nv3, 1), plain(d.nv), (long long)d.no * d.no * d.nv3, x,
+                 plain((long long)d.no * d.NO), plain(1), d.NO, (int)d.nv2);
+  gemm(g, s);
+  launch_sum_rows(P, d.no, MN, Y, s);
+  HIPRT(hipGetLastError());
+}
+
+Gemm gemm_plain(int M, int N, double *C, Idx2 crow, Idx2 ccol, double alpha, double beta) {
+  Gemm g;
+  g.M = M;
+  g.N = N;
+  g.C = C;
+  g.crow = crow;
+  g.ccol = ccol;
+  g.alpha = alpha;
+  g.beta = beta;
   return g;
 }
 
@@ -685,8 +740,8 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
     double *XT = B(ws, "XT");
     double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
     double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
-    gemm(back_vV(d, XT, B(ws, "Gb1"), d.NV, YvV), s);
-    gemm(back_vO(d, XT, B(ws, "Gb3"), nullptr, nullptr, YvO, -1.0), s);
+    back_vV(ws, d, XT, bm_kbcN(d, B(ws, "Gb1"), d.NV), d.NV, YvV, s);
+    gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
     finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
   });
 }
@@ -722,7 +777,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     tau_path(ws, g, d, r, s);
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    gemm(back_vV(d, XT, B(ws, "gLb"), NO, Xtau), s);
+    back_vV(ws, d, XT, bm_kbcN(d, B(ws, "gLb"), NO), NO, Xtau, s);
     double *W = B(ws, "W");
     double *XR = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
     for (int m = 0; m < nvec; m++) {
@@ -753,7 +808,8 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
         gemm(gg, s);
       }
       double *Ukc = buf(ws, "Ukc", (size_t)no * nv, s);
-      launch_fock_like(g->L_OV, R[m].x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), Ukc, s);
+      launch_fock_like(g->L_OV, R[m].x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc,
+                       s);
       // Xi[(j,k,c)][L] = sum_D g_jDkc R^D_L
       double *Xi = buf(ws, "Xi", (size_t)no * no * nv * NO, s);
       {
@@ -768,19 +824,27 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
         gemm(gg, s);
       }
       // R3 before P: W(Rbar; ghat) + W(t; Upsilon)
-      w_dterm(d, W, RA, B(ws, "G1"), B(ws, "tA"), U1, s);
-      w_oterm(d, W, RB, B(ws, "G2"), g->t2_vvoO, Uo, s);
+      w_dterm(d, W, RA, bm_rDbc(d, B(ws, "G1")), B(ws, "tA"), bm_rDbc(d, U1), s);
+      w_oterm(d, W, RB, bm_Lqrc(d, B(ws, "G2")), g->t2_vvoO, bm_Lqrc(d, Uo), s);
       permute(ws, d, W, XR, g->eps_o, g->eps_v, omega[m], r, LocalTerms{}, s);
       // back-contractions
       double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
       double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-      {
-        Gemm gg = back_vV(d, XR, B(ws, "Gb1"), NV, YvV);
-        gg.nseg = 2;  // - sum_L Xtau[(i,j,a)][L] R^D_L
-        gg.seg[1] = seg(Xtau, plain(NO), plain(1), 0, R[m].x1, plain(1), plain(NO), 0, NO, -1.0);
+      back_vV(ws, d, XR, bm_kbcN(d, B(ws, "Gb1"), NV), NV, YvV, s);
+      {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
+        Gemm gg;
+        gg.M = no * no * nv;
+        gg.N = NV;
+        gg.C = YvV;
+        gg.crow = plain(NV);
+        gg.ccol = plain(1);
+        gg.alpha = -1.0;
+        gg.beta = 1.0;
+        gg.nseg = 1;
+        gg.seg[0] = seg(Xtau, plain(NO), plain(1), 0, R[m].x1, plain(1), plain(NO), 0, NO);
         gemm(gg, s);
       }
-      gemm(back_vO(d, XR, B(ws, "Gb3"), XT, Xi, YvO, -1.0), s);
+      gemm(back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), XT, bm_jkcL(d, Xi), YvO, -1.0), s);
       finish_right_like(ws, d, XR, XT, Ukc, YvV, YvO, 1, &rho[m], s);
     }
   });
@@ -789,8 +853,187 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
 int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
                          const mlcc3_vec *L, mlcc3_out *sigma, const mlcc3_opts *opts, void *stream) {
   return guarded([&] {
-    (void)ws; (void)g; (void)nvec; (void)omega; (void)L; (void)sigma; (void)opts; (void)stream;
-    throw Status{MLCC3_EUNSUPPORTED, "left transform not built yet"};
+    check(ws != nullptr, "ws is NULL");
+    validate_ground(g);
+    validate_vecs(g, nvec, omega, L, sigma);
+    reg_ground(g);
+    for (int m = 0; m < nvec; m++) {
+      reg_vec(g, L[m].x1, L[m].x2_vVoo, L[m].x2_vvoO);
+      reg_vec(g, sigma[m].x1, sigma[m].x2_vVoo, sigma[m].x2_vvoO);
+    }
+    const mlcc3_opts o = opts_or_default(opts);
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(ws->device);
+    const Dims d = dims_of(g);
+    const Range r = range_of(o, mlcc3_num_triples(d.no));
+    if (o.check_finite) {
+      ground_finite(ws, g, s);
+      for (int m = 0; m < nvec; m++) vec_finite(ws, d, L[m], s);
+    }
+    guard_check(g, omega, nvec, o.guard, s);
+    if (d.no < 2 || d.nv < 2 || r.tb == r.te) {
+      for (int m = 0; m < nvec; m++) zero_out(d, &sigma[m], s);
+      return;
+    }
+    prepare_ground(ws, g, o.reuse_ground != 0, s);
+    const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
+    tau_path(ws, g, d, r, s);
+    double *XT = B(ws, "XT");
+    double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
+    back_vV(ws, d, XT, bm_kbcN(d, B(ws, "gLb"), NO), NO, Xtau, s);
+    double *W = B(ws, "W");
+    double *XL = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
+    double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
+    for (int m = 0; m < nvec; m++) {
+      const double *L1 = L[m].x1, *L2a = L[m].x2_vVoo, *L2b = L[m].x2_vvoO;
+      double *LA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
+      double *LV = buf(ws, "LV", (size_t)no * no * d.nv2, s);
+      launch_pack_vVoo(L2a, no, nv, NV, 0, LA, s);
+      launch_pack_vvoo(L2a, no, nv, NV, LV, s);
+      // L3 before P (SI transpose transformation, exact-transpose index placement):
+      //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc  (+ local terms in the permute pass)
+      w_dterm(d, W, LA, bm_rbcD(d, B(ws, "Gb1")), nullptr, BMap{}, s);
+      w_oterm(d, W, L2b, bm_qrcL(d, B(ws, "Gb3")), nullptr, BMap{}, s);
+      LocalTerms lt;
+      lt.L1 = L1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
+      permute(ws, d, W, XL, g->eps_o, g->eps_v, omega[m], r, lt, s);
+      // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
+      double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+      double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+      back_vV(ws, d, XL, BMap{B(ws, "G1"), plain(1), plain(d.nv2), (long long)NV * d.nv2}, NV, QvV, s);
+      gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
+           s);
+      // intermediates of the singles
+      // Bq[r][(b,c)][E] = sum_{(p,q,a)} L~[p][q][r][a][b][c] t^{aE}_{pq}
+      double *Bq = buf(ws, "Bq", (size_t)no * d.nv2 * NV, s);
+      {
+        Gemm gg = gemm_plain((int)d.nv2, NV, Bq, plain(NV), plain(1), 1.0, 0.0);
+        gg.nbatch = no;
+        gg.cbatch = d.nv2 * NV;
+        gg.nseg = 1;
+        gg.seg[0] = seg(XL, plain(1), split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), plain(NV), plain(1),
+                        0, no * no * nv);
+        gemm(gg, s);
+      }
+      // Aq[(q,r,c)][M] = sum L~[p][q][r][a][b][c] t^{ab}_{pM};  Qtau likewise with tau~ and L^{ab}_{pL}
+      double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);
+      double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);
+      back_qrc(ws, d, XL, g->t2_vvoO, Aq, s);
+      back_qrc(ws, d, XT, L2b, Qtau, s);
+      double *V = buf(ws, "Vkc", (size_t)no * nv, s);  // V_kc = sum tau~ L^{ab}_{ij} = sum_q Qtau[q][k][c][q]
+      launch_diag_sum(Qtau, no, nv, NO, V, s);
+      HIPRT(hipGetLastError());
+      double *s1 = sigma[m].x1;
+      HIPRT(hipMemsetAsync(s1, 0, sizeof(double) * NV * NO, s));
+      // (i) sigma^D_L += sum_kc V_kc (2 g_kcLD - g_kDLc) = sum_J [2 s_J L_LD - sum_k L_kD u_J[k][L]]
+      {
+        double *sJ = buf(ws, "vs_J", (size_t)nc, s);
+        double *uJ = buf(ws, "vu_J", (size_t)nc * no * NO, s);
+        // s_J = sum_kc V_kc L^J_kc  (A: [J][(k,c)] from L_OV)
+        Gemm g1 = gemm_plain(nc, 1, sJ, plain(1), plain(1), 1.0, 0.0);
+        g1.nseg = 1;
+        g1.seg[0] = seg(g->L_OV, plain((long long)NO * NV), split(nv, NV, 1), 0, V, plain(1), plain(1), 0, no * nv);
+        gemm(g1, s);
+        // u_J[k][L] = sum_c L_OV[J][L][c] V[k][c]   (rows (J,L))
+        Gemm g3 = gemm_plain(nc * NO, no, uJ, split(NO, (long long)no * NO, 1), plain(NO), 1.0, 0.0);
+        g3.nseg = 1;
+        g3.seg[0] = seg(g->L_OV, plain(NV), plain(1), 0, V, plain(1), plain(nv), 0, nv);
+        gemm(g3, s);
+        // sigma[D][L] += 2 sum_J L_OV[J][L][D] s_J   (rows (L,D))
+        Gemm g4 = gemm_plain(NO * NV, 1, s1, split(NV, 1, NO), plain(0), 2.0, 1.0);
+        g4.nseg = 1;
+        g4.seg[0] = seg(g->L_OV, plain(1), plain((long long)NO * NV), 0, sJ, plain(1), plain(1), 0, nc);
+        gemm(g4, s);
+        // sigma[D][L] -= sum_{(J,k)} L_OV[J][k][D] u_J[k][L]
+        Gemm g5 = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
+        g5.nseg = 1;
+        g5.seg[0] = seg(g->L_OV, plain(1), split(no, (long long)NO * NV, NV), 0, uJ, plain(NO), plain(1), 0, nc * no);
+        gemm(g5, s);
+      }
+      // (ii) sigma^D_L -= sum L^{aD}_{ij} Xtau[(i,j,a)][L] ; (iii) -= sum g_jDkc Qtau[(j,k,c)][L]
+      {
+        Gemm gg = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
+        gg.nseg = 2;
+        gg.seg[0] = seg(LA, plain(1), plain(NV), 0, Xtau, plain(NO), plain(1), 0, no * no * nv);
+        gg.seg[1] = seg(B(ws, "gDo"), plain(1), plain(NV), 0, Qtau, plain(NO), plain(1), 0, no * no * nv);
+        gemm(gg, s);
+      }
+      // (iv) sigma^D_l += sum_{J,c} Lh_cD (Hp - H2)[l][J][c] - sum_{J,M} L_MD H3[l][J][M]
+      double *Hp = buf(ws, "Hp", (size_t)no * nc * nv, s);
+      double *H2 = buf(ws, "H2", (size_t)no * nc * nv, s);
+      double *H3 = buf(ws, "H3", (size_t)no * nc * NO, s);
+      {
+        // Hp[l][J][c] = sum_{(b,E)} Lh_bE Bq[l][b][c][E]
+        Gemm gg = gemm_plain(nc, nv, Hp, plain(nv), plain(1), 1.0, 0.0);
+        gg.nbatch = no;
+        gg.cbatch = (long long)nc * nv;
+        gg.nseg = 1;
+        gg.seg[0] = seg(LhvV, plain((long long)nv * NV), plain(1), 0, Bq, split(NV, (long long)nv * NV, 1), plain(NV),
+                        d.nv2 * NV, nv * NV);
+        gemm(gg, s);
+        // H2[l][J][c] = sum_{(j,M)} Lh_Mj Aq[j][l][c][M]
+        Gemm g2 = gemm_plain(nc, nv, H2, plain(nv), plain(1), 1.0, 0.0);
+        g2.nbatch = no;
+        g2.cbatch = (long long)nc * nv;
+        g2.nseg = 1;
+        g2.seg[0] = seg(LhOO, plain((long long)NO * NO), split(NO, 1, NO), 0, Aq,
+                        split(NO, (long long)no * nv * NO, 1), plain(NO), (long long)nv * NO, no * NO);
+        gemm(g2, s);
+        // H3[l][J][M] = sum_{(k,c)} Lh_ck Aq[l][k][c][M]
+        Gemm g3 = gemm_plain(nc, NO, H3, plain(NO), plain(1), 1.0, 0.0);
+        g3.nbatch = no;
+        g3.cbatch = (long long)nc * NO;
+        g3.nseg = 1;
+        g3.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Aq, plain(NO), plain(1),
+                        (long long)no * nv * NO, no * nv);
+        gemm(g3, s);
+        // sigma[D][l] += sum Lh_cD (Hp - H2)
+        Gemm g4 = gemm_plain(NV, no, s1, plain(NO), plain(1), 1.0, 1.0);
+        g4.nseg = 2;
+        g4.seg[0] = seg(LhvV, plain(1), plain(NV), 0, Hp, plain(1), plain((long long)nc * nv), 0, nc * nv);
+        g4.seg[1] = seg(LhvV, plain(1), plain(NV), 0, H2, plain(1), plain((long long)nc * nv), 0, nc * nv, -1.0);
+        gemm(g4, s);
+        // sigma[D][l] -= sum L_MD H3
+        Gemm g5 = gemm_plain(NV, no, s1, plain(NO), plain(1), -1.0, 1.0);
+        g5.nseg = 1;
+        g5.seg[0] = seg(g->L_OV, plain(1), plain(NV), 0, H3, plain(1), plain((long long)nc * NO), 0, nc * NO);
+        gemm(g5, s);
+      }
+      // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE He[J][d][E]
+      {
+        double *Am = buf(ws, "Am", (size_t)no * nc * no * nv, s);
+        double *Z = buf(ws, "Zl", (size_t)nc * no * nv, s);
+        double *He = buf(ws, "He", (size_t)nc * nv * NV, s);
+        // Am[j][J][(k,d)] = sum_M Lh_Mj Aq[j][k][d][M]
+        Gemm g1 = gemm_plain(nc, no * nv, Am, plain((long long)no * nv), plain(1), 1.0, 0.0);
+        g1.nbatch = no;
+        g1.cbatch = (long long)nc * no * nv;
+        g1.nseg = 1;
+        g1.seg[0] = seg(LhOO, plain((long long)NO * NO), plain(NO), 1, Aq, plain(1), plain(NO), (long long)no * nv * NO,
+                        NO);
+        gemm(g1, s);
+        launch_left_Z(Am, Hp, nc, no, nv, Z, s);
+        HIPRT(hipGetLastError());
+        // He[J][(d,E)] = sum_{(k,c)} Lh_ck Bq[k][d][c][E]
+        Gemm g2 = gemm_plain(nc, nv * NV, He, plain((long long)nv * NV), plain(1), 1.0, 0.0);
+        g2.nseg = 1;
+        g2.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Bq, split(nv, d.nv2 * NV, NV),
+                        split(NV, (long long)nv * NV, 1), 0, no * nv);
+        gemm(g2, s);
+        // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(J,E)} He[J][d][E] L_LE
+        Gemm g3 = gemm_plain(nv, NO, s1, plain(NO), plain(1), 1.0, 1.0);
+        g3.nseg = 2;
+        g3.seg[0] = seg(Z, plain(1), plain(nv), 0, LhOO, split(no, (long long)NO * NO, 1), plain(NO), 0, nc * no);
+        g3.seg[1] = seg(He, plain(NV), split(NV, (long long)nv * NV, 1), 0, g->L_OV, split(NV, (long long)NO * NV, 1),
+                        plain(NV), 0, nc * NV, -1.0);
+        gemm(g3, s);
+      }
+      DoublesRaw y;
+      y.YvV = QvV; y.YvO = QvO; y.Yvv = nullptr;
+      y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
+      launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
+      HIPRT(hipGetLastError());
+    }
   });
 }
 

@@ -34,15 +34,20 @@ void launch_lhat(const double *LOO, const double *LOV, const double *LvV, const 
 void launch_dlhat(const double *LOV, const double *LhvV, const double *LhOO, const double *R1, int nc, int NO,
                   int NV, int nv, double *dOO, double *dvV, double *dvO, hipStream_t s);
 void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV, int no, int nv,
-                      double *tmp_s, double *tmp_y, double *out, hipStream_t s);
+                      double *tmp_s, double *tmp_y, double *tmp_z, double *out, hipStream_t s);
 void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA, hipStream_t s);
 void launch_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB, hipStream_t s);
 void launch_pack_vvoo(const double *x, int no, int nv, int NV, double *xV, hipStream_t s);
-void launch_permute_denom(const double *W, double *Xt, const UniqueTriple *ut, int nu, int no, int nv,
+// W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
+void launch_permute_denom(const double *W, double *Xu, double *Xt, const UniqueTriple *ut, int nu, int no, int nv,
                           const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
                           const LocalTerms &lt, hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
+// out[i] = sum_r P[r][i], r = 0..rows-1 (fixed order)
+void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s);
+void launch_diag_sum(const double *Q, int no, int nv, int NO, double *V, hipStream_t s);
+void launch_left_Z(const double *Am, const double *Hp, int nc, int no, int nv, double *Z, hipStream_t s);
 void launch_singles_out(const double *part1, int no, int nv, int NO, int NV, double *x1, hipStream_t s);
 void launch_doubles_out(const DoublesRaw &y, double *out_a, double *out_b, hipStream_t s);
 

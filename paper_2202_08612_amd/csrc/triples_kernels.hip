@@ -128,19 +128,25 @@ __global__ void k_fock_y(const double *LOV, const double *x, int nc, int NO, int
   y[id] = s;
 }
 
-__global__ void k_fock_out(const double *LOV, const double *s, const double *y, int nc, int NO, int NV,
-                           int no, int nv, double *out) {
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= no * nv) return;
-  const int c = id % nv, k = id / nv;
+__global__ void k_fock_z(const double *LOV, const double *s, const double *y, int nc, int NO, int NV, int no,
+                         int nv, double *z) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * no * nv) return;
+  const int c = id % nv, k = (id / nv) % no;
+  const long long J = id / ((long long)no * nv);
+  const double *l = LOV + J * NO * NV;
+  double e = 2.0 * l[(long long)k * NV + c] * s[J];
+  const double *yy = y + (J * no + k) * NO;
+  for (int L = 0; L < NO; L++) e -= yy[L] * l[(long long)L * NV + c];
+  z[id] = e;
+}
+
+// out[k][c] = sum_J z[J][k][c]  (fixed summation order)
+__global__ void k_sum_rows(const double *z, long long rows, long long n, double *out) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= n) return;
   double acc = 0.0;
-  for (int J = 0; J < nc; J++) {
-    const double *l = LOV + (long long)J * NO * NV;
-    double e = 2.0 * l[(long long)k * NV + c] * s[J];
-    const double *yy = y + ((long long)J * no + k) * NO;
-    for (int L = 0; L < NO; L++) e -= yy[L] * l[(long long)L * NV + c];
-    acc += e;
-  }
+  for (long long J = 0; J < rows; J++) acc += z[J * n + id];
   out[id] = acc;
 }
 
@@ -177,55 +183,134 @@ __global__ void k_pack_vvoo(const double *x, int no, int nv, int NV, double *xV)
 }
 
 // ------------------------------------------ permutation / denominator / contravariant
-// One block per (unique triple u, first virtual a).  For v=(a,b,c):
-//   S(v') = sum over the six pair permutations s of W_{o.s}[v'.s]        (P, eq. tau3)
-//   X~(v) = -(4S(abc) - 2S(bac) - 2S(cba) - 2S(acb) + S(cab) + S(bca)) / (eps - omega)
-// and X~ is written to every distinct ordering o.s of the triple at v.s (X~ is
-// pair-symmetric).  All-equal triples and triples outside the requested range get 0.
+// Two LDS-tiled passes over 16^3 sub-cubes of the virtual index space.
+//
+// pass 1 (k_sym_denom): for unique triple o and output tile (TA,TB,TC)
+//   X_o[v] = -(sum over the six pair permutations s of W_{o.s}[v.s]) / (eps - omega)   (P, eq. tau3)
+//   Each source sub-cube W_{o.s}[tile.s] is read coalesced (c fastest) into LDS and
+//   gathered through the permuted local index.
+// pass 2 (k_contra_scatter): X~_o[v] = 4X - 2X^{bac} - 2X^{cba} - 2X^{acb} + X^{cab} + X^{bca}
+//   (virtual permutations t at fixed ijk, same LDS gather), then X~ is written to every
+//   distinct ordering o.s at index v.s (X~ is pair-symmetric), staged through LDS so the
+//   global stores are coalesced.  All-equal triples and triples outside the requested
+//   range produce zero blocks.
 __device__ __constant__ int c_perm[6][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {0, 2, 1}, {2, 0, 1}, {1, 2, 0}};
+__device__ __constant__ double c_coef[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
 
-__global__ __launch_bounds__(256) void k_permute_denom(const double *__restrict__ W, double *__restrict__ Xt,
-                                                       const UniqueTriple *ut, int no, int nv,
-                                                       const double *eps_o, const double *eps_v,
-                                                       double omega, long long tb, long long te,
-                                                       LocalTerms lt) {
+constexpr int TT = 16;              // sub-cube edge
+constexpr int LY = TT + 1, LX = (TT + 1) * (TT + 1);  // odd strides (in doubles) against bank conflicts
+constexpr int SUB = TT * LX;
+
+// load the sub-cube of block src starting at (X0,Y0,Z0) into lds[x*LX + y*LY + z]
+__device__ __forceinline__ void load_cube(const double *__restrict__ src, int nv, int X0, int Y0, int Z0,
+                                          double *lds) {
+  const int tid = threadIdx.x;
+  const int y = tid >> 4, z = tid & 15;
+  const long long nv2 = (long long)nv * nv;
+#pragma unroll 4
+  for (int x = 0; x < TT; x++) {
+    const int gx = X0 + x, gy = Y0 + y, gz = Z0 + z;
+    double v = 0.0;
+    if (gx < nv && gy < nv && gz < nv) v = src[gx * nv2 + (long long)gy * nv + gz];
+    lds[x * LX + y * LY + z] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W, double *__restrict__ Xu,
+                                                   const UniqueTriple *ut, int no, int nv, const double *eps_o,
+                                                   const double *eps_v, double omega, long long tb, long long te,
+                                                   LocalTerms lt) {
+  __shared__ double cube[SUB];
   const UniqueTriple u = ut[blockIdx.x];
-  const int a = blockIdx.y;
+  const int nt = (nv + TT - 1) / TT;
+  const int T[3] = {(int)blockIdx.y / (nt * nt), ((int)blockIdx.y / nt) % nt, (int)blockIdx.y % nt};
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
   const bool active = !(u.i == u.j && u.j == u.k) && u.canon >= tb && u.canon < te;
-  long long base[6];
-  for (int s = 0; s < 6; s++)
-    base[s] = ((long long)(o[c_perm[s][0]] * no + o[c_perm[s][1]]) * no + o[c_perm[s][2]]) * nv3;
-  const double eocc = eps_o[u.i] + eps_o[u.j] + eps_o[u.k];
-  for (int bc = threadIdx.x; bc < nv2; bc += blockDim.x) {
-    const int b = bc / nv, c = bc % nv;
-    const int v[3] = {a, b, c};
-    double val = 0.0;
-    if (active) {
-      // virtual permutations tau of v with contravariant coefficients
-      const int tv[6][3] = {{a, b, c}, {b, a, c}, {c, b, a}, {a, c, b}, {c, a, b}, {b, c, a}};
-      const double coef[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
-      double acc = 0.0;
-      for (int t = 0; t < 6; t++) {
-        double S = 0.0;
-        for (int s = 0; s < 6; s++) {
-          const int x = tv[t][c_perm[s][0]], y = tv[t][c_perm[s][1]], z = tv[t][c_perm[s][2]];
-          S += W[base[s] + (x * nv + y) * (long long)nv + z];
-          if (lt.L1) {
-            const int p = o[c_perm[s][0]], q = o[c_perm[s][1]], r = o[c_perm[s][2]];
-            S += lt.L1[(long long)x * lt.NO + p] * lt.gov[(((long long)q * no + r) * nv + y) * nv + z] +
-                 lt.LV[(((long long)p * no + q) * nv + x) * nv + y] * lt.F[(long long)r * nv + z];
-          }
-        }
-        acc += coef[t] * S;
-      }
-      const double den = eps_v[a] + eps_v[b] + eps_v[c] - eocc - omega;
-      val = -acc / den;
-    }
+  const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
+  double acc[TT];
+#pragma unroll
+  for (int r = 0; r < TT; r++) acc[r] = 0.0;
+  if (active) {
     for (int s = 0; s < 6; s++) {
-      if (!((u.mask >> s) & 1)) continue;
-      Xt[base[s] + (v[c_perm[s][0]] * nv + v[c_perm[s][1]]) * (long long)nv + v[c_perm[s][2]]] = val;
+      const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
+      const long long base = ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
+      __syncthreads();
+      load_cube(W + base, nv, TT * T[s0], TT * T[s1], TT * T[s2], cube);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < TT; r++) {
+        const int v[3] = {r, lb, lc};
+        acc[r] += cube[v[s0] * LX + v[s1] * LY + v[s2]];
+      }
+      if (lt.L1) {  // local terms of the left triples: L^x_p g_qyrz + L^{xy}_{pq} F_rz
+        const int p = o[s0], q = o[s1], rr = o[s2];
+#pragma unroll 4
+        for (int r = 0; r < TT; r++) {
+          const int g[3] = {TT * T[0] + r, TT * T[1] + lb, TT * T[2] + lc};
+          if (g[0] >= nv || g[1] >= nv || g[2] >= nv) continue;
+          const int x = g[s0], y = g[s1], z = g[s2];
+          acc[r] += lt.L1[(long long)x * lt.NO + p] * lt.gov[(((long long)q * no + rr) * nv + y) * nv + z] +
+                    lt.LV[(((long long)p * no + q) * nv + x) * nv + y] * lt.F[(long long)rr * nv + z];
+        }
+      }
+    }
+  }
+  const double eocc = eps_o[u.i] + eps_o[u.j] + eps_o[u.k];
+  double *dst = Xu + (long long)blockIdx.x * nv3;
+  const int gb = TT * T[1] + lb, gc = TT * T[2] + lc;
+  if (gb >= nv || gc >= nv) return;
+#pragma unroll
+  for (int r = 0; r < TT; r++) {
+    const int ga = TT * T[0] + r;
+    if (ga >= nv) break;
+    const double den = eps_v[ga] + eps_v[gb] + eps_v[gc] - eocc - omega;
+    dst[ga * nv2 + (long long)gb * nv + gc] = active ? -acc[r] / den : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, double *__restrict__ Xt,
+                                                        const UniqueTriple *ut, int no, int nv) {
+  __shared__ double cube[SUB];
+  const UniqueTriple u = ut[blockIdx.x];
+  const int nt = (nv + TT - 1) / TT;
+  const int T[3] = {(int)blockIdx.y / (nt * nt), ((int)blockIdx.y / nt) % nt, (int)blockIdx.y % nt};
+  const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
+  const int o[3] = {u.i, u.j, u.k};
+  const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
+  const double *src = Xu + (long long)blockIdx.x * nv3;
+  double acc[TT];
+#pragma unroll
+  for (int r = 0; r < TT; r++) acc[r] = 0.0;
+  for (int t = 0; t < 6; t++) {
+    const int t0 = c_perm[t][0], t1 = c_perm[t][1], t2 = c_perm[t][2];
+    __syncthreads();
+    load_cube(src, nv, TT * T[t0], TT * T[t1], TT * T[t2], cube);
+    __syncthreads();
+    const double cf = c_coef[t];
+#pragma unroll
+    for (int r = 0; r < TT; r++) {
+      const int v[3] = {r, lb, lc};
+      acc[r] += cf * cube[v[t0] * LX + v[t1] * LY + v[t2]];
+    }
+  }
+  // stage X~ of this tile (local index v) and write each distinct ordering coalesced
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < TT; r++) cube[r * LX + lb * LY + lc] = acc[r];
+  __syncthreads();
+  for (int s = 0; s < 6; s++) {
+    if (!((u.mask >> s) & 1)) continue;
+    const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
+    double *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
+    // output local index w = v.s, i.e. w_n = v_{s_n}; the writer of w reads v with v_{s_n} = w_n
+    const int W0 = TT * T[s0], W1 = TT * T[s1], W2 = TT * T[s2];
+    for (int r = 0; r < TT; r++) {
+      const int w[3] = {r, lb, lc};
+      if (W0 + w[0] >= nv || W1 + w[1] >= nv || W2 + w[2] >= nv) continue;
+      int v[3];
+      v[s0] = w[0]; v[s1] = w[1]; v[s2] = w[2];
+      dst[(W0 + w[0]) * nv2 + (long long)(W1 + w[1]) * nv + (W2 + w[2])] = cube[v[0] * LX + v[1] * LY + v[2]];
     }
   }
 }
@@ -319,6 +404,27 @@ __global__ void k_doubles_out(DoublesRaw y, double *out_a, double *out_b) {
   }
 }
 
+// V[r][c] = sum_q Q[q][r][c][q]   (Q stored [q][r][c][L], L over all occupied)
+__global__ void k_diag_sum(const double *Q, int no, int nv, int NO, double *V) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= no * nv) return;
+  const int c = id % nv, r = id / nv;
+  double acc = 0.0;
+  for (int q = 0; q < no; q++) acc += Q[(((long long)q * no + r) * nv + c) * NO + q];
+  V[id] = acc;
+}
+
+// Z[J][k][d] = sum_j Am[j][J][k][d] - Hp[k][J][d]
+__global__ void k_left_Z(const double *Am, const double *Hp, int nc, int no, int nv, double *Z) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)nc * no * nv) return;
+  const int dd = id % nv, k = (id / nv) % no;
+  const long long J = id / ((long long)no * nv);
+  double acc = 0.0;
+  for (int j = 0; j < no; j++) acc += Am[(long long)j * nc * no * nv + id];
+  Z[id] = acc - Hp[((long long)k * nc + J) * nv + dd];
+}
+
 // ------------------------------------------------------------- host launchers
 #define L1D(kern, n, ...) \
   do { if (!g_dry && (n) > 0) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(256), 0, s, __VA_ARGS__); } while (0)
@@ -341,10 +447,11 @@ void launch_dlhat(const double *LOV, const double *LhvV, const double *LhOO, con
 }
 
 void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV, int no, int nv,
-                      double *tmp_s, double *tmp_y, double *out, hipStream_t s) {
+                      double *tmp_s, double *tmp_y, double *tmp_z, double *out, hipStream_t s) {
   if (!g_dry) hipLaunchKernelGGL(k_fock_s, dim3(nc), dim3(256), 0, s, LOV, x, nc, NO, NV, tmp_s);
   L1D(k_fock_y, (long long)nc * no * NO, LOV, x, nc, NO, NV, no, tmp_y);
-  L1D(k_fock_out, (long long)no * nv, LOV, tmp_s, tmp_y, nc, NO, NV, no, nv, out);
+  L1D(k_fock_z, (long long)nc * no * nv, LOV, tmp_s, tmp_y, nc, NO, NV, no, nv, tmp_z);
+  L1D(k_sum_rows, (long long)no * nv, tmp_z, (long long)nc, (long long)no * nv, out);
 }
 
 void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA, hipStream_t s) {
@@ -357,12 +464,14 @@ void launch_pack_vvoo(const double *x, int no, int nv, int NV, double *xV, hipSt
   L1D(k_pack_vvoo, (long long)no * no * nv * nv, x, no, nv, NV, xV);
 }
 
-void launch_permute_denom(const double *W, double *Xt, const UniqueTriple *ut, int nu, int no, int nv,
-                          const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
+void launch_permute_denom(const double *W, double *Xu, double *Xt, const UniqueTriple *ut, int nu, int no,
+                          int nv, const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
                           const LocalTerms &lt, hipStream_t s) {
   if (nu <= 0 || nv <= 0 || g_dry) return;
-  hipLaunchKernelGGL(k_permute_denom, dim3(nu, nv), dim3(256), 0, s, W, Xt, ut, no, nv, eps_o, eps_v, omega,
+  const int nt = (nv + TT - 1) / TT;
+  hipLaunchKernelGGL(k_sym_denom, dim3(nu, nt * nt * nt), dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, omega,
                      tb, te, lt);
+  hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xt, ut, no, nv);
 }
 
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
@@ -370,6 +479,18 @@ void launch_small_right(const double *X, const double *T, const double *gov, con
   if (no <= 0 || nv <= 0 || g_dry) return;
   hipLaunchKernelGGL(k_small_right, dim3(no * no * nv), dim3(64), nv * sizeof(double), s, X, T, gov, F, U,
                      no, nv, part1, Yvv);
+}
+
+void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s) {
+  L1D(k_sum_rows, n, P, rows, n, out);
+}
+
+void launch_diag_sum(const double *Q, int no, int nv, int NO, double *V, hipStream_t s) {
+  L1D(k_diag_sum, (long long)no * nv, Q, no, nv, NO, V);
+}
+
+void launch_left_Z(const double *Am, const double *Hp, int nc, int no, int nv, double *Z, hipStream_t s) {
+  L1D(k_left_Z, (long long)nc * no * nv, Am, Hp, nc, no, nv, Z);
 }
 
 void launch_singles_out(const double *part1, int no, int nv, int NO, int NV, double *x1, hipStream_t s) {

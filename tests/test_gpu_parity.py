@@ -137,3 +137,42 @@ def test_errors(lib, ws):
     assert e.value.code == lib.ENONFINITE
     # the workspace is still usable afterwards
     _ = lib.ground_residual(ws, g)
+
+
+@pytest.mark.parametrize("d", SMALL, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
+def test_left_transform(lib, ws, d):
+    p, orc, g = _setup(lib, d, 77)
+    L = I.left_vectors(p, 2)
+    om = I.omegas(False, 2)
+    out = lib.left_transform(ws, g, om, [lib.vec_to_device(v) for v in L])
+    for m in range(2):
+        _check(out[m], orc.left_transform(om[m], L[m]))
+
+
+@pytest.mark.parametrize("rng", [(0, 4), (347, 352)])
+def test_left_full_shape_subsets(lib, ws, rng):
+    from oracle.oracle import Oracle
+    p = I.make_config(1)
+    orc = Oracle(p)
+    g = lib.Ground(p)
+    L = I.left_vectors(p, 1)[0]
+    out = lib.left_transform(ws, g, [0.4], [lib.vec_to_device(L)], triple_range=rng)[0]
+    _check(out, orc.left_transform(0.4, L, *rng))
+
+
+def test_adjoint_identity_full_config1(lib, ws):
+    """<L, J R>_G = <J^T L, R>_G at the full config-1 size, GPU only, per block pairing."""
+    p = I.make_config(1)
+    d = p.dims
+    g = lib.Ground(p)
+    R = I.right_vectors(p, 1)[0]
+    L = I.left_vectors(p, 1)[0]
+    for Lpart in ("x1", "x2"):
+        Lp = {k: (v if k.startswith(Lpart) else 0 * v) for k, v in L.items()}
+        sig = lib.to_numpy(lib.left_transform(ws, g, [0.4], [lib.vec_to_device(Lp)], reuse_ground=True)[0])
+        for Rpart in ("x1", "x2"):
+            Rp = {k: (v if k.startswith(Rpart) else 0 * v) for k, v in R.items()}
+            rho = lib.to_numpy(lib.right_transform(ws, g, [0.4], [lib.vec_to_device(Rp)], reuse_ground=True)[0])
+            lhs = pair_form_blocks(d, Lp, rho)
+            rhs = pair_form_blocks(d, sig, Rp)
+            assert abs(lhs - rhs) <= 1e-10 * abs(lhs), (Lpart, Rpart, lhs, rhs)
