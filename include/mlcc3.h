@@ -99,6 +99,14 @@ int mlcc3_ws_destroy(mlcc3_ws ws);
 /* Bytes of device memory currently held by the workspace. */
 int64_t mlcc3_ws_bytes(mlcc3_ws ws);
 
+/* Optional phase timer: when enabled, HIP events are recorded on the call's stream around
+ * every d-contraction GEMM launch (phase 0: the W = sum_D x^{aD}_{ij} G_{bDck} GEMMs of
+ * tau3, R3 and L3).  Enabling (or re-enabling) clears the recorded marks.
+ * mlcc3_ws_phase_stats waits for the recorded events and returns the number of launches,
+ * their summed device time in ms and the FLOPs executed by those launches. */
+int mlcc3_ws_timing(mlcc3_ws ws, int32_t enable);
+int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *total_ms, double *flops);
+
 void mlcc3_opts_default(mlcc3_opts *o);
 
 /* Number of unique active occupied triples i>=j>=k, not all equal: C(n_o+2,3) - n_o. */

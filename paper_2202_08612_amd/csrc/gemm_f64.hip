@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
   __shared__ double Bs[2][BK][PB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int z = blockIdx.z;
+  const int z = blockIdx.z / g.ksplit, part = blockIdx.z % g.ksplit;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
 
@@ -44,8 +44,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
 
   for (int s = 0; s < g.nseg; s++) {
     const Seg &sg = g.seg[s];
-    const int K = sg.K;
-    if (K <= 0) continue;
+    // K slice of this part (multiples of BK); loads beyond K are masked
+    const int chunk = ((sg.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+    const int kbeg = part * chunk;
+    const int K = min(sg.K, kbeg + chunk);
+    if (kbeg >= K) continue;
     const double *Ap = sg.A.p + (long long)z * sg.A.batch;
     const double *Bp = sg.B.p + (long long)z * sg.B.batch;
     const double scale = sg.scale;
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
       boff[u] = bok[u] ? ioff(sg.B.col, n) : 0;
     }
     auto load = [&](int kt) {
-      const int kb = kt * BK;
+      const int kb = kbeg + kt * BK;
       if (AKF) {
         const int k = kb + tid % BK;
         const bool kin = k < K;
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
       }
     };
 
-    const int nkt = (K + BK - 1) / BK;
+    const int nkt = (K - kbeg + BK - 1) / BK;
     __syncthreads();  // previous segment's readers are done with both buffers
     load(0);
     store(0);
@@ -136,6 +139,22 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
   // epilogue: on gfx950 lane l, register v of a 16x16 f64 tile holds row l/16 + 4v, column l%16.
   // All old C values are loaded before the first store so the loads are not serialised
   // behind stores to the same array.
+  if (g.ksplit > 1) {
+    double *Pp = g.P + ((long long)z * g.ksplit + part) * (long long)g.M * g.N;
+#pragma unroll
+    for (int j = 0; j < TN; j++) {
+      const int n = n0 + wn0 + 16 * j + (lane & 15);
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
+          if (m < g.M) Pp[(long long)m * g.N + n] = acc[i][j][v];
+        }
+    }
+    return;
+  }
   double *Cp = g.C + (long long)z * g.cbatch;
   long long ro[TM][4], co[TN];
   bool rok[TM][4], cok[TN];
@@ -179,13 +198,34 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
   }
 }
 
+// C = alpha * sum_part P[batch][part] + beta * C through the output maps (fixed order)
+__global__ void k_splitk_reduce(const Gemm g) {
+  const long long MN = (long long)g.M * g.N;
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= MN * g.nbatch) return;
+  const int z = (int)(id / MN);
+  const long long e = id - (long long)z * MN;
+  const int m = (int)(e / g.N), n = (int)(e - (long long)m * g.N);
+  const double *P = g.P + (long long)z * g.ksplit * MN + e;
+  double acc = 0.0;
+  for (int p = 0; p < g.ksplit; p++) acc += P[p * MN];
+  double *Cp = g.C + (long long)z * g.cbatch + ioff(g.crow, m) + ioff(g.ccol, n);
+  double r = g.alpha * acc;
+  if (g.beta != 0.0) r += g.beta * *Cp;
+  *Cp = r;
+}
+
 template <int TM, int TN>
 static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf) {
-  dim3 grid((g.N + 32 * TN - 1) / (32 * TN), (g.M + 32 * TM - 1) / (32 * TM), g.nbatch);
+  dim3 grid((g.N + 32 * TN - 1) / (32 * TN), (g.M + 32 * TM - 1) / (32 * TM), g.nbatch * g.ksplit);
   if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true>), grid, dim3(256), 0, s, g);
   else if (akf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, false>), grid, dim3(256), 0, s, g);
   else if (bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, true>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, false>), grid, dim3(256), 0, s, g);
+  if (g.ksplit > 1) {
+    const long long n = (long long)g.M * g.N * g.nbatch;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }
 
@@ -196,9 +236,23 @@ bool g_dry = false;
 
 static int pick(int n) { return n <= 32 ? 1 : (n <= 64 ? 2 : 4); }
 
+long long gemm_tiles(const Gemm &g) {
+  int tm = pick(g.M), tn = pick(g.N);
+  long long ktot = 0;
+  for (int i = 0; i < g.nseg; i++) ktot += g.seg[i].K;
+  if (ktot <= 64) { tm = tm > 2 ? 2 : tm; tn = tn > 2 ? 2 : tn; }
+  auto blocks = [&](int a, int b) {
+    return (long long)((g.M + 32 * a - 1) / (32 * a)) * ((g.N + 32 * b - 1) / (32 * b)) * g.nbatch;
+  };
+  while (blocks(tm, tn) < 512 && (tm > 2 || tn > 2)) {
+    if (tm >= tn) tm /= 2; else tn /= 2;
+  }
+  return blocks(tm, tn);
+}
+
 hipError_t gemm_f64(const Gemm &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g_dry) return hipSuccess;
-  if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
+  if (g.nseg < 1 || g.nseg > 2 || g.ksplit < 1 || (g.ksplit > 1 && !g.P)) return hipErrorInvalidValue;
   const bool akf = unit(g.seg[0].A.col);
   const bool bnf = unit(g.seg[0].B.col);
   int tm = pick(g.M), tn = pick(g.N);

@@ -50,6 +50,9 @@ struct Extent {
 };
 thread_local std::vector<Extent> t_ext;
 
+thread_local mlcc3_ws t_ws = nullptr;   // workspace of the running call (timing, split-K scratch)
+thread_local hipStream_t t_stream = nullptr;
+
 void reg(const void *p, long long count, const char *name) {
   if (!p || count <= 0) return;
   t_ext.push_back({(uintptr_t)p, (uintptr_t)p + (uintptr_t)count * sizeof(double), name});
@@ -65,6 +68,15 @@ struct mlcc3_ws_s {
   mlcc3_ground key{};
   int nu = 0;
   uintptr_t fake_next = (uintptr_t)1 << 44;  // dry-run address space
+  // optional per-phase timing (HIP events on the call's stream)
+  bool timing = false;
+  struct Mark {
+    int phase;
+    double flops;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -257,7 +269,47 @@ void gemm(const Gemm &g, hipStream_t s) {
     check_range(sg.B.p, sg.B.row, sg.K, sg.B.col, g.N, sg.B.batch, g.nbatch, "B");
   }
   check_range(g.C, g.crow, g.M, g.ccol, g.N, g.cbatch, g.nbatch, "C");
-  HIPCHK(gemm_f64(g, s));
+  long long ktot = 0;
+  for (int i = 0; i < g.nseg; i++) ktot += g.seg[i].K;
+  const long long tiles = gemm_tiles(g);
+  Gemm h = g;
+  if (tiles < 256 && ktot >= 2048 && t_ws) {
+    // too few workgroups for a long K: split K and reduce the partial tiles
+    long long ks = std::min<long long>((512 + tiles - 1) / tiles, ktot / 512);
+    ks = std::max<long long>(1, std::min<long long>(ks, 64));
+    if (ks > 1) {
+      h.ksplit = (int)ks;
+      h.P = buf(t_ws, "gemm_splitk", (size_t)(ks * g.nbatch * (long long)g.M * g.N), t_stream);
+    }
+  }
+  HIPCHK(gemm_f64(h, s));
+}
+
+hipEvent_t pool_event(mlcc3_ws ws) {
+  if (!ws->pool.empty()) {
+    hipEvent_t e = ws->pool.back();
+    ws->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+// GEMM recorded under a timing phase (0 = d-contraction) when the workspace timer is on
+void gemm_timed(const Gemm &g, int phase, hipStream_t s) {
+  mlcc3_ws ws = t_ws;
+  if (!ws || !ws->timing || g_dry) {
+    gemm(g, s);
+    return;
+  }
+  double fl = 0.0;
+  for (int i = 0; i < g.nseg; i++) fl += 2.0 * g.M * (double)g.N * g.seg[i].K * g.nbatch;
+  mlcc3_ws_s::Mark mk{phase, fl, pool_event(ws), pool_event(ws)};
+  HIPCHK(hipEventRecord(mk.a, s));
+  gemm(g, s);
+  HIPCHK(hipEventRecord(mk.b, s));
+  ws->marks.push_back(mk);
 }
 
 void reg_ground(const mlcc3_ground *g) {
@@ -488,7 +540,7 @@ void w_dterm(const Dims &d, double *W, const double *xA1, BMap G1, const double 
   g.nseg = xA2 ? 2 : 1;
   g.seg[0] = seg(xA1, plain(d.NV), plain(1), 0, G1.p, G1.row, G1.col, G1.batch, d.NV);
   if (xA2) g.seg[1] = seg(xA2, plain(d.NV), plain(1), 0, G2.p, G2.row, G2.col, G2.batch, d.NV);
-  gemm(g, s);
+  gemm_timed(g, 0, s);
 }
 
 // W[p][q][r][a][b][c] -= sum_L x^{ab}_{pL} G(L,(q,r,c))  (+ second segment); x stored [a][b][p][L]
@@ -702,12 +754,50 @@ int mlcc3_ws_destroy(mlcc3_ws ws) {
       HIPCHK(hipDeviceSynchronize());
       for (auto &kv : ws->bufs)
         if (kv.second.first) (void)hipFree(kv.second.first);
+      for (auto &m : ws->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+      }
+      for (auto e : ws->pool) (void)hipEventDestroy(e);
     }
     delete ws;
   });
 }
 
 int64_t mlcc3_ws_bytes(mlcc3_ws ws) { return ws ? ws->total : 0; }
+
+int mlcc3_ws_timing(mlcc3_ws ws, int32_t enable) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    ws->timing = enable != 0;
+    if (!g_dry)
+      for (auto &m : ws->marks) {
+        ws->pool.push_back(m.a);
+        ws->pool.push_back(m.b);
+      }
+    ws->marks.clear();
+  });
+}
+
+int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *total_ms, double *flops) {
+  return guarded([&] {
+    check(ws && launches && total_ms && flops, "NULL argument");
+    *launches = 0;
+    *total_ms = 0.0;
+    *flops = 0.0;
+    for (auto &m : ws->marks) {
+      if (m.phase != phase) continue;
+      float ms = 0.f;
+      if (!g_dry) {
+        HIPCHK(hipEventSynchronize(m.b));
+        HIPCHK(hipEventElapsedTime(&ms, m.a, m.b));
+      }
+      *launches += 1;
+      *total_ms += ms;
+      *flops += m.flops;
+    }
+  });
+}
 
 double mlcc3_flops(const mlcc3_ground *g, int32_t which, int32_t nvec) {
   if (!g) return 0.0;
@@ -721,6 +811,8 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
                           void *stream) {
   return guarded([&] {
     check(ws != nullptr, "ws is NULL");
+    t_ws = ws;
+    t_stream = (hipStream_t)stream;
     validate_ground(g);
     validate_out(g, out);
     reg_ground(g);
@@ -750,6 +842,8 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
                           const mlcc3_vec *R, mlcc3_out *rho, const mlcc3_opts *opts, void *stream) {
   return guarded([&] {
     check(ws != nullptr, "ws is NULL");
+    t_ws = ws;
+    t_stream = (hipStream_t)stream;
     validate_ground(g);
     validate_vecs(g, nvec, omega, R, rho);
     reg_ground(g);
@@ -854,6 +948,8 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
                          const mlcc3_vec *L, mlcc3_out *sigma, const mlcc3_opts *opts, void *stream) {
   return guarded([&] {
     check(ws != nullptr, "ws is NULL");
+    t_ws = ws;
+    t_stream = (hipStream_t)stream;
     validate_ground(g);
     validate_vecs(g, nvec, omega, L, sigma);
     reg_ground(g);

@@ -36,10 +36,16 @@ struct Gemm {
   Idx2 crow, ccol;
   long long cbatch = 0;
   double alpha = 1.0, beta = 0.0;   // C = alpha * sum_seg scale*A*B + beta * C
+  // split-K: ksplit > 1 gives each (batch, part) workgroup a slice of every segment's K;
+  // partial tiles go to P[batch][part][M][N] and a fixed-order reduction applies alpha/beta.
+  int ksplit = 1;
+  double *P = nullptr;
 };
 
 // FP64 MFMA GEMM (v_mfma_f64_16x16x4_f64), LDS-staged, 256 threads per block.
 hipError_t gemm_f64(const Gemm &g, hipStream_t s);
+// number of workgroups gemm_f64 launches for g with ksplit = 1
+long long gemm_tiles(const Gemm &g);
 
 // Dry-run mode (environment MLCC3_DRYRUN=1): no device calls, no kernel launches; the
 // host orchestration and its bounds self-checks still run.  Used to validate every

@@ -49,6 +49,9 @@ _lib.mlcc3_ws_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
 _lib.mlcc3_ws_destroy.argtypes = [ctypes.c_void_p]
 _lib.mlcc3_ws_bytes.argtypes = [ctypes.c_void_p]
 _lib.mlcc3_ws_bytes.restype = ctypes.c_int64
+_lib.mlcc3_ws_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.mlcc3_ws_phase_stats.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.mlcc3_num_triples.argtypes = [ctypes.c_int32]
 _lib.mlcc3_num_triples.restype = ctypes.c_int64
 _lib.mlcc3_opts_default.argtypes = [ctypes.POINTER(_Opts)]
@@ -64,7 +67,7 @@ _lib.mlcc3_status_string.argtypes = [ctypes.c_int]
 _lib.mlcc3_status_string.restype = ctypes.c_char_p
 _lib.mlcc3_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_opts_default",
+EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_ws_timing", "mlcc3_ws_phase_stats", "mlcc3_opts_default",
             "mlcc3_num_triples", "mlcc3_ground_residual", "mlcc3_right_transform",
             "mlcc3_left_transform", "mlcc3_flops", "mlcc3_status_string", "mlcc3_last_error"]
 
@@ -100,6 +103,14 @@ class Workspace:
 
     def bytes(self):
         return int(_lib.mlcc3_ws_bytes(self.h))
+
+    def timing(self, enable=True):
+        _check(_lib.mlcc3_ws_timing(self.h, 1 if enable else 0))
+
+    def phase_stats(self, phase=0):
+        n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.mlcc3_ws_phase_stats(self.h, phase, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        return {"launches": int(n.value), "ms": float(ms.value), "flops": float(fl.value)}
 
     def close(self):
         if self.h:
