@@ -209,6 +209,58 @@ class Brute:
         return s1, s2
 
 
+    # -- transition densities ---------------------------------------------------
+    def lambda3(self, lam1, lam2):
+        """lambda3 from the L3 recipe with (lambda1, lambda2) at omega = 0 (ground-state multipliers)."""
+        return self.L3(lam1, lam2, 0.0)
+
+    def density_m0(self, L1, L2, omega):
+        """Triples terms of the left transition density D^{m-0} (SI left density), D[p][q]
+        multiplies A_pq; occupied orbitals first."""
+        o, v = self.o, self.v
+        t2 = self.t2
+        tau = self.tau3()
+        tt = tilde3(tau)
+        Lt = tilde3(self.L3(L1, L2, omega))
+        D = np.zeros((self.N, self.N))
+        D[o, o] -= 0.5 * np.einsum("abcijl,abcijk->kl", Lt, tau)
+        D[o, v] += np.einsum("abij,abdijl->ld", L2, tt)
+        D[o, v] -= np.einsum("abcijk,acil,bdjk->ld", Lt, t2, t2)
+        D[v, v] += 0.5 * np.einsum("abcijk,abdijk->cd", Lt, tau)
+        return D
+
+    def density_0m(self, lam1, lam2, R1, R2, omega):
+        """Triples terms of the right transition density D^{0-m} (SI right density) and the
+        triples overlap s = (1/6) sum lambda~3 R3.  The occupied diagonal carries 2s; the
+        -s D^{0-0} term is left to the caller.  Doubles of R enter as Rbar = Delta R."""
+        o, v = self.o, self.v
+        t2 = self.t2
+        tau = self.tau3()
+        lt = tilde3(self.lambda3(lam1, lam2))
+        R3 = self.R3(R1, R2, omega)
+        Rt = tilde3(R3)
+        Rb = self.Delta * R2
+        l2t = 2.0 * lam2 - np.einsum("baij->abij", lam2)
+        D = np.zeros((self.N, self.N))
+        D[o, o] -= np.einsum("abcijl,ai,bcjk->kl", lt, R1, t2)
+        D[o, o] -= 0.5 * np.einsum("abcijl,abcijk->kl", lt, R3)
+        D[o, v] += (np.einsum("abcijk,ai,bcdjkl->ld", lt, R1, tau)
+                    - np.einsum("abcijk,ai,bcdjlk->ld", lt, R1, tau)
+                    + np.einsum("abij,abdijl->ld", l2t, Rt))
+        D[o, v] += 0.5 * (2.0 * np.einsum("abcijk,abij,cdkl->ld", lt, Rb, t2)
+                          - np.einsum("abcijk,abij,cdlk->ld", lt, Rb, t2))
+        D[o, v] -= (np.einsum("abcijk,acil,bdjk->ld", lt, Rb, t2)
+                    + np.einsum("abcijk,adik,bcjl->ld", lt, Rb, t2))
+        D[o, v] -= 0.5 * np.einsum("abcijk,abcijl,dk->ld", lt, tau, R1)
+        D[o, v] -= 0.5 * np.einsum("abcijk,abdijk,cl->ld", lt, tau, R1)
+        D[v, o] += 0.5 * np.einsum("abcijk,abij->ck", lt, Rb)
+        D[v, v] += np.einsum("abcijk,ai,bdjk->cd", lt, R1, t2)
+        D[v, v] += 0.5 * np.einsum("abcijk,abdijk->cd", lt, R3)
+        s = float(np.sum(lt * R3)) / 6.0
+        D[o, o] += 2.0 * s * np.eye(self.NO)
+        return D, s
+
+
 # ----------------------------------------------------------------------------
 # block views matching the C-ABI layouts
 def blocks2(X, n_o, n_v):

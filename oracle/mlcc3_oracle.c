@@ -914,3 +914,291 @@ int orc_triples_block(const orc_problem *P, int kind, double omega, const double
   ctx_free(&c);
   return 0;
 }
+
+/* ------------------------------------------------------------ densities -- */
+/* store the block X (of unique triple o) for every distinct ordering into Y[p][q][r][abc] */
+static void store_orderings(const ctx *c, const int o[3], const double *X, double *Y, double *tmp) {
+  const int no = c->no, nv = c->nv;
+  const size_t n3 = (size_t)nv * nv * nv;
+  int ids[6], n = orderings(o, ids);
+  for (int m = 0; m < n; m++) {
+    const int *S = PERM[ids[m]];
+    reorder(nv, S, X, tmp);
+    memcpy(Y + ((size_t)(o[S[0]] * no + o[S[1]]) * no + o[S[2]]) * n3, tmp, n3 * sizeof(double));
+  }
+}
+
+int orc_densities(const orc_problem *P, const double *t2_vVoO, const double *t2_vVOo, double omega,
+                  const double *L1, const double *L2a, const double *L2b, const double *R1,
+                  const double *R2a, const double *R2b, const double *l1, const double *l2a,
+                  const double *l2b, int64_t tb, int64_t te, double *Dm0, double *D0m, double *sout) {
+  ctx c;
+  ctx_init(&c, P);
+  const int no = c.no, nv = c.nv, NO = c.NO, NV = c.NV, N = NO + NV;
+  const size_t n3 = (size_t)nv * nv * nv, nord = (size_t)no * no * no;
+  int64_t nt = orc_num_triples(no);
+  range_ok(&tb, &te, nt);
+  int *T = (int *)malloc(sizeof(int) * 3 * (nt + 1));
+  triple_list(no, T);
+  rvec rv;
+  rvec_init(&c, &rv, R1, R2a, R2b);
+  /* left vectors repacked (no Delta) for the L3 recipe */
+  double *lDL = zalloc((size_t)no * no * nv * NV), *lLL = zalloc((size_t)no * nv * nv * NO);
+  double *lDl = zalloc((size_t)no * no * nv * NV), *lLl = zalloc((size_t)no * nv * nv * NO);
+  for (int a = 0; a < nv; a++)
+    for (int D = 0; D < NV; D++)
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++) {
+          lDL[IDX4(i, j, a, D, no, nv, NV)] = L2a[IDX4(a, D, i, j, NV, no, no)];
+          lDl[IDX4(i, j, a, D, no, nv, NV)] = l2a[IDX4(a, D, i, j, NV, no, no)];
+        }
+  for (int a = 0; a < nv; a++)
+    for (int b = 0; b < nv; b++)
+      for (int i = 0; i < no; i++)
+        for (int L = 0; L < NO; L++) {
+          lLL[IDX4(i, a, b, L, nv, nv, NO)] = L2b[IDX4(a, b, i, L, nv, no, NO)];
+          lLl[IDX4(i, a, b, L, nv, nv, NO)] = l2b[IDX4(a, b, i, L, nv, no, NO)];
+        }
+  /* all-ordering storage of tau, tau~, L~, lambda~, R3, R3~ */
+  double *Tau = zalloc(nord * n3), *TauT = zalloc(nord * n3), *Lt = zalloc(nord * n3),
+         *Lam = zalloc(nord * n3), *R3 = zalloc(nord * n3), *R3t = zalloc(nord * n3);
+  double *X = zalloc(n3), *Xt = zalloc(n3), *Wt = zalloc(n3), *tmp = zalloc(n3);
+  bsrc st = {0}, sl = {0}, sa = {0}, sr = {0};
+  st.kind = 0;
+  sl.kind = 2; sl.omega = omega; sl.L1 = L1; sl.L2a = L2a; sl.lD = lDL; sl.lL = lLL;
+  sa.kind = 2; sa.omega = 0.0; sa.L1 = l1; sa.L2a = l2a; sa.lD = lDl; sa.lL = lLl;
+  sr.kind = 1; sr.omega = omega; sr.rv = &rv;
+  for (int64_t t = tb; t < te; t++) {
+    const int o[3] = {T[3 * t], T[3 * t + 1], T[3 * t + 2]};
+    build_block(&c, &st, o, X, Wt);
+    store_orderings(&c, o, X, Tau, tmp);
+    contravariant(nv, X, Xt);
+    store_orderings(&c, o, Xt, TauT, tmp);
+    build_block(&c, &sl, o, X, Wt);
+    contravariant(nv, X, Xt);
+    store_orderings(&c, o, Xt, Lt, tmp);
+    build_block(&c, &sa, o, X, Wt);
+    contravariant(nv, X, Xt);
+    store_orderings(&c, o, Xt, Lam, tmp);
+    build_block(&c, &sr, o, X, Wt);
+    store_orderings(&c, o, X, R3, tmp);
+    contravariant(nv, X, Xt);
+    store_orderings(&c, o, Xt, R3t, tmp);
+  }
+#define BLK(A, p, q, r) ((A) + ((size_t)((p) * no + (q)) * no + (r)) * n3)
+#define E3(x, y, z) (((size_t)(x) * nv + (y)) * nv + (z))
+  const double *t2a = P->t2_vVoo, *t2b = P->t2_vvoO;
+  /* amplitude accessors on the blocks */
+#define TA(a, D, i, j) t2a[IDX4(a, D, i, j, NV, no, no)]            /* t^{aD}_{ij}   */
+#define TB(a, b, i, L) t2b[IDX4(a, b, i, L, nv, no, NO)]            /* t^{ab}_{iL}   */
+  memset(Dm0, 0, sizeof(double) * N * N);
+  memset(D0m, 0, sizeof(double) * N * N);
+  /* ---- D^{m-0} ---- */
+  /* D_kl -= 1/2 sum L~^{abc}_{ijl} tau^{abc}_{ijk} ;  D_cd += 1/2 sum L~^{abc}_{ijk} tau^{abd}_{ijk} */
+  for (int k = 0; k < no; k++)
+    for (int l = 0; l < no; l++) {
+      double acc = 0.0;
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++) {
+          const double *A = BLK(Lt, i, j, l), *B = BLK(Tau, i, j, k);
+          for (size_t e = 0; e < n3; e++) acc += A[e] * B[e];
+        }
+      Dm0[k * N + l] -= 0.5 * acc;
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int cc = 0; cc < nv; cc++)
+    for (int d = 0; d < nv; d++) {
+      double acc = 0.0;
+      for (size_t q = 0; q < nord; q++)
+        for (int a = 0; a < nv; a++)
+          for (int b = 0; b < nv; b++) acc += Lt[q * n3 + E3(a, b, cc)] * Tau[q * n3 + E3(a, b, d)];
+      Dm0[(NO + cc) * N + NO + d] += 0.5 * acc;
+    }
+  /* D_ld += sum L^{ab}_{ij} tau~^{abd}_{ijl} */
+  for (int l = 0; l < no; l++)
+    for (int d = 0; d < nv; d++) {
+      double acc = 0.0;
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++)
+          for (int a = 0; a < nv; a++)
+            for (int b = 0; b < nv; b++) acc += L2a[IDX4(a, b, i, j, NV, no, no)] * BLK(TauT, i, j, l)[E3(a, b, d)];
+      Dm0[l * N + NO + d] += acc;
+    }
+  /* D_LD -= sum L~^{abc}_{ijk} t^{ac}_{iL} t^{bD}_{jk}, through V_jkbL = sum_{iac} L~ t^{ac}_{iL} */
+  double *V = zalloc((size_t)no * no * nv * NO);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int j = 0; j < no; j++)
+    for (int k = 0; k < no; k++)
+      for (int b = 0; b < nv; b++)
+        for (int L = 0; L < NO; L++) {
+          double acc = 0.0;
+          for (int i = 0; i < no; i++) {
+            const double *A = BLK(Lt, i, j, k);
+            for (int a = 0; a < nv; a++)
+              for (int cc = 0; cc < nv; cc++) acc += A[E3(a, b, cc)] * TB(a, cc, i, L);
+          }
+          V[IDX4(j, k, b, L, no, nv, NO)] = acc;
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int L = 0; L < NO; L++)
+    for (int D = 0; D < NV; D++) {
+      double acc = 0.0;
+      for (int j = 0; j < no; j++)
+        for (int k = 0; k < no; k++)
+          for (int b = 0; b < nv; b++) acc += V[IDX4(j, k, b, L, no, nv, NO)] * TA(b, D, j, k);
+      Dm0[L * N + NO + D] -= acc;
+    }
+  /* ---- D^{0-m} ---- */
+  /* X^{bc}_{jk} = sum_{ai} lambda~^{abc}_{ijk} R^a_i */
+  double *Xl = zalloc((size_t)no * no * nv * nv);
+  for (int j = 0; j < no; j++)
+    for (int k = 0; k < no; k++)
+      for (int b = 0; b < nv; b++)
+        for (int cc = 0; cc < nv; cc++) {
+          double acc = 0.0;
+          for (int i = 0; i < no; i++)
+            for (int a = 0; a < nv; a++) acc += BLK(Lam, i, j, k)[E3(a, b, cc)] * R1[a * NO + i];
+          Xl[IDX4(j, k, b, cc, no, nv, nv)] = acc;
+        }
+  /* D_Kl -= sum lambda~^{abc}_{ijl} R^a_i t^{bc}_{jK} */
+  for (int K = 0; K < NO; K++)
+    for (int l = 0; l < no; l++) {
+      double acc = 0.0;
+      for (int j = 0; j < no; j++)
+        for (int b = 0; b < nv; b++)
+          for (int cc = 0; cc < nv; cc++) acc += Xl[IDX4(j, l, b, cc, no, nv, nv)] * TB(b, cc, j, K);
+      D0m[K * N + l] -= acc;
+    }
+  /* D_kl -= 1/2 sum lambda~^{abc}_{ijl} R^{abc}_{ijk};  Z_kl = sum lambda~_{ijk} tau_{ijl} */
+  double *Zt = zalloc((size_t)no * no);
+  for (int k = 0; k < no; k++)
+    for (int l = 0; l < no; l++) {
+      double acc = 0.0, z = 0.0;
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++) {
+          const double *A = BLK(Lam, i, j, l), *B = BLK(R3, i, j, k);
+          const double *A2 = BLK(Lam, i, j, k), *B2 = BLK(Tau, i, j, l);
+          for (size_t e = 0; e < n3; e++) { acc += A[e] * B[e]; z += A2[e] * B2[e]; }
+        }
+      D0m[k * N + l] -= 0.5 * acc;
+      Zt[k * no + l] = z;
+    }
+  /* D_ld += sum X^{bc}_{jk} (tau^{bcd}_{jkl} - tau^{bcd}_{jlk}) + sum lambda~^{ab}_{ij} R~^{abd}_{ijl} */
+  for (int l = 0; l < no; l++)
+    for (int d = 0; d < nv; d++) {
+      double acc = 0.0;
+      for (int j = 0; j < no; j++)
+        for (int k = 0; k < no; k++)
+          for (int b = 0; b < nv; b++)
+            for (int cc = 0; cc < nv; cc++)
+              acc += Xl[IDX4(j, k, b, cc, no, nv, nv)] *
+                     (BLK(Tau, j, k, l)[E3(b, cc, d)] - BLK(Tau, j, l, k)[E3(b, cc, d)]);
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++)
+          for (int a = 0; a < nv; a++)
+            for (int b = 0; b < nv; b++) {
+              const double lt = 2.0 * l2a[IDX4(a, b, i, j, NV, no, no)] - l2a[IDX4(b, a, i, j, NV, no, no)];
+              acc += lt * BLK(R3t, i, j, l)[E3(a, b, d)];
+            }
+      D0m[l * N + NO + d] += acc;
+    }
+  /* Rbar accessors */
+#define RBA(a, D, i, j) (((a) == (D) && (i) == (j) ? 2.0 : 1.0) * R2a[IDX4(a, D, i, j, NV, no, no)])
+#define RBB(a, b, i, L) (((a) == (b) && (i) == (L) ? 2.0 : 1.0) * R2b[IDX4(a, b, i, L, nv, no, NO)])
+  /* Y_kc = sum lambda~^{abc}_{ijk} Rbar^{ab}_{ij} */
+  double *Yc = zalloc((size_t)no * nv);
+  for (int k = 0; k < no; k++)
+    for (int cc = 0; cc < nv; cc++) {
+      double acc = 0.0;
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++)
+          for (int a = 0; a < nv; a++)
+            for (int b = 0; b < nv; b++) acc += BLK(Lam, i, j, k)[E3(a, b, cc)] * RBA(a, b, i, j);
+      Yc[k * nv + cc] = acc;
+    }
+  /* D_LD += 1/2 sum Y_kc (2 t^{cD}_{kL} - t^{cD}_{Lk})
+           - sum lambda~^{abc}_{ijk} (Rbar^{ac}_{iL} t^{bD}_{jk} + Rbar^{aD}_{ik} t^{bc}_{jL})
+     D_lD -= 1/2 sum Z_kl R^D_k ;  D_Ld -= 1/2 sum Zv_cd R^c_L */
+  double *Zv = zalloc((size_t)nv * nv);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int cc = 0; cc < nv; cc++)
+    for (int d = 0; d < nv; d++) {
+      double z = 0.0, r = 0.0;
+      for (size_t q = 0; q < nord; q++)
+        for (int a = 0; a < nv; a++)
+          for (int b = 0; b < nv; b++) {
+            z += Lam[q * n3 + E3(a, b, cc)] * Tau[q * n3 + E3(a, b, d)];
+            r += Lam[q * n3 + E3(a, b, cc)] * R3[q * n3 + E3(a, b, d)];
+          }
+      Zv[cc * nv + d] = z;
+      D0m[(NO + cc) * N + NO + d] += 0.5 * r;   /* D_cd += 1/2 sum lambda~^{abc} R^{abd} */
+    }
+  /* V2_jkbL = sum_{iac} lambda~^{abc}_{ijk} Rbar^{ac}_{iL};  V3_ikaL = sum_{jbc} lambda~^{abc}_{ijk} t^{bc}_{jL} */
+  double *V2 = zalloc((size_t)no * no * nv * NO), *V3 = zalloc((size_t)no * no * nv * NO);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int p = 0; p < no; p++)
+    for (int q = 0; q < no; q++)
+      for (int x = 0; x < nv; x++)
+        for (int L = 0; L < NO; L++) {
+          double a2 = 0.0, a3 = 0.0;
+          for (int r = 0; r < no; r++) {
+            /* V2 with (j,k,b) = (p,q,x), i = r */
+            const double *A = BLK(Lam, r, p, q);
+            for (int a = 0; a < nv; a++)
+              for (int cc = 0; cc < nv; cc++) a2 += A[E3(a, x, cc)] * RBB(a, cc, r, L);
+            /* V3 with (i,k,a) = (p,q,x), j = r */
+            const double *B = BLK(Lam, p, r, q);
+            for (int b = 0; b < nv; b++)
+              for (int cc = 0; cc < nv; cc++) a3 += B[E3(x, b, cc)] * TB(b, cc, r, L);
+          }
+          V2[IDX4(p, q, x, L, no, nv, NO)] = a2;
+          V3[IDX4(p, q, x, L, no, nv, NO)] = a3;
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int L = 0; L < NO; L++)
+    for (int D = 0; D < NV; D++) {
+      double acc = 0.0;
+      for (int k = 0; k < no; k++)
+        for (int cc = 0; cc < nv; cc++)
+          acc += 0.5 * Yc[k * nv + cc] *
+                 (2.0 * t2_vVoO[IDX4(cc, D, k, L, NV, no, NO)] - t2_vVOo[IDX4(cc, D, L, k, NV, NO, no)]);
+      for (int p = 0; p < no; p++)
+        for (int q = 0; q < no; q++)
+          for (int x = 0; x < nv; x++)
+            acc -= V2[IDX4(p, q, x, L, no, nv, NO)] * TA(x, D, p, q) + V3[IDX4(p, q, x, L, no, nv, NO)] * RBA(x, D, p, q);
+      if (L < no)
+        for (int k = 0; k < no; k++) acc -= 0.5 * Zt[k * no + L] * R1[D * NO + k];
+      if (D < nv)
+        for (int cc = 0; cc < nv; cc++) acc -= 0.5 * Zv[cc * nv + D] * R1[cc * NO + L];
+      D0m[L * N + NO + D] += acc;
+    }
+  /* D_ck += 1/2 Y_kc ;  D_cD += sum X^{bc}_{jk} t^{bD}_{jk} */
+  for (int cc = 0; cc < nv; cc++) {
+    for (int k = 0; k < no; k++) D0m[(NO + cc) * N + k] += 0.5 * Yc[k * nv + cc];
+    for (int D = 0; D < NV; D++) {
+      double acc = 0.0;
+      for (int j = 0; j < no; j++)
+        for (int k = 0; k < no; k++)
+          for (int b = 0; b < nv; b++) acc += Xl[IDX4(j, k, b, cc, no, nv, nv)] * TA(b, D, j, k);
+      D0m[(NO + cc) * N + NO + D] += acc;
+    }
+  }
+  /* s = 1/6 sum lambda~ R3 ; D_LL += 2 s */
+  double sdot = 0.0;
+  for (size_t e = 0; e < nord * n3; e++) sdot += Lam[e] * R3[e];
+  const double sv = sdot / 6.0;
+  for (int L = 0; L < NO; L++) D0m[L * N + L] += 2.0 * sv;
+  *sout = sv;
+#undef BLK
+#undef E3
+#undef TA
+#undef TB
+#undef RBA
+#undef RBB
+  free(T); free(lDL); free(lLL); free(lDl); free(lLl);
+  free(Tau); free(TauT); free(Lt); free(Lam); free(R3); free(R3t);
+  free(X); free(Xt); free(Wt); free(tmp); free(Xl); free(Zt); free(Yc); free(Zv); free(V); free(V2); free(V3);
+  rvec_free(&rv);
+  ctx_free(&c);
+  return 0;
+}

@@ -34,6 +34,16 @@ int orc_right_transform(const orc_problem *P, double omega, const double *R1,
 int orc_left_transform(const orc_problem *P, double omega, const double *L1,
                        const double *L2_vVoo, const double *L2_vvoO, int64_t tb, int64_t te,
                        double *sig1, double *sig2_vVoo, double *sig2_vvoO);
+/* Triples terms of the transition densities for one excited state (SI left and right
+ * density equations).  Dm0 and D0m are [N][N] (N = N_O + N_V, occupied first), element
+ * [p][q] multiplies A_pq.  lam* is the ground-state multiplier vector (lambda3 from the L3
+ * recipe at omega = 0), t2_vVoO[n_v][N_V][n_o][N_O] = t^{cD}_{kL} and
+ * t2_vVOo[n_v][N_V][N_O][n_o] = t^{cD}_{Lk}.  *s = (1/6) sum lambda~3 R3; 2s is added to the
+ * occupied diagonal of D0m.  Only unique triples in [tb, te) carry triples amplitudes. */
+int orc_densities(const orc_problem *P, const double *t2_vVoO, const double *t2_vVOo, double omega,
+                  const double *L1, const double *L2a, const double *L2b, const double *R1,
+                  const double *R2a, const double *R2b, const double *l1, const double *l2a,
+                  const double *l2b, int64_t tb, int64_t te, double *Dm0, double *D0m, double *s);
 /* The covariant n_v^3 block X^{abc}_{ijk} of one unique triple (kind 0 = tau3,
  * 1 = R3, 2 = L3), for symmetry and closed-form checks. */
 int orc_triples_block(const orc_problem *P, int kind, double omega, const double *x1,

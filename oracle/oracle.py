@@ -94,6 +94,19 @@ class Oracle:
     def left_transform(self, omega, vec, tb=0, te=-1):
         return self._vec_call(lib().orc_left_transform, omega, vec, tb, te)
 
+    def densities(self, omega, Lvec, Rvec, lam, t2_vVoO, t2_vVOo, tb=0, te=-1):
+        """(D^{m-0}, D^{0-m}, s) triples terms for one state (see mlcc3_oracle.h)."""
+        d = self.d
+        N = d.N_O + d.N_V
+        Dm0, D0m = np.zeros((N, N)), np.zeros((N, N))
+        s = ctypes.c_double()
+        args = [_c(t2_vVoO), _c(t2_vVOo)]
+        vecs = [_c(v[k]) for v in (Lvec, Rvec, lam) for k in ("x1", "x2_vVoo", "x2_vvoO")]
+        lib().orc_densities(ctypes.byref(self.P), _ptr(args[0]), _ptr(args[1]), ctypes.c_double(omega),
+                            *[_ptr(x) for x in vecs], ctypes.c_int64(tb), ctypes.c_int64(te),
+                            _ptr(Dm0), _ptr(D0m), ctypes.byref(s))
+        return Dm0, D0m, float(s.value)
+
     def triples_block(self, kind, i, j, k, omega=0.0, vec=None):
         d = self.d
         out = np.zeros((d.n_v, d.n_v, d.n_v))

@@ -297,3 +297,91 @@ def test_inactive_rotation_covariance(which):
     o = Oracle(q).ground_residual()
     ref = {"x1": n1, **blocks2(n2, d.n_o, d.n_v)}
     assert max(compare_out(o, ref).values()) < 1e-12
+
+
+# ------------------------------------------------------------------ densities
+DENS = [I.Dims(3, 4, 4, 6, 10), I.Dims(4, 5, 5, 7, 9), I.Dims(3, 3, 3, 3, 5), I.Dims(2, 3, 4, 5, 6)]
+
+
+def _dens_inputs(d, seed):
+    p = I.make_problem(d, seed, with_density_blocks=True)
+    b = Brute(d.n_o, d.n_v, p.eps_o, p.eps_v, I.full_cholesky(seed, d), p.t1,
+              I.full_doubles(seed, I.TID_T2, d, 0.02))
+    return p, b
+
+
+@pytest.mark.parametrize("d", DENS)
+def test_densities_brute_equals_restricted_loop(d):
+    seed = 7
+    p, b = _dens_inputs(d, seed)
+    L1, L2 = I.full_vector(seed, d, 64)
+    R1, R2 = I.full_vector(seed, d, 0)
+    l1, l2 = I.full_vector(seed, d, 128, normalise=False, sigma1=0.01, sigma2=0.02)
+    Dm0 = b.density_m0(L1, L2, 0.45)
+    D0m, s = b.density_0m(l1, l2, R1, R2, 0.45)
+    orc = Oracle(p)
+    Om0, O0m, os_ = orc.densities(0.45, I.trial_vector(seed, d, 64), I.trial_vector(seed, d, 0),
+                                  I.lambda_vector(p), p.t2_vVoO, p.t2_vVOo)
+    assert rel(Om0, Dm0) < 1e-13 and rel(O0m, D0m) < 1e-13 and abs(os_ - s) <= 1e-13 * abs(s)
+
+
+def test_density_trace_identities():
+    """tr D^{m-0} = 0 and tr D^{0-m} = 2 N_O s: the occupied-occupied and virtual-virtual
+    terms cancel in the trace and D_LL carries 2s (SI density equations)."""
+    d = I.Dims(4, 5, 5, 7, 9)
+    p, b = _dens_inputs(d, 3)
+    orc = Oracle(p)
+    Dm0, D0m, s = orc.densities(0.5, I.trial_vector(3, d, 64), I.trial_vector(3, d, 0), I.lambda_vector(p),
+                                p.t2_vVoO, p.t2_vVOo)
+    scale = np.abs(Dm0).max()
+    assert abs(np.trace(Dm0)) < 1e-14 * scale
+    assert abs(np.trace(D0m) - 2 * d.N_O * s) < 1e-14 * np.abs(D0m).max()
+    assert abs(s) > 0
+
+
+def test_density_linearity_and_ccsd_reduction():
+    d = I.Dims(3, 4, 4, 6, 10)
+    p, b = _dens_inputs(d, 5)
+    orc = Oracle(p)
+    lam = I.lambda_vector(p)
+    L, L2v = I.trial_vector(5, d, 64), I.trial_vector(5, d, 65)
+    R, R2v = I.trial_vector(5, d, 0), I.trial_vector(5, d, 1)
+    a = orc.densities(0.4, L, R, lam, p.t2_vVoO, p.t2_vVOo)
+    c = orc.densities(0.4, L2v, R2v, lam, p.t2_vVoO, p.t2_vVOo)
+    m = orc.densities(0.4, vec_lin(0.3, L, 1.1, L2v), vec_lin(0.3, R, 1.1, R2v), lam, p.t2_vVoO, p.t2_vVOo)
+    assert rel(m[0], 0.3 * a[0] + 1.1 * c[0]) < 1e-13      # D^{m-0} linear in L
+    assert rel(m[1], 0.3 * a[1] + 1.1 * c[1]) < 1e-13      # D^{0-m} linear in R
+    d1 = I.Dims(1, 4, 4, 6, 10)
+    p1, b1 = _dens_inputs(d1, 5)
+    L1, L2 = I.full_vector(5, d1, 64)
+    R1, R2 = I.full_vector(5, d1, 0)
+    l1, l2 = I.full_vector(5, d1, 128, normalise=False, sigma1=0.01, sigma2=0.02)
+    assert np.abs(b1.density_m0(L1, L2, 0.4)).max() < 1e-17
+    D0m, s = b1.density_0m(l1, l2, R1, R2, 0.4)
+    assert np.abs(D0m).max() < 1e-17 and abs(s) < 1e-30
+
+
+def test_density_inactive_rotation_covariance():
+    """Rotating inactive orbitals rotates D as C^T D C."""
+    d = I.Dims(3, 3, 5, 6, 9)
+    seed = 17
+    p, b = _dens_inputs(d, seed)
+    Cocc, Cvir = _rot(d.N_O, d.n_o, 1), _rot(d.N_V, d.n_v, 2)
+    C = np.zeros((d.N, d.N))
+    C[:d.N_O, :d.N_O] = Cocc
+    C[d.N_O:, d.N_O:] = Cvir
+    L1, L2 = I.full_vector(seed, d, 64)
+    R1, R2 = I.full_vector(seed, d, 0)
+    l1, l2 = I.full_vector(seed, d, 128, normalise=False, sigma1=0.01, sigma2=0.02)
+
+    def r1(x):
+        return Cvir.T @ x @ Cocc
+
+    def r2(x):
+        return np.einsum("abij,aA,bB,iI,jJ->ABIJ", x, Cvir, Cvir, Cocc, Cocc)
+
+    b2 = Brute(d.n_o, d.n_v, p.eps_o, p.eps_v, np.einsum("Jpq,pP,qQ->JPQ", b.L, C, C), r1(b.t1), r2(b.t2))
+    assert rel(b2.density_m0(r1(L1), r2(L2), 0.4), C.T @ b.density_m0(L1, L2, 0.4) @ C) < 1e-12
+    D0, s0 = b.density_0m(l1, l2, R1, R2, 0.4)
+    D1, s1 = b2.density_0m(r1(l1), r2(l2), r1(R1), r2(R2), 0.4)
+    assert rel(D1, C.T @ D0 @ C) < 1e-12 and abs(s1 - s0) < 1e-12 * abs(s0)
