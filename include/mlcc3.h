@@ -129,6 +129,26 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
 int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
                          const mlcc3_vec *L, mlcc3_out *sigma, const mlcc3_opts *opts, void *stream);
 
+/* Triples terms of the transition densities of nstate excited states (SI left and right
+ * density equations, Implementation section: occupied and virtual loops).
+ *   D_m0[m][N][N]: left transition density D^{m-0} of state m from the left vector L[m]
+ *                  (L3 at omega[m]) and tau3;
+ *   D_0m[m][N][N]: right transition density D^{0-m} from R[m] (R3 at omega[m]), the
+ *                  ground-state multipliers `lambda` (lambda3 from the L3 recipe at omega = 0)
+ *                  and tau3; the doubles of R enter as Rbar = (1 + delta_{ai,bj}) R;
+ *   s[m]         = (1/6) sum lambda~3 R3; 2 s[m] is already added to the occupied diagonal
+ *                  of D_0m, the term -s D^{0-0} is left to the caller.
+ * N = N_O + N_V, occupied orbitals first; element [p][q] multiplies A_pq.  D and s are
+ * device arrays, overwritten.  t2_vVoO[n_v][N_V][n_o][N_O] = t^{cD}_{kL} and
+ * t2_vVOo[n_v][N_V][N_O][n_o] = t^{cD}_{Lk} are the extra doubles blocks of the right
+ * density (device).  With a triple range only the unique triples in the range carry
+ * triples amplitudes (terms coupling two occupied triples are then not additive over
+ * ranges). */
+int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2_vVoO, const double *t2_vVOo,
+                            int32_t nstate, const double *omega, const mlcc3_vec *L, const mlcc3_vec *R,
+                            const mlcc3_vec *lambda, double *D_m0, double *D_0m, double *s,
+                            const mlcc3_opts *opts, void *stream);
+
 /* Algorithmic FLOPs of one call (which: 0 ground residual, 1 right, 2 left) for nvec
  * vectors over the full triple list: U = 2 N_V n_v^3 (n_o^3 - n_o); ground 2U,
  * right/left (1 + 3 nvec) U (Implementation section cost model with the exact

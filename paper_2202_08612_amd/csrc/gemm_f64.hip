@@ -230,6 +230,14 @@ static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf)
 }
 
 // unit stride inside each run of the index (two-level maps with s0 = 1 are contiguous in runs of d)
+hipError_t gemm_reduce_parts(const Gemm &g, hipStream_t s) {
+  if (g_dry || g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (g.ksplit < 1 || !g.P) return hipErrorInvalidValue;
+  const long long n = (long long)g.M * g.N * g.nbatch;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
 static bool unit(const Idx2 &f) { return f.s0 == 1; }
 
 bool g_dry = false;

@@ -274,9 +274,10 @@ void gemm(const Gemm &g, hipStream_t s) {
   const long long tiles = gemm_tiles(g);
   Gemm h = g;
   if (tiles < 256 && ktot >= 2048 && t_ws) {
-    // too few workgroups for a long K: split K and reduce the partial tiles
-    long long ks = std::min<long long>((512 + tiles - 1) / tiles, ktot / 512);
-    ks = std::max<long long>(1, std::min<long long>(ks, 64));
+    // too few workgroups for a long K: split K (about 2048 workgroups, >= 1024 K each) and
+    // reduce the partial tiles in a fixed order
+    long long ks = std::min<long long>((2048 + tiles - 1) / tiles, ktot / 1024);
+    ks = std::max<long long>(1, std::min<long long>(ks, 4096));
     if (ks > 1) {
       h.ksplit = (int)ks;
       h.P = buf(t_ws, "gemm_splitk", (size_t)(ks * g.nbatch * (long long)g.M * g.N), t_stream);
@@ -562,20 +563,20 @@ void w_oterm(const Dims &d, double *W, const double *xB1, BMap G1, const double 
 }
 
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
-             double omega, Range r, const LocalTerms &lt, hipStream_t s) {
+             double omega, Range r, const LocalTerms &lt, hipStream_t s, double *Xc = nullptr) {
   double *Xu = buf(ws, "Xu", (size_t)ws->nu * d.nv3, s);
-  launch_permute_denom(W, Xu, Xt, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, omega,
-                       r.tb, r.te, lt, s);
+  launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v,
+                       omega, r.tb, r.te, lt, s);
   HIPRT(hipGetLastError());
 }
 
-// tau~ for all ordered triples into "XT"
-void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s) {
+// tau~ for all ordered triples into "XT" (and covariant tau into Xc when given)
+void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s, double *Xc = nullptr) {
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
   w_dterm(d, W, B(ws, "tA"), bm_rDbc(d, B(ws, "G1")), nullptr, BMap{}, s);
   w_oterm(d, W, g->t2_vvoO, bm_Lqrc(d, B(ws, "G2")), nullptr, BMap{}, s);
-  permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, s);
+  permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, s, Xc);
 }
 
 // Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
@@ -715,6 +716,141 @@ void finish_right_like(mlcc3_ws ws, const Dims &d, const double *X, const double
   y.no = d.no; y.nv = d.nv; y.NO = d.NO; y.NV = d.NV; y.delta = delta;
   launch_doubles_out(y, out->x2_vVoo, out->x2_vvoO, s);
   HIPRT(hipGetLastError());
+}
+
+
+// one-index transformed blocks of a right vector: Rbar packs "RA" [p][q][a][D] and "RB"
+// [a][b][p][L], Upsilon_bDck "U1", Upsilon_Ljck "Uo", Upsilon_kc "Ukc", Xi_jLkc "Xi"
+void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &R, hipStream_t s) {
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
+  double *RA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
+  double *RB = buf(ws, "RB", (size_t)nv * nv * no * NO, s);
+  launch_pack_vVoo(R.x2_vVoo, no, nv, NV, 1, RA, s);
+  launch_rbar_vvoO(R.x2_vvoO, no, nv, NO, RB, s);
+  double *dOO = buf(ws, "dOO", (size_t)nc * NO * NO, s);
+  double *dvV = buf(ws, "dvV", (size_t)nc * nv * NV, s);
+  double *dvO = buf(ws, "dvO", (size_t)nc * nv * NO, s);
+  launch_dlhat(g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R.x1, nc, NO, NV, nv, dOO, dvV, dvO, s);
+  HIPRT(hipGetLastError());
+  double *U1 = buf(ws, "U1", (size_t)no * NV * d.nv2, s);
+  {
+    Gemm gg = asm_vVvo(d, U1);
+    gg.nseg = 2;
+    gg.seg[0] = asm_vVvo_seg(d, dvV, B(ws, "LhvO"));
+    gg.seg[1] = asm_vVvo_seg(d, B(ws, "LhvV"), dvO);
+    gemm(gg, s);
+  }
+  double *Uo = buf(ws, "Uo", (size_t)NO * no * no * nv, s);
+  {
+    Gemm gg = asm_oovo(d, Uo);
+    gg.nseg = 2;
+    gg.seg[0] = asm_oovo_seg(d, dOO, B(ws, "LhvO"));
+    gg.seg[1] = asm_oovo_seg(d, B(ws, "LhOO"), dvO);
+    gemm(gg, s);
+  }
+  double *Ukc = buf(ws, "Ukc", (size_t)no * nv, s);
+  launch_fock_like(g->L_OV, R.x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc, s);
+  double *Xi = buf(ws, "Xi", (size_t)no * no * nv * NO, s);
+  {
+    Gemm gg;
+    gg.M = no * no * nv;
+    gg.N = NO;
+    gg.C = Xi;
+    gg.crow = plain(NO);
+    gg.ccol = plain(1);
+    gg.nseg = 1;
+    gg.seg[0] = seg(B(ws, "gDo"), plain(NV), plain(1), 0, R.x1, plain(NO), plain(1), 0, NV);
+    gemm(gg, s);
+  }
+}
+
+// R3 of a prepared right vector: contravariant into Xt, covariant into Xc (optional)
+void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, double omega, Range r, double *Xt, double *Xc,
+              hipStream_t s) {
+  double *W = B(ws, "W");
+  w_dterm(d, W, B(ws, "RA"), bm_rDbc(d, B(ws, "G1")), B(ws, "tA"), bm_rDbc(d, B(ws, "U1")), s);
+  w_oterm(d, W, B(ws, "RB"), bm_Lqrc(d, B(ws, "G2")), g->t2_vvoO, bm_Lqrc(d, B(ws, "Uo")), s);
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, LocalTerms{}, s, Xc);
+}
+
+// L3 (transpose-transformation recipe) of a left-type vector into Xt; packs LA/LV under the given names
+void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &L, double omega, Range r,
+              double *Xt, const char *laname, const char *lvname, hipStream_t s) {
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+  double *LA = buf(ws, laname, (size_t)no * no * nv * NV, s);
+  double *LV = buf(ws, lvname, (size_t)no * no * d.nv2, s);
+  launch_pack_vVoo(L.x2_vVoo, no, nv, NV, 0, LA, s);
+  launch_pack_vvoo(L.x2_vVoo, no, nv, NV, 0, LV, s);
+  double *W = B(ws, "W");
+  w_dterm(d, W, LA, bm_rbcD(d, B(ws, "Gb1")), nullptr, BMap{}, s);
+  w_oterm(d, W, L.x2_vvoO, bm_qrcL(d, B(ws, "Gb3")), nullptr, BMap{}, s);
+  LocalTerms lt;
+  lt.L1 = L.x1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, lt, s);
+}
+
+// ------------------------------------------------------ density contractions
+// C[k][l] = alpha sum_{(i,j),(abc)} X1[i][j][k][abc] X2[i][j][l][abc] + beta C
+void g_kl(const Dims &d, const double *X1, const double *X2, double *C, long long ldc, double alpha, double beta,
+          hipStream_t s) {
+  Gemm g = gemm_plain(d.no, d.no, C, plain(ldc), plain(1), alpha, beta);
+  g.nseg = 1;
+  g.seg[0] = seg(X1, plain(d.nv3), split((int)d.nv3, (long long)d.no * d.nv3, 1), 0, X2,
+                 split((int)d.nv3, (long long)d.no * d.nv3, 1), plain(d.nv3), 0, (int)(d.no * d.no * d.nv3));
+  gemm(g, s);
+}
+// C[c][d] = alpha sum_{(ijk,ab)} X1[ijk][ab][c] X2[ijk][ab][d] + beta C
+void g_cd(const Dims &d, const double *X1, const double *X2, double *C, long long ldc, double alpha, double beta,
+          hipStream_t s) {
+  Gemm g = gemm_plain(d.nv, d.nv, C, plain(ldc), plain(1), alpha, beta);
+  g.nseg = 1;
+  g.seg[0] = seg(X1, plain(1), plain(d.nv), 0, X2, plain(d.nv), plain(1), 0, (int)(d.nord * d.nv2));
+  gemm(g, s);
+}
+// out[(l,d)] = alpha sum_{(ij),(ab)} X[i][j][l][ab][d] Y[i][j][a][b] + beta out; out row map given
+void g_ld(const Dims &d, const double *X, const double *Y, double *C, Idx2 crow, double alpha, double beta,
+          hipStream_t s) {
+  Gemm g = gemm_plain(d.no * d.nv, 1, C, crow, plain(1), alpha, beta);
+  g.nseg = 1;
+  g.seg[0] = seg(X, split(d.nv, d.nv3, 1), split((int)d.nv2, (long long)d.no * d.nv3, d.nv), 0, Y, plain(1),
+                 plain(1), 0, (int)(d.no * d.no * d.nv2));
+  gemm(g, s);
+}
+// run g over its nbatch batches into partial buffers and sum them (fixed order) into g's output
+void gemm_sumz(mlcc3_ws ws, const Gemm &g, hipStream_t s) {
+  const long long MN = (long long)g.M * g.N;
+  double *P = buf(ws, "sumz_part", (size_t)(MN * g.nbatch), s);
+  Gemm h = g;
+  h.C = P;
+  h.crow = plain(g.N);
+  h.ccol = plain(1);
+  h.cbatch = MN;
+  h.alpha = 1.0;
+  h.beta = 0.0;
+  gemm(h, s);
+  Gemm r = g;
+  r.ksplit = g.nbatch;
+  r.nbatch = 1;
+  r.P = P;
+  r.cbatch = 0;
+  check_range(r.C, r.crow, r.M, r.ccol, r.N, 0, 1, "C");
+  HIPRT(gemm_reduce_parts(r, s));
+}
+// V[(j,k,b)][L] = sum_{i,(a,c)} X[i][j][k][a][b][c] Y[a][c][i][L]   (Y in the [a][b][i][L] block layout)
+void v_jkbL(mlcc3_ws ws, const Dims &d, const double *X, const double *Y, double *V, hipStream_t s) {
+  Gemm g = gemm_plain(d.no * d.no * d.nv, d.NO, V, plain(d.NO), plain(1), 1.0, 0.0);
+  g.nbatch = d.no;
+  g.nseg = 1;
+  g.seg[0] = seg(X, split(d.nv, d.nv3, d.nv), split(d.nv, d.nv2, 1), (long long)d.no * d.no * d.nv3, Y,
+                 plain((long long)d.no * d.NO), plain(1), d.NO, (int)d.nv2);
+  gemm_sumz(ws, g, s);
+}
+// D[L][N_O + D] += alpha sum_{kk} V[kk][L] T[kk][D]  (K = n_o^2 n_v; T [(.,.,.)][N_V])
+void d_LD(const Dims &d, const double *V, const double *T, double *Dm, long long N, double alpha, hipStream_t s) {
+  Gemm g = gemm_plain(d.NO, d.NV, Dm + d.NO, plain(N), plain(1), alpha, 1.0);
+  g.nseg = 1;
+  g.seg[0] = seg(V, plain(1), plain(d.NO), 0, T, plain(d.NV), plain(1), 0, d.no * d.no * d.nv);
+  gemm(g, s);
 }
 
 }  // namespace
@@ -875,52 +1011,9 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     double *W = B(ws, "W");
     double *XR = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
     for (int m = 0; m < nvec; m++) {
-      // vector prep: Rbar blocks, one-index transformed integrals Upsilon, Upsilon_kc, Xi
-      double *RA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
-      double *RB = buf(ws, "RB", (size_t)nv * nv * no * NO, s);
-      launch_pack_vVoo(R[m].x2_vVoo, no, nv, NV, 1, RA, s);
-      launch_rbar_vvoO(R[m].x2_vvoO, no, nv, NO, RB, s);
-      double *dOO = buf(ws, "dOO", (size_t)nc * NO * NO, s);
-      double *dvV = buf(ws, "dvV", (size_t)nc * nv * NV, s);
-      double *dvO = buf(ws, "dvO", (size_t)nc * nv * NO, s);
-      launch_dlhat(g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R[m].x1, nc, NO, NV, nv, dOO, dvV, dvO, s);
-      HIPRT(hipGetLastError());
-      double *U1 = buf(ws, "U1", (size_t)no * NV * d.nv2, s);
-      {
-        Gemm gg = asm_vVvo(d, U1);
-        gg.nseg = 2;
-        gg.seg[0] = asm_vVvo_seg(d, dvV, B(ws, "LhvO"));
-        gg.seg[1] = asm_vVvo_seg(d, B(ws, "LhvV"), dvO);
-        gemm(gg, s);
-      }
-      double *Uo = buf(ws, "Uo", (size_t)NO * no * no * nv, s);
-      {
-        Gemm gg = asm_oovo(d, Uo);
-        gg.nseg = 2;
-        gg.seg[0] = asm_oovo_seg(d, dOO, B(ws, "LhvO"));
-        gg.seg[1] = asm_oovo_seg(d, B(ws, "LhOO"), dvO);
-        gemm(gg, s);
-      }
-      double *Ukc = buf(ws, "Ukc", (size_t)no * nv, s);
-      launch_fock_like(g->L_OV, R[m].x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc,
-                       s);
-      // Xi[(j,k,c)][L] = sum_D g_jDkc R^D_L
-      double *Xi = buf(ws, "Xi", (size_t)no * no * nv * NO, s);
-      {
-        Gemm gg;
-        gg.M = no * no * nv;
-        gg.N = NO;
-        gg.C = Xi;
-        gg.crow = plain(NO);
-        gg.ccol = plain(1);
-        gg.nseg = 1;
-        gg.seg[0] = seg(B(ws, "gDo"), plain(NV), plain(1), 0, R[m].x1, plain(NO), plain(1), 0, NV);
-        gemm(gg, s);
-      }
-      // R3 before P: W(Rbar; ghat) + W(t; Upsilon)
-      w_dterm(d, W, RA, bm_rDbc(d, B(ws, "G1")), B(ws, "tA"), bm_rDbc(d, U1), s);
-      w_oterm(d, W, RB, bm_Lqrc(d, B(ws, "G2")), g->t2_vvoO, bm_Lqrc(d, Uo), s);
-      permute(ws, d, W, XR, g->eps_o, g->eps_v, omega[m], r, LocalTerms{}, s);
+      right_vector_prep(ws, g, d, R[m], s);
+      build_R3(ws, g, d, omega[m], r, XR, nullptr, s);
+      double *Ukc = B(ws, "Ukc"), *Xi = B(ws, "Xi");
       // back-contractions
       double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
       double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
@@ -985,7 +1078,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
       double *LA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
       double *LV = buf(ws, "LV", (size_t)no * no * d.nv2, s);
       launch_pack_vVoo(L2a, no, nv, NV, 0, LA, s);
-      launch_pack_vvoo(L2a, no, nv, NV, LV, s);
+      launch_pack_vvoo(L2a, no, nv, NV, 0, LV, s);
       // L3 before P (SI transpose transformation, exact-transpose index placement):
       //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc  (+ local terms in the permute pass)
       w_dterm(d, W, LA, bm_rbcD(d, B(ws, "Gb1")), nullptr, BMap{}, s);
@@ -1128,6 +1221,174 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
       y.YvV = QvV; y.YvO = QvO; y.Yvv = nullptr;
       y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
       launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
+      HIPRT(hipGetLastError());
+    }
+  });
+}
+
+
+int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2_vVoO, const double *t2_vVOo,
+                            int32_t nstate, const double *omega, const mlcc3_vec *L, const mlcc3_vec *R,
+                            const mlcc3_vec *lambda, double *D_m0, double *D_0m, double *s_out,
+                            const mlcc3_opts *opts, void *stream) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    t_ws = ws;
+    t_stream = (hipStream_t)stream;
+    validate_ground(g);
+    check(nstate >= 1, "nstate must be >= 1");
+    check(omega && L && R && lambda && D_m0 && D_0m && s_out, "NULL argument");
+    const Dims d = dims_of(g);
+    const long long N = (long long)d.NO + d.NV;
+    const bool act = d.no > 0 && d.nv > 0;
+    check(!act || (t2_vVoO && t2_vVOo), "NULL density t2 block");
+    std::vector<mlcc3_out> dummy(nstate);
+    for (int m = 0; m < nstate; m++) {
+      check(std::isfinite(omega[m]), "omega must be finite");
+      check(L[m].x1 && R[m].x1 && (!act || (L[m].x2_vVoo && L[m].x2_vvoO && R[m].x2_vVoo && R[m].x2_vvoO)),
+            "NULL pointer in a vector");
+    }
+    check(lambda->x1 && (!act || (lambda->x2_vVoo && lambda->x2_vvoO)), "NULL pointer in lambda");
+    reg_ground(g);
+    reg(t2_vVoO, (long long)d.nv * d.NV * d.no * d.NO, "t2_vVoO");
+    reg(t2_vVOo, (long long)d.nv * d.NV * d.NO * d.no, "t2_vVOo");
+    for (int m = 0; m < nstate; m++) {
+      reg_vec(g, L[m].x1, L[m].x2_vVoo, L[m].x2_vvoO);
+      reg_vec(g, R[m].x1, R[m].x2_vVoo, R[m].x2_vvoO);
+    }
+    reg_vec(g, lambda->x1, lambda->x2_vVoo, lambda->x2_vvoO);
+    reg(D_m0, nstate * N * N, "D_m0");
+    reg(D_0m, nstate * N * N, "D_0m");
+    reg(s_out, nstate, "s");
+    const mlcc3_opts o = opts_or_default(opts);
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(ws->device);
+    const Range r = range_of(o, mlcc3_num_triples(d.no));
+    if (o.check_finite) {
+      ground_finite(ws, g, s);
+      for (int m = 0; m < nstate; m++) {
+        vec_finite(ws, d, L[m], s);
+        vec_finite(ws, d, R[m], s);
+      }
+      vec_finite(ws, d, *lambda, s);
+    }
+    guard_check(g, omega, nstate, o.guard, s);
+    HIPRT(hipMemsetAsync(D_m0, 0, sizeof(double) * nstate * N * N, s));
+    HIPRT(hipMemsetAsync(D_0m, 0, sizeof(double) * nstate * N * N, s));
+    HIPRT(hipMemsetAsync(s_out, 0, sizeof(double) * nstate, s));
+    if (d.no < 2 || d.nv < 2 || r.tb == r.te) return;  // no triples: the triples terms vanish
+    prepare_ground(ws, g, o.reuse_ground != 0, s);
+    const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+    const size_t nbig = (size_t)(d.nord * d.nv3);
+    double *XTc = buf(ws, "XTc", nbig, s);
+    tau_path(ws, g, d, r, s, XTc);
+    double *XT = B(ws, "XT");
+    double *XLam = buf(ws, "XLam", nbig, s);
+    build_L3(ws, g, d, *lambda, 0.0, r, XLam, "LAlam", "LVlam", s);   // lambda3: L3 recipe at omega = 0
+    double *lam2t = buf(ws, "lam2t", (size_t)no * no * d.nv2, s);
+    launch_pack_vvoo(lambda->x2_vVoo, no, nv, NV, 2, lam2t, s);
+    double *XL = buf(ws, "XR", nbig, s);
+    double *XRt = buf(ws, "XRt", nbig, s);
+    double *XRc = buf(ws, "XRc", nbig, s);
+    double *tA = B(ws, "tA");
+    double *V = buf(ws, "dens_V", (size_t)no * no * nv * NO, s);
+    double *Xl = buf(ws, "dens_Xl", (size_t)no * no * d.nv2, s);
+    double *Yc = buf(ws, "dens_Yc", (size_t)no * nv, s);
+    double *Zt = buf(ws, "dens_Zt", (size_t)no * no, s);
+    double *Zv = buf(ws, "dens_Zv", (size_t)d.nv2, s);
+    double *Rbv = buf(ws, "dens_Rbv", (size_t)no * no * d.nv2, s);
+    double *part = buf(ws, "dot_part", 512, s);
+    for (int m = 0; m < nstate; m++) {
+      double *Dm = D_m0 + (long long)m * N * N, *D0 = D_0m + (long long)m * N * N;
+      build_L3(ws, g, d, L[m], omega[m], r, XL, "LA", "LV", s);
+      right_vector_prep(ws, g, d, R[m], s);
+      build_R3(ws, g, d, omega[m], r, XRt, XRc, s);
+      // ---- D^{m-0} (SI left density) ----
+      g_kl(d, XTc, XL, Dm, N, -0.5, 1.0, s);                          // D_kl -= 1/2 L~_{ijl} tau_{ijk}
+      g_cd(d, XL, XTc, Dm + NO * N + NO, N, 0.5, 1.0, s);             // D_cd += 1/2 L~^{abc} tau^{abd}
+      g_ld(d, XT, B(ws, "LV"), Dm + NO, split(nv, N, 1), 1.0, 1.0, s);  // D_ld += L^{ab}_{ij} tau~^{abd}_{ijl}
+      v_jkbL(ws, d, XL, g->t2_vvoO, V, s);                            // V = sum L~ t^{ac}_{iL}
+      d_LD(d, V, tA, Dm, N, -1.0, s);                                 // D_LD -= V t^{bD}_{jk}
+      // ---- D^{0-m} (SI right density) ----
+      {  // X^{bc}_{jk} = sum_{ai} lambda~^{abc}_{ijk} R^a_i
+        Gemm gg = gemm_plain(no * no * (int)d.nv2, 1, Xl, plain(1), plain(1), 1.0, 0.0);
+        gg.nseg = 1;
+        gg.seg[0] = seg(XLam, split((int)d.nv2, d.nv3, 1), split(nv, (long long)no * no * d.nv3, d.nv2), 0, R[m].x1,
+                        split(nv, 1, NO), plain(1), 0, no * nv);
+        gemm(gg, s);
+      }
+      {  // D_Kl -= sum t^{bc}_{jK} X^{bc}_{jl}
+        Gemm gg = gemm_plain(NO, no, D0, plain(N), plain(1), -1.0, 1.0);
+        gg.nseg = 1;
+        gg.seg[0] = seg(g->t2_vvoO, plain(1), split((int)d.nv2, NO, (long long)no * NO), 0, Xl,
+                        split((int)d.nv2, (long long)no * d.nv2, 1), plain(d.nv2), 0, no * (int)d.nv2);
+        gemm(gg, s);
+      }
+      g_kl(d, XRc, XLam, D0, N, -0.5, 1.0, s);                        // D_kl -= 1/2 lambda~_{ijl} R_{ijk}
+      {  // D_ld += sum X^{bc}_{jk} tau^{bcd}_{jkl}
+        Gemm gg = gemm_plain(no * nv, 1, D0 + NO, split(nv, N, 1), plain(1), 1.0, 1.0);
+        gg.nseg = 1;
+        gg.seg[0] = seg(XTc, split(nv, d.nv3, 1), split((int)d.nv2, (long long)no * d.nv3, nv), 0, Xl, plain(1),
+                        plain(1), 0, no * no * (int)d.nv2);
+        gemm(gg, s);
+      }
+      {  // D_ld -= sum X^{bc}_{jk} tau^{bcd}_{jlk}   (summed over j batches)
+        Gemm gg = gemm_plain(no * nv, 1, D0 + NO, split(nv, N, 1), plain(1), -1.0, 1.0);
+        gg.nbatch = no;
+        gg.nseg = 1;
+        gg.seg[0] = seg(XTc, split(nv, (long long)no * d.nv3, 1), split((int)d.nv2, d.nv3, nv),
+                        (long long)no * no * d.nv3, Xl, plain(1), plain(1), (long long)no * d.nv2, no * (int)d.nv2);
+        gemm_sumz(ws, gg, s);
+      }
+      g_ld(d, XRt, lam2t, D0 + NO, split(nv, N, 1), 1.0, 1.0, s);    // D_ld += lambda~^{ab}_{ij} R~^{abd}_{ijl}
+      launch_pack_vvoo(R[m].x2_vVoo, no, nv, NV, 1, Rbv, s);           // Rbar^{ab}_{ij}
+      g_ld(d, XLam, Rbv, Yc, plain(1), 1.0, 0.0, s);                   // Y_kc = sum lambda~^{abc}_{ijk} Rbar^{ab}_{ij}
+      {  // D_LD += 1/2 sum Y_kc (2 t^{cD}_{kL} - t^{cD}_{Lk})
+        Gemm gg = gemm_plain(NO * NV, 1, D0 + NO, split(NV, N, 1), plain(1), 1.0, 1.0);
+        gg.nseg = 2;
+        gg.seg[0] = seg(t2_vVoO, split(NV, 1, (long long)no * NO), split(nv, NO, (long long)NV * no * NO), 0, Yc,
+                        plain(1), plain(1), 0, no * nv, 1.0);
+        gg.seg[1] = seg(t2_vVOo, split(NV, no, (long long)NO * no), split(nv, 1, (long long)NV * NO * no), 0, Yc,
+                        plain(1), plain(1), 0, no * nv, -0.5);
+        gemm(gg, s);
+      }
+      v_jkbL(ws, d, XLam, B(ws, "RB"), V, s);                          // V2 = sum lambda~ Rbar^{ac}_{iL}
+      d_LD(d, V, tA, D0, N, -1.0, s);                                  // D_LD -= V2 t^{bD}_{jk}
+      {  // V3[i][(k,a)][L] = sum_{j,bc} lambda~^{abc}_{ijk} t^{bc}_{jL};  D_LD -= V3 Rbar^{aD}_{ik}
+        Gemm gg = gemm_plain(no * nv, NO, V, plain(NO), plain(1), 1.0, 0.0);
+        gg.nbatch = no;
+        gg.cbatch = (long long)no * nv * NO;
+        gg.nseg = 1;
+        gg.seg[0] = seg(XLam, split(nv, d.nv3, d.nv2), split((int)d.nv2, (long long)no * d.nv3, 1),
+                        (long long)no * no * d.nv3, g->t2_vvoO, split((int)d.nv2, NO, (long long)no * NO), plain(1),
+                        0, no * (int)d.nv2);
+        gemm(gg, s);
+        d_LD(d, V, B(ws, "RA"), D0, N, -1.0, s);
+      }
+      g_kl(d, XLam, XTc, Zt, no, 1.0, 0.0, s);                         // Z_kl = sum lambda~_{ijk} tau_{ijl}
+      {  // D_lD -= 1/2 sum_k Z_kl R^D_k
+        Gemm gg = gemm_plain(no, NV, D0 + NO, plain(N), plain(1), -0.5, 1.0);
+        gg.nseg = 1;
+        gg.seg[0] = seg(Zt, plain(1), plain(no), 0, R[m].x1, plain(1), plain(NO), 0, no);
+        gemm(gg, s);
+      }
+      g_cd(d, XLam, XTc, Zv, nv, 1.0, 0.0, s);                         // Zv_cd = sum lambda~^{abc} tau^{abd}
+      {  // D_Ld -= 1/2 sum_c R^c_L Zv_cd
+        Gemm gg = gemm_plain(NO, nv, D0 + NO, plain(N), plain(1), -0.5, 1.0);
+        gg.nseg = 1;
+        gg.seg[0] = seg(R[m].x1, plain(1), plain(NO), 0, Zv, plain(nv), plain(1), 0, nv);
+        gemm(gg, s);
+      }
+      launch_add_vo(D0, NO, (int)N, no, nv, Yc, 0.5, s);             // D_ck += 1/2 Y_kc
+      {  // D_cD += sum X^{bc}_{jk} t^{bD}_{jk}
+        Gemm gg = gemm_plain(nv, NV, D0 + NO * N + NO, plain(N), plain(1), 1.0, 1.0);
+        gg.nseg = 1;
+        gg.seg[0] = seg(Xl, plain(1), plain(nv), 0, tA, plain(NV), plain(1), 0, no * no * nv);
+        gemm(gg, s);
+      }
+      g_cd(d, XLam, XRc, D0 + NO * N + NO, N, 0.5, 1.0, s);            // D_cd += 1/2 lambda~^{abc} R^{abd}
+      launch_dot(XLam, XRc, (long long)nbig, 1.0 / 6.0, part, s_out + m, s);   // s = 1/6 sum lambda~ R3
+      launch_add_diag(D0, NO, (int)N, s_out + m, 2.0, s);              // D_LL += 2 s
       HIPRT(hipGetLastError());
     }
   });

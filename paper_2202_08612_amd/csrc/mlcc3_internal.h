@@ -44,6 +44,8 @@ struct Gemm {
 
 // FP64 MFMA GEMM (v_mfma_f64_16x16x4_f64), LDS-staged, 256 threads per block.
 hipError_t gemm_f64(const Gemm &g, hipStream_t s);
+// C = alpha * sum_{part < ksplit} P[batch][part][M][N] + beta * C through g's output maps
+hipError_t gemm_reduce_parts(const Gemm &g, hipStream_t s);
 // number of workgroups gemm_f64 launches for g with ksplit = 1
 long long gemm_tiles(const Gemm &g);
 

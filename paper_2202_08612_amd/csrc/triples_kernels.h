@@ -37,11 +37,17 @@ void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV
                       double *tmp_s, double *tmp_y, double *tmp_z, double *out, hipStream_t s);
 void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA, hipStream_t s);
 void launch_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB, hipStream_t s);
-void launch_pack_vvoo(const double *x, int no, int nv, int NV, double *xV, hipStream_t s);
+void launch_pack_vvoo(const double *x, int no, int nv, int NV, int mode, double *xV, hipStream_t s);
+// out[0] = scale * sum a[i] b[i]; part holds 512 doubles of scratch
+void launch_dot(const double *a, const double *b, long long n, double scale, double *part, double *out,
+                hipStream_t s);
+void launch_add_diag(double *D, int NO, int N, const double *sv, double f, hipStream_t s);
+void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, double f, hipStream_t s);
 // W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
-void launch_permute_denom(const double *W, double *Xu, double *Xt, const UniqueTriple *ut, int nu, int no, int nv,
-                          const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
-                          const LocalTerms &lt, hipStream_t s);
+// (and, if Xc is not NULL, the covariant X to every ordering)
+void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
+                          int no, int nv, const double *eps_o, const double *eps_v, double omega, long long tb,
+                          long long te, const LocalTerms &lt, hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
 // out[i] = sum_r P[r][i], r = 0..rows-1 (fixed order)

@@ -173,13 +173,52 @@ __global__ void k_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB)
   xB[id] = v;
 }
 
-// xV[p][q][a][b] = x^{ab}_{pq} (all-active block)
-__global__ void k_pack_vvoo(const double *x, int no, int nv, int NV, double *xV) {
+// xV[p][q][a][b] = x^{ab}_{pq} (all-active block); mode 1: (1 + delta_{ab} delta_{pq}) x,
+// mode 2: contravariant doubles 2 x^{ab}_{pq} - x^{ba}_{pq}
+__global__ void k_pack_vvoo(const double *x, int no, int nv, int NV, int mode, double *xV) {
   long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (id >= (long long)no * no * nv * nv) return;
   const int b = id % nv, a = (id / nv) % nv, q = (id / ((long long)nv * nv)) % no,
             p = id / ((long long)nv * nv * no);
-  xV[id] = x[(((long long)a * NV + b) * no + p) * no + q];
+  double v = x[(((long long)a * NV + b) * no + p) * no + q];
+  if (mode == 1 && a == b && p == q) v *= 2.0;
+  if (mode == 2) v = 2.0 * v - x[(((long long)b * NV + a) * no + p) * no + q];
+  xV[id] = v;
+}
+
+// deterministic dot product: per-block partial sums, then one block adds them in order
+__global__ void k_dot_partial(const double *a, const double *b, long long n, double *part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    acc += a[i] * b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_dot_final(const double *part, int np, double scale, double *out) {
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int i = 0; i < np; i++) acc += part[i];
+  out[0] = scale * acc;
+}
+
+// D[L][L] += f * s[0] for all L < NO (row stride N)
+__global__ void k_add_diag(double *D, int NO, int N, const double *s, double f) {
+  int L = blockIdx.x * blockDim.x + threadIdx.x;
+  if (L < NO) D[(long long)L * N + L] += f * s[0];
+}
+
+// D[N_O + c][k] += f * Y[k][c]
+__global__ void k_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, double f) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= no * nv) return;
+  const int c = id % nv, k = id / nv;
+  D[(long long)(NO + c) * N + k] += f * Y[id];
 }
 
 // ------------------------------------------ permutation / denominator / contravariant
@@ -270,7 +309,7 @@ __global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W,
 }
 
 __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, double *__restrict__ Xt,
-                                                        const UniqueTriple *ut, int no, int nv) {
+                                                        const UniqueTriple *ut, int no, int nv, int covariant) {
   __shared__ double cube[SUB];
   const UniqueTriple u = ut[blockIdx.x];
   const int nt = (nv + TT - 1) / TT;
@@ -282,12 +321,13 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
   double acc[TT];
 #pragma unroll
   for (int r = 0; r < TT; r++) acc[r] = 0.0;
-  for (int t = 0; t < 6; t++) {
+  const int nterm = covariant ? 1 : 6;  // covariant mode copies X itself to every ordering
+  for (int t = 0; t < nterm; t++) {
     const int t0 = c_perm[t][0], t1 = c_perm[t][1], t2 = c_perm[t][2];
     __syncthreads();
     load_cube(src, nv, TT * T[t0], TT * T[t1], TT * T[t2], cube);
     __syncthreads();
-    const double cf = c_coef[t];
+    const double cf = covariant ? 1.0 : c_coef[t];
 #pragma unroll
     for (int r = 0; r < TT; r++) {
       const int v[3] = {r, lb, lc};
@@ -460,18 +500,34 @@ void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double 
 void launch_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB, hipStream_t s) {
   L1D(k_rbar_vvoO, (long long)nv * nv * no * NO, x, no, nv, NO, xB);
 }
-void launch_pack_vvoo(const double *x, int no, int nv, int NV, double *xV, hipStream_t s) {
-  L1D(k_pack_vvoo, (long long)no * no * nv * nv, x, no, nv, NV, xV);
+void launch_pack_vvoo(const double *x, int no, int nv, int NV, int mode, double *xV, hipStream_t s) {
+  L1D(k_pack_vvoo, (long long)no * no * nv * nv, x, no, nv, NV, mode, xV);
 }
 
-void launch_permute_denom(const double *W, double *Xu, double *Xt, const UniqueTriple *ut, int nu, int no,
-                          int nv, const double *eps_o, const double *eps_v, double omega, long long tb, long long te,
-                          const LocalTerms &lt, hipStream_t s) {
+void launch_dot(const double *a, const double *b, long long n, double scale, double *part, double *out,
+                hipStream_t s) {
+  if (g_dry) return;
+  hipLaunchKernelGGL(k_dot_partial, dim3(512), dim3(256), 0, s, a, b, n, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, part, 512, scale, out);
+}
+
+void launch_add_diag(double *D, int NO, int N, const double *sv, double f, hipStream_t s) {
+  L1D(k_add_diag, (long long)NO, D, NO, N, sv, f);
+}
+
+void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, double f, hipStream_t s) {
+  L1D(k_add_vo, (long long)no * nv, D, NO, N, no, nv, Y, f);
+}
+
+void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
+                          int no, int nv, const double *eps_o, const double *eps_v, double omega, long long tb,
+                          long long te, const LocalTerms &lt, hipStream_t s) {
   if (nu <= 0 || nv <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
   hipLaunchKernelGGL(k_sym_denom, dim3(nu, nt * nt * nt), dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, omega,
                      tb, te, lt);
-  hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xt, ut, no, nv);
+  hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xt, ut, no, nv, 0);
+  if (Xc) hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xc, ut, no, nv, 1);
 }
 
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,

@@ -61,6 +61,10 @@ for _fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
     getattr(_lib, _fn).argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.c_int32, _dp,
                                    ctypes.POINTER(_Vec), ctypes.POINTER(_Vec), ctypes.POINTER(_Opts),
                                    ctypes.c_void_p]
+_lib.mlcc3_triples_densities.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, _dp, ctypes.POINTER(_Vec), ctypes.POINTER(_Vec),
+                                         ctypes.POINTER(_Vec), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(_Opts), ctypes.c_void_p]
 _lib.mlcc3_flops.argtypes = [ctypes.POINTER(_Ground), ctypes.c_int32, ctypes.c_int32]
 _lib.mlcc3_flops.restype = ctypes.c_double
 _lib.mlcc3_status_string.argtypes = [ctypes.c_int]
@@ -69,7 +73,7 @@ _lib.mlcc3_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_ws_timing", "mlcc3_ws_phase_stats", "mlcc3_opts_default",
             "mlcc3_num_triples", "mlcc3_ground_residual", "mlcc3_right_transform",
-            "mlcc3_left_transform", "mlcc3_flops", "mlcc3_status_string", "mlcc3_last_error"]
+            "mlcc3_left_transform", "mlcc3_triples_densities", "mlcc3_flops", "mlcc3_status_string", "mlcc3_last_error"]
 
 
 class MLCC3Error(RuntimeError):
@@ -209,3 +213,22 @@ def left_transform(ws, ground, omegas, vecs, outs=None, **kw):
 
 def to_numpy(out):
     return {k: v.detach().cpu().numpy() for k, v in out.items()}
+
+
+def triples_densities(ws, ground, omegas, Lvecs, Rvecs, lam, t2_vVoO, t2_vVOo, **kw):
+    """Triples terms of D^{m-0}, D^{0-m} ([nstate][N][N]) and s ([nstate]) on the device."""
+    d = ground.dims
+    n = len(Lvecs)
+    assert len(Rvecs) == n
+    N = d.N_O + d.N_V
+    Dm0 = torch.empty((n, N, N), dtype=torch.float64, device=ws.device)
+    D0m = torch.empty((n, N, N), dtype=torch.float64, device=ws.device)
+    sv = torch.empty((n,), dtype=torch.float64, device=ws.device)
+    a = _dev(t2_vVoO, ws.device)
+    b = _dev(t2_vVOo, ws.device)
+    om = (ctypes.c_double * n)(*[float(w) for w in omegas])
+    o = make_opts(**kw)
+    _check(_lib.mlcc3_triples_densities(ws.h, ctypes.byref(ground.c), a.data_ptr(), b.data_ptr(), n, om,
+                                        _vecs(Lvecs), _vecs(Rvecs), _vecs([lam]), Dm0.data_ptr(),
+                                        D0m.data_ptr(), sv.data_ptr(), ctypes.byref(o), _stream(ws.device)))
+    return Dm0, D0m, sv

@@ -71,6 +71,11 @@ def test_all_launches_in_bounds(lib, d):
         if rc == -7 and "not built" in lib.mlcc3_last_error().decode():
             continue
         assert rc == 0, (fn, lib.mlcc3_last_error())
+    lam = (V * 1)(V(*p[50:53]))
+    rc = lib.mlcc3_triples_densities(ws, ctypes.byref(g), ctypes.c_void_p(p[53]), ctypes.c_void_p(p[54]), nvec, om,
+                                     vin, vout, lam, ctypes.c_void_p(p[55]), ctypes.c_void_p(p[56]),
+                                     ctypes.c_void_p(p[57]), ctypes.byref(o), None)
+    assert rc == 0, ("densities", lib.mlcc3_last_error())
     assert lib.mlcc3_ws_destroy(ws) == 0
 
 

@@ -176,3 +176,60 @@ def test_adjoint_identity_full_config1(lib, ws):
             lhs = pair_form_blocks(d, Lp, rho)
             rhs = pair_form_blocks(d, sig, Rp)
             assert abs(lhs - rhs) <= 1e-10 * abs(lhs), (Lpart, Rpart, lhs, rhs)
+
+
+# ------------------------------------------------------------------ densities
+def _dens_case(lib, d, seed, cfg=None):
+    from oracle.oracle import Oracle
+    p = I.make_config(cfg, with_density_blocks=True) if cfg is not None else \
+        I.make_problem(d, seed, with_density_blocks=True)
+    return p, Oracle(p), lib.Ground(p)
+
+
+def _check_dens(got, ref, tol=TOL):
+    Dm0, D0m, s = got
+    for a, b in ((Dm0, ref[0]), (D0m, ref[1])):
+        a = a.detach().cpu().numpy()
+        assert np.all(np.isfinite(a))
+        assert rel(a, b) <= tol, rel(a, b)
+        assert maxrel(a, b) <= tol, maxrel(a, b)
+    assert abs(float(s) - ref[2]) <= tol * abs(ref[2])
+
+
+@pytest.mark.parametrize("d", SMALL, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
+def test_densities(lib, ws, d):
+    p, orc, g = _dens_case(lib, d, 31)
+    Ls, Rs = I.left_vectors(p, 2), I.right_vectors(p, 2)
+    lam = I.lambda_vector(p)
+    om = I.omegas(False, 2)
+    Dm0, D0m, s = lib.triples_densities(ws, g, om, [lib.vec_to_device(v) for v in Ls],
+                                        [lib.vec_to_device(v) for v in Rs], lib.vec_to_device(lam),
+                                        p.t2_vVoO, p.t2_vVOo)
+    for m in range(2):
+        ref = orc.densities(om[m], Ls[m], Rs[m], lam, p.t2_vVoO, p.t2_vVOo)
+        _check_dens((Dm0[m], D0m[m], s[m]), ref)
+
+
+@pytest.mark.parametrize("rng", [(0, 6), (340, 352)])
+def test_densities_full_shape_subsets(lib, ws, rng):
+    p, orc, g = _dens_case(lib, None, None, cfg=1)
+    L, R, lam = I.left_vectors(p, 1)[0], I.right_vectors(p, 1)[0], I.lambda_vector(p)
+    got = lib.triples_densities(ws, g, [0.4], [lib.vec_to_device(L)], [lib.vec_to_device(R)],
+                                lib.vec_to_device(lam), p.t2_vVoO, p.t2_vVOo, triple_range=rng)
+    ref = orc.densities(0.4, L, R, lam, p.t2_vVoO, p.t2_vVOo, *rng)
+    _check_dens((got[0][0], got[1][0], got[2][0]), ref)
+
+
+def test_density_traces_full_config1(lib, ws):
+    """tr D^{m-0} = 0 and tr D^{0-m} = 2 N_O s over every triple at the full config-1 size."""
+    p, orc, g = _dens_case(lib, None, None, cfg=1)
+    d = p.dims
+    Ls, Rs = I.left_vectors(p, 2), I.right_vectors(p, 2)
+    Dm0, D0m, s = lib.triples_densities(ws, g, [0.4, 0.5], [lib.vec_to_device(v) for v in Ls],
+                                        [lib.vec_to_device(v) for v in Rs], lib.vec_to_device(I.lambda_vector(p)),
+                                        p.t2_vVoO, p.t2_vVOo)
+    for m in range(2):
+        A, B = Dm0[m].cpu().numpy(), D0m[m].cpu().numpy()
+        assert np.all(np.isfinite(A)) and np.all(np.isfinite(B))
+        assert abs(np.trace(A)) <= 1e-11 * np.abs(A).max()
+        assert abs(np.trace(B) - 2 * d.N_O * float(s[m])) <= 1e-11 * np.abs(B).max()
