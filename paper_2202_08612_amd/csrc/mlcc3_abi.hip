@@ -468,6 +468,11 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
     gg.seg[0] = seg(g->L_OV, plain(1), plain(LOVs), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
     gemm(gg, s);
   }
+  // transposed copies so every d- and back-contraction reads unit-stride rows:
+  // GL1[k][D][b][c] = ghat_Dbkc (L3 d-term), G1t[k][b][c][D] = ghat_bDck (sigma^{aD}_{ij})
+  launch_transpose(Gb1, buf(ws, "GL1", (size_t)no * NV * d.nv2, s), no, (int)d.nv2, NV, s);
+  launch_transpose(G1, buf(ws, "G1t", (size_t)no * NV * d.nv2, s), no, NV, (int)d.nv2, s);
+  HIPRT(hipGetLastError());
   // F_kc
   double *F = buf(ws, "F", (size_t)no * nv, s);
   launch_fock_like(g->L_OV, g->t1, nc, NO, NV, no, nv, buf(ws, "fock_s", nc, s),
@@ -512,6 +517,14 @@ double *B(mlcc3_ws ws, const char *name) {
   return (double *)it->second.first;
 }
 
+// the occupied-term operands read inside the permutation kernel: x [n_v][n_v][n_o][N_O] and a
+// G block of n_o^2 n_v N_O elements (either layout)
+void reg_check_occ(const Dims &d, const double *x, const double *G) {
+  const long long nx = (long long)d.nv * d.nv * d.no * d.NO, ng = (long long)d.no * d.no * d.nv * d.NO;
+  check_range(x, plain(1), (int)nx, plain(0), 1, 0, 1, "occupied-term x");
+  check_range(G, plain(1), (int)ng, plain(0), 1, 0, 1, "occupied-term G");
+}
+
 // ------------------------------------------------------------ W and X~ builders
 // B operand of the d-contraction for batch r: element (D, (b,c)) of G_r
 struct BMap {
@@ -541,6 +554,7 @@ void w_dterm(const Dims &d, double *W, const double *xA1, BMap G1, const double 
   g.nseg = xA2 ? 2 : 1;
   g.seg[0] = seg(xA1, plain(d.NV), plain(1), 0, G1.p, G1.row, G1.col, G1.batch, d.NV);
   if (xA2) g.seg[1] = seg(xA2, plain(d.NV), plain(1), 0, G2.p, G2.row, G2.col, G2.batch, d.NV);
+  g.kind = 1;
   gemm_timed(g, 0, s);
 }
 
@@ -562,11 +576,25 @@ void w_oterm(const Dims &d, double *W, const double *xB1, BMap G1, const double 
   gemm(g, s);
 }
 
+// occupied-term operands: G stored [L][q][r][c] (G2, Uo) or [q][r][c][L] (Gb3)
+void occ_add(OccTerm &ot, const Dims &d, const double *x, const double *G, bool Lfirst) {
+  const int sg = ot.nseg++;
+  ot.NO = d.NO;
+  ot.x[sg] = x;
+  ot.G[sg] = G;
+  if (Lfirst) {
+    ot.gL[sg] = (long long)d.no * d.no * d.nv; ot.gqr[sg] = d.nv; ot.gz[sg] = 1;
+  } else {
+    ot.gL[sg] = 1; ot.gqr[sg] = (long long)d.nv * d.NO; ot.gz[sg] = d.NO;
+  }
+  reg_check_occ(d, x, G);
+}
+
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
-             double omega, Range r, const LocalTerms &lt, hipStream_t s, double *Xc = nullptr) {
+             double omega, Range r, const LocalTerms &lt, const OccTerm &ot, hipStream_t s, double *Xc = nullptr) {
   double *Xu = buf(ws, "Xu", (size_t)ws->nu * d.nv3, s);
   launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v,
-                       omega, r.tb, r.te, lt, s);
+                       omega, r.tb, r.te, lt, ot, s);
   HIPRT(hipGetLastError());
 }
 
@@ -575,8 +603,9 @@ void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
   w_dterm(d, W, B(ws, "tA"), bm_rDbc(d, B(ws, "G1")), nullptr, BMap{}, s);
-  w_oterm(d, W, g->t2_vvoO, bm_Lqrc(d, B(ws, "G2")), nullptr, BMap{}, s);
-  permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, s, Xc);
+  OccTerm ot;
+  occ_add(ot, d, g->t2_vvoO, B(ws, "G2"), true);
+  permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, ot, s, Xc);
 }
 
 // Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
@@ -769,8 +798,10 @@ void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, double omega, R
               hipStream_t s) {
   double *W = B(ws, "W");
   w_dterm(d, W, B(ws, "RA"), bm_rDbc(d, B(ws, "G1")), B(ws, "tA"), bm_rDbc(d, B(ws, "U1")), s);
-  w_oterm(d, W, B(ws, "RB"), bm_Lqrc(d, B(ws, "G2")), g->t2_vvoO, bm_Lqrc(d, B(ws, "Uo")), s);
-  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, LocalTerms{}, s, Xc);
+  OccTerm ot;
+  occ_add(ot, d, B(ws, "RB"), B(ws, "G2"), true);
+  occ_add(ot, d, g->t2_vvoO, B(ws, "Uo"), true);
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, LocalTerms{}, ot, s, Xc);
 }
 
 // L3 (transpose-transformation recipe) of a left-type vector into Xt; packs LA/LV under the given names
@@ -782,11 +813,12 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   launch_pack_vVoo(L.x2_vVoo, no, nv, NV, 0, LA, s);
   launch_pack_vvoo(L.x2_vVoo, no, nv, NV, 0, LV, s);
   double *W = B(ws, "W");
-  w_dterm(d, W, LA, bm_rbcD(d, B(ws, "Gb1")), nullptr, BMap{}, s);
-  w_oterm(d, W, L.x2_vvoO, bm_qrcL(d, B(ws, "Gb3")), nullptr, BMap{}, s);
+  w_dterm(d, W, LA, bm_rDbc(d, B(ws, "GL1")), nullptr, BMap{}, s);
+  OccTerm ot;
+  occ_add(ot, d, L.x2_vvoO, B(ws, "Gb3"), false);
   LocalTerms lt;
   lt.L1 = L.x1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
-  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, lt, s);
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, lt, ot, s);
 }
 
 // ------------------------------------------------------ density contractions
@@ -1070,26 +1102,18 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
     back_vV(ws, d, XT, bm_kbcN(d, B(ws, "gLb"), NO), NO, Xtau, s);
-    double *W = B(ws, "W");
     double *XL = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
     for (int m = 0; m < nvec; m++) {
-      const double *L1 = L[m].x1, *L2a = L[m].x2_vVoo, *L2b = L[m].x2_vvoO;
-      double *LA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
-      double *LV = buf(ws, "LV", (size_t)no * no * d.nv2, s);
-      launch_pack_vVoo(L2a, no, nv, NV, 0, LA, s);
-      launch_pack_vvoo(L2a, no, nv, NV, 0, LV, s);
-      // L3 before P (SI transpose transformation, exact-transpose index placement):
-      //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc  (+ local terms in the permute pass)
-      w_dterm(d, W, LA, bm_rbcD(d, B(ws, "Gb1")), nullptr, BMap{}, s);
-      w_oterm(d, W, L2b, bm_qrcL(d, B(ws, "Gb3")), nullptr, BMap{}, s);
-      LocalTerms lt;
-      lt.L1 = L1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
-      permute(ws, d, W, XL, g->eps_o, g->eps_v, omega[m], r, lt, s);
+      const double *L2b = L[m].x2_vvoO;
+      // L3 (SI transpose transformation, exact-transpose index placement):
+      //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc + local terms
+      build_L3(ws, g, d, L[m], omega[m], r, XL, "LA", "LV", s);
+      double *LA = B(ws, "LA");
       // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
       double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
       double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-      back_vV(ws, d, XL, BMap{B(ws, "G1"), plain(1), plain(d.nv2), (long long)NV * d.nv2}, NV, QvV, s);
+      back_vV(ws, d, XL, bm_kbcN(d, B(ws, "G1t"), NV), NV, QvV, s);
       gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
            s);
       // intermediates of the singles

@@ -21,6 +21,16 @@ struct LocalTerms {
   int NO = 0;
 };
 
+// Occupied (N_O-sized) term of W, applied inside the permutation pass:
+//   W[p][q][r][x][y][z] -= sum_seg sum_L x_seg[x][y][p][L] G_seg(L, q, r, z)
+// x in the [a][b][i][L] block layout; G(L,q,r,z) = G[L*gL + (q*n_o + r)*gqr + z*gz].
+struct OccTerm {
+  const double *x[2] = {nullptr, nullptr};
+  const double *G[2] = {nullptr, nullptr};
+  long long gL[2] = {0, 0}, gqr[2] = {0, 0}, gz[2] = {0, 0};
+  int nseg = 0, NO = 0;
+};
+
 // Raw (pre-symmetrisation) doubles blocks; delta=1 applies Delta^{-1}.
 struct DoublesRaw {
   const double *YvV = nullptr;  // [i][j][a][D]
@@ -47,9 +57,11 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
 // (and, if Xc is not NULL, the covariant X to every ordering)
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, double omega, long long tb,
-                          long long te, const LocalTerms &lt, hipStream_t s);
+                          long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
+// out[z][c][r] = in[z][r][c], z < batch
+void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s);
 // out[i] = sum_r P[r][i], r = 0..rows-1 (fixed order)
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s);
 void launch_diag_sum(const double *Q, int no, int nv, int NO, double *V, hipStream_t s);

@@ -246,19 +246,56 @@ __device__ __forceinline__ void load_cube(const double *__restrict__ src, int nv
   const int tid = threadIdx.x;
   const int y = tid >> 4, z = tid & 15;
   const long long nv2 = (long long)nv * nv;
-#pragma unroll 4
-  for (int x = 0; x < TT; x++) {
-    const int gx = X0 + x, gy = Y0 + y, gz = Z0 + z;
-    double v = 0.0;
-    if (gx < nv && gy < nv && gz < nv) v = src[gx * nv2 + (long long)gy * nv + gz];
-    lds[x * LX + y * LY + z] = v;
+  const bool yz = (Y0 + y) < nv && (Z0 + z) < nv;
+  const double *row = src + (long long)(Y0 + y) * nv + (Z0 + z);
+  double v[TT];
+#pragma unroll
+  for (int x = 0; x < TT; x++) v[x] = (yz && X0 + x < nv) ? row[(X0 + x) * nv2] : 0.0;
+#pragma unroll
+  for (int x = 0; x < TT; x++) lds[x * LX + y * LY + z] = v[x];
+}
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// cube[x][y][z] -= sum_L x(X0+x, Y0+y, p, L) G(L, q, r, Z0+z) for the sub-cube in LDS; wave w
+// takes the x-slices w, w+4, w+8, w+12, each a 16x16 (y,z) tile of v_mfma_f64_16x16x4_f64
+// (operand lane l: A row y = l%16, k = l/16; B k = l/16, column z = l%16; result row
+// l/16 + 4v, column l%16).
+__device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int no, int nv, int p, int q, int r, int X0, int Y0,
+                                              int Z0, double *cube) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ly = lane & 15, lk = lane >> 4;
+  const int NO = ot.NO;
+  const int gy = Y0 + ly, gz = Z0 + ly;
+  constexpr int KC = 8;  // k-steps whose operands are loaded before their MFMAs issue
+  for (int xs = wave; xs < TT; xs += 4) {
+    const int gx = X0 + xs;
+    if (gx >= nv) break;
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    for (int sg = 0; sg < ot.nseg; sg++) {
+      const double *xa = ot.x[sg] + ((long long)(gx * nv + gy) * no + p) * NO;
+      const double *gb = ot.G[sg] + (long long)(q * no + r) * ot.gqr[sg] + (long long)gz * ot.gz[sg];
+      for (int k0 = 0; k0 < NO; k0 += 4 * KC) {
+        double a[KC], b[KC];
+#pragma unroll
+        for (int u = 0; u < KC; u++) {
+          const int L = k0 + 4 * u + lk;
+          a[u] = (L < NO && gy < nv) ? xa[L] : 0.0;
+          b[u] = (L < NO && gz < nv) ? gb[(long long)L * ot.gL[sg]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < KC; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) cube[xs * LX + (lk + 4 * v) * LY + ly] -= acc[v];
   }
 }
 
 __global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W, double *__restrict__ Xu,
                                                    const UniqueTriple *ut, int no, int nv, const double *eps_o,
                                                    const double *eps_v, double omega, long long tb, long long te,
-                                                   LocalTerms lt) {
+                                                   LocalTerms lt, OccTerm ot) {
   __shared__ double cube[SUB];
   const UniqueTriple u = ut[blockIdx.x];
   const int nt = (nv + TT - 1) / TT;
@@ -276,6 +313,10 @@ __global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W,
       const long long base = ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
       __syncthreads();
       load_cube(W + base, nv, TT * T[s0], TT * T[s1], TT * T[s2], cube);
+      if (ot.nseg > 0) {
+        __syncthreads();
+        occ_term_cube(ot, no, nv, o[s0], o[s1], o[s2], TT * T[s0], TT * T[s1], TT * T[s2], cube);
+      }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < TT; r++) {
@@ -465,6 +506,23 @@ __global__ void k_left_Z(const double *Am, const double *Hp, int nc, int no, int
   Z[id] = acc - Hp[((long long)k * nc + J) * nv + dd];
 }
 
+// out[k][c][r] = in[k][r][c] for R x C matrices, 32x32 LDS tiles
+__global__ void k_transpose(const double *__restrict__ in, double *__restrict__ out, int R, int C) {
+  __shared__ double t[32][33];
+  const long long base = (long long)blockIdx.z * R * C;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + y, c = c0 + tx;
+    t[y][tx] = (r < R && c < C) ? in[base + (long long)r * C + c] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int c = c0 + y, r = r0 + tx;
+    if (r < R && c < C) out[base + (long long)c * R + r] = t[tx][y];
+  }
+}
+
 // ------------------------------------------------------------- host launchers
 #define L1D(kern, n, ...) \
   do { if (!g_dry && (n) > 0) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(256), 0, s, __VA_ARGS__); } while (0)
@@ -521,11 +579,11 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
 
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, double omega, long long tb,
-                          long long te, const LocalTerms &lt, hipStream_t s) {
+                          long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s) {
   if (nu <= 0 || nv <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
   hipLaunchKernelGGL(k_sym_denom, dim3(nu, nt * nt * nt), dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, omega,
-                     tb, te, lt);
+                     tb, te, lt, ot);
   hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xt, ut, no, nv, 0);
   if (Xc) hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xc, ut, no, nv, 1);
 }
@@ -535,6 +593,11 @@ void launch_small_right(const double *X, const double *T, const double *gov, con
   if (no <= 0 || nv <= 0 || g_dry) return;
   hipLaunchKernelGGL(k_small_right, dim3(no * no * nv), dim3(64), nv * sizeof(double), s, X, T, gov, F, U,
                      no, nv, part1, Yvv);
+}
+
+void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s) {
+  if (g_dry || batch <= 0 || R <= 0 || C <= 0) return;
+  hipLaunchKernelGGL(k_transpose, dim3((C + 31) / 32, (R + 31) / 32, batch), dim3(256), 0, s, in, out, R, C);
 }
 
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s) {
