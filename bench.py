@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cfg", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
+                         "the FETCH_SIZE / WRITE_SIZE counters, and exit")
     ap.add_argument("--cpu-triples", type=int, default=48, help="unique triples in the CPU-baseline sample")
     return ap.parse_args()
 
@@ -84,6 +87,16 @@ def main():
               f"(the multi-GPU layout, sharding unique occupied triples, is design only)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}), flush=True)
+        return
     from paper_2202_08612_amd import inputs as I
     from paper_2202_08612_amd import mlcc3
 
@@ -135,13 +148,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded counter-based generator; paper's workload recipe)",
-        "config": {"workload": f"config {cfg}: ground-state triples residual + right + left transform, 1 vector, "
+        "config": {"workload": "CC3 triples: ground-state residual + right + left transform, 1 vector, "
                                f"n_o={d.n_o} n_v={d.n_v} N_O={d.N_O} N_V={d.N_V} Cholesky rank {d.n_chol}, FP64",
                    "n_o": d.n_o, "n_v": d.n_v, "N_O": d.N_O, "N_V": d.N_V, "n_chol": d.n_chol,
                    "flops_per_step": flops_step, "precision": "fp64",
                    "pct_fp64_peak": round(100 * value / 1e3 / FP64_PEAK_TFLOPS, 2),
                    "pct_fp32_peak": round(100 * value / 1e3 / FP32_PEAK_TFLOPS, 2)},
-        "roofline": {"bound": "mfma", "kernel": "k_gemm_f64 (d-contraction W = sum_D x^{aD}_{ij} G_{bDck})",
+        "roofline": {"bound": "mfma", "kernel": "k_dcontract_f64 (d-contraction W = sum_D x^{aD}_{ij} G_{bDck})",
                      "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
                      "launches": st["launches"], "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 4)},

@@ -203,10 +203,6 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
   gemm_body<TM, TN, AKF, BNF>(g);
 }
 
-// the d-contraction W = sum_D x^{aD}_{ij} G_{bDck} (same body; its own symbol so that
-// profiles and the in-library timer name the same kernel)
-__global__ __launch_bounds__(256) void k_gemm_dcontract_f64(const Gemm g) { gemm_body<4, 4, true, true>(g); }
-
 // C = alpha * sum_part P[batch][part] + beta * C through the output maps (fixed order)
 __global__ void k_splitk_reduce(const Gemm g) {
   const long long MN = (long long)g.M * g.N;
@@ -227,9 +223,7 @@ __global__ void k_splitk_reduce(const Gemm g) {
 template <int TM, int TN>
 static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf) {
   dim3 grid((g.N + 32 * TN - 1) / (32 * TN), (g.M + 32 * TM - 1) / (32 * TM), g.nbatch * g.ksplit);
-  if (TM == 4 && TN == 4 && akf && bnf && g.kind == 1)
-    hipLaunchKernelGGL(k_gemm_dcontract_f64, grid, dim3(256), 0, s, g);
-  else if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true>), grid, dim3(256), 0, s, g);
+  if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true>), grid, dim3(256), 0, s, g);
   else if (akf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, false>), grid, dim3(256), 0, s, g);
   else if (bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, true>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, false>), grid, dim3(256), 0, s, g);

@@ -18,6 +18,7 @@
 
 #include "../../include/mlcc3.h"
 #include "mlcc3_internal.h"
+#include "dcontract.h"
 #include "triples_kernels.h"
 
 using namespace mlcc3;
@@ -297,18 +298,28 @@ hipEvent_t pool_event(mlcc3_ws ws) {
   return e;
 }
 
-// GEMM recorded under a timing phase (0 = d-contraction) when the workspace timer is on
-void gemm_timed(const Gemm &g, int phase, hipStream_t s) {
+// d-contraction launch with the bounds self-check of its operands, recorded under timing
+// phase 0 when the workspace timer is on
+void dcontract(const Dcontract &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return;
+  for (int i = 0; i < g.nseg; i++) {
+    const DcSeg &sg = g.seg[i];
+    if (sg.K <= 0) continue;
+    check_range(sg.A, plain(sg.lda), g.M, plain(1), sg.K, 0, 1, "A (d-contraction)");
+    check_range(sg.B, plain(sg.ldb), sg.K, plain(1), g.N, sg.bbatch, g.nbatch, "B (d-contraction)");
+  }
+  check_range(g.C, split(g.crow_d, g.crow_s1, g.crow_s0), g.M, plain(1), g.N, g.cbatch, g.nbatch,
+              "C (d-contraction)");
   mlcc3_ws ws = t_ws;
   if (!ws || !ws->timing || g_dry) {
-    gemm(g, s);
+    HIPCHK(dcontract_f64(g, s));
     return;
   }
   double fl = 0.0;
   for (int i = 0; i < g.nseg; i++) fl += 2.0 * g.M * (double)g.N * g.seg[i].K * g.nbatch;
-  mlcc3_ws_s::Mark mk{phase, fl, pool_event(ws), pool_event(ws)};
+  mlcc3_ws_s::Mark mk{0, fl, pool_event(ws), pool_event(ws)};
   HIPCHK(hipEventRecord(mk.a, s));
-  gemm(g, s);
+  HIPCHK(dcontract_f64(g, s));
   HIPCHK(hipEventRecord(mk.b, s));
   ws->marks.push_back(mk);
 }
@@ -526,54 +537,36 @@ void reg_check_occ(const Dims &d, const double *x, const double *G) {
 }
 
 // ------------------------------------------------------------ W and X~ builders
-// B operand of the d-contraction for batch r: element (D, (b,c)) of G_r
+// GEMM operand given as a strided map: element (row, col) of batch z
 struct BMap {
   const double *p;
   Idx2 row, col;
   long long batch;
 };
-// G stored [r][D][b][c]
-BMap bm_rDbc(const Dims &d, const double *G) { return {G, plain(d.nv2), plain(1), (long long)d.NV * d.nv2}; }
-// G stored [r][b][c][D]
-BMap bm_rbcD(const Dims &d, const double *G) { return {G, plain(1), plain(d.NV), (long long)d.NV * d.nv2}; }
-// occupied-term B operand (L, (q,r,c)): stored [L][q][r][c]
-BMap bm_Lqrc(const Dims &d, const double *G) { return {G, plain((long long)d.no * d.no * d.nv), plain(1), 0}; }
-// stored [q][r][c][L]
-BMap bm_qrcL(const Dims &d, const double *G) { return {G, plain(1), plain(d.NO), 0}; }
 
 // W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G_r(D,(b,c))  (+ second segment)
-void w_dterm(const Dims &d, double *W, const double *xA1, BMap G1, const double *xA2, BMap G2, hipStream_t s) {
-  Gemm g;
+void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, const double *xA2, const double *G2,
+             hipStream_t s) {
+  Dcontract g;
   g.M = d.no * d.no * d.nv;
   g.N = (int)d.nv2;
   g.nbatch = d.no;
   g.C = W;
-  g.crow = split(d.nv, (long long)d.no * d.nv3, d.nv2);
-  g.ccol = plain(1);
+  g.crow_d = d.nv;
+  g.crow_s1 = (long long)d.no * d.nv3;
+  g.crow_s0 = d.nv2;
   g.cbatch = d.nv3;
   g.nseg = xA2 ? 2 : 1;
-  g.seg[0] = seg(xA1, plain(d.NV), plain(1), 0, G1.p, G1.row, G1.col, G1.batch, d.NV);
-  if (xA2) g.seg[1] = seg(xA2, plain(d.NV), plain(1), 0, G2.p, G2.row, G2.col, G2.batch, d.NV);
-  g.kind = 1;
-  gemm_timed(g, 0, s);
-}
-
-// W[p][q][r][a][b][c] -= sum_L x^{ab}_{pL} G(L,(q,r,c))  (+ second segment); x stored [a][b][p][L]
-void w_oterm(const Dims &d, double *W, const double *xB1, BMap G1, const double *xB2, BMap G2, hipStream_t s) {
-  Gemm g;
-  g.M = (int)d.nv2;
-  g.N = d.no * d.no * d.nv;
-  g.nbatch = d.no;
-  g.C = W;
-  g.crow = plain(d.nv);
-  g.ccol = split(d.nv, d.nv3, 1);
-  g.cbatch = (long long)d.no * d.no * d.nv3;
-  g.alpha = -1.0;
-  g.beta = 1.0;
-  g.nseg = xB2 ? 2 : 1;
-  g.seg[0] = seg(xB1, plain((long long)d.no * d.NO), plain(1), d.NO, G1.p, G1.row, G1.col, G1.batch, d.NO);
-  if (xB2) g.seg[1] = seg(xB2, plain((long long)d.no * d.NO), plain(1), d.NO, G2.p, G2.row, G2.col, G2.batch, d.NO);
-  gemm(g, s);
+  const double *x[2] = {xA1, xA2}, *G[2] = {G1, G2};
+  for (int i = 0; i < g.nseg; i++) {
+    g.seg[i].A = x[i];
+    g.seg[i].lda = d.NV;
+    g.seg[i].B = G[i];
+    g.seg[i].ldb = d.nv2;
+    g.seg[i].bbatch = (long long)d.NV * d.nv2;
+    g.seg[i].K = d.NV;
+  }
+  dcontract(g, s);
 }
 
 // occupied-term operands: G stored [L][q][r][c] (G2, Uo) or [q][r][c][L] (Gb3)
@@ -602,7 +595,7 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
 void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s, double *Xc = nullptr) {
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
-  w_dterm(d, W, B(ws, "tA"), bm_rDbc(d, B(ws, "G1")), nullptr, BMap{}, s);
+  w_dterm(d, W, B(ws, "tA"), B(ws, "G1"), nullptr, nullptr, s);
   OccTerm ot;
   occ_add(ot, d, g->t2_vvoO, B(ws, "G2"), true);
   permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, ot, s, Xc);
@@ -797,7 +790,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
 void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, double omega, Range r, double *Xt, double *Xc,
               hipStream_t s) {
   double *W = B(ws, "W");
-  w_dterm(d, W, B(ws, "RA"), bm_rDbc(d, B(ws, "G1")), B(ws, "tA"), bm_rDbc(d, B(ws, "U1")), s);
+  w_dterm(d, W, B(ws, "RA"), B(ws, "G1"), B(ws, "tA"), B(ws, "U1"), s);
   OccTerm ot;
   occ_add(ot, d, B(ws, "RB"), B(ws, "G2"), true);
   occ_add(ot, d, g->t2_vvoO, B(ws, "Uo"), true);
@@ -813,7 +806,7 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   launch_pack_vVoo(L.x2_vVoo, no, nv, NV, 0, LA, s);
   launch_pack_vvoo(L.x2_vVoo, no, nv, NV, 0, LV, s);
   double *W = B(ws, "W");
-  w_dterm(d, W, LA, bm_rDbc(d, B(ws, "GL1")), nullptr, BMap{}, s);
+  w_dterm(d, W, LA, B(ws, "GL1"), nullptr, nullptr, s);
   OccTerm ot;
   occ_add(ot, d, L.x2_vvoO, B(ws, "Gb3"), false);
   LocalTerms lt;

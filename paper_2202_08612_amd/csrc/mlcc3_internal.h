@@ -40,7 +40,6 @@ struct Gemm {
   // partial tiles go to P[batch][part][M][N] and a fixed-order reduction applies alpha/beta.
   int ksplit = 1;
   double *P = nullptr;
-  int kind = 0;   // 1: the d-contraction of the triples (launched under its own kernel symbol)
 };
 
 // FP64 MFMA GEMM (v_mfma_f64_16x16x4_f64), LDS-staged, 256 threads per block.
