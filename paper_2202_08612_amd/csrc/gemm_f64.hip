@@ -13,12 +13,6 @@ namespace mlcc3 {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ long long ioff(const Idx2 &f, int x) {
-  if (f.d <= 0) return (long long)x * f.s0;
-  const int q = x / f.d;
-  return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
-}
-
 constexpr int BK = 16;
 
 template <int TM, int TN, bool AKF, bool BNF>

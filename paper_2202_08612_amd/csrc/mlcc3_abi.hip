@@ -18,7 +18,7 @@
 
 #include "../../include/mlcc3.h"
 #include "mlcc3_internal.h"
-#include "dcontract.h"
+#include "tile_gemm.h"
 #include "triples_kernels.h"
 
 using namespace mlcc3;
@@ -298,30 +298,38 @@ hipEvent_t pool_event(mlcc3_ws ws) {
   return e;
 }
 
-// d-contraction launch with the bounds self-check of its operands, recorded under timing
-// phase 0 when the workspace timer is on
-void dcontract(const Dcontract &g, hipStream_t s) {
+// large-tile GEMM launch with the bounds self-check of its operands; the d-contraction is
+// recorded under timing phase 0 when the workspace timer is on
+void tgemm(const TileGemm &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return;
   for (int i = 0; i < g.nseg; i++) {
-    const DcSeg &sg = g.seg[i];
+    const TgSeg &sg = g.seg[i];
     if (sg.K <= 0) continue;
-    check_range(sg.A, plain(sg.lda), g.M, plain(1), sg.K, 0, 1, "A (d-contraction)");
-    check_range(sg.B, plain(sg.ldb), sg.K, plain(1), g.N, sg.bbatch, g.nbatch, "B (d-contraction)");
+    if (g.ak) check_range(sg.A, sg.amap, g.M, plain(1), sg.K, sg.abatch, g.nbatch, "A (tile GEMM)");
+    else check_range(sg.A, sg.amap, sg.K, plain(1), g.M, sg.abatch, g.nbatch, "A (tile GEMM)");
+    check_range(sg.B, plain(sg.ldb), sg.K, plain(1), g.N, sg.bbatch, g.nbatch, "B (tile GEMM)");
   }
-  check_range(g.C, split(g.crow_d, g.crow_s1, g.crow_s0), g.M, plain(1), g.N, g.cbatch, g.nbatch,
-              "C (d-contraction)");
+  check_range(g.C, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (tile GEMM)");
   mlcc3_ws ws = t_ws;
-  if (!ws || !ws->timing || g_dry) {
-    HIPCHK(dcontract_f64(g, s));
+  if (!g.dcontract || !ws || !ws->timing || g_dry) {
+    HIPCHK(tile_gemm_f64(g, s));
     return;
   }
   double fl = 0.0;
   for (int i = 0; i < g.nseg; i++) fl += 2.0 * g.M * (double)g.N * g.seg[i].K * g.nbatch;
   mlcc3_ws_s::Mark mk{0, fl, pool_event(ws), pool_event(ws)};
   HIPCHK(hipEventRecord(mk.a, s));
-  HIPCHK(dcontract_f64(g, s));
+  HIPCHK(tile_gemm_f64(g, s));
   HIPCHK(hipEventRecord(mk.b, s));
   ws->marks.push_back(mk);
+}
+
+TgSeg tseg(const double *A, Idx2 amap, long long abatch, const double *B, long long ldb, long long bbatch, int K) {
+  TgSeg sg;
+  sg.A = A; sg.amap = amap; sg.abatch = abatch;
+  sg.B = B; sg.ldb = ldb; sg.bbatch = bbatch;
+  sg.K = K;
+  return sg;
 }
 
 void reg_ground(const mlcc3_ground *g) {
@@ -547,26 +555,18 @@ struct BMap {
 // W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G_r(D,(b,c))  (+ second segment)
 void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, const double *xA2, const double *G2,
              hipStream_t s) {
-  Dcontract g;
+  TileGemm g;
   g.M = d.no * d.no * d.nv;
   g.N = (int)d.nv2;
   g.nbatch = d.no;
   g.C = W;
-  g.crow_d = d.nv;
-  g.crow_s1 = (long long)d.no * d.nv3;
-  g.crow_s0 = d.nv2;
+  g.cmap = split(d.nv, (long long)d.no * d.nv3, d.nv2);
   g.cbatch = d.nv3;
   g.nseg = xA2 ? 2 : 1;
+  g.dcontract = 1;
   const double *x[2] = {xA1, xA2}, *G[2] = {G1, G2};
-  for (int i = 0; i < g.nseg; i++) {
-    g.seg[i].A = x[i];
-    g.seg[i].lda = d.NV;
-    g.seg[i].B = G[i];
-    g.seg[i].ldb = d.nv2;
-    g.seg[i].bbatch = (long long)d.NV * d.nv2;
-    g.seg[i].K = d.NV;
-  }
-  dcontract(g, s);
+  for (int i = 0; i < g.nseg; i++) g.seg[i] = tseg(x[i], plain(d.NV), 0, G[i], d.nv2, (long long)d.NV * d.nv2, d.NV);
+  tgemm(g, s);
 }
 
 // occupied-term operands: G stored [L][q][r][c] (G2, Uo) or [q][r][c][L] (Gb3)
@@ -603,26 +603,38 @@ void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
 
 // Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
 // writes one partial product per k into P[k][(i,j,a)][n] and a fixed-order sum reduces them.
-void back_vV(mlcc3_ws ws, const Dims &d, const double *X, BMap G, int N, double *Y, hipStream_t s) {
+void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N, double *Y, hipStream_t s) {
   const long long MN = (long long)d.no * d.no * d.nv * N;
   double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
-  Gemm g;
-  g.M = d.no * d.no * d.nv;
-  g.N = N;
-  g.nbatch = d.no;
-  g.C = P;
-  g.crow = plain(N);
-  g.ccol = plain(1);
-  g.cbatch = MN;
-  g.nseg = 1;
-  g.seg[0] = seg(X, split(d.nv, (long long)d.no * d.nv3, d.nv2), plain(1), d.nv3, G.p, G.row, G.col, G.batch,
-                 (int)d.nv2);
-  gemm(g, s);
+  const Idx2 xrow = split(d.nv, (long long)d.no * d.nv3, d.nv2);
+  if (N >= 96) {
+    TileGemm g;
+    g.M = d.no * d.no * d.nv;
+    g.N = N;
+    g.nbatch = d.no;
+    g.C = P;
+    g.cmap = plain(N);
+    g.cbatch = MN;
+    g.nseg = 1;
+    g.seg[0] = tseg(X, xrow, d.nv3, G, N, d.nv2 * N, (int)d.nv2);
+    tgemm(g, s);
+  } else {
+    // narrow N (N_O): the generic GEMM picks 32-wide tiles
+    Gemm g;
+    g.M = d.no * d.no * d.nv;
+    g.N = N;
+    g.nbatch = d.no;
+    g.C = P;
+    g.crow = plain(N);
+    g.ccol = plain(1);
+    g.cbatch = MN;
+    g.nseg = 1;
+    g.seg[0] = seg(X, xrow, plain(1), d.nv3, G, plain(N), plain(1), d.nv2 * N, (int)d.nv2);
+    gemm(g, s);
+  }
   launch_sum_rows(P, d.no, MN, Y, s);
   HIPRT(hipGetLastError());
 }
-// G stored [k][b][c][n] with n-extent N
-BMap bm_kbcN(const Dims &d, const double *G, int N) { return {G, plain(N), plain(1), d.nv2 * N}; }
 
 // Y[i][(a,b)][L] = alpha * sum_{(j,k,c)} X~[i][j][k][a][b][c] G((j,k,c),L)   (+ second segment)
 Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2, double *Y, double alpha) {
@@ -993,7 +1005,7 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
     double *XT = B(ws, "XT");
     double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
     double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
-    back_vV(ws, d, XT, bm_kbcN(d, B(ws, "Gb1"), d.NV), d.NV, YvV, s);
+    back_vV(ws, d, XT, B(ws, "Gb1"), d.NV, YvV, s);
     gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
     finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
   });
@@ -1032,7 +1044,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     tau_path(ws, g, d, r, s);
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    back_vV(ws, d, XT, bm_kbcN(d, B(ws, "gLb"), NO), NO, Xtau, s);
+    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, s);
     double *W = B(ws, "W");
     double *XR = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
     for (int m = 0; m < nvec; m++) {
@@ -1042,7 +1054,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
       // back-contractions
       double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
       double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-      back_vV(ws, d, XR, bm_kbcN(d, B(ws, "Gb1"), NV), NV, YvV, s);
+      back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, s);
       {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
         Gemm gg;
         gg.M = no * no * nv;
@@ -1094,7 +1106,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     tau_path(ws, g, d, r, s);
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    back_vV(ws, d, XT, bm_kbcN(d, B(ws, "gLb"), NO), NO, Xtau, s);
+    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, s);
     double *XL = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
     for (int m = 0; m < nvec; m++) {
@@ -1106,20 +1118,24 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
       // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
       double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
       double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-      back_vV(ws, d, XL, bm_kbcN(d, B(ws, "G1t"), NV), NV, QvV, s);
+      back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, s);
       gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
            s);
       // intermediates of the singles
       // Bq[r][(b,c)][E] = sum_{(p,q,a)} L~[p][q][r][a][b][c] t^{aE}_{pq}
       double *Bq = buf(ws, "Bq", (size_t)no * d.nv2 * NV, s);
       {
-        Gemm gg = gemm_plain((int)d.nv2, NV, Bq, plain(NV), plain(1), 1.0, 0.0);
+        TileGemm gg;
+        gg.M = (int)d.nv2;
+        gg.N = NV;
         gg.nbatch = no;
+        gg.ak = 0;
+        gg.C = Bq;
+        gg.cmap = plain(NV);
         gg.cbatch = d.nv2 * NV;
         gg.nseg = 1;
-        gg.seg[0] = seg(XL, plain(1), split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), plain(NV), plain(1),
-                        0, no * no * nv);
-        gemm(gg, s);
+        gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), NV, 0, no * no * nv);
+        tgemm(gg, s);
       }
       // Aq[(q,r,c)][M] = sum L~[p][q][r][a][b][c] t^{ab}_{pM};  Qtau likewise with tau~ and L^{ab}_{pL}
       double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);

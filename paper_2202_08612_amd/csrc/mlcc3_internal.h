@@ -14,6 +14,11 @@ struct Idx2 {
 };
 
 inline Idx2 plain(long long s0) { Idx2 f; f.s0 = s0; f.d = 0; return f; }
+__host__ __device__ __forceinline__ long long ioff(const Idx2 &f, int x) {
+  if (f.d <= 0) return (long long)x * f.s0;
+  const int q = x / f.d;
+  return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
+}
 inline Idx2 split(int d, long long s1, long long s0) { Idx2 f; f.d = d; f.s1 = s1; f.s0 = s0; return f; }
 
 // A(m,k) = p[row(m) + col(k) + z*batch]; B(k,n) = p[row(k) + col(n) + z*batch]
