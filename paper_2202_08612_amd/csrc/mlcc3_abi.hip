@@ -448,6 +448,10 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
     gg.seg[0] = seg(LhOO, plain(1), plain((long long)NO * NO), 0, g->L_OV, plain(LOVs), split(nv, NV, 1), 0, nc);
     gemm(gg, s);
   }
+  // Gb3L[L][j][k][c] (the occupied term of L3 reads G with L outermost); t2xT[i][a][L][b] = t^{ab}_{iL}
+  launch_transpose(Gb3, buf(ws, "Gb3L", (size_t)no * no * nv * NO, s), 1, no * no * nv, NO, s);
+  launch_occ_xT(g->t2_vvoO, no, nv, NO, buf(ws, "t2xT", (size_t)no * nv * NO * nv, s), s);
+  HIPRT(hipGetLastError());
   // gov[j][k][b][c] = g_jbkc (bare)
   double *gov = buf(ws, "gov", (size_t)no * no * d.nv2, s);
   {
@@ -569,18 +573,22 @@ void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, cons
   tgemm(g, s);
 }
 
-// occupied-term operands: G stored [L][q][r][c] (G2, Uo) or [q][r][c][L] (Gb3)
-void occ_add(OccTerm &ot, const Dims &d, const double *x, const double *G, bool Lfirst) {
+// occupied-term operands: xT[p][a][L][b] (launch_occ_xT of an [a][b][p][L] block) and G stored
+// [L][q][r][c] (G2, Uo, Gb3L)
+void occ_add(OccTerm &ot, const Dims &d, const double *xT, const double *G) {
   const int sg = ot.nseg++;
   ot.NO = d.NO;
-  ot.x[sg] = x;
+  ot.x[sg] = xT;
   ot.G[sg] = G;
-  if (Lfirst) {
-    ot.gL[sg] = (long long)d.no * d.no * d.nv; ot.gqr[sg] = d.nv; ot.gz[sg] = 1;
-  } else {
-    ot.gL[sg] = 1; ot.gqr[sg] = (long long)d.nv * d.NO; ot.gz[sg] = d.NO;
-  }
-  reg_check_occ(d, x, G);
+  reg_check_occ(d, xT, G);
+}
+
+// transposed occupied-term copy of an [a][b][p][L] block into workspace buffer `name`
+const double *occ_xT(mlcc3_ws ws, const Dims &d, const double *x, const char *name, hipStream_t s) {
+  double *xT = buf(ws, name, (size_t)d.no * d.nv * d.NO * d.nv, s);
+  launch_occ_xT(x, d.no, d.nv, d.NO, xT, s);
+  HIPRT(hipGetLastError());
+  return xT;
 }
 
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
@@ -597,7 +605,7 @@ void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
   w_dterm(d, W, B(ws, "tA"), B(ws, "G1"), nullptr, nullptr, s);
   OccTerm ot;
-  occ_add(ot, d, g->t2_vvoO, B(ws, "G2"), true);
+  occ_add(ot, d, B(ws, "t2xT"), B(ws, "G2"));
   permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, ot, s, Xc);
 }
 
@@ -804,8 +812,8 @@ void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, double omega, R
   double *W = B(ws, "W");
   w_dterm(d, W, B(ws, "RA"), B(ws, "G1"), B(ws, "tA"), B(ws, "U1"), s);
   OccTerm ot;
-  occ_add(ot, d, B(ws, "RB"), B(ws, "G2"), true);
-  occ_add(ot, d, g->t2_vvoO, B(ws, "Uo"), true);
+  occ_add(ot, d, occ_xT(ws, d, B(ws, "RB"), "RBxT", s), B(ws, "G2"));
+  occ_add(ot, d, B(ws, "t2xT"), B(ws, "Uo"));
   permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, LocalTerms{}, ot, s, Xc);
 }
 
@@ -820,7 +828,7 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   double *W = B(ws, "W");
   w_dterm(d, W, LA, B(ws, "GL1"), nullptr, nullptr, s);
   OccTerm ot;
-  occ_add(ot, d, L.x2_vvoO, B(ws, "Gb3"), false);
+  occ_add(ot, d, occ_xT(ws, d, L.x2_vvoO, "LBxT", s), B(ws, "Gb3L"));
   LocalTerms lt;
   lt.L1 = L.x1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
   permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, lt, ot, s);

@@ -22,12 +22,12 @@ struct LocalTerms {
 };
 
 // Occupied (N_O-sized) term of W, applied inside the permutation pass:
-//   W[p][q][r][x][y][z] -= sum_seg sum_L x_seg[x][y][p][L] G_seg(L, q, r, z)
-// x in the [a][b][i][L] block layout; G(L,q,r,z) = G[L*gL + (q*n_o + r)*gqr + z*gz].
+//   W[p][q][r][x][y][z] -= sum_seg sum_L x_seg(x, y, p, L) G_seg[L][q][r][z]
+// with x stored transposed as xT[p][x][L][y] (launch_occ_xT) so that the MFMA operand
+// loads run along y, and G stored [L][q][r][z].
 struct OccTerm {
   const double *x[2] = {nullptr, nullptr};
   const double *G[2] = {nullptr, nullptr};
-  long long gL[2] = {0, 0}, gqr[2] = {0, 0}, gz[2] = {0, 0};
   int nseg = 0, NO = 0;
 };
 
@@ -60,6 +60,8 @@ void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, c
                           long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
+// xT[p][a][L][b] = x[a][b][p][L]  (x: [n_v][n_v][n_o][N_O])
+void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s);
 // out[z][c][r] = in[z][r][c], z < batch
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s);
 // out[i] = sum_r P[r][i], r = 0..rows-1 (fixed order)

@@ -237,27 +237,50 @@ __device__ __constant__ int c_perm[6][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {0,
 __device__ __constant__ double c_coef[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
 
 constexpr int TT = 16;              // sub-cube edge
+
+// Work item of workgroup blockIdx.x in the passes over (unique triple, sub-cube): workgroups
+// are dealt round-robin over the 8 XCDs, so XCD x is given the contiguous range
+// [x*floor(n/8) + min(x, n%8), ...) of the order (triple, T0, T1, T2) with T2 (the unit-stride
+// index c) fastest.  The sub-cubes that share cache lines of a row (rows of n_v doubles are
+// not 128-byte aligned in general) then run on the same XCD at about the same time, and the
+// partial lines they write are merged in its L2.
+__device__ __forceinline__ void pass_item(int nu, int nt, int &tri, int (&T)[3]) {
+  const int nt3 = nt * nt * nt;
+  const long long n = (long long)nu * nt3, bid = blockIdx.x;
+  const long long x = bid % 8, slot = bid / 8, q = n / 8, rem = n % 8;
+  const long long L = x * q + (x < rem ? x : rem) + slot;
+  tri = (int)(L / nt3);
+  const int t = (int)(L - (long long)tri * nt3);
+  T[0] = t / (nt * nt);
+  T[1] = (t / nt) % nt;
+  T[2] = t % nt;
+}
 constexpr int LY = TT + 1, LX = (TT + 1) * (TT + 1);  // odd strides (in doubles) against bank conflicts
 constexpr int SUB = TT * LX;
 
-// load the sub-cube of block src starting at (X0,Y0,Z0) into lds[x*LX + y*LY + z]
-__device__ __forceinline__ void load_cube(const double *__restrict__ src, int nv, int X0, int Y0, int Z0,
-                                          double *lds) {
+// sub-cube of block src starting at (X0,Y0,Z0): thread (y,z) = (tid/16, tid%16) loads the
+// 16 x-values of its (y,z) line into registers; cube_store puts them at lds[x*LX + y*LY + z]
+__device__ __forceinline__ void cube_load(const double *__restrict__ src, int nv, int X0, int Y0, int Z0,
+                                          double (&v)[TT]) {
   const int tid = threadIdx.x;
   const int y = tid >> 4, z = tid & 15;
   const long long nv2 = (long long)nv * nv;
   const bool yz = (Y0 + y) < nv && (Z0 + z) < nv;
   const double *row = src + (long long)(Y0 + y) * nv + (Z0 + z);
-  double v[TT];
 #pragma unroll
   for (int x = 0; x < TT; x++) v[x] = (yz && X0 + x < nv) ? row[(X0 + x) * nv2] : 0.0;
+}
+
+__device__ __forceinline__ void cube_store(const double (&v)[TT], double *lds) {
+  const int tid = threadIdx.x;
+  const int y = tid >> 4, z = tid & 15;
 #pragma unroll
   for (int x = 0; x < TT; x++) lds[x * LX + y * LY + z] = v[x];
 }
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-// cube[x][y][z] -= sum_L x(X0+x, Y0+y, p, L) G(L, q, r, Z0+z) for the sub-cube in LDS; wave w
+// cube[x][y][z] -= sum_L xT[p][X0+x][L][Y0+y] G[L][q][r][Z0+z] for the sub-cube in LDS; wave w
 // takes the x-slices w, w+4, w+8, w+12, each a 16x16 (y,z) tile of v_mfma_f64_16x16x4_f64
 // (operand lane l: A row y = l%16, k = l/16; B k = l/16, column z = l%16; result row
 // l/16 + 4v, column l%16).
@@ -267,41 +290,59 @@ __device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int no, int nv,
   const int ly = lane & 15, lk = lane >> 4;
   const int NO = ot.NO;
   const int gy = Y0 + ly, gz = Z0 + ly;
-  constexpr int KC = 8;  // k-steps whose operands are loaded before their MFMAs issue
-  for (int xs = wave; xs < TT; xs += 4) {
-    const int gx = X0 + xs;
-    if (gx >= nv) break;
-    d4v acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int KC = 4;  // k-steps per chunk (16 values of L)
+  constexpr int XS = TT / 4;  // x-slices per wave: w, w+4, w+8, w+12, taken two at a time
+  const long long qr = (long long)no * no * nv;  // L stride of G
+#pragma unroll
+  for (int h = 0; h < XS; h += 2) {
+    d4v acc[2];
+    acc[0] = d4v{0.0, 0.0, 0.0, 0.0};
+    acc[1] = acc[0];
     for (int sg = 0; sg < ot.nseg; sg++) {
-      const double *xa = ot.x[sg] + ((long long)(gx * nv + gy) * no + p) * NO;
-      const double *gb = ot.G[sg] + (long long)(q * no + r) * ot.gqr[sg] + (long long)gz * ot.gz[sg];
+      const double *gb = ot.G[sg] + (long long)(q * no + r) * nv + gz;
       for (int k0 = 0; k0 < NO; k0 += 4 * KC) {
-        double a[KC], b[KC];
+        double a[2][KC], b[KC];
 #pragma unroll
         for (int u = 0; u < KC; u++) {
           const int L = k0 + 4 * u + lk;
-          a[u] = (L < NO && gy < nv) ? xa[L] : 0.0;
-          b[u] = (L < NO && gz < nv) ? gb[(long long)L * ot.gL[sg]] : 0.0;
+          b[u] = (L < NO && gz < nv) ? gb[L * qr] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < KC; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+        for (int e = 0; e < 2; e++) {
+          const int gx = X0 + wave + 4 * (h + e);
+          const double *xa = ot.x[sg] + ((long long)p * nv + gx) * NO * nv + gy;
+#pragma unroll
+          for (int u = 0; u < KC; u++) {
+            const int L = k0 + 4 * u + lk;
+            a[e][u] = (L < NO && gy < nv && gx < nv) ? xa[L * nv] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < KC; u++)
+#pragma unroll
+          for (int e = 0; e < 2; e++) acc[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e][u], b[u], acc[e], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; v++) cube[xs * LX + (lk + 4 * v) * LY + ly] -= acc[v];
+    for (int e = 0; e < 2; e++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) cube[(wave + 4 * (h + e)) * LX + (lk + 4 * v) * LY + ly] -= acc[e][v];
   }
 }
 
-__global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W, double *__restrict__ Xu,
-                                                   const UniqueTriple *ut, int no, int nv, const double *eps_o,
-                                                   const double *eps_v, double omega, long long tb, long long te,
-                                                   LocalTerms lt, OccTerm ot) {
+__device__ __forceinline__ int sel3(int a0, int a1, int a2, int i) { return i == 0 ? a0 : (i == 1 ? a1 : a2); }
+
+__global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__ W, double *__restrict__ Xu,
+                                                      const UniqueTriple *ut, int no, int nv, const double *eps_o,
+                                                      const double *eps_v, double omega, long long tb, long long te,
+                                                      LocalTerms lt, OccTerm ot, int nu) {
   __shared__ double cube[SUB];
-  const UniqueTriple u = ut[blockIdx.x];
   const int nt = (nv + TT - 1) / TT;
-  const int T[3] = {(int)blockIdx.y / (nt * nt), ((int)blockIdx.y / nt) % nt, (int)blockIdx.y % nt};
+  int tri, T[3];
+  pass_item(nu, nt, tri, T);
+  const int T0 = T[0], T1 = T[1], T2 = T[2];
+  const UniqueTriple u = ut[tri];
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
-  const int o[3] = {u.i, u.j, u.k};
   const bool active = !(u.i == u.j && u.j == u.k) && u.canon >= tb && u.canon < te;
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
   double acc[TT];
@@ -310,26 +351,33 @@ __global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W,
   if (active) {
     for (int s = 0; s < 6; s++) {
       const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
-      const long long base = ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
-      __syncthreads();
-      load_cube(W + base, nv, TT * T[s0], TT * T[s1], TT * T[s2], cube);
+      const int p = sel3(u.i, u.j, u.k, s0), q = sel3(u.i, u.j, u.k, s1), rr = sel3(u.i, u.j, u.k, s2);
+      const int X0 = TT * sel3(T0, T1, T2, s0), Y0 = TT * sel3(T0, T1, T2, s1), Z0 = TT * sel3(T0, T1, T2, s2);
+      {
+        double v[TT];
+        cube_load(W + ((long long)(p * no + q) * no + rr) * nv3, nv, X0, Y0, Z0, v);
+        __syncthreads();
+        cube_store(v, cube);
+      }
       if (ot.nseg > 0) {
         __syncthreads();
-        occ_term_cube(ot, no, nv, o[s0], o[s1], o[s2], TT * T[s0], TT * T[s1], TT * T[s2], cube);
+        occ_term_cube(ot, no, nv, p, q, rr, X0, Y0, Z0, cube);
       }
       __syncthreads();
+      // output local index v = (r, lb, lc) reads the source cube at (v_{s0}, v_{s1}, v_{s2})
+      const int w0 = s0 == 0 ? LX : (s1 == 0 ? LY : 1);
+      const int w1 = s0 == 1 ? LX : (s1 == 1 ? LY : 1);
+      const int w2 = s0 == 2 ? LX : (s1 == 2 ? LY : 1);
+      const double *cb = cube + lb * w1 + lc * w2;
 #pragma unroll
-      for (int r = 0; r < TT; r++) {
-        const int v[3] = {r, lb, lc};
-        acc[r] += cube[v[s0] * LX + v[s1] * LY + v[s2]];
-      }
+      for (int r = 0; r < TT; r++) acc[r] += cb[r * w0];
       if (lt.L1) {  // local terms of the left triples: L^x_p g_qyrz + L^{xy}_{pq} F_rz
-        const int p = o[s0], q = o[s1], rr = o[s2];
-#pragma unroll 4
+        const int gb = TT * T1 + lb, gc = TT * T2 + lc;
+#pragma unroll
         for (int r = 0; r < TT; r++) {
-          const int g[3] = {TT * T[0] + r, TT * T[1] + lb, TT * T[2] + lc};
-          if (g[0] >= nv || g[1] >= nv || g[2] >= nv) continue;
-          const int x = g[s0], y = g[s1], z = g[s2];
+          const int ga = TT * T0 + r;
+          if (ga >= nv || gb >= nv || gc >= nv) continue;
+          const int x = sel3(ga, gb, gc, s0), y = sel3(ga, gb, gc, s1), z = sel3(ga, gb, gc, s2);
           acc[r] += lt.L1[(long long)x * lt.NO + p] * lt.gov[(((long long)q * no + rr) * nv + y) * nv + z] +
                     lt.LV[(((long long)p * no + q) * nv + x) * nv + y] * lt.F[(long long)rr * nv + z];
         }
@@ -337,12 +385,12 @@ __global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W,
     }
   }
   const double eocc = eps_o[u.i] + eps_o[u.j] + eps_o[u.k];
-  double *dst = Xu + (long long)blockIdx.x * nv3;
-  const int gb = TT * T[1] + lb, gc = TT * T[2] + lc;
+  double *dst = Xu + (long long)tri * nv3;
+  const int gb = TT * T1 + lb, gc = TT * T2 + lc;
   if (gb >= nv || gc >= nv) return;
 #pragma unroll
   for (int r = 0; r < TT; r++) {
-    const int ga = TT * T[0] + r;
+    const int ga = TT * T0 + r;
     if (ga >= nv) break;
     const double den = eps_v[ga] + eps_v[gb] + eps_v[gc] - eocc - omega;
     dst[ga * nv2 + (long long)gb * nv + gc] = active ? -acc[r] / den : 0.0;
@@ -350,23 +398,31 @@ __global__ __launch_bounds__(256) void k_sym_denom(const double *__restrict__ W,
 }
 
 __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, double *__restrict__ Xt,
-                                                        const UniqueTriple *ut, int no, int nv, int covariant) {
+                                                        const UniqueTriple *ut, int no, int nv, int covariant, int nu) {
   __shared__ double cube[SUB];
-  const UniqueTriple u = ut[blockIdx.x];
   const int nt = (nv + TT - 1) / TT;
-  const int T[3] = {(int)blockIdx.y / (nt * nt), ((int)blockIdx.y / nt) % nt, (int)blockIdx.y % nt};
+  int tri, T[3];
+  pass_item(nu, nt, tri, T);
+  const UniqueTriple u = ut[tri];
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
-  const double *src = Xu + (long long)blockIdx.x * nv3;
+  const double *src = Xu + (long long)tri * nv3;
   double acc[TT];
 #pragma unroll
   for (int r = 0; r < TT; r++) acc[r] = 0.0;
   const int nterm = covariant ? 1 : 6;  // covariant mode copies X itself to every ordering
+  // the sub-cube of term t+1 is loaded into registers while term t is gathered
+  double nxt[TT];
+  cube_load(src, nv, TT * T[0], TT * T[1], TT * T[2], nxt);
   for (int t = 0; t < nterm; t++) {
     const int t0 = c_perm[t][0], t1 = c_perm[t][1], t2 = c_perm[t][2];
     __syncthreads();
-    load_cube(src, nv, TT * T[t0], TT * T[t1], TT * T[t2], cube);
+    cube_store(nxt, cube);
+    if (t + 1 < nterm) {
+      const int u0 = c_perm[t + 1][0], u1 = c_perm[t + 1][1], u2 = c_perm[t + 1][2];
+      cube_load(src, nv, TT * T[u0], TT * T[u1], TT * T[u2], nxt);
+    }
     __syncthreads();
     const double cf = covariant ? 1.0 : c_coef[t];
 #pragma unroll
@@ -394,6 +450,19 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
       dst[(W0 + w[0]) * nv2 + (long long)(W1 + w[1]) * nv + (W2 + w[2])] = cube[v[0] * LX + v[1] * LY + v[2]];
     }
   }
+}
+
+// xT[p][a][L][b] = x[a][b][p][L]
+__global__ void k_occ_xT(const double *__restrict__ x, int no, int nv, int NO, double *__restrict__ xT) {
+  const long long n = (long long)no * nv * NO * nv;
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const int b = (int)(id % nv);
+  long long t = id / nv;
+  const int L = (int)(t % NO);
+  t /= NO;
+  const int a = (int)(t % nv), p = (int)(t / nv);
+  xT[id] = x[(((long long)a * nv + b) * no + p) * NO + L];
 }
 
 // -------------------------------------------------------------- wave helpers
@@ -582,10 +651,10 @@ void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, c
                           long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s) {
   if (nu <= 0 || nv <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
-  hipLaunchKernelGGL(k_sym_denom, dim3(nu, nt * nt * nt), dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, omega,
-                     tb, te, lt, ot);
-  hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xt, ut, no, nv, 0);
-  if (Xc) hipLaunchKernelGGL(k_contra_scatter, dim3(nu, nt * nt * nt), dim3(256), 0, s, Xu, Xc, ut, no, nv, 1);
+  const dim3 grid((unsigned)((long long)nu * nt * nt * nt));
+  hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, omega, tb, te, lt, ot, nu);
+  hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xt, ut, no, nv, 0, nu);
+  if (Xc) hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu);
 }
 
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
@@ -593,6 +662,10 @@ void launch_small_right(const double *X, const double *T, const double *gov, con
   if (no <= 0 || nv <= 0 || g_dry) return;
   hipLaunchKernelGGL(k_small_right, dim3(no * no * nv), dim3(64), nv * sizeof(double), s, X, T, gov, F, U,
                      no, nv, part1, Yvv);
+}
+
+void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s) {
+  L1D(k_occ_xT, (long long)no * nv * NO * nv, x, no, nv, NO, xT);
 }
 
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s) {
