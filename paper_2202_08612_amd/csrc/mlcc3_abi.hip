@@ -274,7 +274,7 @@ void gemm(const Gemm &g, hipStream_t s) {
   for (int i = 0; i < g.nseg; i++) ktot += g.seg[i].K;
   const long long tiles = gemm_tiles(g);
   Gemm h = g;
-  if (tiles < 256 && ktot >= 2048 && t_ws) {
+  if (tiles < 1024 && ktot >= 2048 && t_ws) {
     // too few workgroups for a long K: split K (about 2048 workgroups, >= 1024 K each) and
     // reduce the partial tiles in a fixed order
     long long ks = std::min<long long>((2048 + tiles - 1) / tiles, ktot / 1024);
@@ -311,6 +311,47 @@ void tgemm(const TileGemm &g, hipStream_t s) {
   }
   check_range(g.C, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (tile GEMM)");
   mlcc3_ws ws = t_ws;
+  if (!g.dcontract) {
+    // split K when the 128x128 tiles fill the 512 workgroup slots (two per CU) in few, ragged
+    // rounds: the part count with the best filled fraction of the last round (>= 256 K each)
+    const long long tiles = tile_gemm_blocks(g);
+    int kmin = g.seg[0].K;
+    for (int i = 1; i < g.nseg; i++) kmin = std::min(kmin, g.seg[i].K);
+    int ks = 1;
+    double best = 0.0;
+    for (int k = 1; k <= 8 && tiles < 2048; k++) {
+      if (k > 1 && kmin / k < 256) break;
+      const double w = tiles * k / 512.0, eff = w / std::ceil(w);
+      if (eff > best + 0.05) {
+        best = eff;
+        ks = k;
+      }
+    }
+    if (ks > 1 && ws) {
+      TileGemm h = g;
+      h.ksplit = ks;
+      h.C = buf(ws, "tile_splitk", (size_t)ks * g.nbatch * (long long)g.M * g.N, s);
+      h.cmap = plain(g.N);
+      h.cbatch = (long long)g.M * g.N;
+      h.alpha = 1.0;
+      h.beta = 0.0;
+      HIPCHK(tile_gemm_f64(h, s));
+      Gemm r;
+      r.M = g.M;
+      r.N = g.N;
+      r.nbatch = g.nbatch;
+      r.ksplit = ks;
+      r.P = h.C;
+      r.C = g.C;
+      r.crow = g.cmap;
+      r.ccol = plain(1);
+      r.cbatch = g.cbatch;
+      r.alpha = g.alpha;
+      r.beta = g.beta;
+      HIPCHK(gemm_reduce_parts(r, s));
+      return;
+    }
+  }
   if (!g.dcontract || !ws || !ws->timing || g_dry) {
     HIPCHK(tile_gemm_f64(g, s));
     return;

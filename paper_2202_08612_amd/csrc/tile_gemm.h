@@ -26,6 +26,9 @@ struct TileGemm {
   long long cbatch = 0;
   double alpha = 1.0, beta = 0.0;
   int dcontract = 0;   // the d-contraction of the triples: launched under its own kernel symbol
+  // split-K: batch index zz of the launch = z * ksplit + part; part takes the part-th slice of
+  // every segment's K (multiples of 16).  The host points C at a partial buffer for it.
+  int ksplit = 1;
 };
 
 hipError_t tile_gemm_f64(const TileGemm &g, hipStream_t s);

@@ -47,8 +47,9 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
-  const int z = blockIdx.x / (mt * nt);
-  int t = blockIdx.x - z * (mt * nt);
+  const int zz = blockIdx.x / (mt * nt);
+  const int z = zz / g.ksplit, part = zz - z * g.ksplit;
+  int t = blockIdx.x - zz * (mt * nt);
   const int grp = t / (GM * nt), gbase = grp * GM;
   const int gsz = min(GM, mt - gbase);
   t -= grp * GM * nt;
@@ -69,10 +70,14 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
 
   for (int s = 0; s < g.nseg; s++) {
     const TgSeg &sg = g.seg[s];
-    const int K = sg.K;
+    // K slice [kb, K) of this part
+    const int chunk = ((sg.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+    const int kb = part * chunk;
+    const int K = min(sg.K, kb + chunk);
+    if (kb >= K) continue;  // uniform over the workgroup
     const double *Ap = sg.A + (long long)z * sg.abatch;
     const double *Bp = sg.B + (long long)z * sg.bbatch;
-    const int nkt = (K + BK - 1) / BK;
+    const int nkt = (K - kb + BK - 1) / BK;
     long long aoff[4];
     if (AK) {
 #pragma unroll
@@ -84,7 +89,7 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
 
     auto load = [&](int kt) {
       if (AK) {
-        const int k = kt * BK + 2 * akp;
+        const int k = kb + kt * BK + 2 * akp;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           d2 v = d2{0.0, 0.0};
@@ -103,7 +108,7 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
         const int m = m0 + 2 * np;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          const int k = kt * BK + kr + 4 * u;
+          const int k = kb + kt * BK + kr + 4 * u;
           d2 v = d2{0.0, 0.0};
           if (k < K) {
             const double *p = Ap + moff(sg.amap, k) + m;
@@ -120,7 +125,7 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
       const int n = n0 + 2 * np;
 #pragma unroll
       for (int u = 0; u < 4; u++) {
-        const int k = kt * BK + kr + 4 * u;
+        const int k = kb + kt * BK + kr + 4 * u;
         d2 v = d2{0.0, 0.0};
         if (k < K) {
           const double *p = Bp + (long long)k * sg.ldb + n;
@@ -178,7 +183,7 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
   }
 
   // lane l, register v of a 16x16 f64 MFMA tile: row l/16 + 4v, column l%16
-  double *Cp = g.C + (long long)z * g.cbatch;
+  double *Cp = g.C + (long long)zz * g.cbatch;
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -223,7 +228,7 @@ Idx2 branchless(Idx2 f) {
 }  // namespace
 
 long long tile_gemm_blocks(const TileGemm &g) {
-  return (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch;
+  return (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.ksplit;
 }
 
 hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
@@ -231,6 +236,7 @@ hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g_dry) return hipSuccess;
   if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
   if (g.dcontract && !g.ak) return hipErrorInvalidValue;
+  if (g.ksplit < 1 || (g.ksplit > 1 && g.beta != 0.0)) return hipErrorInvalidValue;
   const long long T = tile_gemm_blocks(g);
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
   // 16-byte loads need even offsets of every loaded pair and 16-byte aligned bases
