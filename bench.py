@@ -9,8 +9,12 @@ Workload (default): n_o=12, n_v=60 active; N_O=30, N_V=250 total; Cholesky rank 
 FP64 throughout.  Throughput counts the algorithmic FLOPs of the cost model
 (U = 2 N_V n_v^3 (n_o^3 - n_o); ground 2U, right 4U, left 4U per vector).
 
+The same step is then timed with the d-contractions in FP32 MFMA ("mixed"): its throughput,
+its speedup over FP64 and the errors of every output against the FP64 path are reported in
+the "mixed" object of the JSON line.
+
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
-runs on one GPU), --steps, --warmup, --no-cpu-baseline, --cfg.
+runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --cfg.
 """
 from __future__ import annotations
 
@@ -39,6 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cfg", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 MFMA) step")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -59,6 +64,35 @@ def unit_flops(d, tb, te):
                     n += len({(i, j, k), (j, i, k), (k, j, i), (i, k, j), (k, i, j), (j, k, i)})
                 t += 1
     return 2.0 * d.N_V * d.n_v ** 3 * n
+
+
+def mixed_report(args, d, flops_step, dt64, outs64, timed, L):
+    """The same step with the d-contractions in FP32 MFMA: throughput, speedup and the errors of
+    every output against the FP64 path (which the GPU tests hold within 1e-10 of the oracle)."""
+    import numpy as np
+    from paper_2202_08612_amd import mlcc3
+    from tests.helpers import pair_form_blocks
+    dt, st, outs = timed("fp32")
+    err = {}
+    for name, a, b in (("Omega", outs["om"], outs64["om"]), ("rho", outs["rho"][0], outs64["rho"][0]),
+                       ("sigma", outs["sig"][0], outs64["sig"][0])):
+        for k in ("x1", "x2_vVoo", "x2_vvoO"):
+            x, y = a[k].double(), b[k].double()
+            ny = float(y.norm())
+            err[f"{name}.{k}"] = {"rel": float((x - y).norm()) / ny if ny > 0 else 0.0,
+                                  "max_abs": float((x - y).abs().max()),
+                                  "max_rel": float((x - y).abs().max() / y.abs().max()) if ny > 0 else 0.0}
+    Lh = mlcc3.to_numpy(L[0])
+    p64 = pair_form_blocks(d, Lh, mlcc3.to_numpy(outs64["rho"][0]))
+    pmx = pair_form_blocks(d, Lh, mlcc3.to_numpy(outs["rho"][0]))
+    worst = max(max(v["rel"], v["max_rel"]) for v in err.values())
+    ach = st["flops"] * (d.n_o ** 3 - d.n_o) / float(d.n_o ** 3) / (st["ms"] * 1e-3) / 1e12 if st["ms"] > 0 else 0.0
+    return {"precision": "fp32 MFMA d-contractions (FP32 sums per 32-deep K slab, FP64 across slabs), everything else FP64",
+            "value": round(flops_step / (dt / args.steps) / 1e9, 1), "unit": "GFLOP/s",
+            "ms_per_step": round(dt / args.steps * 1e3, 3), "speedup_vs_fp64": round(dt64 / dt, 3),
+            "dcontract_tflops": round(ach, 2), "dcontract_frac_fp32_peak": round(ach / FP32_PEAK_TFLOPS, 4),
+            "worst_rel_err_vs_fp64": worst, "pair_LAR_rel_err": abs(pmx - p64) / abs(p64) if p64 else 0.0,
+            "within_1e-6": bool(worst <= 1e-6 and abs(pmx - p64) <= 1e-6 * abs(p64)), "errors": err}
 
 
 def dcontract_traffic(d):
@@ -124,26 +158,32 @@ def main():
     w = float(I.omegas(cfg, 1)[0])
     R = [mlcc3.vec_to_device(I.right_vectors(prob, 1)[0], dev)]
     L = [mlcc3.vec_to_device(I.left_vectors(prob, 1)[0], dev)]
-    outs = {"om": mlcc3.empty_out(d, dev), "rho": [mlcc3.empty_out(d, dev)], "sig": [mlcc3.empty_out(d, dev)]}
+    def new_outs():
+        return {"om": mlcc3.empty_out(d, dev), "rho": [mlcc3.empty_out(d, dev)], "sig": [mlcc3.empty_out(d, dev)]}
 
-    def step():
+    def step(outs, precision):
         # the ground-state integral preparation runs once per step (first call) and is reused
-        mlcc3.ground_residual(ws, g, out=outs["om"])
-        mlcc3.right_transform(ws, g, [w], R, outs=outs["rho"], reuse_ground=True)
-        mlcc3.left_transform(ws, g, [w], L, outs=outs["sig"], reuse_ground=True)
+        mlcc3.ground_residual(ws, g, out=outs["om"], precision=precision)
+        mlcc3.right_transform(ws, g, [w], R, outs=outs["rho"], reuse_ground=True, precision=precision)
+        mlcc3.left_transform(ws, g, [w], L, outs=outs["sig"], reuse_ground=True, precision=precision)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ws.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = ws.phase_stats(0)
-    ws.timing(False)
+    def timed(precision):
+        outs = new_outs()
+        for _ in range(args.warmup):
+            step(outs, precision)
+        torch.cuda.synchronize()
+        ws.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(outs, precision)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ws.phase_stats(0)
+        ws.timing(False)
+        return dt, st, outs
+
+    dt, st, outs = timed("fp64")
     ms = dt / args.steps * 1e3
     flops_step = g.flops(0) + g.flops(1, 1) + g.flops(2, 1)
     value = flops_step / (dt / args.steps) / 1e9
@@ -175,6 +215,8 @@ def main():
                      "launches": st["launches"], "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 4)},
         "cpu_baseline": None,
     }
+    if not args.no_mixed:
+        res["mixed"] = mixed_report(args, d, flops_step, dt, outs, timed, L)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_triples)
     print(json.dumps(res), flush=True)

@@ -19,6 +19,7 @@
 #include "../../include/mlcc3.h"
 #include "mlcc3_internal.h"
 #include "tile_gemm.h"
+#include "dcontract_mixed.h"
 #include "triples_kernels.h"
 
 using namespace mlcc3;
@@ -53,6 +54,7 @@ thread_local std::vector<Extent> t_ext;
 
 thread_local mlcc3_ws t_ws = nullptr;   // workspace of the running call (timing, split-K scratch)
 thread_local hipStream_t t_stream = nullptr;
+thread_local int t_prec = MLCC3_FP64;   // arithmetic of the d-contractions of the running call
 
 void reg(const void *p, long long count, const char *name) {
   if (!p || count <= 0) return;
@@ -259,6 +261,13 @@ void check_range(const double *p, const Idx2 &row, int R, const Idx2 &col, int C
   for (const Extent &e : t_ext)
     if (e.lo <= lo && hi <= e.hi) return;
   throw Status{MLCC3_EHIP, std::string("internal bounds check failed for GEMM operand ") + what};
+}
+
+void check_bytes(const void *p, size_t bytes, const char *what) {
+  const uintptr_t lo = (uintptr_t)p, hi = lo + bytes;
+  for (const Extent &e : t_ext)
+    if (e.lo <= lo && hi <= e.hi) return;
+  throw Status{MLCC3_EHIP, std::string("internal bounds check failed for ") + what};
 }
 
 void gemm(const Gemm &g, hipStream_t s) {
@@ -600,6 +609,52 @@ struct BMap {
 // W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G_r(D,(b,c))  (+ second segment)
 void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, const double *xA2, const double *G2,
              hipStream_t s) {
+  const int nseg = xA2 ? 2 : 1;
+  const double *x[2] = {xA1, xA2}, *G[2] = {G1, G2};
+  if (t_prec == MLCC3_FP32) {
+    // FP32 MFMA on rounded, zero-padded copies of the operands; W and all later steps stay FP64
+    mlcc3_ws ws = t_ws;
+    MixGemm g;
+    g.M = d.no * d.no * d.nv;
+    g.N = (int)d.nv2;
+    g.nbatch = d.no;
+    g.C = W;
+    g.cmap = split(d.nv, (long long)d.no * d.nv3, d.nv2);
+    g.cbatch = d.nv3;
+    g.nseg = nseg;
+    const int Kp = (d.NV + 3) / 4 * 4, Np = ((int)d.nv2 + 3) / 4 * 4;
+    static const char *an[2] = {"mx_A0", "mx_A1"}, *bn[2] = {"mx_B0", "mx_B1"};
+    for (int i = 0; i < nseg; i++) {
+      const size_t na = (size_t)g.M * Kp, nb = (size_t)d.no * Kp * Np;
+      float *A = (float *)buf(ws, an[i], (na + 1) / 2, s);
+      float *Bm = (float *)buf(ws, bn[i], (nb + 1) / 2, s);
+      check_range(x[i], plain(d.NV), g.M, plain(1), d.NV, 0, 1, "A (d-contraction)");
+      check_range(G[i], plain(d.nv2), d.NV, plain(1), (int)d.nv2, (long long)d.NV * d.nv2, d.no, "B (d-contraction)");
+      check_bytes(A, na * sizeof(float), "FP32 A (d-contraction)");
+      check_bytes(Bm, nb * sizeof(float), "FP32 B (d-contraction)");
+      HIPCHK(pad_to_f32(x[i], 1, g.M, d.NV, A, g.M, Kp, s));
+      HIPCHK(pad_to_f32(G[i], d.no, d.NV, (int)d.nv2, Bm, Kp, Np, s));
+      g.seg[i].A = A;
+      g.seg[i].lda = Kp;
+      g.seg[i].B = Bm;
+      g.seg[i].ldb = Np;
+      g.seg[i].bbatch = (long long)Kp * Np;
+      g.seg[i].Kp = Kp;
+      g.seg[i].Np = Np;
+    }
+    check_range(W, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (d-contraction)");
+    if (!ws || !ws->timing || g_dry) {
+      HIPCHK(dcontract_f32(g, s));
+      return;
+    }
+    const double fl = 2.0 * g.M * (double)g.N * d.NV * g.nbatch * nseg;
+    mlcc3_ws_s::Mark mk{0, fl, pool_event(ws), pool_event(ws)};
+    HIPCHK(hipEventRecord(mk.a, s));
+    HIPCHK(dcontract_f32(g, s));
+    HIPCHK(hipEventRecord(mk.b, s));
+    ws->marks.push_back(mk);
+    return;
+  }
   TileGemm g;
   g.M = d.no * d.no * d.nv;
   g.N = (int)d.nv2;
@@ -607,9 +662,8 @@ void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, cons
   g.C = W;
   g.cmap = split(d.nv, (long long)d.no * d.nv3, d.nv2);
   g.cbatch = d.nv3;
-  g.nseg = xA2 ? 2 : 1;
+  g.nseg = nseg;
   g.dcontract = 1;
-  const double *x[2] = {xA1, xA2}, *G[2] = {G1, G2};
   for (int i = 0; i < g.nseg; i++) g.seg[i] = tseg(x[i], plain(d.NV), 0, G[i], d.nv2, (long long)d.NV * d.nv2, d.NV);
   tgemm(g, s);
 }
@@ -783,7 +837,8 @@ mlcc3_opts opts_or_default(const mlcc3_opts *o) {
   mlcc3_opts_default(&r);
   if (o) r = *o;
   check(r.precision == MLCC3_FP64 || r.precision == MLCC3_FP32 || r.precision == MLCC3_BF16X3, "bad precision");
-  if (r.precision != MLCC3_FP64) throw Status{MLCC3_EUNSUPPORTED, "only MLCC3_FP64 is implemented"};
+  if (r.precision == MLCC3_BF16X3) throw Status{MLCC3_EUNSUPPORTED, "MLCC3_BF16X3 is not implemented"};
+  t_prec = r.precision;
   return r;
 }
 

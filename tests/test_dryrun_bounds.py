@@ -51,14 +51,16 @@ def _fake(n):
 CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1)]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("d", CASES, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
-def test_all_launches_in_bounds(lib, d):
+def test_all_launches_in_bounds(lib, d, prec):
     ws = ctypes.c_void_p()
     assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
     p = _fake(64)
     g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:8])
     o = O()
     lib.mlcc3_opts_default(ctypes.byref(o))
+    o.precision = prec
     out = (V * 1)(V(*p[8:11]))
     rc = lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None)
     assert rc == 0, lib.mlcc3_last_error()
