@@ -149,6 +149,27 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
                             const mlcc3_vec *lambda, double *D_m0, double *D_0m, double *s,
                             const mlcc3_opts *opts, void *stream);
 
+/* Pairing maps of trial vectors, for gradients through the transforms.
+ * The left and right vectors are paired by G(L, R) = sum L1 R1 + sum_{(AI)>=(BJ)} L~ R with
+ * L~^{AB}_{IJ} = 2 L^{AB}_{IJ} - L^{BA}_{IJ} (the contravariant form of the doubles,
+ * Implementation section; the left transform is the adjoint of the right one under G).  An
+ * amplitude X^{AB}_{IJ} = X^{BA}_{JI} is stored at up to four positions of the two blocks.
+ *   MLCC3_MAP_SYMMETRIZE:    out = the mean over the positions of each amplitude (makes any
+ *                            block pair consistent and pair-symmetric);
+ *   MLCC3_MAP_GRAD_TO_LEFT:  in = an elementwise (Euclidean) gradient g over the block arrays;
+ *                            out = the left vector L with G(L, y) = <g, y> for every consistent y:
+ *                            L = (2 s + s^{BA}_{IJ}) / 3, s = the sum of g over the positions;
+ *   MLCC3_MAP_LEFT_TO_GRAD:  in = a consistent vector S; out = the elementwise representer h of
+ *                            G(S, .) on consistent vectors, spread evenly over the positions:
+ *                            h = (2 S - S^{BA}_{IJ}) / (number of positions).
+ * With rho = J R (right transform of the symmetrised R), the gradient of a loss with elementwise
+ * gradient g over rho is LEFT_TO_GRAD(sigma) with sigma the left transform of GRAD_TO_LEFT(g).
+ * Singles are copied.  Only the dimensions of g are read; in/out are nvec device vectors,
+ * outputs must not alias inputs.  Enqueued on stream. */
+enum { MLCC3_MAP_SYMMETRIZE = 0, MLCC3_MAP_GRAD_TO_LEFT = 1, MLCC3_MAP_LEFT_TO_GRAD = 2 };
+int mlcc3_vec_map(mlcc3_ws ws, const mlcc3_ground *g, int32_t mode, int32_t nvec, const mlcc3_vec *in,
+                  mlcc3_out *out, void *stream);
+
 /* Algorithmic FLOPs of one call (which: 0 ground residual, 1 right, 2 left) for nvec
  * vectors over the full triple list: U = 2 N_V n_v^3 (n_o^3 - n_o); ground 2U,
  * right/left (1 + 3 nvec) U (Implementation section cost model with the exact

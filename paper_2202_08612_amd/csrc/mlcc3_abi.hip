@@ -1076,6 +1076,36 @@ int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *
   });
 }
 
+int mlcc3_vec_map(mlcc3_ws ws, const mlcc3_ground *g, int32_t mode, int32_t nvec, const mlcc3_vec *in,
+                  mlcc3_out *out, void *stream) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    check(g != nullptr, "ground is NULL");
+    check(g->N_O >= 1 && g->N_V >= 1 && g->n_o >= 0 && g->n_o <= g->N_O && g->n_v >= 0 && g->n_v <= g->N_V,
+          "bad dimensions");
+    check(mode >= MLCC3_MAP_SYMMETRIZE && mode <= MLCC3_MAP_LEFT_TO_GRAD, "bad mode");
+    check(nvec >= 1 && in && out, "need nvec >= 1 and non-NULL vector arrays");
+    const bool act = g->n_o > 0 && g->n_v > 0;
+    for (int m = 0; m < nvec; m++) {
+      check(in[m].x1 && (!act || (in[m].x2_vVoo && in[m].x2_vvoO)), "NULL pointer in an input vector");
+      check(out[m].x1 && (!act || (out[m].x2_vVoo && out[m].x2_vvoO)), "NULL pointer in an output vector");
+      check(in[m].x2_vVoo != out[m].x2_vVoo && in[m].x2_vvoO != out[m].x2_vvoO, "outputs must not alias inputs");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(ws->device);
+    const long long n1 = (long long)g->N_V * g->N_O;
+    for (int m = 0; m < nvec; m++) {
+      if (!g_dry && in[m].x1 != out[m].x1)
+        HIPRT(hipMemcpyAsync(out[m].x1, in[m].x1, n1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (act) {
+        launch_vec_map(in[m].x2_vVoo, in[m].x2_vvoO, g->n_o, g->n_v, g->N_O, g->N_V, mode, out[m].x2_vVoo,
+                       out[m].x2_vvoO, s);
+        HIPRT(hipGetLastError());
+      }
+    }
+  });
+}
+
 double mlcc3_flops(const mlcc3_ground *g, int32_t which, int32_t nvec) {
   if (!g) return 0.0;
   const double no = g->n_o, nv = g->n_v, NV = g->N_V;

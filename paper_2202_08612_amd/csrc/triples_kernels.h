@@ -60,6 +60,10 @@ void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, c
                           long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
+// pairing maps of the doubles blocks (mode 0 symmetrise, 1 gradient -> left vector, 2 left
+// vector -> gradient representer); outputs must not alias inputs
+void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,
+                    double *oB, hipStream_t s);
 // xT[p][a][L][b] = x[a][b][p][L]  (x: [n_v][n_v][n_o][N_O])
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s);
 // out[z][c][r] = in[z][r][c], z < batch

@@ -465,6 +465,83 @@ __global__ void k_occ_xT(const double *__restrict__ x, int no, int nv, int NO, d
   xT[id] = x[(((long long)a * nv + b) * no + p) * NO + L];
 }
 
+// ------------------------------------------------- pairing maps of doubles vectors
+// The doubles X^{AB}_{IJ} = X^{BA}_{JI} are stored on two overlapping blocks,
+// A2[a][D][i][j] = X^{aD}_{ij} and B2[a][b][i][L] = X^{ab}_{iL}.  An amplitude (A,I,B,J) sits at
+// up to four positions: A2(A,B,I,J) if A < n_v, J < n_o; A2(B,A,J,I) if B < n_v, I < n_o;
+// B2(A,B,I,J) if A, B < n_v, I < n_o; B2(B,A,J,I) if A, B < n_v, J < n_o (coinciding
+// positions count once).
+struct PosList {
+  int n = 0;
+  long long off[4];  // offsets into A2 (>= 0) or B2 (encoded as -1 - offset)
+};
+
+__device__ __forceinline__ void amp_positions(int A, int I, int B, int J, int no, int nv, int NO, int NV,
+                                              PosList &pl) {
+  long long cand[4];
+  int nc = 0;
+  if (A < nv && I < no && J < no) cand[nc++] = (((long long)A * NV + B) * no + I) * no + J;
+  if (B < nv && I < no && J < no) cand[nc++] = (((long long)B * NV + A) * no + J) * no + I;
+  if (A < nv && B < nv && I < no) cand[nc++] = -1 - ((((long long)A * nv + B) * no + I) * NO + J);
+  if (A < nv && B < nv && J < no) cand[nc++] = -1 - ((((long long)B * nv + A) * no + J) * NO + I);
+  pl.n = 0;
+  for (int c = 0; c < nc; c++) {
+    bool dup = false;
+    for (int e = 0; e < pl.n; e++) dup = dup || (pl.off[e] == cand[c]);
+    if (!dup) pl.off[pl.n++] = cand[c];
+  }
+}
+
+__device__ __forceinline__ double pos_val(const double *A2, const double *B2, long long o) {
+  return o >= 0 ? A2[o] : B2[-1 - o];
+}
+
+// mode 0: average over the positions of each amplitude (a consistent, pair-symmetric vector)
+// mode 1: Euclidean gradient g -> left vector L with G(L, y) = <g, y> on consistent y:
+//         L = (2 s + s^{BA}_{IJ}) / 3, s = sum of g over the positions of the amplitude
+// mode 2: consistent vector S -> representer h with <h, y> = G(S, y) on consistent y:
+//         h = (2 S - S^{BA}_{IJ}) / (number of positions)
+__global__ void k_vec_map(const double *__restrict__ A2, const double *__restrict__ B2, int no, int nv, int NO, int NV,
+                          int mode, double *__restrict__ oA, double *__restrict__ oB) {
+  const long long nA = (long long)nv * NV * no * no, nB = (long long)nv * nv * no * NO;
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= nA + nB) return;
+  int A, I, B, J;
+  if (id < nA) {
+    long long t = id;
+    J = (int)(t % no); t /= no;
+    I = (int)(t % no); t /= no;
+    B = (int)(t % NV);
+    A = (int)(t / NV);
+  } else {
+    long long t = id - nA;
+    J = (int)(t % NO); t /= NO;
+    I = (int)(t % no); t /= no;
+    B = (int)(t % nv);
+    A = (int)(t / nv);
+  }
+  PosList pu, ps;
+  amp_positions(A, I, B, J, no, nv, NO, NV, pu);
+  double r;
+  if (mode == 0) {
+    double sum = 0.0;
+    for (int e = 0; e < pu.n; e++) sum += pos_val(A2, B2, pu.off[e]);
+    r = sum / pu.n;
+  } else if (mode == 1) {
+    amp_positions(B, I, A, J, no, nv, NO, NV, ps);
+    double su = 0.0, ss = 0.0;
+    for (int e = 0; e < pu.n; e++) su += pos_val(A2, B2, pu.off[e]);
+    for (int e = 0; e < ps.n; e++) ss += pos_val(A2, B2, ps.off[e]);
+    r = (2.0 * su + ss) / 3.0;
+  } else {
+    amp_positions(B, I, A, J, no, nv, NO, NV, ps);
+    const double self = id < nA ? A2[id] : B2[id - nA];
+    r = (2.0 * self - pos_val(A2, B2, ps.off[0])) / pu.n;
+  }
+  if (id < nA) oA[id] = r;
+  else oB[id - nA] = r;
+}
+
 // -------------------------------------------------------------- wave helpers
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -662,6 +739,11 @@ void launch_small_right(const double *X, const double *T, const double *gov, con
   if (no <= 0 || nv <= 0 || g_dry) return;
   hipLaunchKernelGGL(k_small_right, dim3(no * no * nv), dim3(64), nv * sizeof(double), s, X, T, gov, F, U,
                      no, nv, part1, Yvv);
+}
+
+void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,
+                    double *oB, hipStream_t s) {
+  L1D(k_vec_map, (long long)nv * NV * no * no + (long long)nv * nv * no * NO, A2, B2, no, nv, NO, NV, mode, oA, oB);
 }
 
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s) {

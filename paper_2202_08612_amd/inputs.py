@@ -35,6 +35,9 @@ Array layouts (C order, last index fastest), matching ``include/mlcc3.h``:
 from __future__ import annotations
 
 import dataclasses
+import concurrent.futures
+import os
+
 import numpy as np
 
 _U64 = np.uint64
@@ -124,11 +127,28 @@ def cholesky_block(seed, d: Dims, rows, cols, sigma=0.05, chunk=64):
     lo = np.minimum(p, q)
     hi = np.maximum(p, q)
     out = np.empty((d.n_chol, rows.size, cols.size), dtype=np.float64)
-    for j0 in range(0, d.n_chol, chunk):
+
+    def fill(j0):
         j1 = min(d.n_chol, j0 + chunk)
         J = np.arange(j0, j1, dtype=np.int64)[:, None, None]
         out[j0:j1] = sigma * _normal(_key(seed, TID_L, J, lo[None], hi[None]))
+
+    _parallel(fill, range(0, d.n_chol, chunk))
     return out
+
+
+def _parallel(fn, items):
+    """Run fn over items on a few threads (numpy releases the GIL in the element-wise work);
+    every item writes a disjoint slice, so the result does not depend on the schedule."""
+    items = list(items)
+    nthr = min(len(items), max(1, min(16, os.cpu_count() or 1)))
+    if nthr <= 1:
+        for it in items:
+            fn(it)
+        return
+    with concurrent.futures.ThreadPoolExecutor(nthr) as ex:
+        for _ in ex.map(fn, items):
+            pass
 
 
 def singles(seed, tid, d: Dims, sigma):
@@ -143,9 +163,15 @@ def doubles_block(seed, tid, d: Dims, A, B, I, J, sigma):
     B = np.asarray(B, dtype=np.int64)[None, :, None, None]
     I = np.asarray(I, dtype=np.int64)[None, None, :, None]
     J = np.asarray(J, dtype=np.int64)[None, None, None, :]
-    u = A * d.N_O + I
-    v = B * d.N_O + J
-    return sigma * _normal(_key(seed, tid, np.minimum(u, v), np.maximum(u, v)))
+    out = np.empty((A.shape[0], B.shape[1], I.shape[2], J.shape[3]), dtype=np.float64)
+
+    def fill(a):
+        u = A[a:a + 1] * d.N_O + I
+        v = B * d.N_O + J
+        out[a:a + 1] = sigma * _normal(_key(seed, tid, np.minimum(u, v), np.maximum(u, v)))
+
+    _parallel(fill, range(A.shape[0]))
+    return out
 
 
 def doubles_blocks(seed, tid, d: Dims, sigma, with_density_blocks=False):

@@ -65,6 +65,8 @@ _lib.mlcc3_triples_densities.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground
                                          ctypes.c_int32, _dp, ctypes.POINTER(_Vec), ctypes.POINTER(_Vec),
                                          ctypes.POINTER(_Vec), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(_Opts), ctypes.c_void_p]
+_lib.mlcc3_vec_map.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(_Vec), ctypes.POINTER(_Vec), ctypes.c_void_p]
 _lib.mlcc3_flops.argtypes = [ctypes.POINTER(_Ground), ctypes.c_int32, ctypes.c_int32]
 _lib.mlcc3_flops.restype = ctypes.c_double
 _lib.mlcc3_status_string.argtypes = [ctypes.c_int]
@@ -73,7 +75,9 @@ _lib.mlcc3_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_ws_timing", "mlcc3_ws_phase_stats", "mlcc3_opts_default",
             "mlcc3_num_triples", "mlcc3_ground_residual", "mlcc3_right_transform",
-            "mlcc3_left_transform", "mlcc3_triples_densities", "mlcc3_flops", "mlcc3_status_string", "mlcc3_last_error"]
+            "mlcc3_left_transform", "mlcc3_triples_densities", "mlcc3_vec_map", "mlcc3_flops",
+            "mlcc3_status_string", "mlcc3_last_error"]
+MAP_SYMMETRIZE, MAP_GRAD_TO_LEFT, MAP_LEFT_TO_GRAD = 0, 1, 2
 
 
 class MLCC3Error(RuntimeError):
@@ -200,6 +204,15 @@ def _transform(fn, ws, ground, omegas, vecs, outs=None, **kw):
     o = make_opts(**kw)
     _check(fn(ws.h, ctypes.byref(ground.c), n, om, _vecs(vecs), _vecs(outs), ctypes.byref(o),
               _stream(ws.device)))
+    return outs
+
+
+def vec_map(ws, ground, mode, vecs, outs=None):
+    """Pairing maps of trial vectors (MAP_SYMMETRIZE, MAP_GRAD_TO_LEFT, MAP_LEFT_TO_GRAD)."""
+    n = len(vecs)
+    outs = [empty_out(ground.dims, ws.device) for _ in range(n)] if outs is None else outs
+    _check(_lib.mlcc3_vec_map(ws.h, ctypes.byref(ground.c), int(mode), n, _vecs(vecs), _vecs(outs),
+                              _stream(ws.device)))
     return outs
 
 
