@@ -1,0 +1,93 @@
+"""The core-excitation-shaped workload at full size (n_o=8 with one core-like orbital near -15,
+n_v=60, N_O=90, N_V=1100, Cholesky rank 2500; 8 right and 8 left vectors; transition densities),
+checked by properties that hold at any size (the oracle is too slow at N_V=1100 for a test):
+batched calls equal single calls, the adjoint identity per block pairing, triple-range
+additivity, the density trace identities, and the mixed form within 1e-6 of FP64.
+"""
+import numpy as np
+import pytest
+
+from paper_2202_08612_amd import inputs as I
+from tests.helpers import pair_form_blocks, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2202_08612_amd import mlcc3
+    return mlcc3
+
+
+@pytest.fixture(scope="module")
+def ws(lib):
+    w = lib.Workspace(0)
+    yield w
+    w.close()
+
+
+@pytest.fixture(scope="module")
+def case(lib):
+    p = I.make_config(4, with_density_blocks=True)
+    return p, lib.Ground(p)
+
+
+def test_config4_right_left_batched_adjoint_mixed(lib, ws, case):
+    import torch
+    p, g = case
+    d = p.dims
+    om = [float(x) for x in I.omegas(4, 8)]
+    Rs, Ls = I.right_vectors(p, 8), I.left_vectors(p, 8)
+    Rd, Ld = [lib.vec_to_device(r) for r in Rs], [lib.vec_to_device(v) for v in Ls]
+    rho = lib.right_transform(ws, g, om, Rd)
+    sig = lib.left_transform(ws, g, om, Ld, reuse_ground=True)
+    for m in (0, 7):
+        single = lib.right_transform(ws, g, [om[m]], [Rd[m]], reuse_ground=True)[0]
+        for k in single:
+            assert torch.equal(single[k], rho[m][k]), (m, k)
+    for m in range(8):
+        a = pair_form_blocks(d, Ls[m], lib.to_numpy(rho[m]))
+        b = pair_form_blocks(d, lib.to_numpy(sig[m]), Rs[m])
+        assert abs(a - b) <= 1e-10 * abs(a), (m, a, b)
+    rmx = lib.right_transform(ws, g, om, Rd, reuse_ground=True, precision="fp32")
+    smx = lib.left_transform(ws, g, om, Ld, reuse_ground=True, precision="fp32")
+    for m in range(8):
+        for k in rho[m]:
+            x, y = rmx[m][k].cpu().numpy(), rho[m][k].cpu().numpy()
+            assert rel(x, y) <= 1e-6, ("rho", m, k, rel(x, y))
+            x, y = smx[m][k].cpu().numpy(), sig[m][k].cpu().numpy()
+            assert rel(x, y) <= 1e-6, ("sigma", m, k, rel(x, y))
+
+
+def test_config4_range_additivity(lib, ws, case):
+    p, g = case
+    R = lib.vec_to_device(I.right_vectors(p, 1)[0])
+    nt = lib.num_triples(p.dims.n_o)
+    w = float(I.omegas(4, 1)[0])
+    full = lib.right_transform(ws, g, [w], [R], reuse_ground=True)[0]
+    parts = [lib.right_transform(ws, g, [w], [R], triple_range=r, reuse_ground=True)[0]
+             for r in ((0, 37), (37, 80), (80, nt))]
+    for k in full:
+        tot = sum(x[k] for x in parts)
+        assert float((tot - full[k]).norm() / full[k].norm()) < 1e-13, k
+
+
+def test_config4_densities_traces_and_mixed(lib, ws, case):
+    p, g = case
+    d = p.dims
+    om = [float(x) for x in I.omegas(4, 8)]
+    Ls = [lib.vec_to_device(v) for v in I.left_vectors(p, 8)]
+    Rs = [lib.vec_to_device(v) for v in I.right_vectors(p, 8)]
+    lam = lib.vec_to_device(I.lambda_vector(p))
+    Dm0, D0m, s = lib.triples_densities(ws, g, om, Ls, Rs, lam, p.t2_vVoO, p.t2_vVOo, reuse_ground=True)
+    Dm0x, D0mx, sx = lib.triples_densities(ws, g, om, Ls, Rs, lam, p.t2_vVoO, p.t2_vVOo, reuse_ground=True,
+                                           precision="fp32")
+    for m in range(8):
+        a, b = Dm0[m].cpu().numpy(), D0m[m].cpu().numpy()
+        assert np.all(np.isfinite(a)) and np.all(np.isfinite(b))
+        assert abs(np.trace(a)) <= 1e-10 * np.abs(a).sum(), m
+        assert abs(np.trace(b) - 2 * d.N_O * float(s[m])) <= 1e-10 * np.abs(b).sum(), m
+        assert rel(Dm0x[m].cpu().numpy(), a) <= 1e-6 and rel(D0mx[m].cpu().numpy(), b) <= 1e-6, m
+        assert abs(float(sx[m]) - float(s[m])) <= 1e-6 * abs(float(s[m])), m
