@@ -41,105 +41,110 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
-  const int z = blockIdx.x / (mt * nt);
-  int t = blockIdx.x - z * (mt * nt);
-  const int grp = t / (GM * nt), gbase = grp * GM;
-  const int gsz = min(GM, mt - gbase);
-  t -= grp * GM * nt;
-  const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
-  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 32;
+  const long long ntiles = (long long)mt * nt * g.nbatch * g.nvec;
+  for (long long L = blockIdx.x; L < ntiles; L += gridDim.x) {
+    const long long zf = L / (mt * nt);
+    const int vv = (int)(zf / g.nbatch), z = (int)(zf - (long long)vv * g.nbatch);
+    int t = (int)(L - zf * (mt * nt));
+    const int grp = t / (GM * nt), gbase = grp * GM;
+    const int gsz = min(GM, mt - gbase);
+    t -= grp * GM * nt;
+    const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 32;
 
-  f4 acc[4][2];
-  d4 acc64[4][2];
+    f4 acc[4][2];
+    d4 acc64[4][2];
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-
-  // staging: A rows ar + 32u with k quad 4*aq; B rows (k) br + 16u with n quad 4*bq
-  const int aq = tid & 7, ar = tid >> 3;
-  const int bq = tid & 15, br = tid >> 4;
-  f4 ra[4], rb[2];
-
-  for (int s = 0; s < g.nseg; s++) {
-    const MixSeg &sg = g.seg[s];
-    const int Kp = sg.Kp;
-    const float *Bp = sg.B + (long long)z * sg.bbatch;
-    const int nkt = (Kp + BK - 1) / BK;
-    auto load = [&](int kt) {
-      const int k = kt * BK + 4 * aq;
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int m = m0 + ar + 32 * u;
-        ra[u] = (m < g.M && k < Kp) ? *(const f4 *)(sg.A + (long long)m * sg.lda + k) : f4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < 2; j++) {
+        acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       }
-      const int n = n0 + 4 * bq;
-#pragma unroll
-      for (int u = 0; u < 2; u++) {
-        const int k2 = kt * BK + br + 16 * u;
-        rb[u] = (k2 < Kp && n < sg.Np) ? *(const f4 *)(Bp + (long long)k2 * sg.ldb + n) : f4{0.f, 0.f, 0.f, 0.f};
-      }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-      for (int u = 0; u < 4; u++) *(f4 *)&As[buf][(ar + 32 * u) * PA + 4 * aq] = ra[u];
-#pragma unroll
-      for (int u = 0; u < 2; u++) *(f4 *)&Bs[buf][(br + 16 * u) * PB + 4 * bq] = rb[u];
-    };
 
-    __syncthreads();  // the previous segment's readers are done with both buffers
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int kt = 0; kt < nkt; kt++) {
-      const int cur = kt & 1;
-      if (kt + 1 < nkt) load(kt + 1);
-      const float *as = &As[cur][(wm0 + (lane & 15)) * PA + (lane >> 4)];
-      const float *bs = &Bs[cur][(lane >> 4) * PB + wn0 + (lane & 15)];
+    // staging: A rows ar + 32u with k quad 4*aq; B rows (k) br + 16u with n quad 4*bq
+    const int aq = tid & 7, ar = tid >> 3;
+    const int bq = tid & 15, br = tid >> 4;
+    f4 ra[4], rb[2];
+
+    for (int s = 0; s < g.nseg; s++) {
+      const MixSeg &sg = g.seg[s];
+      const int Kp = sg.Kp;
+      const float *Ap = sg.A + vv * sg.avec;
+      const float *Bp = sg.B + vv * sg.bvec + (long long)z * sg.bbatch;
+      const int nkt = (Kp + BK - 1) / BK;
+      auto load = [&](int kt) {
+        const int k = kt * BK + 4 * aq;
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        float a[4], b[2];
+        for (int u = 0; u < 4; u++) {
+          const int m = m0 + ar + 32 * u;
+          ra[u] = (m < g.M && k < Kp) ? *(const f4 *)(Ap + (long long)m * sg.lda + k) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+        const int n = n0 + 4 * bq;
 #pragma unroll
-        for (int i = 0; i < 4; i++) a[i] = as[16 * i * PA + kk];
+        for (int u = 0; u < 2; u++) {
+          const int k2 = kt * BK + br + 16 * u;
+          rb[u] = (k2 < Kp && n < sg.Np) ? *(const f4 *)(Bp + (long long)k2 * sg.ldb + n) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+      };
+      auto store = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < 2; j++) b[j] = bs[kk * PB + 16 * j];
+        for (int u = 0; u < 4; u++) *(f4 *)&As[buf][(ar + 32 * u) * PA + 4 * aq] = ra[u];
+#pragma unroll
+        for (int u = 0; u < 2; u++) *(f4 *)&Bs[buf][(br + 16 * u) * PB + 4 * bq] = rb[u];
+      };
+
+      __syncthreads();  // the previous segment's readers are done with both buffers
+      load(0);
+      store(0);
+      __syncthreads();
+      for (int kt = 0; kt < nkt; kt++) {
+        const int cur = kt & 1;
+        if (kt + 1 < nkt) load(kt + 1);
+        const float *as = &As[cur][(wm0 + (lane & 15)) * PA + (lane >> 4)];
+        const float *bs = &Bs[cur][(lane >> 4) * PB + wn0 + (lane & 15)];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          float a[4], b[2];
+#pragma unroll
+          for (int i = 0; i < 4; i++) a[i] = as[16 * i * PA + kk];
+#pragma unroll
+          for (int j = 0; j < 2; j++) b[j] = bs[kk * PB + 16 * j];
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nkt) store(cur ^ 1);
+        // slab done: move the FP32 partial sums into the FP64 accumulator
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-          for (int j = 0; j < 2; j++)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      if (kt + 1 < nkt) store(cur ^ 1);
-      // slab done: move the FP32 partial sums into the FP64 accumulator
+          for (int j = 0; j < 2; j++) {
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+            for (int v = 0; v < 4; v++) acc64[i][j][v] += (double)acc[i][j][v];
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+        __syncthreads();
+      }
+    }
+
+    double *Cp = g.C + vv * g.cvec + (long long)z * g.cbatch;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int m = m0 + wm0 + 16 * i + 4 * (lane >> 4) + v;
+        if (m >= g.M) continue;
+        double *crow = Cp + moff(g.cmap, m);
 #pragma unroll
         for (int j = 0; j < 2; j++) {
-#pragma unroll
-          for (int v = 0; v < 4; v++) acc64[i][j][v] += (double)acc[i][j][v];
-          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          const int n = n0 + wn0 + 16 * j + (lane & 15);
+          if (n < g.N) crow[n] = acc64[i][j][v];
         }
-      __syncthreads();
-    }
-  }
-
-  double *Cp = g.C + (long long)z * g.cbatch;
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const int m = m0 + wm0 + 16 * i + 4 * (lane >> 4) + v;
-      if (m >= g.M) continue;
-      double *crow = Cp + moff(g.cmap, m);
-#pragma unroll
-      for (int j = 0; j < 2; j++) {
-        const int n = n0 + wn0 + 16 * j + (lane & 15);
-        if (n < g.N) crow[n] = acc64[i][j][v];
       }
-    }
+  }  // tiles of a persistent workgroup
 }
 
 // dst[b][r][c] = src[b][r][c] rounded to FP32 for r < R, c < C; zero for R <= r < Rp, C <= c < Cp
@@ -164,22 +169,23 @@ hipError_t pad_to_f32(const double *src, int nb, int R, int C, float *dst, int R
 }
 
 hipError_t dcontract_f32(const MixGemm &g0, hipStream_t s) {
-  if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g_dry) return hipSuccess;
+  if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g0.nvec <= 0 || g_dry) return hipSuccess;
   if (g0.nseg < 1 || g0.nseg > 2) return hipErrorInvalidValue;
   MixGemm g = g0;
   for (int i = 0; i < g.nseg; i++) {
     const MixSeg &sg = g.seg[i];
-    if (sg.Kp % 4 || sg.Np % 4 || sg.lda % 4 || sg.ldb % 4 || sg.bbatch % 4 || sg.Np < g.N ||
-        (uintptr_t)sg.A % 16 || (uintptr_t)sg.B % 16)
+    if (sg.Kp % 4 || sg.Np % 4 || sg.lda % 4 || sg.ldb % 4 || sg.bbatch % 4 || sg.avec % 4 || sg.bvec % 4 ||
+        sg.Np < g.N || (uintptr_t)sg.A % 16 || (uintptr_t)sg.B % 16)
       return hipErrorInvalidValue;
   }
   if (g.cmap.d <= 0) {
     g.cmap.d = 0x7fffffff;
     g.cmap.s1 = 0;
   }
-  const long long T = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch;
+  const long long T = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.nvec;
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dcontract_f32, dim3((unsigned)T), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_dcontract_f32, dim3((unsigned)(g.persist > 0 && g.persist < T ? g.persist : T)), dim3(256), 0,
+                     s, g);
   return hipGetLastError();
 }
 

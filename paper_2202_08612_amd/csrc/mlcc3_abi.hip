@@ -255,9 +255,11 @@ long long max_off(const Idx2 &f, int X) {
 }
 
 void check_range(const double *p, const Idx2 &row, int R, const Idx2 &col, int Cc, long long batch, int nb,
-                 const char *what) {
+                 const char *what, long long vstride = 0, int nvec = 1) {
   const uintptr_t lo = (uintptr_t)p;
-  const uintptr_t hi = lo + (uintptr_t)(max_off(row, R) + max_off(col, Cc) + batch * (nb - 1) + 1) * sizeof(double);
+  const uintptr_t hi =
+      lo + (uintptr_t)(max_off(row, R) + max_off(col, Cc) + batch * (nb - 1) + vstride * (nvec - 1) + 1) *
+               sizeof(double);
   for (const Extent &e : t_ext)
     if (e.lo <= lo && hi <= e.hi) return;
   throw Status{MLCC3_EHIP, std::string("internal bounds check failed for GEMM operand ") + what};
@@ -314,13 +316,13 @@ void tgemm(const TileGemm &g, hipStream_t s) {
   for (int i = 0; i < g.nseg; i++) {
     const TgSeg &sg = g.seg[i];
     if (sg.K <= 0) continue;
-    if (g.ak) check_range(sg.A, sg.amap, g.M, plain(1), sg.K, sg.abatch, g.nbatch, "A (tile GEMM)");
-    else check_range(sg.A, sg.amap, sg.K, plain(1), g.M, sg.abatch, g.nbatch, "A (tile GEMM)");
-    check_range(sg.B, plain(sg.ldb), sg.K, plain(1), g.N, sg.bbatch, g.nbatch, "B (tile GEMM)");
+    if (g.ak) check_range(sg.A, sg.amap, g.M, plain(1), sg.K, sg.abatch, g.nbatch, "A (tile GEMM)", sg.avec, g.nvec);
+    else check_range(sg.A, sg.amap, sg.K, plain(1), g.M, sg.abatch, g.nbatch, "A (tile GEMM)", sg.avec, g.nvec);
+    check_range(sg.B, plain(sg.ldb), sg.K, plain(1), g.N, sg.bbatch, g.nbatch, "B (tile GEMM)", sg.bvec, g.nvec);
   }
-  check_range(g.C, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (tile GEMM)");
+  check_range(g.C, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (tile GEMM)", g.cvec, g.nvec);
   mlcc3_ws ws = t_ws;
-  if (!g.dcontract) {
+  if (!g.dcontract && g.nvec == 1) {
     // split K when the 128x128 tiles fill the 512 workgroup slots (two per CU) in few, ragged
     // rounds: the part count with the best filled fraction of the last round (>= 256 K each)
     const long long tiles = tile_gemm_blocks(g);
@@ -341,7 +343,8 @@ void tgemm(const TileGemm &g, hipStream_t s) {
       h.ksplit = ks;
       h.C = buf(ws, "tile_splitk", (size_t)ks * g.nbatch * (long long)g.M * g.N, s);
       h.cmap = plain(g.N);
-      h.cbatch = (long long)g.M * g.N;
+      h.cpart = (long long)g.M * g.N;
+      h.cbatch = ks * h.cpart;
       h.alpha = 1.0;
       h.beta = 0.0;
       HIPCHK(tile_gemm_f64(h, s));
@@ -366,7 +369,7 @@ void tgemm(const TileGemm &g, hipStream_t s) {
     return;
   }
   double fl = 0.0;
-  for (int i = 0; i < g.nseg; i++) fl += 2.0 * g.M * (double)g.N * g.seg[i].K * g.nbatch;
+  for (int i = 0; i < g.nseg; i++) fl += 2.0 * g.M * (double)g.N * g.seg[i].K * g.nbatch * g.nvec;
   mlcc3_ws_s::Mark mk{0, fl, pool_event(ws), pool_event(ws)};
   HIPCHK(hipEventRecord(mk.a, s));
   HIPCHK(tile_gemm_f64(g, s));
@@ -606,11 +609,33 @@ struct BMap {
   long long batch;
 };
 
-// W[p][q][r][a][b][c] = sum_D xA[(p,q,a)][D] G_r(D,(b,c))  (+ second segment)
-void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, const double *xA2, const double *G2,
-             hipStream_t s) {
-  const int nseg = xA2 ? 2 : 1;
-  const double *x[2] = {xA1, xA2}, *G[2] = {G1, G2};
+// one product term of the d-contraction: x [(p,q,a)][D] and G [r][D][(b,c)], vector v of a
+// group at x + v*xv, G + v*Gv (stride 0: shared by the group)
+struct DSeg {
+  const double *x = nullptr;
+  long long xv = 0;
+  const double *G = nullptr;
+  long long Gv = 0;
+};
+
+// persistent grid of the d-contraction: two workgroups per CU
+int persist_grid() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, cus = 0;
+    if (!g_dry && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      n = 2 * cus;
+    else
+      n = 512;
+  }
+  return n;
+}
+
+// W_v[p][q][r][a][b][c] = sum_seg sum_D x_seg,v[(p,q,a)][D] G_seg,v[r][D][(b,c)] for the nb vectors
+// of a group (W_v at W + v*|W|), one persistent launch for the whole group
+void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStream_t s) {
+  const long long Wv = d.nord * d.nv3;
   if (t_prec == MLCC3_FP32) {
     // FP32 MFMA on rounded, zero-padded copies of the operands; W and all later steps stay FP64
     mlcc3_ws ws = t_ws;
@@ -618,36 +643,45 @@ void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, cons
     g.M = d.no * d.no * d.nv;
     g.N = (int)d.nv2;
     g.nbatch = d.no;
+    g.nvec = nb;
     g.C = W;
     g.cmap = split(d.nv, (long long)d.no * d.nv3, d.nv2);
     g.cbatch = d.nv3;
+    g.cvec = Wv;
     g.nseg = nseg;
+    g.persist = persist_grid();
     const int Kp = (d.NV + 3) / 4 * 4, Np = ((int)d.nv2 + 3) / 4 * 4;
     static const char *an[2] = {"mx_A0", "mx_A1"}, *bn[2] = {"mx_B0", "mx_B1"};
     for (int i = 0; i < nseg; i++) {
-      const size_t na = (size_t)g.M * Kp, nb = (size_t)d.no * Kp * Np;
-      float *A = (float *)buf(ws, an[i], (na + 1) / 2, s);
-      float *Bm = (float *)buf(ws, bn[i], (nb + 1) / 2, s);
-      check_range(x[i], plain(d.NV), g.M, plain(1), d.NV, 0, 1, "A (d-contraction)");
-      check_range(G[i], plain(d.nv2), d.NV, plain(1), (int)d.nv2, (long long)d.NV * d.nv2, d.no, "B (d-contraction)");
-      check_bytes(A, na * sizeof(float), "FP32 A (d-contraction)");
-      check_bytes(Bm, nb * sizeof(float), "FP32 B (d-contraction)");
-      HIPCHK(pad_to_f32(x[i], 1, g.M, d.NV, A, g.M, Kp, s));
-      HIPCHK(pad_to_f32(G[i], d.no, d.NV, (int)d.nv2, Bm, Kp, Np, s));
+      const int na_v = seg[i].xv ? nb : 1, nb_v = seg[i].Gv ? nb : 1;
+      const size_t sa = (size_t)g.M * Kp, sb = (size_t)d.no * Kp * Np;
+      float *A = (float *)buf(ws, an[i], (sa * na_v + 1) / 2, s);
+      float *Bm = (float *)buf(ws, bn[i], (sb * nb_v + 1) / 2, s);
+      check_range(seg[i].x, plain(d.NV), g.M, plain(1), d.NV, 0, 1, "A (d-contraction)", seg[i].xv, nb);
+      check_range(seg[i].G, plain(d.nv2), d.NV, plain(1), (int)d.nv2, (long long)d.NV * d.nv2, d.no,
+                  "B (d-contraction)", seg[i].Gv, nb);
+      check_bytes(A, sa * na_v * sizeof(float), "FP32 A (d-contraction)");
+      check_bytes(Bm, sb * nb_v * sizeof(float), "FP32 B (d-contraction)");
+      for (int v = 0; v < na_v; v++)
+        HIPCHK(pad_to_f32(seg[i].x + v * seg[i].xv, 1, g.M, d.NV, A + v * sa, g.M, Kp, s));
+      for (int v = 0; v < nb_v; v++)
+        HIPCHK(pad_to_f32(seg[i].G + v * seg[i].Gv, d.no, d.NV, (int)d.nv2, Bm + v * sb, Kp, Np, s));
       g.seg[i].A = A;
       g.seg[i].lda = Kp;
+      g.seg[i].avec = seg[i].xv ? (long long)sa : 0;
       g.seg[i].B = Bm;
       g.seg[i].ldb = Np;
       g.seg[i].bbatch = (long long)Kp * Np;
+      g.seg[i].bvec = seg[i].Gv ? (long long)sb : 0;
       g.seg[i].Kp = Kp;
       g.seg[i].Np = Np;
     }
-    check_range(W, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (d-contraction)");
+    check_range(W, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (d-contraction)", g.cvec, nb);
     if (!ws || !ws->timing || g_dry) {
       HIPCHK(dcontract_f32(g, s));
       return;
     }
-    const double fl = 2.0 * g.M * (double)g.N * d.NV * g.nbatch * nseg;
+    const double fl = 2.0 * g.M * (double)g.N * d.NV * g.nbatch * nseg * nb;
     mlcc3_ws_s::Mark mk{0, fl, pool_event(ws), pool_event(ws)};
     HIPCHK(hipEventRecord(mk.a, s));
     HIPCHK(dcontract_f32(g, s));
@@ -659,38 +693,65 @@ void w_dterm(const Dims &d, double *W, const double *xA1, const double *G1, cons
   g.M = d.no * d.no * d.nv;
   g.N = (int)d.nv2;
   g.nbatch = d.no;
+  g.nvec = nb;
   g.C = W;
   g.cmap = split(d.nv, (long long)d.no * d.nv3, d.nv2);
   g.cbatch = d.nv3;
+  g.cvec = Wv;
   g.nseg = nseg;
   g.dcontract = 1;
-  for (int i = 0; i < g.nseg; i++) g.seg[i] = tseg(x[i], plain(d.NV), 0, G[i], d.nv2, (long long)d.NV * d.nv2, d.NV);
+  g.persist = persist_grid();
+  for (int i = 0; i < g.nseg; i++) {
+    g.seg[i] = tseg(seg[i].x, plain(d.NV), 0, seg[i].G, d.nv2, (long long)d.NV * d.nv2, d.NV);
+    g.seg[i].avec = seg[i].xv;
+    g.seg[i].bvec = seg[i].Gv;
+  }
   tgemm(g, s);
 }
 
 // occupied-term operands: xT[p][a][L][b] (launch_occ_xT of an [a][b][p][L] block) and G stored
-// [L][q][r][c] (G2, Uo, Gb3L)
-void occ_add(OccTerm &ot, const Dims &d, const double *xT, const double *G) {
+// [L][q][r][c] (G2, Uo, Gb3L); vector v of a group at + v*xv, + v*gv (stride 0: shared)
+void occ_add(OccTerm &ot, const Dims &d, const double *xT, long long xv, const double *G, long long gv, int nb) {
   const int sg = ot.nseg++;
   ot.NO = d.NO;
   ot.x[sg] = xT;
   ot.G[sg] = G;
-  reg_check_occ(d, xT, G);
+  ot.xv[sg] = xv;
+  ot.gv[sg] = gv;
+  for (int v = 0; v < nb; v++) reg_check_occ(d, xT + v * xv, G + v * gv);
 }
 
-// transposed occupied-term copy of an [a][b][p][L] block into workspace buffer `name`
-const double *occ_xT(mlcc3_ws ws, const Dims &d, const double *x, const char *name, hipStream_t s) {
-  double *xT = buf(ws, name, (size_t)d.no * d.nv * d.NO * d.nv, s);
-  launch_occ_xT(x, d.no, d.nv, d.NO, xT, s);
+// transposed occupied-term copies of nb [a][b][p][L] blocks (block v at x[v]) into workspace
+// buffer `name`, stacked with the stride returned in *stride
+const double *occ_xT(mlcc3_ws ws, const Dims &d, const double *const *x, int nb, const char *name, long long *stride,
+                     hipStream_t s) {
+  const long long n = (long long)d.no * d.nv * d.NO * d.nv;
+  double *xT = buf(ws, name, (size_t)(n * nb), s);
+  for (int v = 0; v < nb; v++) launch_occ_xT(x[v], d.no, d.nv, d.NO, xT + v * n, s);
   HIPRT(hipGetLastError());
+  *stride = n;
   return xT;
 }
 
+// symmetrise, divide and convert the W blocks of nb vectors (W_v at W + v*|W|) into X~_v at
+// Xt + v*|W| (and covariant X into Xc likewise); one launch per pass for the whole group
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
-             double omega, Range r, const LocalTerms &lt, const OccTerm &ot, hipStream_t s, double *Xc = nullptr) {
-  double *Xu = buf(ws, "Xu", (size_t)ws->nu * d.nv3, s);
-  launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v,
-                       omega, r.tb, r.te, lt, ot, s);
+             const double *omega, int nb, Range r, const LocalTerms &lt, const OccTerm &ot, hipStream_t s,
+             double *Xc = nullptr) {
+  check(nb >= 1 && nb <= kMaxVecBatch, "vector group too large");
+  const long long Wv = d.nord * d.nv3, Xuv = (long long)ws->nu * d.nv3;
+  double *Xu = buf(ws, "Xu", (size_t)(Xuv * nb), s);
+  VecBatch vb;
+  vb.nvec = nb;
+  vb.w = Wv;
+  vb.xu = Xuv;
+  vb.xt = Wv;
+  for (int v = 0; v < nb; v++) vb.omega[v] = omega[v];
+  check_bytes(W, sizeof(double) * Wv * nb, "W (permutation)");
+  check_bytes(Xt, sizeof(double) * Wv * nb, "X~ (permutation)");
+  if (Xc) check_bytes(Xc, sizeof(double) * Wv * nb, "covariant X (permutation)");
+  launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, vb,
+                       r.tb, r.te, lt, ot, s);
   HIPRT(hipGetLastError());
 }
 
@@ -698,10 +759,14 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
 void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s, double *Xc = nullptr) {
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
-  w_dterm(d, W, B(ws, "tA"), B(ws, "G1"), nullptr, nullptr, s);
+  DSeg sg;
+  sg.x = B(ws, "tA");
+  sg.G = B(ws, "G1");
+  w_dterm(d, W, 1, &sg, 1, s);
   OccTerm ot;
-  occ_add(ot, d, B(ws, "t2xT"), B(ws, "G2"));
-  permute(ws, d, W, XT, g->eps_o, g->eps_v, 0.0, r, LocalTerms{}, ot, s, Xc);
+  occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1);
+  const double zero = 0.0;
+  permute(ws, d, W, XT, g->eps_o, g->eps_v, &zero, 1, r, LocalTerms{}, ot, s, Xc);
 }
 
 // Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
@@ -857,12 +922,24 @@ void finish_right_like(mlcc3_ws ws, const Dims &d, const double *X, const double
 }
 
 
-// one-index transformed blocks of a right vector: Rbar packs "RA" [p][q][a][D] and "RB"
-// [a][b][p][L], Upsilon_bDck "U1", Upsilon_Ljck "Uo", Upsilon_kc "Ukc", Xi_jLkc "Xi"
-void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &R, hipStream_t s) {
+// per-vector sizes of the prepared right-vector blocks (stacked for a group of vectors)
+struct RightSizes {
+  long long RA, RB, U1, Uo, Ukc, Xi;
+};
+RightSizes right_sizes(const Dims &d) {
+  return {(long long)d.no * d.no * d.nv * d.NV, (long long)d.nv * d.nv * d.no * d.NO, (long long)d.no * d.NV * d.nv2,
+          (long long)d.NO * d.no * d.no * d.nv, (long long)d.no * d.nv, (long long)d.no * d.no * d.nv * d.NO};
+}
+
+// one-index transformed blocks of right vector `slot` of a group of nb: Rbar packs "RA"
+// [p][q][a][D] and "RB" [a][b][p][L], Upsilon_bDck "U1", Upsilon_Ljck "Uo", Upsilon_kc "Ukc",
+// Xi_jLkc "Xi"; each buffer holds nb blocks, this vector's at slot * size
+void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &R, int slot, int nb,
+                       hipStream_t s) {
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
-  double *RA = buf(ws, "RA", (size_t)no * no * nv * NV, s);
-  double *RB = buf(ws, "RB", (size_t)nv * nv * no * NO, s);
+  const RightSizes z = right_sizes(d);
+  double *RA = buf(ws, "RA", (size_t)(z.RA * nb), s) + slot * z.RA;
+  double *RB = buf(ws, "RB", (size_t)(z.RB * nb), s) + slot * z.RB;
   launch_pack_vVoo(R.x2_vVoo, no, nv, NV, 1, RA, s);
   launch_rbar_vvoO(R.x2_vvoO, no, nv, NO, RB, s);
   double *dOO = buf(ws, "dOO", (size_t)nc * NO * NO, s);
@@ -870,7 +947,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
   double *dvO = buf(ws, "dvO", (size_t)nc * nv * NO, s);
   launch_dlhat(g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R.x1, nc, NO, NV, nv, dOO, dvV, dvO, s);
   HIPRT(hipGetLastError());
-  double *U1 = buf(ws, "U1", (size_t)no * NV * d.nv2, s);
+  double *U1 = buf(ws, "U1", (size_t)(z.U1 * nb), s) + slot * z.U1;
   {
     Gemm gg = asm_vVvo(d, U1);
     gg.nseg = 2;
@@ -878,7 +955,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
     gg.seg[1] = asm_vVvo_seg(d, B(ws, "LhvV"), dvO);
     gemm(gg, s);
   }
-  double *Uo = buf(ws, "Uo", (size_t)NO * no * no * nv, s);
+  double *Uo = buf(ws, "Uo", (size_t)(z.Uo * nb), s) + slot * z.Uo;
   {
     Gemm gg = asm_oovo(d, Uo);
     gg.nseg = 2;
@@ -886,9 +963,9 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
     gg.seg[1] = asm_oovo_seg(d, B(ws, "LhOO"), dvO);
     gemm(gg, s);
   }
-  double *Ukc = buf(ws, "Ukc", (size_t)no * nv, s);
+  double *Ukc = buf(ws, "Ukc", (size_t)(z.Ukc * nb), s) + slot * z.Ukc;
   launch_fock_like(g->L_OV, R.x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc, s);
-  double *Xi = buf(ws, "Xi", (size_t)no * no * nv * NO, s);
+  double *Xi = buf(ws, "Xi", (size_t)(z.Xi * nb), s) + slot * z.Xi;
   {
     Gemm gg;
     gg.M = no * no * nv;
@@ -902,32 +979,80 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
   }
 }
 
-// R3 of a prepared right vector: contravariant into Xt, covariant into Xc (optional)
-void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, double omega, Range r, double *Xt, double *Xc,
-              hipStream_t s) {
-  double *W = B(ws, "W");
-  w_dterm(d, W, B(ws, "RA"), B(ws, "G1"), B(ws, "tA"), B(ws, "U1"), s);
+// R3 of the nb prepared right vectors of a group (slots 0..nb-1 of the prep buffers):
+// contravariant into Xt_v = Xt + v*|W|, covariant into Xc (optional)
+void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *R, const double *omega, int nb,
+              Range r, double *Xt, double *Xc, hipStream_t s) {
+  const RightSizes z = right_sizes(d);
+  double *W = buf(ws, "W", (size_t)(d.nord * d.nv3 * nb), s);
+  DSeg sg[2];
+  sg[0].x = B(ws, "RA");
+  sg[0].xv = z.RA;
+  sg[0].G = B(ws, "G1");
+  sg[1].x = B(ws, "tA");
+  sg[1].G = B(ws, "U1");
+  sg[1].Gv = z.U1;
+  w_dterm(d, W, nb, sg, 2, s);
+  std::vector<const double *> rb(nb);
+  for (int v = 0; v < nb; v++) rb[v] = B(ws, "RB") + v * z.RB;
+  long long xv = 0;
+  const double *RBxT = occ_xT(ws, d, rb.data(), nb, "RBxT", &xv, s);
   OccTerm ot;
-  occ_add(ot, d, occ_xT(ws, d, B(ws, "RB"), "RBxT", s), B(ws, "G2"));
-  occ_add(ot, d, B(ws, "t2xT"), B(ws, "Uo"));
-  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, LocalTerms{}, ot, s, Xc);
+  occ_add(ot, d, RBxT, xv, B(ws, "G2"), 0, nb);
+  occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "Uo"), z.Uo, nb);
+  (void)R;
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, LocalTerms{}, ot, s, Xc);
 }
 
-// L3 (transpose-transformation recipe) of a left-type vector into Xt; packs LA/LV under the given names
-void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &L, double omega, Range r,
-              double *Xt, const char *laname, const char *lvname, hipStream_t s) {
+// L3 (transpose-transformation recipe) of nb left-type vectors into Xt_v = Xt + v*|W|; packs
+// LA/LV (stacked, under the given names) and the singles copy "L1s"
+void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *L, const double *omega, int nb,
+              Range r, double *Xt, const char *laname, const char *lvname, hipStream_t s) {
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
-  double *LA = buf(ws, laname, (size_t)no * no * nv * NV, s);
-  double *LV = buf(ws, lvname, (size_t)no * no * d.nv2, s);
-  launch_pack_vVoo(L.x2_vVoo, no, nv, NV, 0, LA, s);
-  launch_pack_vvoo(L.x2_vVoo, no, nv, NV, 0, LV, s);
-  double *W = B(ws, "W");
-  w_dterm(d, W, LA, B(ws, "GL1"), nullptr, nullptr, s);
+  const long long sLA = (long long)no * no * nv * NV, sLV = (long long)no * no * d.nv2, sL1 = (long long)NV * NO;
+  double *LA = buf(ws, laname, (size_t)(sLA * nb), s);
+  double *LV = buf(ws, lvname, (size_t)(sLV * nb), s);
+  double *L1 = buf(ws, "L1s", (size_t)(sL1 * nb), s);
+  std::vector<const double *> lb(nb);
+  for (int v = 0; v < nb; v++) {
+    launch_pack_vVoo(L[v].x2_vVoo, no, nv, NV, 0, LA + v * sLA, s);
+    launch_pack_vvoo(L[v].x2_vVoo, no, nv, NV, 0, LV + v * sLV, s);
+    if (!g_dry)
+      HIPRT(hipMemcpyAsync(L1 + v * sL1, L[v].x1, sizeof(double) * sL1, hipMemcpyDeviceToDevice, s));
+    lb[v] = L[v].x2_vvoO;
+  }
+  double *W = buf(ws, "W", (size_t)(d.nord * d.nv3 * nb), s);
+  DSeg sg;
+  sg.x = LA;
+  sg.xv = sLA;
+  sg.G = B(ws, "GL1");
+  w_dterm(d, W, nb, &sg, 1, s);
+  long long xv = 0;
+  const double *LBxT = occ_xT(ws, d, lb.data(), nb, "LBxT", &xv, s);
   OccTerm ot;
-  occ_add(ot, d, occ_xT(ws, d, L.x2_vvoO, "LBxT", s), B(ws, "Gb3L"));
+  occ_add(ot, d, LBxT, xv, B(ws, "Gb3L"), 0, nb);
   LocalTerms lt;
-  lt.L1 = L.x1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
-  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, r, lt, ot, s);
+  lt.L1 = L1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
+  lt.L1v = sL1;
+  lt.LVv = sLV;
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, lt, ot, s);
+}
+
+// vectors per group: several vectors share one launch of the d-contraction and of the
+// permutation passes; a group holds two ordered-triple buffers (W, X~) per vector, kept within
+// 45% of device memory (environment MLCC3_VEC_BATCH caps the group size)
+int group_size(mlcc3_ws ws, const Dims &d, int nvec) {
+  int cap = kMaxVecBatch;
+  if (const char *e = std::getenv("MLCC3_VEC_BATCH")) cap = std::max(1, std::min(cap, std::atoi(e)));
+  size_t total = (size_t)256 << 30;
+  if (!g_dry) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0) total = tot;
+  }
+  const double per = 2.2 * sizeof(double) * (double)(d.nord * d.nv3) + 1.0;
+  const int fit = (int)std::max(1.0, std::floor(0.45 * (double)total / per));
+  (void)ws;
+  return std::max(1, std::min({nvec, cap, fit}));
 }
 
 // ------------------------------------------------------ density contractions
@@ -1179,31 +1304,39 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
     back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, s);
-    double *W = B(ws, "W");
-    double *XR = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
-    for (int m = 0; m < nvec; m++) {
-      right_vector_prep(ws, g, d, R[m], s);
-      build_R3(ws, g, d, omega[m], r, XR, nullptr, s);
-      double *Ukc = B(ws, "Ukc"), *Xi = B(ws, "Xi");
-      // back-contractions
-      double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
-      double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-      back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, s);
-      {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
-        Gemm gg;
-        gg.M = no * no * nv;
-        gg.N = NV;
-        gg.C = YvV;
-        gg.crow = plain(NV);
-        gg.ccol = plain(1);
-        gg.alpha = -1.0;
-        gg.beta = 1.0;
-        gg.nseg = 1;
-        gg.seg[0] = seg(Xtau, plain(NO), plain(1), 0, R[m].x1, plain(1), plain(NO), 0, NO);
-        gemm(gg, s);
+    // vectors in groups: R3 of a whole group in one d-contraction launch and one launch per
+    // permutation pass, then the back-contractions vector by vector
+    const int ng = group_size(ws, d, nvec);
+    const RightSizes z = right_sizes(d);
+    for (int m0 = 0; m0 < nvec; m0 += ng) {
+      const int nb = std::min(ng, nvec - m0);
+      double *XRg = buf(ws, "XR", (size_t)(d.nord * d.nv3 * nb), s);
+      for (int v = 0; v < nb; v++) right_vector_prep(ws, g, d, R[m0 + v], v, nb, s);
+      build_R3(ws, g, d, R + m0, omega + m0, nb, r, XRg, nullptr, s);
+      for (int v = 0; v < nb; v++) {
+        const int m = m0 + v;
+        double *XR = XRg + v * d.nord * d.nv3;
+        double *Ukc = B(ws, "Ukc") + v * z.Ukc, *Xi = B(ws, "Xi") + v * z.Xi;
+        // back-contractions
+        double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+        double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+        back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, s);
+        {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
+          Gemm gg;
+          gg.M = no * no * nv;
+          gg.N = NV;
+          gg.C = YvV;
+          gg.crow = plain(NV);
+          gg.ccol = plain(1);
+          gg.alpha = -1.0;
+          gg.beta = 1.0;
+          gg.nseg = 1;
+          gg.seg[0] = seg(Xtau, plain(NO), plain(1), 0, R[m].x1, plain(1), plain(NO), 0, NO);
+          gemm(gg, s);
+        }
+        gemm(back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), XT, bm_jkcL(d, Xi), YvO, -1.0), s);
+        finish_right_like(ws, d, XR, XT, Ukc, YvV, YvO, 1, &rho[m], s);
       }
-      gemm(back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), XT, bm_jkcL(d, Xi), YvO, -1.0), s);
-      finish_right_like(ws, d, XR, XT, Ukc, YvV, YvO, 1, &rho[m], s);
     }
   });
 }
@@ -1241,154 +1374,163 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
     back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, s);
-    double *XL = buf(ws, "XR", (size_t)(d.nord * d.nv3), s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
-    for (int m = 0; m < nvec; m++) {
-      const double *L2b = L[m].x2_vvoO;
+    // vectors in groups: L3 of a whole group in one d-contraction launch and one launch per
+    // permutation pass, then the back-contractions vector by vector
+    const int ng = group_size(ws, d, nvec);
+    const long long sLA = (long long)no * no * nv * NV;
+    for (int m0 = 0; m0 < nvec; m0 += ng) {
+      const int nb = std::min(ng, nvec - m0);
+      double *XLg = buf(ws, "XR", (size_t)(d.nord * d.nv3 * nb), s);
       // L3 (SI transpose transformation, exact-transpose index placement):
       //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc + local terms
-      build_L3(ws, g, d, L[m], omega[m], r, XL, "LA", "LV", s);
-      double *LA = B(ws, "LA");
-      // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
-      double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
-      double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-      back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, s);
-      gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
-           s);
-      // intermediates of the singles
-      // Bq[r][(b,c)][E] = sum_{(p,q,a)} L~[p][q][r][a][b][c] t^{aE}_{pq}
-      double *Bq = buf(ws, "Bq", (size_t)no * d.nv2 * NV, s);
-      {
-        TileGemm gg;
-        gg.M = (int)d.nv2;
-        gg.N = NV;
-        gg.nbatch = no;
-        gg.ak = 0;
-        gg.C = Bq;
-        gg.cmap = plain(NV);
-        gg.cbatch = d.nv2 * NV;
-        gg.nseg = 1;
-        gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), NV, 0, no * no * nv);
-        tgemm(gg, s);
-      }
-      // Aq[(q,r,c)][M] = sum L~[p][q][r][a][b][c] t^{ab}_{pM};  Qtau likewise with tau~ and L^{ab}_{pL}
-      double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);
-      double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);
-      back_qrc(ws, d, XL, g->t2_vvoO, Aq, s);
-      back_qrc(ws, d, XT, L2b, Qtau, s);
-      double *V = buf(ws, "Vkc", (size_t)no * nv, s);  // V_kc = sum tau~ L^{ab}_{ij} = sum_q Qtau[q][k][c][q]
-      launch_diag_sum(Qtau, no, nv, NO, V, s);
-      HIPRT(hipGetLastError());
-      double *s1 = sigma[m].x1;
-      HIPRT(hipMemsetAsync(s1, 0, sizeof(double) * NV * NO, s));
-      // (i) sigma^D_L += sum_kc V_kc (2 g_kcLD - g_kDLc) = sum_J [2 s_J L_LD - sum_k L_kD u_J[k][L]]
-      {
-        double *sJ = buf(ws, "vs_J", (size_t)nc, s);
-        double *uJ = buf(ws, "vu_J", (size_t)nc * no * NO, s);
-        // s_J = sum_kc V_kc L^J_kc  (A: [J][(k,c)] from L_OV)
-        Gemm g1 = gemm_plain(nc, 1, sJ, plain(1), plain(1), 1.0, 0.0);
-        g1.nseg = 1;
-        g1.seg[0] = seg(g->L_OV, plain((long long)NO * NV), split(nv, NV, 1), 0, V, plain(1), plain(1), 0, no * nv);
-        gemm(g1, s);
-        // u_J[k][L] = sum_c L_OV[J][L][c] V[k][c]   (rows (J,L))
-        Gemm g3 = gemm_plain(nc * NO, no, uJ, split(NO, (long long)no * NO, 1), plain(NO), 1.0, 0.0);
-        g3.nseg = 1;
-        g3.seg[0] = seg(g->L_OV, plain(NV), plain(1), 0, V, plain(1), plain(nv), 0, nv);
-        gemm(g3, s);
-        // sigma[D][L] += 2 sum_J L_OV[J][L][D] s_J   (rows (L,D))
-        Gemm g4 = gemm_plain(NO * NV, 1, s1, split(NV, 1, NO), plain(0), 2.0, 1.0);
-        g4.nseg = 1;
-        g4.seg[0] = seg(g->L_OV, plain(1), plain((long long)NO * NV), 0, sJ, plain(1), plain(1), 0, nc);
-        gemm(g4, s);
-        // sigma[D][L] -= sum_{(J,k)} L_OV[J][k][D] u_J[k][L]
-        Gemm g5 = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
-        g5.nseg = 1;
-        g5.seg[0] = seg(g->L_OV, plain(1), split(no, (long long)NO * NV, NV), 0, uJ, plain(NO), plain(1), 0, nc * no);
-        gemm(g5, s);
-      }
-      // (ii) sigma^D_L -= sum L^{aD}_{ij} Xtau[(i,j,a)][L] ; (iii) -= sum g_jDkc Qtau[(j,k,c)][L]
-      {
-        Gemm gg = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
-        gg.nseg = 2;
-        gg.seg[0] = seg(LA, plain(1), plain(NV), 0, Xtau, plain(NO), plain(1), 0, no * no * nv);
-        gg.seg[1] = seg(B(ws, "gDo"), plain(1), plain(NV), 0, Qtau, plain(NO), plain(1), 0, no * no * nv);
-        gemm(gg, s);
-      }
-      // (iv) sigma^D_l += sum_{J,c} Lh_cD (Hp - H2)[l][J][c] - sum_{J,M} L_MD H3[l][J][M]
-      double *Hp = buf(ws, "Hp", (size_t)no * nc * nv, s);
-      double *H2 = buf(ws, "H2", (size_t)no * nc * nv, s);
-      double *H3 = buf(ws, "H3", (size_t)no * nc * NO, s);
-      {
-        // Hp[l][J][c] = sum_{(b,E)} Lh_bE Bq[l][b][c][E]
-        Gemm gg = gemm_plain(nc, nv, Hp, plain(nv), plain(1), 1.0, 0.0);
-        gg.nbatch = no;
-        gg.cbatch = (long long)nc * nv;
-        gg.nseg = 1;
-        gg.seg[0] = seg(LhvV, plain((long long)nv * NV), plain(1), 0, Bq, split(NV, (long long)nv * NV, 1), plain(NV),
-                        d.nv2 * NV, nv * NV);
-        gemm(gg, s);
-        // H2[l][J][c] = sum_{(j,M)} Lh_Mj Aq[j][l][c][M]
-        Gemm g2 = gemm_plain(nc, nv, H2, plain(nv), plain(1), 1.0, 0.0);
-        g2.nbatch = no;
-        g2.cbatch = (long long)nc * nv;
-        g2.nseg = 1;
-        g2.seg[0] = seg(LhOO, plain((long long)NO * NO), split(NO, 1, NO), 0, Aq,
-                        split(NO, (long long)no * nv * NO, 1), plain(NO), (long long)nv * NO, no * NO);
-        gemm(g2, s);
-        // H3[l][J][M] = sum_{(k,c)} Lh_ck Aq[l][k][c][M]
-        Gemm g3 = gemm_plain(nc, NO, H3, plain(NO), plain(1), 1.0, 0.0);
-        g3.nbatch = no;
-        g3.cbatch = (long long)nc * NO;
-        g3.nseg = 1;
-        g3.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Aq, plain(NO), plain(1),
-                        (long long)no * nv * NO, no * nv);
-        gemm(g3, s);
-        // sigma[D][l] += sum Lh_cD (Hp - H2)
-        Gemm g4 = gemm_plain(NV, no, s1, plain(NO), plain(1), 1.0, 1.0);
-        g4.nseg = 2;
-        g4.seg[0] = seg(LhvV, plain(1), plain(NV), 0, Hp, plain(1), plain((long long)nc * nv), 0, nc * nv);
-        g4.seg[1] = seg(LhvV, plain(1), plain(NV), 0, H2, plain(1), plain((long long)nc * nv), 0, nc * nv, -1.0);
-        gemm(g4, s);
-        // sigma[D][l] -= sum L_MD H3
-        Gemm g5 = gemm_plain(NV, no, s1, plain(NO), plain(1), -1.0, 1.0);
-        g5.nseg = 1;
-        g5.seg[0] = seg(g->L_OV, plain(1), plain(NV), 0, H3, plain(1), plain((long long)nc * NO), 0, nc * NO);
-        gemm(g5, s);
-      }
-      // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE He[J][d][E]
-      {
-        double *Am = buf(ws, "Am", (size_t)no * nc * no * nv, s);
-        double *Z = buf(ws, "Zl", (size_t)nc * no * nv, s);
-        double *He = buf(ws, "He", (size_t)nc * nv * NV, s);
-        // Am[j][J][(k,d)] = sum_M Lh_Mj Aq[j][k][d][M]
-        Gemm g1 = gemm_plain(nc, no * nv, Am, plain((long long)no * nv), plain(1), 1.0, 0.0);
-        g1.nbatch = no;
-        g1.cbatch = (long long)nc * no * nv;
-        g1.nseg = 1;
-        g1.seg[0] = seg(LhOO, plain((long long)NO * NO), plain(NO), 1, Aq, plain(1), plain(NO), (long long)no * nv * NO,
-                        NO);
-        gemm(g1, s);
-        launch_left_Z(Am, Hp, nc, no, nv, Z, s);
+      build_L3(ws, g, d, L + m0, omega + m0, nb, r, XLg, "LA", "LV", s);
+      for (int v = 0; v < nb; v++) {
+        const int m = m0 + v;
+        const double *L2b = L[m].x2_vvoO;
+        double *XL = XLg + v * d.nord * d.nv3;
+        double *LA = B(ws, "LA") + v * sLA;
+        // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
+        double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+        double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+        back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, s);
+        gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
+             s);
+        // intermediates of the singles
+        // Bq[r][(b,c)][E] = sum_{(p,q,a)} L~[p][q][r][a][b][c] t^{aE}_{pq}
+        double *Bq = buf(ws, "Bq", (size_t)no * d.nv2 * NV, s);
+        {
+          TileGemm gg;
+          gg.M = (int)d.nv2;
+          gg.N = NV;
+          gg.nbatch = no;
+          gg.ak = 0;
+          gg.C = Bq;
+          gg.cmap = plain(NV);
+          gg.cbatch = d.nv2 * NV;
+          gg.nseg = 1;
+          gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), NV, 0, no * no * nv);
+          tgemm(gg, s);
+        }
+        // Aq[(q,r,c)][M] = sum L~[p][q][r][a][b][c] t^{ab}_{pM};  Qtau likewise with tau~ and L^{ab}_{pL}
+        double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);
+        double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);
+        back_qrc(ws, d, XL, g->t2_vvoO, Aq, s);
+        back_qrc(ws, d, XT, L2b, Qtau, s);
+        double *V = buf(ws, "Vkc", (size_t)no * nv, s);  // V_kc = sum tau~ L^{ab}_{ij} = sum_q Qtau[q][k][c][q]
+        launch_diag_sum(Qtau, no, nv, NO, V, s);
         HIPRT(hipGetLastError());
-        // He[J][(d,E)] = sum_{(k,c)} Lh_ck Bq[k][d][c][E]
-        Gemm g2 = gemm_plain(nc, nv * NV, He, plain((long long)nv * NV), plain(1), 1.0, 0.0);
-        g2.nseg = 1;
-        g2.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Bq, split(nv, d.nv2 * NV, NV),
-                        split(NV, (long long)nv * NV, 1), 0, no * nv);
-        gemm(g2, s);
-        // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(J,E)} He[J][d][E] L_LE
-        Gemm g3 = gemm_plain(nv, NO, s1, plain(NO), plain(1), 1.0, 1.0);
-        g3.nseg = 2;
-        g3.seg[0] = seg(Z, plain(1), plain(nv), 0, LhOO, split(no, (long long)NO * NO, 1), plain(NO), 0, nc * no);
-        g3.seg[1] = seg(He, plain(NV), split(NV, (long long)nv * NV, 1), 0, g->L_OV, split(NV, (long long)NO * NV, 1),
-                        plain(NV), 0, nc * NV, -1.0);
-        gemm(g3, s);
+        double *s1 = sigma[m].x1;
+        HIPRT(hipMemsetAsync(s1, 0, sizeof(double) * NV * NO, s));
+        // (i) sigma^D_L += sum_kc V_kc (2 g_kcLD - g_kDLc) = sum_J [2 s_J L_LD - sum_k L_kD u_J[k][L]]
+        {
+          double *sJ = buf(ws, "vs_J", (size_t)nc, s);
+          double *uJ = buf(ws, "vu_J", (size_t)nc * no * NO, s);
+          // s_J = sum_kc V_kc L^J_kc  (A: [J][(k,c)] from L_OV)
+          Gemm g1 = gemm_plain(nc, 1, sJ, plain(1), plain(1), 1.0, 0.0);
+          g1.nseg = 1;
+          g1.seg[0] = seg(g->L_OV, plain((long long)NO * NV), split(nv, NV, 1), 0, V, plain(1), plain(1), 0, no * nv);
+          gemm(g1, s);
+          // u_J[k][L] = sum_c L_OV[J][L][c] V[k][c]   (rows (J,L))
+          Gemm g3 = gemm_plain(nc * NO, no, uJ, split(NO, (long long)no * NO, 1), plain(NO), 1.0, 0.0);
+          g3.nseg = 1;
+          g3.seg[0] = seg(g->L_OV, plain(NV), plain(1), 0, V, plain(1), plain(nv), 0, nv);
+          gemm(g3, s);
+          // sigma[D][L] += 2 sum_J L_OV[J][L][D] s_J   (rows (L,D))
+          Gemm g4 = gemm_plain(NO * NV, 1, s1, split(NV, 1, NO), plain(0), 2.0, 1.0);
+          g4.nseg = 1;
+          g4.seg[0] = seg(g->L_OV, plain(1), plain((long long)NO * NV), 0, sJ, plain(1), plain(1), 0, nc);
+          gemm(g4, s);
+          // sigma[D][L] -= sum_{(J,k)} L_OV[J][k][D] u_J[k][L]
+          Gemm g5 = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
+          g5.nseg = 1;
+          g5.seg[0] = seg(g->L_OV, plain(1), split(no, (long long)NO * NV, NV), 0, uJ, plain(NO), plain(1), 0, nc * no);
+          gemm(g5, s);
+        }
+        // (ii) sigma^D_L -= sum L^{aD}_{ij} Xtau[(i,j,a)][L] ; (iii) -= sum g_jDkc Qtau[(j,k,c)][L]
+        {
+          Gemm gg = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
+          gg.nseg = 2;
+          gg.seg[0] = seg(LA, plain(1), plain(NV), 0, Xtau, plain(NO), plain(1), 0, no * no * nv);
+          gg.seg[1] = seg(B(ws, "gDo"), plain(1), plain(NV), 0, Qtau, plain(NO), plain(1), 0, no * no * nv);
+          gemm(gg, s);
+        }
+        // (iv) sigma^D_l += sum_{J,c} Lh_cD (Hp - H2)[l][J][c] - sum_{J,M} L_MD H3[l][J][M]
+        double *Hp = buf(ws, "Hp", (size_t)no * nc * nv, s);
+        double *H2 = buf(ws, "H2", (size_t)no * nc * nv, s);
+        double *H3 = buf(ws, "H3", (size_t)no * nc * NO, s);
+        {
+          // Hp[l][J][c] = sum_{(b,E)} Lh_bE Bq[l][b][c][E]
+          Gemm gg = gemm_plain(nc, nv, Hp, plain(nv), plain(1), 1.0, 0.0);
+          gg.nbatch = no;
+          gg.cbatch = (long long)nc * nv;
+          gg.nseg = 1;
+          gg.seg[0] = seg(LhvV, plain((long long)nv * NV), plain(1), 0, Bq, split(NV, (long long)nv * NV, 1), plain(NV),
+                          d.nv2 * NV, nv * NV);
+          gemm(gg, s);
+          // H2[l][J][c] = sum_{(j,M)} Lh_Mj Aq[j][l][c][M]
+          Gemm g2 = gemm_plain(nc, nv, H2, plain(nv), plain(1), 1.0, 0.0);
+          g2.nbatch = no;
+          g2.cbatch = (long long)nc * nv;
+          g2.nseg = 1;
+          g2.seg[0] = seg(LhOO, plain((long long)NO * NO), split(NO, 1, NO), 0, Aq,
+                          split(NO, (long long)no * nv * NO, 1), plain(NO), (long long)nv * NO, no * NO);
+          gemm(g2, s);
+          // H3[l][J][M] = sum_{(k,c)} Lh_ck Aq[l][k][c][M]
+          Gemm g3 = gemm_plain(nc, NO, H3, plain(NO), plain(1), 1.0, 0.0);
+          g3.nbatch = no;
+          g3.cbatch = (long long)nc * NO;
+          g3.nseg = 1;
+          g3.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Aq, plain(NO), plain(1),
+                          (long long)no * nv * NO, no * nv);
+          gemm(g3, s);
+          // sigma[D][l] += sum Lh_cD (Hp - H2)
+          Gemm g4 = gemm_plain(NV, no, s1, plain(NO), plain(1), 1.0, 1.0);
+          g4.nseg = 2;
+          g4.seg[0] = seg(LhvV, plain(1), plain(NV), 0, Hp, plain(1), plain((long long)nc * nv), 0, nc * nv);
+          g4.seg[1] = seg(LhvV, plain(1), plain(NV), 0, H2, plain(1), plain((long long)nc * nv), 0, nc * nv, -1.0);
+          gemm(g4, s);
+          // sigma[D][l] -= sum L_MD H3
+          Gemm g5 = gemm_plain(NV, no, s1, plain(NO), plain(1), -1.0, 1.0);
+          g5.nseg = 1;
+          g5.seg[0] = seg(g->L_OV, plain(1), plain(NV), 0, H3, plain(1), plain((long long)nc * NO), 0, nc * NO);
+          gemm(g5, s);
+        }
+        // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE He[J][d][E]
+        {
+          double *Am = buf(ws, "Am", (size_t)no * nc * no * nv, s);
+          double *Z = buf(ws, "Zl", (size_t)nc * no * nv, s);
+          double *He = buf(ws, "He", (size_t)nc * nv * NV, s);
+          // Am[j][J][(k,d)] = sum_M Lh_Mj Aq[j][k][d][M]
+          Gemm g1 = gemm_plain(nc, no * nv, Am, plain((long long)no * nv), plain(1), 1.0, 0.0);
+          g1.nbatch = no;
+          g1.cbatch = (long long)nc * no * nv;
+          g1.nseg = 1;
+          g1.seg[0] = seg(LhOO, plain((long long)NO * NO), plain(NO), 1, Aq, plain(1), plain(NO),
+                          (long long)no * nv * NO, NO);
+          gemm(g1, s);
+          launch_left_Z(Am, Hp, nc, no, nv, Z, s);
+          HIPRT(hipGetLastError());
+          // He[J][(d,E)] = sum_{(k,c)} Lh_ck Bq[k][d][c][E]
+          Gemm g2 = gemm_plain(nc, nv * NV, He, plain((long long)nv * NV), plain(1), 1.0, 0.0);
+          g2.nseg = 1;
+          g2.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Bq, split(nv, d.nv2 * NV, NV),
+                          split(NV, (long long)nv * NV, 1), 0, no * nv);
+          gemm(g2, s);
+          // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(J,E)} He[J][d][E] L_LE
+          Gemm g3 = gemm_plain(nv, NO, s1, plain(NO), plain(1), 1.0, 1.0);
+          g3.nseg = 2;
+          g3.seg[0] = seg(Z, plain(1), plain(nv), 0, LhOO, split(no, (long long)NO * NO, 1), plain(NO), 0, nc * no);
+          g3.seg[1] = seg(He, plain(NV), split(NV, (long long)nv * NV, 1), 0, g->L_OV, split(NV, (long long)NO * NV, 1),
+                          plain(NV), 0, nc * NV, -1.0);
+          gemm(g3, s);
+        }
+        DoublesRaw y;
+        y.YvV = QvV; y.YvO = QvO; y.Yvv = nullptr;
+        y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
+        launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
+        HIPRT(hipGetLastError());
       }
-      DoublesRaw y;
-      y.YvV = QvV; y.YvO = QvO; y.Yvv = nullptr;
-      y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
-      launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
-      HIPRT(hipGetLastError());
     }
   });
 }
@@ -1451,7 +1593,8 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     tau_path(ws, g, d, r, s, XTc);
     double *XT = B(ws, "XT");
     double *XLam = buf(ws, "XLam", nbig, s);
-    build_L3(ws, g, d, *lambda, 0.0, r, XLam, "LAlam", "LVlam", s);   // lambda3: L3 recipe at omega = 0
+    const double zero = 0.0;
+    build_L3(ws, g, d, lambda, &zero, 1, r, XLam, "LAlam", "LVlam", s);   // lambda3: L3 recipe at omega = 0
     double *lam2t = buf(ws, "lam2t", (size_t)no * no * d.nv2, s);
     launch_pack_vvoo(lambda->x2_vVoo, no, nv, NV, 2, lam2t, s);
     double *XL = buf(ws, "XR", nbig, s);
@@ -1467,9 +1610,9 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     double *part = buf(ws, "dot_part", 512, s);
     for (int m = 0; m < nstate; m++) {
       double *Dm = D_m0 + (long long)m * N * N, *D0 = D_0m + (long long)m * N * N;
-      build_L3(ws, g, d, L[m], omega[m], r, XL, "LA", "LV", s);
-      right_vector_prep(ws, g, d, R[m], s);
-      build_R3(ws, g, d, omega[m], r, XRt, XRc, s);
+      build_L3(ws, g, d, L + m, omega + m, 1, r, XL, "LA", "LV", s);
+      right_vector_prep(ws, g, d, R[m], 0, 1, s);
+      build_R3(ws, g, d, R + m, omega + m, 1, r, XRt, XRc, s);
       // ---- D^{m-0} (SI left density) ----
       g_kl(d, XTc, XL, Dm, N, -0.5, 1.0, s);                          // D_kl -= 1/2 L~_{ijl} tau_{ijk}
       g_cd(d, XL, XTc, Dm + NO * N + NO, N, 0.5, 1.0, s);             // D_cd += 1/2 L~^{abc} tau^{abd}

@@ -47,162 +47,167 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
-  const int zz = blockIdx.x / (mt * nt);
-  const int z = zz / g.ksplit, part = zz - z * g.ksplit;
-  int t = blockIdx.x - zz * (mt * nt);
-  const int grp = t / (GM * nt), gbase = grp * GM;
-  const int gsz = min(GM, mt - gbase);
-  t -= grp * GM * nt;
-  const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
-  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const long long ntiles = (long long)mt * nt * g.nbatch * g.nvec * g.ksplit;
+  for (long long L = blockIdx.x; L < ntiles; L += gridDim.x) {
+    const long long zz = L / (mt * nt);
+    const long long zf = zz / g.ksplit;
+    const int part = (int)(zz - zf * g.ksplit);
+    const int vv = (int)(zf / g.nbatch), z = (int)(zf - (long long)vv * g.nbatch);
+    int t = (int)(L - zz * (mt * nt));
+    const int grp = t / (GM * nt), gbase = grp * GM;
+    const int gsz = min(GM, mt - gbase);
+    t -= grp * GM * nt;
+    const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
 
-  d4 acc[4][4];
+    d4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < 4; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // staging: A K-contiguous: rows ar + 32u, k pair 2*akp; A M-contiguous and B: rows (k)
-  // kr + 4u, pair 2*np along m or n
-  const int akp = tid & 7, ar = tid >> 3;
-  const int np = tid & 63, kr = tid >> 6;
-  d2 ra[4], rb[4];
+    // staging: A K-contiguous: rows ar + 32u, k pair 2*akp; A M-contiguous and B: rows (k)
+    // kr + 4u, pair 2*np along m or n
+    const int akp = tid & 7, ar = tid >> 3;
+    const int np = tid & 63, kr = tid >> 6;
+    d2 ra[4], rb[4];
 
-  for (int s = 0; s < g.nseg; s++) {
-    const TgSeg &sg = g.seg[s];
-    // K slice [kb, K) of this part
-    const int chunk = ((sg.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
-    const int kb = part * chunk;
-    const int K = min(sg.K, kb + chunk);
-    if (kb >= K) continue;  // uniform over the workgroup
-    const double *Ap = sg.A + (long long)z * sg.abatch;
-    const double *Bp = sg.B + (long long)z * sg.bbatch;
-    const int nkt = (K - kb + BK - 1) / BK;
-    long long aoff[4];
-    if (AK) {
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int m = m0 + ar + 32 * u;
-        aoff[u] = m < g.M ? moff(sg.amap, m) : -1;
-      }
-    }
-
-    auto load = [&](int kt) {
+    for (int s = 0; s < g.nseg; s++) {
+      const TgSeg &sg = g.seg[s];
+      // K slice [kb, K) of this part
+      const int chunk = ((sg.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+      const int kb = part * chunk;
+      const int K = min(sg.K, kb + chunk);
+      if (kb >= K) continue;  // uniform over the workgroup
+      const double *Ap = sg.A + vv * sg.avec + (long long)z * sg.abatch;
+      const double *Bp = sg.B + vv * sg.bvec + (long long)z * sg.bbatch;
+      const int nkt = (K - kb + BK - 1) / BK;
+      long long aoff[4];
       if (AK) {
-        const int k = kb + kt * BK + 2 * akp;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          d2 v = d2{0.0, 0.0};
-          if (aoff[u] >= 0) {
-            const double *p = Ap + aoff[u] + k;
-            if (VEC && k + 1 < K) {
-              v = *(const d2 *)p;
-            } else {
-              if (k < K) v.x = p[0];
-              if (k + 1 < K) v.y = p[1];
-            }
-          }
-          ra[u] = v;
+          const int m = m0 + ar + 32 * u;
+          aoff[u] = m < g.M ? moff(sg.amap, m) : -1;
         }
-      } else {
-        const int m = m0 + 2 * np;
+      }
+
+      auto load = [&](int kt) {
+        if (AK) {
+          const int k = kb + kt * BK + 2 * akp;
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            d2 v = d2{0.0, 0.0};
+            if (aoff[u] >= 0) {
+              const double *p = Ap + aoff[u] + k;
+              if (VEC && k + 1 < K) {
+                v = *(const d2 *)p;
+              } else {
+                if (k < K) v.x = p[0];
+                if (k + 1 < K) v.y = p[1];
+              }
+            }
+            ra[u] = v;
+          }
+        } else {
+          const int m = m0 + 2 * np;
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int k = kb + kt * BK + kr + 4 * u;
+            d2 v = d2{0.0, 0.0};
+            if (k < K) {
+              const double *p = Ap + moff(sg.amap, k) + m;
+              if (VEC && m + 1 < g.M) {
+                v = *(const d2 *)p;
+              } else {
+                if (m < g.M) v.x = p[0];
+                if (m + 1 < g.M) v.y = p[1];
+              }
+            }
+            ra[u] = v;
+          }
+        }
+        const int n = n0 + 2 * np;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           const int k = kb + kt * BK + kr + 4 * u;
           d2 v = d2{0.0, 0.0};
           if (k < K) {
-            const double *p = Ap + moff(sg.amap, k) + m;
-            if (VEC && m + 1 < g.M) {
+            const double *p = Bp + (long long)k * sg.ldb + n;
+            if (VEC && n + 1 < g.N) {
               v = *(const d2 *)p;
             } else {
-              if (m < g.M) v.x = p[0];
-              if (m + 1 < g.M) v.y = p[1];
+              if (n < g.N) v.x = p[0];
+              if (n + 1 < g.N) v.y = p[1];
             }
           }
-          ra[u] = v;
+          rb[u] = v;
         }
-      }
-      const int n = n0 + 2 * np;
+      };
+      auto store = [&](int buf) {
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int k = kb + kt * BK + kr + 4 * u;
-        d2 v = d2{0.0, 0.0};
-        if (k < K) {
-          const double *p = Bp + (long long)k * sg.ldb + n;
-          if (VEC && n + 1 < g.N) {
-            v = *(const d2 *)p;
+        for (int u = 0; u < 4; u++) {
+          if (AK) {
+            double *pa = &As[buf][(ar + 32 * u) * PA + 2 * akp];
+            pa[0] = ra[u].x;
+            pa[1] = ra[u].y;
           } else {
-            if (n < g.N) v.x = p[0];
-            if (n + 1 < g.N) v.y = p[1];
+            *(d2 *)&As[buf][(kr + 4 * u) * PB + 2 * np] = ra[u];
           }
         }
-        rb[u] = v;
-      }
-    };
-    auto store = [&](int buf) {
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        if (AK) {
-          double *pa = &As[buf][(ar + 32 * u) * PA + 2 * akp];
-          pa[0] = ra[u].x;
-          pa[1] = ra[u].y;
-        } else {
-          *(d2 *)&As[buf][(kr + 4 * u) * PB + 2 * np] = ra[u];
+        for (int u = 0; u < 4; u++) *(d2 *)&Bs[buf][(kr + 4 * u) * PB + 2 * np] = rb[u];
+      };
+
+      __syncthreads();  // the previous segment's readers are done with both buffers
+      load(0);
+      store(0);
+      __syncthreads();
+      for (int kt = 0; kt < nkt; kt++) {
+        const int cur = kt & 1;
+        if (kt + 1 < nkt) load(kt + 1);
+        const double *as = AK ? &As[cur][(wm0 + (lane & 15)) * PA + (lane >> 4)]
+                              : &As[cur][(lane >> 4) * PB + wm0 + (lane & 15)];
+        const double *bs = &Bs[cur][(lane >> 4) * PB + wn0 + (lane & 15)];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          double a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; i++) a[i] = AK ? as[16 * i * PA + kk] : as[kk * PB + 16 * i];
+#pragma unroll
+          for (int j = 0; j < 4; j++) b[j] = bs[kk * PB + 16 * j];
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nkt) store(cur ^ 1);
+        __syncthreads();
+      }
+    }
+
+    // lane l, register v of a 16x16 f64 MFMA tile: row l/16 + 4v, column l%16
+    double *Cp = g.C + vv * g.cvec + (long long)z * g.cbatch + part * g.cpart;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
+        if (m >= g.M) continue;
+        double *crow = Cp + moff(g.cmap, m);
+        double old[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int n = n0 + wn0 + 16 * j + (lane & 15);
+          old[j] = (BETA && n < g.N) ? crow[n] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int n = n0 + wn0 + 16 * j + (lane & 15);
+          if (n < g.N) crow[n] = BETA ? g.alpha * acc[i][j][v] + g.beta * old[j] : g.alpha * acc[i][j][v];
         }
       }
-#pragma unroll
-      for (int u = 0; u < 4; u++) *(d2 *)&Bs[buf][(kr + 4 * u) * PB + 2 * np] = rb[u];
-    };
-
-    __syncthreads();  // the previous segment's readers are done with both buffers
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int kt = 0; kt < nkt; kt++) {
-      const int cur = kt & 1;
-      if (kt + 1 < nkt) load(kt + 1);
-      const double *as = AK ? &As[cur][(wm0 + (lane & 15)) * PA + (lane >> 4)]
-                            : &As[cur][(lane >> 4) * PB + wm0 + (lane & 15)];
-      const double *bs = &Bs[cur][(lane >> 4) * PB + wn0 + (lane & 15)];
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) a[i] = AK ? as[16 * i * PA + kk] : as[kk * PB + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 4; j++) b[j] = bs[kk * PB + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-          for (int j = 0; j < 4; j++)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      if (kt + 1 < nkt) store(cur ^ 1);
-      __syncthreads();
-    }
-  }
-
-  // lane l, register v of a 16x16 f64 MFMA tile: row l/16 + 4v, column l%16
-  double *Cp = g.C + (long long)zz * g.cbatch;
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
-      if (m >= g.M) continue;
-      double *crow = Cp + moff(g.cmap, m);
-      double old[4];
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int n = n0 + wn0 + 16 * j + (lane & 15);
-        old[j] = (BETA && n < g.N) ? crow[n] : 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int n = n0 + wn0 + 16 * j + (lane & 15);
-        if (n < g.N) crow[n] = BETA ? g.alpha * acc[i][j][v] + g.beta * old[j] : g.alpha * acc[i][j][v];
-      }
-    }
+  }  // tiles of a persistent workgroup
 }
 
 template <bool VEC>
@@ -228,12 +233,12 @@ Idx2 branchless(Idx2 f) {
 }  // namespace
 
 long long tile_gemm_blocks(const TileGemm &g) {
-  return (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.ksplit;
+  return (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.nvec * g.ksplit;
 }
 
 hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
   TileGemm g = g0;
-  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g_dry) return hipSuccess;
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g.nvec <= 0 || g_dry) return hipSuccess;
   if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
   if (g.dcontract && !g.ak) return hipErrorInvalidValue;
   if (g.ksplit < 1 || (g.ksplit > 1 && g.beta != 0.0)) return hipErrorInvalidValue;
@@ -244,11 +249,11 @@ hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
   for (int i = 0; i < g.nseg; i++) {
     const TgSeg &sg = g.seg[i];
     vec = vec && even_map(sg.amap) && sg.ldb % 2 == 0 && sg.abatch % 2 == 0 && sg.bbatch % 2 == 0 &&
-          (uintptr_t)sg.A % 16 == 0 && (uintptr_t)sg.B % 16 == 0;
+          sg.avec % 2 == 0 && sg.bvec % 2 == 0 && (uintptr_t)sg.A % 16 == 0 && (uintptr_t)sg.B % 16 == 0;
   }
   for (int i = 0; i < g.nseg; i++) g.seg[i].amap = branchless(g.seg[i].amap);
   g.cmap = branchless(g.cmap);
-  const dim3 grid((unsigned)T), block(256);
+  const dim3 grid((unsigned)(g.persist > 0 && g.persist < T ? g.persist : T)), block(256);
   const bool beta = g.beta != 0.0;
   if (g.dcontract) {
     if (beta) return hipErrorInvalidValue;

@@ -14,9 +14,10 @@ struct UniqueTriple {
 
 // Extra local terms of the left triples (SI L3): L^a_i g_jbkc + L^{ab}_{ij} F_kc.
 struct LocalTerms {
-  const double *L1 = nullptr;   // [N_V][N_O]
+  const double *L1 = nullptr;   // [N_V][N_O]  (vector v at + v*L1v)
   const double *gov = nullptr;  // g_jbkc as [j][k][b][c]
-  const double *LV = nullptr;   // L^{ab}_{ij} as [i][j][a][b]
+  const double *LV = nullptr;   // L^{ab}_{ij} as [i][j][a][b]  (vector v at + v*LVv)
+  long long L1v = 0, LVv = 0;
   const double *F = nullptr;    // F_kc as [k][c]
   int NO = 0;
 };
@@ -28,6 +29,7 @@ struct LocalTerms {
 struct OccTerm {
   const double *x[2] = {nullptr, nullptr};
   const double *G[2] = {nullptr, nullptr};
+  long long xv[2] = {0, 0}, gv[2] = {0, 0};  // per-vector strides (0: shared by all vectors)
   int nseg = 0, NO = 0;
 };
 
@@ -53,11 +55,20 @@ void launch_dot(const double *a, const double *b, long long n, double scale, dou
                 hipStream_t s);
 void launch_add_diag(double *D, int NO, int N, const double *sv, double f, hipStream_t s);
 void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, double f, hipStream_t s);
+// Several trial vectors in one launch: vector v < nvec reads W + v*w, writes Xu + v*xu,
+// Xt + v*xt (Xc likewise) and uses omega[v].
+constexpr int kMaxVecBatch = 32;
+struct VecBatch {
+  int nvec = 1;
+  long long w = 0, xu = 0, xt = 0;
+  double omega[kMaxVecBatch] = {0.0};
+};
+
 // W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
 // (and, if Xc is not NULL, the covariant X to every ordering)
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
-                          int no, int nv, const double *eps_o, const double *eps_v, double omega, long long tb,
-                          long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s);
+                          int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
+                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
 // pairing maps of the doubles blocks (mode 0 symmetrise, 1 gradient -> left vector, 2 left

@@ -238,19 +238,21 @@ __device__ __constant__ double c_coef[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
 
 constexpr int TT = 16;              // sub-cube edge
 
-// Work item of workgroup blockIdx.x in the passes over (unique triple, sub-cube): workgroups
-// are dealt round-robin over the 8 XCDs, so XCD x is given the contiguous range
-// [x*floor(n/8) + min(x, n%8), ...) of the order (triple, T0, T1, T2) with T2 (the unit-stride
-// index c) fastest.  The sub-cubes that share cache lines of a row (rows of n_v doubles are
-// not 128-byte aligned in general) then run on the same XCD at about the same time, and the
-// partial lines they write are merged in its L2.
-__device__ __forceinline__ void pass_item(int nu, int nt, int &tri, int (&T)[3]) {
+// Work item of workgroup blockIdx.x in the passes over (vector, unique triple, sub-cube):
+// workgroups are dealt round-robin over the 8 XCDs, so XCD x is given the contiguous range
+// [x*floor(n/8) + min(x, n%8), ...) of the order (vector, triple, T0, T1, T2) with T2 (the
+// unit-stride index c) fastest.  The sub-cubes that share cache lines of a row (rows of n_v
+// doubles are not 128-byte aligned in general) then run on the same XCD at about the same
+// time, and the partial lines they write are merged in its L2.
+__device__ __forceinline__ void pass_item(int nvec, int nu, int nt, int &vec, int &tri, int (&T)[3]) {
   const int nt3 = nt * nt * nt;
-  const long long n = (long long)nu * nt3, bid = blockIdx.x;
+  const long long n = (long long)nvec * nu * nt3, bid = blockIdx.x;
   const long long x = bid % 8, slot = bid / 8, q = n / 8, rem = n % 8;
   const long long L = x * q + (x < rem ? x : rem) + slot;
-  tri = (int)(L / nt3);
-  const int t = (int)(L - (long long)tri * nt3);
+  const long long vt = L / nt3;
+  vec = (int)(vt / nu);
+  tri = (int)(vt - (long long)vec * nu);
+  const int t = (int)(L - vt * nt3);
   T[0] = t / (nt * nt);
   T[1] = (t / nt) % nt;
   T[2] = t % nt;
@@ -284,8 +286,8 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // takes the x-slices w, w+4, w+8, w+12, each a 16x16 (y,z) tile of v_mfma_f64_16x16x4_f64
 // (operand lane l: A row y = l%16, k = l/16; B k = l/16, column z = l%16; result row
 // l/16 + 4v, column l%16).
-__device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int no, int nv, int p, int q, int r, int X0, int Y0,
-                                              int Z0, double *cube) {
+__device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int vec, int no, int nv, int p, int q, int r, int X0,
+                                              int Y0, int Z0, double *cube) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ly = lane & 15, lk = lane >> 4;
   const int NO = ot.NO;
@@ -299,7 +301,7 @@ __device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int no, int nv,
     acc[0] = d4v{0.0, 0.0, 0.0, 0.0};
     acc[1] = acc[0];
     for (int sg = 0; sg < ot.nseg; sg++) {
-      const double *gb = ot.G[sg] + (long long)(q * no + r) * nv + gz;
+      const double *gb = ot.G[sg] + vec * ot.gv[sg] + (long long)(q * no + r) * nv + gz;
       for (int k0 = 0; k0 < NO; k0 += 4 * KC) {
         double a[2][KC], b[KC];
 #pragma unroll
@@ -310,7 +312,7 @@ __device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int no, int nv,
 #pragma unroll
         for (int e = 0; e < 2; e++) {
           const int gx = X0 + wave + 4 * (h + e);
-          const double *xa = ot.x[sg] + ((long long)p * nv + gx) * NO * nv + gy;
+          const double *xa = ot.x[sg] + vec * ot.xv[sg] + ((long long)p * nv + gx) * NO * nv + gy;
 #pragma unroll
           for (int u = 0; u < KC; u++) {
             const int L = k0 + 4 * u + lk;
@@ -334,12 +336,16 @@ __device__ __forceinline__ int sel3(int a0, int a1, int a2, int i) { return i ==
 
 __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__ W, double *__restrict__ Xu,
                                                       const UniqueTriple *ut, int no, int nv, const double *eps_o,
-                                                      const double *eps_v, double omega, long long tb, long long te,
+                                                      const double *eps_v, VecBatch vb, long long tb, long long te,
                                                       LocalTerms lt, OccTerm ot, int nu) {
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
-  int tri, T[3];
-  pass_item(nu, nt, tri, T);
+  int vec, tri, T[3];
+  pass_item(vb.nvec, nu, nt, vec, tri, T);
+  W += vec * vb.w;
+  Xu += vec * vb.xu;
+  const double omega = vb.omega[vec];
+  const double *L1 = lt.L1 + vec * lt.L1v, *LV = lt.LV + vec * lt.LVv;
   const int T0 = T[0], T1 = T[1], T2 = T[2];
   const UniqueTriple u = ut[tri];
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
       }
       if (ot.nseg > 0) {
         __syncthreads();
-        occ_term_cube(ot, no, nv, p, q, rr, X0, Y0, Z0, cube);
+        occ_term_cube(ot, vec, no, nv, p, q, rr, X0, Y0, Z0, cube);
       }
       __syncthreads();
       // output local index v = (r, lb, lc) reads the source cube at (v_{s0}, v_{s1}, v_{s2})
@@ -378,8 +384,8 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
           const int ga = TT * T0 + r;
           if (ga >= nv || gb >= nv || gc >= nv) continue;
           const int x = sel3(ga, gb, gc, s0), y = sel3(ga, gb, gc, s1), z = sel3(ga, gb, gc, s2);
-          acc[r] += lt.L1[(long long)x * lt.NO + p] * lt.gov[(((long long)q * no + rr) * nv + y) * nv + z] +
-                    lt.LV[(((long long)p * no + q) * nv + x) * nv + y] * lt.F[(long long)rr * nv + z];
+          acc[r] += L1[(long long)x * lt.NO + p] * lt.gov[(((long long)q * no + rr) * nv + y) * nv + z] +
+                    LV[(((long long)p * no + q) * nv + x) * nv + y] * lt.F[(long long)rr * nv + z];
         }
       }
     }
@@ -398,11 +404,14 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
 }
 
 __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, double *__restrict__ Xt,
-                                                        const UniqueTriple *ut, int no, int nv, int covariant, int nu) {
+                                                        const UniqueTriple *ut, int no, int nv, int covariant, int nu,
+                                                        int nvec, long long xuv, long long xtv) {
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
-  int tri, T[3];
-  pass_item(nu, nt, tri, T);
+  int vec, tri, T[3];
+  pass_item(nvec, nu, nt, vec, tri, T);
+  Xu += vec * xuv;
+  Xt += vec * xtv;
   const UniqueTriple u = ut[tri];
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
@@ -724,14 +733,17 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
 }
 
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
-                          int no, int nv, const double *eps_o, const double *eps_v, double omega, long long tb,
-                          long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s) {
-  if (nu <= 0 || nv <= 0 || g_dry) return;
+                          int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
+                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s) {
+  if (nu <= 0 || nv <= 0 || vb.nvec <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
-  const dim3 grid((unsigned)((long long)nu * nt * nt * nt));
-  hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, omega, tb, te, lt, ot, nu);
-  hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xt, ut, no, nv, 0, nu);
-  if (Xc) hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu);
+  LocalTerms l = lt;
+  if (!l.L1) l.L1v = l.LVv = 0;
+  const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
+  hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot, nu);
+  hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xt, ut, no, nv, 0, nu, vb.nvec, vb.xu, vb.xt);
+  if (Xc)
+    hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu, vb.nvec, vb.xu, vb.xt);
 }
 
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,

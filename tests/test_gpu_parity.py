@@ -233,3 +233,27 @@ def test_density_traces_full_config1(lib, ws):
         assert np.all(np.isfinite(A)) and np.all(np.isfinite(B))
         assert abs(np.trace(A)) <= 1e-11 * np.abs(A).max()
         assert abs(np.trace(B) - 2 * d.N_O * float(s[m])) <= 1e-11 * np.abs(B).max()
+
+
+def test_vector_groups_equal_single_calls(lib, ws, monkeypatch):
+    """Several vectors share one persistent d-contraction launch and one launch per permutation
+    pass; groups of 2 (environment cap), of 3 and single calls give identical results."""
+    import torch
+    d = I.Dims(5, 17, 7, 37, 23)
+    p = I.make_problem(d, 12)
+    g = lib.Ground(p)
+    om = [0.41, 0.47, 0.53]
+    R = [lib.vec_to_device(v) for v in I.right_vectors(p, 3)]
+    L = [lib.vec_to_device(v) for v in I.left_vectors(p, 3)]
+    for fn, vecs in ((lib.right_transform, R), (lib.left_transform, L)):
+        for prec in ("fp64", "fp32"):
+            monkeypatch.delenv("MLCC3_VEC_BATCH", raising=False)
+            full = fn(ws, g, om, vecs, precision=prec)
+            monkeypatch.setenv("MLCC3_VEC_BATCH", "2")
+            pairs = fn(ws, g, om, vecs, reuse_ground=True, precision=prec)
+            monkeypatch.delenv("MLCC3_VEC_BATCH", raising=False)
+            singles = [fn(ws, g, [om[m]], [vecs[m]], reuse_ground=True, precision=prec)[0] for m in range(3)]
+            for m in range(3):
+                for k in full[m]:
+                    assert torch.equal(full[m][k], pairs[m][k]), (fn.__name__, prec, m, k)
+                    assert torch.equal(full[m][k], singles[m][k]), (fn.__name__, prec, m, k)
