@@ -48,6 +48,10 @@ def parse():
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
     ap.add_argument("--cpu-triples", type=int, default=48, help="unique triples in the CPU-baseline sample")
+    ap.add_argument("--nv-sweep", action="store_true",
+                    help="instead of the step: time the ground residual, right and left transforms and the "
+                         "densities at a fixed active space (n_o=8, n_v=136) over six inactive-space sizes "
+                         "(N_O/N_V 13/217 .. 38/652), one JSON line per size and one with linear fits in N_V")
     return ap.parse_args()
 
 
@@ -64,6 +68,57 @@ def unit_flops(d, tb, te):
                     n += len({(i, j, k), (j, i, k), (k, j, i), (i, k, j), (k, i, j), (j, k, i)})
                 t += 1
     return 2.0 * d.N_V * d.n_v ** 3 * n
+
+
+def nv_sweep(args):
+    """Time per call at a fixed active space while the inactive space grows (the paper reports
+    timings linear in the number of added water molecules, i.e. in N_V)."""
+    import numpy as np
+    import torch
+    from paper_2202_08612_amd import inputs as I
+    from paper_2202_08612_amd import mlcc3
+    dev = torch.device("cuda", 0)
+    ws = mlcc3.Workspace(0)
+    rows = []
+    for k in range(len(I.SWEEP_NV)):
+        d = I.sweep_dims(k)
+        p = I.make_problem(d, 20220217 + 100 + k, with_density_blocks=True)
+        g = mlcc3.Ground(p, dev)
+        R = [mlcc3.vec_to_device(I.right_vectors(p, 1)[0], dev)]
+        L = [mlcc3.vec_to_device(I.left_vectors(p, 1)[0], dev)]
+        lam = mlcc3.vec_to_device(I.lambda_vector(p), dev)
+        w = 0.4
+        calls = {
+            "ground_residual": lambda: mlcc3.ground_residual(ws, g),
+            "right_transform": lambda: mlcc3.right_transform(ws, g, [w], R, reuse_ground=True),
+            "left_transform": lambda: mlcc3.left_transform(ws, g, [w], L, reuse_ground=True),
+            "densities": lambda: mlcc3.triples_densities(ws, g, [w], L, R, lam, p.t2_vVoO, p.t2_vVOo,
+                                                         reuse_ground=True),
+        }
+        row = {"N_O": d.N_O, "N_V": d.N_V, "n_chol": d.n_chol, "n_o": d.n_o, "n_v": d.n_v}
+        for name, fn in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(max(1, args.steps)):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[name + "_ms"] = round(1e3 * float(np.median(ts)), 3)
+        row["right_gflops"] = round(g.flops(1, 1) / (row["right_transform_ms"] * 1e-3) / 1e9, 1)
+        rows.append(row)
+        print(json.dumps({"nv_sweep": row}), flush=True)
+        del g, p
+    nv = np.array([r["N_V"] for r in rows], dtype=float)
+    fits = {}
+    for name in ("ground_residual", "right_transform", "left_transform", "densities"):
+        t = np.array([r[name + "_ms"] for r in rows])
+        b, a = np.polyfit(nv, t, 1)
+        pred = a + b * nv
+        r2 = 1.0 - float(np.sum((t - pred) ** 2) / np.sum((t - t.mean()) ** 2))
+        fits[name] = {"intercept_ms": round(float(a), 3), "ms_per_virtual": round(float(b), 5), "r2": round(r2, 5)}
+    print(json.dumps({"nv_sweep_linear_fit": fits, "active": "n_o=8 n_v=136", "steps": args.steps}), flush=True)
 
 
 def mixed_report(args, d, flops_step, dt64, outs64, timed, L):
@@ -136,6 +191,9 @@ def main():
               f"(the multi-GPU layout, sharding unique occupied triples, is design only)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.nv_sweep:
+        nv_sweep(args)
+        return
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

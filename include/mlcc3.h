@@ -149,6 +149,23 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
                             const mlcc3_vec *lambda, double *D_m0, double *D_0m, double *s,
                             const mlcc3_opts *opts, void *stream);
 
+/* Transition moments and oscillator strengths from transition densities (Theory section: a
+ * density contracted with a one-electron operator, sum_pq D_pq A_pq; the triples terms of the
+ * densities come from mlcc3_triples_densities, the ground-state density D^{0-0} from the same
+ * call with L = lambda and omega = 0).  For state m and operator component x (e.g. the three
+ * dipole components):
+ *   T_m0[m][x] = sum_pq D_m0[m][p][q] A[x][p][q]
+ *   T_0m[m][x] = sum_pq (D_0m[m][p][q] - s[m] D_00[p][q]) A[x][p][q]
+ *   f[m]       = (2/3) omega[m] sum_x T_0m[m][x] T_m0[m][x]
+ * (the EOM-CC oscillator strength; the paper uses it without printing it).  The caller adds the
+ * CCSD parts of the densities before the call when full moments are wanted.  A [ncomp][N][N],
+ * D_m0 and D_0m [nstate][N][N], D_00 [N][N], s [nstate], outputs T_m0, T_0m [nstate][ncomp]
+ * and f [nstate] are device arrays; omega [nstate] is a host array.  Returns after the stream
+ * has finished the work. */
+int mlcc3_oscillator_strengths(mlcc3_ws ws, int32_t N, int32_t ncomp, const double *A, int32_t nstate,
+                               const double *omega, const double *D_m0, const double *D_0m, const double *D_00,
+                               const double *s, double *T_m0, double *T_0m, double *f, void *stream);
+
 /* Pairing maps of trial vectors, for gradients through the transforms.
  * The left and right vectors are paired by G(L, R) = sum L1 R1 + sum_{(AI)>=(BJ)} L~ R with
  * L~^{AB}_{IJ} = 2 L^{AB}_{IJ} - L^{BA}_{IJ} (the contravariant form of the doubles,

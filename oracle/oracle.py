@@ -121,3 +121,24 @@ class Oracle:
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def oscillator_strengths(A, omega, Dm0, D0m, D00, s):
+    """Transition moments and oscillator strengths of states m (plain definition):
+    T^{m0}_x = sum_pq D^{m-0}_pq A^x_pq (Theory section: densities contracted with a one-electron
+    operator), T^{0m}_x = sum_pq (D^{0-m} - s D^{0-0})_pq A^x_pq (the -s D^{0-0} term the SI right
+    density leaves out), f = (2/3) omega sum_x T^{0m}_x T^{m0}_x (the EOM-CC oscillator strength,
+    used but not printed in the paper).  A [ncomp][N][N], Dm0/D0m [nstate][N][N], D00 [N][N]."""
+    A = np.asarray(A, dtype=np.float64)
+    Dm0 = np.asarray(Dm0, dtype=np.float64)
+    D0m = np.asarray(D0m, dtype=np.float64)
+    nstate, ncomp = Dm0.shape[0], A.shape[0]
+    Tm0 = np.zeros((nstate, ncomp))
+    T0m = np.zeros((nstate, ncomp))
+    f = np.zeros(nstate)
+    for m in range(nstate):
+        for x in range(ncomp):
+            Tm0[m, x] = np.sum(Dm0[m] * A[x])
+            T0m[m, x] = np.sum((D0m[m] - s[m] * D00) * A[x])
+        f[m] = 2.0 / 3.0 * omega[m] * np.sum(T0m[m] * Tm0[m])
+    return Tm0, T0m, f

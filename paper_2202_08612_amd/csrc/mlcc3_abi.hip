@@ -1201,6 +1201,26 @@ int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *
   });
 }
 
+int mlcc3_oscillator_strengths(mlcc3_ws ws, int32_t N, int32_t ncomp, const double *A, int32_t nstate,
+                               const double *omega, const double *D_m0, const double *D_0m, const double *D_00,
+                               const double *s, double *T_m0, double *T_0m, double *f, void *stream) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    check(N >= 1 && ncomp >= 1 && nstate >= 1, "need N, ncomp, nstate >= 1");
+    check(A && omega && D_m0 && D_0m && D_00 && s && T_m0 && T_0m && f, "NULL argument");
+    for (int m = 0; m < nstate; m++) check(std::isfinite(omega[m]), "omega must be finite");
+    t_ws = ws;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceGuard dg(ws->device);
+    double *om = buf(ws, "omega_dev", (size_t)nstate, st);
+    if (!g_dry) HIPRT(hipMemcpyAsync(om, omega, sizeof(double) * nstate, hipMemcpyHostToDevice, st));
+    launch_strengths(A, N, ncomp, nstate, D_m0, D_0m, D_00, s, om, T_m0, T_0m, f, st);
+    HIPRT(hipGetLastError());
+    // the host array omega may be released when the call returns
+    if (!g_dry) HIPRT(hipStreamSynchronize(st));
+  });
+}
+
 int mlcc3_vec_map(mlcc3_ws ws, const mlcc3_ground *g, int32_t mode, int32_t nvec, const mlcc3_vec *in,
                   mlcc3_out *out, void *stream) {
   return guarded([&] {

@@ -54,6 +54,10 @@ void launch_pack_vvoo(const double *x, int no, int nv, int NV, int mode, double 
 void launch_dot(const double *a, const double *b, long long n, double scale, double *part, double *out,
                 hipStream_t s);
 void launch_add_diag(double *D, int NO, int N, const double *sv, double f, hipStream_t s);
+// transition moments and oscillator strengths (om: device omegas)
+void launch_strengths(const double *A, int N, int ncomp, int nstate, const double *Dm0, const double *D0m,
+                      const double *D00, const double *sv, const double *om, double *Tm0, double *T0m, double *f,
+                      hipStream_t s);
 void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, double f, hipStream_t s);
 // Several trial vectors in one launch: vector v < nvec reads W + v*w, writes Xu + v*xu,
 // Xt + v*xt (Xc likewise) and uses omega[v].

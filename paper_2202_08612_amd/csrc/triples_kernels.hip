@@ -207,6 +207,49 @@ __global__ void k_dot_final(const double *part, int np, double scale, double *ou
   out[0] = scale * acc;
 }
 
+// transition moments of state m, component x (one workgroup each, fixed-order reduction):
+//   Tm0[m][x] = sum_pq Dm0[m][p][q] A[x][p][q]
+//   T0m[m][x] = sum_pq (D0m[m][p][q] - s[m] D00[p][q]) A[x][p][q]
+__global__ void k_moments(const double *__restrict__ A, long long NN, int ncomp, const double *__restrict__ Dm0,
+                          const double *__restrict__ D0m, const double *__restrict__ D00, const double *sv,
+                          double *Tm0, double *T0m) {
+  __shared__ double r1[256], r2[256], r3[256];
+  const int x = blockIdx.x, m = blockIdx.y;
+  const double *a = A + (long long)x * NN, *dl = Dm0 + (long long)m * NN, *dr = D0m + (long long)m * NN;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (long long i = threadIdx.x; i < NN; i += blockDim.x) {
+    s1 += dl[i] * a[i];
+    s2 += dr[i] * a[i];
+    s3 += D00[i] * a[i];
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  r3[threadIdx.x] = s3;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+      r3[threadIdx.x] += r3[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Tm0[(long long)m * ncomp + x] = r1[0];
+    T0m[(long long)m * ncomp + x] = r2[0] - sv[m] * r3[0];
+  }
+}
+
+// f[m] = (2/3) omega[m] sum_x T0m[m][x] Tm0[m][x]
+__global__ void k_strength(const double *Tm0, const double *T0m, const double *om, int ncomp, int nstate,
+                           double *f) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nstate) return;
+  double acc = 0.0;
+  for (int x = 0; x < ncomp; x++) acc += T0m[(long long)m * ncomp + x] * Tm0[(long long)m * ncomp + x];
+  f[m] = (2.0 / 3.0) * om[m] * acc;
+}
+
 // D[L][L] += f * s[0] for all L < NO (row stride N)
 __global__ void k_add_diag(double *D, int NO, int N, const double *s, double f) {
   int L = blockIdx.x * blockDim.x + threadIdx.x;
@@ -722,6 +765,15 @@ void launch_dot(const double *a, const double *b, long long n, double scale, dou
   if (g_dry) return;
   hipLaunchKernelGGL(k_dot_partial, dim3(512), dim3(256), 0, s, a, b, n, part);
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, part, 512, scale, out);
+}
+
+void launch_strengths(const double *A, int N, int ncomp, int nstate, const double *Dm0, const double *D0m,
+                      const double *D00, const double *sv, const double *om, double *Tm0, double *T0m, double *f,
+                      hipStream_t s) {
+  if (g_dry || N <= 0 || ncomp <= 0 || nstate <= 0) return;
+  hipLaunchKernelGGL(k_moments, dim3(ncomp, nstate), dim3(256), 0, s, A, (long long)N * N, ncomp, Dm0, D0m, D00, sv,
+                     Tm0, T0m);
+  hipLaunchKernelGGL(k_strength, dim3((nstate + 63) / 64), dim3(64), 0, s, Tm0, T0m, om, ncomp, nstate, f);
 }
 
 void launch_add_diag(double *D, int NO, int N, const double *sv, double f, hipStream_t s) {

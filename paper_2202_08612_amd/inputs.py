@@ -98,6 +98,17 @@ CONFIGS = {
 }
 
 
+# Inactive-space sweep at a fixed active space (n_o = 8, n_v = 136), with the occupied and
+# virtual counts of the formaldehyde + 1..6 water series (Results section, table of system
+# sizes); Cholesky rank 3 (N_O + N_V).
+SWEEP_NV = [(13, 217), (18, 304), (23, 391), (28, 478), (33, 565), (38, 652)]
+
+
+def sweep_dims(k: int) -> Dims:
+    NO, NV = SWEEP_NV[k]
+    return Dims(8, 136, NO, NV, 3 * (NO + NV))
+
+
 def config_seed(cfg: int) -> int:
     return 20220217 + int(cfg)
 

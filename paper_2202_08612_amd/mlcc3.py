@@ -67,6 +67,8 @@ _lib.mlcc3_triples_densities.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground
                                          ctypes.POINTER(_Opts), ctypes.c_void_p]
 _lib.mlcc3_vec_map.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.c_int32, ctypes.c_int32,
                                ctypes.POINTER(_Vec), ctypes.POINTER(_Vec), ctypes.c_void_p]
+_lib.mlcc3_oscillator_strengths.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_int32, _dp] + [ctypes.c_void_p] * 7 + [ctypes.c_void_p]
 _lib.mlcc3_flops.argtypes = [ctypes.POINTER(_Ground), ctypes.c_int32, ctypes.c_int32]
 _lib.mlcc3_flops.restype = ctypes.c_double
 _lib.mlcc3_status_string.argtypes = [ctypes.c_int]
@@ -75,7 +77,7 @@ _lib.mlcc3_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_ws_timing", "mlcc3_ws_phase_stats", "mlcc3_opts_default",
             "mlcc3_num_triples", "mlcc3_ground_residual", "mlcc3_right_transform",
-            "mlcc3_left_transform", "mlcc3_triples_densities", "mlcc3_vec_map", "mlcc3_flops",
+            "mlcc3_left_transform", "mlcc3_triples_densities", "mlcc3_vec_map", "mlcc3_oscillator_strengths", "mlcc3_flops",
             "mlcc3_status_string", "mlcc3_last_error"]
 MAP_SYMMETRIZE, MAP_GRAD_TO_LEFT, MAP_LEFT_TO_GRAD = 0, 1, 2
 
@@ -205,6 +207,24 @@ def _transform(fn, ws, ground, omegas, vecs, outs=None, **kw):
     _check(fn(ws.h, ctypes.byref(ground.c), n, om, _vecs(vecs), _vecs(outs), ctypes.byref(o),
               _stream(ws.device)))
     return outs
+
+
+def oscillator_strengths(ws, A, omegas, D_m0, D_0m, D_00, s):
+    """Transition moments T_m0, T_0m ([nstate][ncomp]) and oscillator strengths f ([nstate]) from
+    densities D_m0, D_0m ([nstate][N][N]), D_00 ([N][N]), s ([nstate]) and operator A ([ncomp][N][N])."""
+    dev = ws.device
+    A = _dev(A, dev)
+    ncomp, N = A.shape[0], A.shape[1]
+    D_m0, D_0m, D_00, sv = _dev(D_m0, dev), _dev(D_0m, dev), _dev(D_00, dev), _dev(s, dev)
+    n = D_m0.shape[0]
+    Tm0 = torch.empty((n, ncomp), dtype=torch.float64, device=dev)
+    T0m = torch.empty((n, ncomp), dtype=torch.float64, device=dev)
+    f = torch.empty((n,), dtype=torch.float64, device=dev)
+    om = (ctypes.c_double * n)(*[float(w) for w in omegas])
+    _check(_lib.mlcc3_oscillator_strengths(ws.h, N, ncomp, A.data_ptr(), n, om, D_m0.data_ptr(), D_0m.data_ptr(),
+                                           D_00.data_ptr(), sv.data_ptr(), Tm0.data_ptr(), T0m.data_ptr(),
+                                           f.data_ptr(), _stream(dev)))
+    return Tm0, T0m, f
 
 
 def vec_map(ws, ground, mode, vecs, outs=None):

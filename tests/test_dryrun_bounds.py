@@ -48,7 +48,7 @@ def _fake(n):
     return [base + (i << 38) for i in range(n)]
 
 
-CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1)]
+CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1), I.sweep_dims(5)]
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])

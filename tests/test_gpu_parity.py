@@ -257,3 +257,31 @@ def test_vector_groups_equal_single_calls(lib, ws, monkeypatch):
                 for k in full[m]:
                     assert torch.equal(full[m][k], pairs[m][k]), (fn.__name__, prec, m, k)
                     assert torch.equal(full[m][k], singles[m][k]), (fn.__name__, prec, m, k)
+
+
+def test_oscillator_strengths(lib, ws):
+    """D^{m-0}, D^{0-m}, s and D^{0-0} (densities with L -> lambda, omega = 0) on the GPU, then the
+    moments and strengths with three symmetric operator components, against the oracle."""
+    from oracle.oracle import Oracle, oscillator_strengths
+    d = I.Dims(4, 6, 5, 11, 13)
+    p = I.make_problem(d, 19, with_density_blocks=True)
+    orc = Oracle(p)
+    g = lib.Ground(p)
+    Ls, Rs, lam = I.left_vectors(p, 2), I.right_vectors(p, 2), I.lambda_vector(p)
+    om = [0.43, 0.61]
+    dv = lambda v: lib.vec_to_device(v)
+    Dm0, D0m, s = lib.triples_densities(ws, g, om, [dv(v) for v in Ls], [dv(v) for v in Rs], dv(lam),
+                                        p.t2_vVoO, p.t2_vVOo)
+    D00 = lib.triples_densities(ws, g, [0.0], [dv(lam)], [dv(Rs[0])], dv(lam), p.t2_vVoO, p.t2_vVOo,
+                                reuse_ground=True)[0][0]
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, d.N, d.N))
+    A = A + A.transpose(0, 2, 1)
+    Tm0, T0m, f = lib.oscillator_strengths(ws, A, om, Dm0, D0m, D00, s)
+    rD = [orc.densities(om[m], Ls[m], Rs[m], lam, p.t2_vVoO, p.t2_vVOo) for m in range(2)]
+    rD00 = orc.densities(0.0, lam, Rs[0], lam, p.t2_vVoO, p.t2_vVOo)[0]
+    eT, eT0, ef = oscillator_strengths(A, om, np.stack([x[0] for x in rD]), np.stack([x[1] for x in rD]), rD00,
+                                       [x[2] for x in rD])
+    for a, b in ((Tm0, eT), (T0m, eT0), (f, ef)):
+        a = a.cpu().numpy()
+        assert rel(a, b) <= 1e-10 and maxrel(a, b) <= 1e-10, (rel(a, b), maxrel(a, b))

@@ -385,3 +385,28 @@ def test_density_inactive_rotation_covariance():
     D0, s0 = b.density_0m(l1, l2, R1, R2, 0.4)
     D1, s1 = b2.density_0m(r1(l1), r2(l2), r1(R1), r2(R2), 0.4)
     assert rel(D1, C.T @ D0 @ C) < 1e-12 and abs(s1 - s0) < 1e-12 * abs(s0)
+
+
+# ------------------------------------------------ transition moments / oscillator strengths
+def test_moment_assembly_pins():
+    """A = identity: T^{m0} = tr D^{m-0} = 0 and T^{0m} = tr D^{0-m} - s tr D^{0-0} = 2 N_O s (the
+    trace identities of the densities; D^{0-0} is D^{m-0} with L -> lambda at omega = 0).
+    A = unit matrix E_rs selects D_rs.  Both pin the assembly's terms and the -s D^{0-0} sign."""
+    from oracle.oracle import oscillator_strengths
+    d = I.Dims(4, 5, 5, 7, 9)
+    p, b = _dens_inputs(d, 4)
+    orc = Oracle(p)
+    lam = I.lambda_vector(p)
+    Dm0, D0m, s = orc.densities(0.5, I.trial_vector(4, d, 64), I.trial_vector(4, d, 0), lam, p.t2_vVoO, p.t2_vVOo)
+    D00 = orc.densities(0.0, lam, I.trial_vector(4, d, 0), lam, p.t2_vVoO, p.t2_vVOo)[0]
+    assert abs(np.trace(D00)) < 1e-14 * np.abs(D00).max() and np.abs(D00).max() > 0
+    N = d.N
+    r, c = 2, N - 3
+    E = np.zeros((N, N))
+    E[r, c] = 1.0
+    A = np.stack([np.eye(N), E])
+    Tm0, T0m, f = oscillator_strengths(A, [0.5], Dm0[None], D0m[None], D00, [s])
+    assert abs(Tm0[0, 0]) < 1e-14 * np.abs(Dm0).sum()
+    assert abs(T0m[0, 0] - 2 * d.N_O * s) < 1e-13 * abs(2 * d.N_O * s)
+    assert Tm0[0, 1] == Dm0[r, c] and abs(T0m[0, 1] - (D0m[r, c] - s * D00[r, c])) < 1e-16
+    assert abs(f[0] - 2.0 / 3.0 * 0.5 * (T0m[0] @ Tm0[0])) < 1e-15
