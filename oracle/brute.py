@@ -97,6 +97,22 @@ class Brute:
         self.g0 = np.einsum("Jpq,Jrs->pqrs", L_full, L_full)         # bare
         self.F = self.fock_ov(t1)
         self.Delta = delta2(NV, NO)
+        self.cvs = None
+
+    def set_cvs(self, core):
+        """Core-valence separation (Implementation section, core excited states): triples
+        without a core occupied index are dropped, and the right and left transforms project
+        their input and output vectors onto the elements with at least one core occupied index."""
+        c = np.asarray(core, dtype=bool)
+        self.cvs = c
+        anycore = (c[:, None, None] | c[None, :, None] | c[None, None, :]).astype(float)
+        self.mask = self.mask * anycore[None, None, None]
+
+    def cvs_project(self, X1, X2):
+        if self.cvs is None:
+            return X1, X2
+        c = self.cvs
+        return X1 * c[None, :], X2 * (c[:, None] | c[None, :])[None, None]
 
     # -- building blocks ----------------------------------------------------
     def embed1(self, x1):
@@ -162,6 +178,12 @@ class Brute:
 
     def right_transform(self, R1, R2, omega):
         """Triples contributions to rho = J R (SI right Jacobian transformation)."""
+        if self.cvs is not None:
+            R1, R2 = self.cvs_project(R1, R2)
+            return self.cvs_project(*self._right(R1, R2, omega))
+        return self._right(R1, R2, omega)
+
+    def _right(self, R1, R2, omega):
         o, v = self.o, self.v
         g = self.g
         tt = tilde3(self.tau3())
@@ -188,6 +210,12 @@ class Brute:
 
     def left_transform(self, L1, L2, omega):
         """Triples contributions to sigma = L^T J (SI transpose Jacobian transformation)."""
+        if self.cvs is not None:
+            L1, L2 = self.cvs_project(L1, L2)
+            return self.cvs_project(*self._left(L1, L2, omega))
+        return self._left(L1, L2, omega)
+
+    def _left(self, L1, L2, omega):
         o, v = self.o, self.v
         g, t2 = self.g, self.t2
         tt = tilde3(self.tau3())

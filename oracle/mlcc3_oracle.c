@@ -477,6 +477,47 @@ static int orderings(const int o[3], int ids[6]) {
   return n;
 }
 
+/* CVS: is the unique triple o skipped (no core occupied index)? */
+static int cvs_skip(const orc_problem *P, const int *o) {
+  if (!P->cvs_core) return 0;
+  return !(P->cvs_core[o[0]] || P->cvs_core[o[1]] || P->cvs_core[o[2]]);
+}
+
+/* CVS projection of a vector in place: singles x1[A][I] keep core I; doubles keep the elements
+ * with a core index among the two occupied ones. */
+static void cvs_project(const orc_problem *P, double *x1, double *x2a, double *x2b) {
+  if (!P->cvs_core) return;
+  const unsigned char *c = P->cvs_core;
+  const int no = P->n_o, nv = P->n_v, NO = P->N_O, NV = P->N_V;
+  for (int A = 0; A < NV; A++)
+    for (int I = 0; I < NO; I++)
+      if (!c[I]) x1[A * NO + I] = 0.0;
+  for (int a = 0; a < nv; a++)
+    for (int D = 0; D < NV; D++)
+      for (int i = 0; i < no; i++)
+        for (int j = 0; j < no; j++)
+          if (!c[i] && !c[j]) x2a[(((size_t)a * NV + D) * no + i) * no + j] = 0.0;
+  for (int a = 0; a < nv; a++)
+    for (int b = 0; b < nv; b++)
+      for (int i = 0; i < no; i++)
+        for (int L = 0; L < NO; L++)
+          if (!c[i] && !c[L]) x2b[(((size_t)a * nv + b) * no + i) * NO + L] = 0.0;
+}
+
+/* projected copies of a CVS input vector (plain copies when CVS is off) */
+static void cvs_copy(const orc_problem *P, const double *x1, const double *x2a, const double *x2b, double **y1,
+                     double **y2a, double **y2b) {
+  const size_t n1 = (size_t)P->N_V * P->N_O, na = (size_t)P->n_v * P->N_V * P->n_o * P->n_o,
+               nb = (size_t)P->n_v * P->n_v * P->n_o * P->N_O;
+  *y1 = (double *)malloc(sizeof(double) * (n1 ? n1 : 1));
+  *y2a = (double *)malloc(sizeof(double) * (na ? na : 1));
+  *y2b = (double *)malloc(sizeof(double) * (nb ? nb : 1));
+  memcpy(*y1, x1, sizeof(double) * n1);
+  if (na) memcpy(*y2a, x2a, sizeof(double) * na);
+  if (nb) memcpy(*y2b, x2b, sizeof(double) * nb);
+  cvs_project(P, *y1, *y2a, *y2b);
+}
+
 static int range_ok(int64_t *tb, int64_t *te, int64_t nt) {
   if (*te < 0 || *te > nt) *te = nt;
   if (*tb < 0) *tb = 0;
@@ -590,6 +631,11 @@ int orc_right_transform(const orc_problem *P, double omega, const double *R1, co
                         double *rho2b) {
   ctx c;
   ctx_init(&c, P);
+  double *R1p, *R2ap, *R2bp;
+  cvs_copy(P, R1, R2a, R2b, &R1p, &R2ap, &R2bp);
+  R1 = R1p;
+  R2a = R2ap;
+  R2b = R2bp;
   rvec rv;
   rvec_init(&c, &rv, R1, R2a, R2b);
   const int no = c.no, nv = c.nv, NO = c.NO, NV = c.NV;
@@ -608,6 +654,7 @@ int orc_right_transform(const orc_problem *P, double omega, const double *R1, co
   sr.kind = 1; sr.omega = omega; sr.rv = &rv;
   for (int64_t t = tb; t < te; t++) {
     const int o[3] = {T[3 * t], T[3 * t + 1], T[3 * t + 2]};
+    if (cvs_skip(P, o)) continue;
     build_block(&c, &st, o, X, Wt);
     contravariant(nv, X, Tt);
     build_block(&c, &sr, o, X, Wt);
@@ -655,8 +702,10 @@ int orc_right_transform(const orc_problem *P, double omega, const double *R1, co
   for (int a = 0; a < nv; a++)
     for (int i = 0; i < no; i++) rho1[a * NO + i] = rho[a * no + i];
   write_doubles(&c, YvV, YvO, 1, rho2a, rho2b);
+  cvs_project(P, rho1, rho2a, rho2b);
   free(T); free(X); free(Rt); free(Tt); free(Ro); free(To); free(Wt); free(rho); free(YvV); free(YvO);
   free(Ytmp); free(Xtau);
+  free(R1p); free(R2ap); free(R2bp);
   rvec_free(&rv);
   ctx_free(&c);
   return 0;
@@ -667,6 +716,11 @@ int orc_left_transform(const orc_problem *P, double omega, const double *L1, con
                        double *sig2b) {
   ctx c;
   ctx_init(&c, P);
+  double *L1p, *L2ap, *L2bp;
+  cvs_copy(P, L1, L2a, L2b, &L1p, &L2ap, &L2bp);
+  L1 = L1p;
+  L2a = L2ap;
+  L2b = L2bp;
   const int no = c.no, nv = c.nv, NO = c.NO, NV = c.NV, nc = c.nc;
   const size_t n3 = (size_t)nv * nv * nv, nv2 = (size_t)nv * nv;
   const double *LOV = P->L_OV;
@@ -697,6 +751,7 @@ int orc_left_transform(const orc_problem *P, double omega, const double *L1, con
   sl.kind = 2; sl.omega = omega; sl.L1 = L1; sl.L2a = L2a; sl.lD = lD; sl.lL = lL;
   for (int64_t t = tb; t < te; t++) {
     const int o[3] = {T[3 * t], T[3 * t + 1], T[3 * t + 2]};
+    if (cvs_skip(P, o)) continue;
     build_block(&c, &st, o, X, Wt);
     contravariant(nv, X, Tt);
     build_block(&c, &sl, o, X, Wt);
@@ -873,6 +928,8 @@ int orc_left_transform(const orc_problem *P, double omega, const double *L1, con
     }
   free(Am); free(Hb); free(He);
   write_doubles(&c, QvV, QvO, 0, sig2a, sig2b);
+  cvs_project(P, sig1, sig2a, sig2b);
+  free(L1p); free(L2ap); free(L2bp);
   free(T); free(lD); free(lL); free(X); free(Lt); free(Tt); free(Lo); free(To); free(Wt);
   free(QvV); free(QvO); free(Bq); free(Aq); free(V); free(Xtau); free(Qtau); free(H); free(H3);
   ctx_free(&c);

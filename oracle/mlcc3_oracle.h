@@ -21,6 +21,11 @@
 typedef struct {
   int n_o, n_v, N_O, N_V, n_chol;
   const double *eps_o, *eps_v, *L_OO, *L_OV, *L_vV, *t1, *t2_vVoo, *t2_vvoO;
+  /* core-valence separation (Implementation section, core excited states): NULL = off, else
+   * N_O flags (nonzero = core orbital).  The right and left transforms then skip the unique
+   * triples whose three occupied indices are all valence, and project their input and output
+   * vectors onto the elements with at least one core occupied index. */
+  const unsigned char *cvs_core;
 } orc_problem;
 
 int orc_num_threads(void);

@@ -31,7 +31,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("n_o", ctypes.c_int), ("n_v", ctypes.c_int), ("N_O", ctypes.c_int),
                 ("N_V", ctypes.c_int), ("n_chol", ctypes.c_int)] + \
                [(k, ctypes.POINTER(ctypes.c_double)) for k in
-                ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")]
+                ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")] + \
+               [("cvs_core", ctypes.POINTER(ctypes.c_ubyte))]
 
 
 def lib():
@@ -58,7 +59,9 @@ def _c(a):
 class Oracle:
     """Holds the problem arrays (kept alive for the C side)."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, cvs_core=None):
+        """cvs_core: None, or N_O flags (nonzero = core orbital) for core-valence separation in
+        the right and left transforms."""
         d = prob.dims
         self.d = d
         self._keep = {k: _c(getattr(prob, k)) for k in
@@ -66,6 +69,10 @@ class Oracle:
         self.P = _Problem(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol,
                           *[_ptr(self._keep[k]) for k in
                             ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vvoO")])
+        if cvs_core is not None:
+            self._core = np.ascontiguousarray(np.asarray(cvs_core) != 0, dtype=np.uint8)
+            assert self._core.size == d.N_O
+            self.P.cvs_core = self._core.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
 
     def _outs(self):
         d = self.d

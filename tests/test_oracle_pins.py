@@ -410,3 +410,52 @@ def test_moment_assembly_pins():
     assert abs(T0m[0, 0] - 2 * d.N_O * s) < 1e-13 * abs(2 * d.N_O * s)
     assert Tm0[0, 1] == Dm0[r, c] and abs(T0m[0, 1] - (D0m[r, c] - s * D00[r, c])) < 1e-16
     assert abs(f[0] - 2.0 / 3.0 * 0.5 * (T0m[0] @ Tm0[0])) < 1e-15
+
+
+# ------------------------------------------------------- core-valence separation (CVS)
+CVS_CASES = [(I.Dims(3, 4, 4, 6, 10), [1, 0, 0, 0]), (I.Dims(4, 3, 5, 6, 9), [0, 1, 0, 1, 0]),
+             (I.Dims(3, 3, 3, 3, 5), [0, 0, 1])]
+
+
+@pytest.mark.parametrize("d,core", CVS_CASES, ids=lambda x: str(x))
+def test_cvs_brute_equals_restricted_loop(d, core):
+    """CVS as a mask on the stored triples tensor (brute force) == the restricted loop that skips
+    all-valence triples; inputs and outputs projected onto elements with a core occupied index."""
+    seed = 303
+    p, b = _brute(d, seed, 5.0, 3.0)
+    b.set_cvs(core)
+    orc = Oracle(p, cvs_core=core)
+    R1, R2 = I.full_vector(seed, d, 0)
+    r1, r2 = b.right_transform(R1, R2, 0.45)
+    ref = {"x1": r1, **blocks2(r2, d.n_o, d.n_v)}
+    assert max(compare_out(orc.right_transform(0.45, I.trial_vector(seed, d, 0)), ref).values()) < 1e-13
+    L1, L2 = I.full_vector(seed, d, 64)
+    s1, s2 = b.left_transform(L1, L2, 0.45)
+    ref = {"x1": s1, **blocks2(s2, d.n_o, d.n_v)}
+    assert max(compare_out(orc.left_transform(0.45, I.trial_vector(seed, d, 64)), ref).values()) < 1e-13
+    # the outputs live in the CVS space
+    c = np.asarray(core, bool)
+    assert np.all(r1[:, ~c] == 0) and np.all(r2[:, :, ~c][:, :, :, ~c] == 0)
+
+
+def test_cvs_reductions_and_adjoint():
+    """All occupied orbitals core: CVS == plain.  No active core orbital: every triple is skipped
+    and the outputs vanish.  The adjoint identity holds inside the CVS space."""
+    d = I.Dims(4, 5, 5, 7, 12)
+    seed = 44
+    p = I.make_problem(d, seed)
+    R = I.trial_vector(seed, d, 0)
+    Lv = I.trial_vector(seed, d, 64)
+    plain, allc = Oracle(p), Oracle(p, cvs_core=[1] * d.N_O)
+    for a, b in ((plain.right_transform(0.4, R), allc.right_transform(0.4, R)),
+                 (plain.left_transform(0.4, Lv), allc.left_transform(0.4, Lv))):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    inactive_core = Oracle(p, cvs_core=[0] * d.n_o + [1] * (d.N_O - d.n_o))
+    for out in (inactive_core.right_transform(0.4, R), inactive_core.left_transform(0.4, Lv)):
+        assert all(np.all(v == 0) for v in out.values())
+    cv = Oracle(p, cvs_core=[0, 1, 0, 0, 0])
+    for w in (0.0, 0.37):
+        lhs = pair_form_blocks(d, Lv, cv.right_transform(w, R))
+        rhs = pair_form_blocks(d, cv.left_transform(w, Lv), R)
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs), (w, lhs, rhs)
