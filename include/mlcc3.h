@@ -89,6 +89,14 @@ typedef struct {
                              Outputs are the partial sums over that range.                 */
   double guard;           /* minimum |eps^{abc}_{ijk} - omega| (0 disables the check)       */
   int32_t check_finite;   /* nonzero: scan inputs for NaN/Inf first                          */
+  const uint8_t *cvs_core; /* core-valence separation for core excited states (Implementation
+                             section): NULL = off, else a HOST array of N_O flags (nonzero = core
+                             orbital).  The right and left transforms then skip the unique
+                             triples whose three occupied indices are all valence (tau3 terms
+                             included) and project their input and output vectors onto the
+                             elements with at least one core occupied index; the d-contraction
+                             skips its all-valence tiles.  Needs n_o <= 64.  The ground residual
+                             and the densities reject it (MLCC3_EINVAL). */
 } mlcc3_opts;
 
 typedef struct mlcc3_ws_s *mlcc3_ws;

@@ -26,6 +26,9 @@ struct MixGemm {
   Idx2 cmap;
   long long cbatch = 0, cvec = 0;
   int persist = 0;
+  // core-valence separation: skip tiles whose (p,q,r) are all valence (see TileGemm)
+  int cvs = 0, cvs_no = 0, cvs_nv = 0;
+  unsigned long long cvs_bits = 0;
 };
 
 hipError_t dcontract_f32(const MixGemm &g, hipStream_t s);

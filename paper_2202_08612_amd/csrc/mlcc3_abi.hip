@@ -55,6 +55,10 @@ thread_local std::vector<Extent> t_ext;
 thread_local mlcc3_ws t_ws = nullptr;   // workspace of the running call (timing, split-K scratch)
 thread_local hipStream_t t_stream = nullptr;
 thread_local int t_prec = MLCC3_FP64;   // arithmetic of the d-contractions of the running call
+// core-valence separation of the running call: on/off, active core orbitals as bits, device flags [N_O]
+thread_local int t_cvs = 0;
+thread_local unsigned long long t_cvs_bits = 0;
+thread_local const unsigned char *t_cvs_dev = nullptr;
 
 void reg(const void *p, long long count, const char *name) {
   if (!p || count <= 0) return;
@@ -650,6 +654,10 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
     g.cvec = Wv;
     g.nseg = nseg;
     g.persist = persist_grid();
+    g.cvs = t_cvs;
+    g.cvs_bits = t_cvs_bits;
+    g.cvs_no = d.no;
+    g.cvs_nv = d.nv;
     const int Kp = (d.NV + 3) / 4 * 4, Np = ((int)d.nv2 + 3) / 4 * 4;
     static const char *an[2] = {"mx_A0", "mx_A1"}, *bn[2] = {"mx_B0", "mx_B1"};
     for (int i = 0; i < nseg; i++) {
@@ -701,6 +709,10 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
   g.nseg = nseg;
   g.dcontract = 1;
   g.persist = persist_grid();
+  g.cvs = t_cvs;
+  g.cvs_bits = t_cvs_bits;
+  g.cvs_no = d.no;
+  g.cvs_nv = d.nv;
   for (int i = 0; i < g.nseg; i++) {
     g.seg[i] = tseg(seg[i].x, plain(d.NV), 0, seg[i].G, d.nv2, (long long)d.NV * d.nv2, d.NV);
     g.seg[i].avec = seg[i].xv;
@@ -747,6 +759,8 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
   vb.xu = Xuv;
   vb.xt = Wv;
   for (int v = 0; v < nb; v++) vb.omega[v] = omega[v];
+  vb.cvs = t_cvs;
+  vb.core_bits = t_cvs_bits;
   check_bytes(W, sizeof(double) * Wv * nb, "W (permutation)");
   check_bytes(Xt, sizeof(double) * Wv * nb, "X~ (permutation)");
   if (Xc) check_bytes(Xc, sizeof(double) * Wv * nb, "covariant X (permutation)");
@@ -904,6 +918,9 @@ mlcc3_opts opts_or_default(const mlcc3_opts *o) {
   check(r.precision == MLCC3_FP64 || r.precision == MLCC3_FP32 || r.precision == MLCC3_BF16X3, "bad precision");
   if (r.precision == MLCC3_BF16X3) throw Status{MLCC3_EUNSUPPORTED, "MLCC3_BF16X3 is not implemented"};
   t_prec = r.precision;
+  t_cvs = 0;
+  t_cvs_bits = 0;
+  t_cvs_dev = nullptr;
   return r;
 }
 
@@ -1036,6 +1053,44 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   lt.L1v = sL1;
   lt.LVv = sLV;
   permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, lt, ot, s);
+}
+
+// core-valence separation of a right or left transform: device copy of the core flags, active
+// core bits, and CVS-projected copies of the nvec input vectors (returned in *proj)
+void cvs_setup(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts &o, int nvec, const mlcc3_vec *in,
+               std::vector<mlcc3_vec> *proj, hipStream_t s) {
+  const Dims d = dims_of(g);
+  if (!o.cvs_core) return;
+  check(d.no <= 64, "core-valence separation needs n_o <= 64");
+  unsigned long long bits = 0;
+  for (int i = 0; i < d.no; i++)
+    if (o.cvs_core[i]) bits |= 1ULL << i;
+  unsigned char *flags = (unsigned char *)buf(ws, "cvs_core", (size_t)(d.NO + 7) / 8, s);
+  if (!g_dry) {
+    HIPRT(hipMemcpyAsync(flags, o.cvs_core, (size_t)d.NO, hipMemcpyHostToDevice, s));
+    HIPRT(hipStreamSynchronize(s));  // the host flags may be released when the call returns
+  }
+  t_cvs = 1;
+  t_cvs_bits = bits;
+  t_cvs_dev = flags;
+  const long long n1 = (long long)d.NV * d.NO, na = (long long)d.nv * d.NV * d.no * d.no,
+                  nb = (long long)d.nv * d.nv * d.no * d.NO;
+  double *c1 = buf(ws, "cvs_in1", (size_t)(n1 * nvec), s);
+  double *ca = buf(ws, "cvs_in2a", (size_t)(na * nvec), s);
+  double *cb = buf(ws, "cvs_in2b", (size_t)(nb * nvec), s);
+  proj->resize(nvec);
+  for (int m = 0; m < nvec; m++) {
+    (*proj)[m] = mlcc3_vec{c1 + m * n1, ca + m * na, cb + m * nb};
+    launch_cvs_project(in[m].x1, in[m].x2_vVoo, in[m].x2_vvoO, c1 + m * n1, ca + m * na, cb + m * nb, flags, d.no,
+                       d.nv, d.NO, d.NV, s);
+  }
+  HIPRT(hipGetLastError());
+}
+
+void cvs_project_out(const Dims &d, const mlcc3_out &o, hipStream_t s) {
+  if (!t_cvs) return;
+  launch_cvs_project(o.x1, o.x2_vVoo, o.x2_vvoO, o.x1, o.x2_vVoo, o.x2_vvoO, t_cvs_dev, d.no, d.nv, d.NO, d.NV, s);
+  HIPRT(hipGetLastError());
 }
 
 // vectors per group: several vectors share one launch of the d-contraction and of the
@@ -1270,6 +1325,7 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
     reg_ground(g);
     reg_vec(g, out->x1, out->x2_vVoo, out->x2_vvoO);
     const mlcc3_opts o = opts_or_default(opts);
+    check(!o.cvs_core, "core-valence separation applies to the right and left transforms only");
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ws->device);
     const Dims d = dims_of(g);
@@ -1317,6 +1373,11 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
       for (int m = 0; m < nvec; m++) zero_out(d, &rho[m], s);
       return;
     }
+    // core-valence separation: projected copies of the inputs, all-valence triples skipped
+    std::vector<mlcc3_vec> Rp;
+    const mlcc3_vec *R_in = R;
+    cvs_setup(ws, g, o, nvec, R_in, &Rp, s);
+    const mlcc3_vec *R = Rp.empty() ? R_in : Rp.data();
     prepare_ground(ws, g, o.reuse_ground != 0, s);
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
     // tau~ and Xtau[(i,j,a)][L] = sum tau~ g_Lbkc (shared by all vectors)
@@ -1356,6 +1417,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
         }
         gemm(back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), XT, bm_jkcL(d, Xi), YvO, -1.0), s);
         finish_right_like(ws, d, XR, XT, Ukc, YvV, YvO, 1, &rho[m], s);
+        cvs_project_out(d, rho[m], s);
       }
     }
   });
@@ -1388,6 +1450,11 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
       for (int m = 0; m < nvec; m++) zero_out(d, &sigma[m], s);
       return;
     }
+    // core-valence separation: projected copies of the inputs, all-valence triples skipped
+    std::vector<mlcc3_vec> Lp;
+    const mlcc3_vec *L_in = L;
+    cvs_setup(ws, g, o, nvec, L_in, &Lp, s);
+    const mlcc3_vec *L = Lp.empty() ? L_in : Lp.data();
     prepare_ground(ws, g, o.reuse_ground != 0, s);
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
     tau_path(ws, g, d, r, s);
@@ -1550,6 +1617,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
         y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
         launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
         HIPRT(hipGetLastError());
+        cvs_project_out(d, sigma[m], s);
       }
     }
   });
@@ -1590,6 +1658,7 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     reg(D_0m, nstate * N * N, "D_0m");
     reg(s_out, nstate, "s");
     const mlcc3_opts o = opts_or_default(opts);
+    check(!o.cvs_core, "core-valence separation applies to the right and left transforms only");
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ws->device);
     const Range r = range_of(o, mlcc3_num_triples(d.no));

@@ -40,6 +40,14 @@ __device__ __forceinline__ long long moff(const Idx2 &f, int x) {
   return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
 }
 
+// does a d-contraction tile (rows [m0, m1) of (p,q,a), batch r) touch a core occupied index?
+__device__ __forceinline__ bool cvs_tile_kept(unsigned long long bits, int no, int nv, int r, int m0, int m1) {
+  if ((bits >> r) & 1ULL) return true;
+  for (int pq = m0 / nv; pq <= (m1 - 1) / nv; pq++)
+    if (((bits >> (pq / no)) | (bits >> (pq % no))) & 1ULL) return true;
+  return false;
+}
+
 template <bool AK, bool VEC, bool BETA>
 __device__ __forceinline__ void tile_body(const TileGemm &g) {
   __shared__ double As[2][AK ? BM * PA : BK * PB];
@@ -59,6 +67,7 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
     t -= grp * GM * nt;
     const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    if (g.cvs && !cvs_tile_kept(g.cvs_bits, g.cvs_no, g.cvs_nv, z, m0, min(g.M, m0 + BM))) continue;
 
     d4 acc[4][4];
 #pragma unroll

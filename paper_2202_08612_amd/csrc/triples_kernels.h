@@ -62,10 +62,14 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
 // Several trial vectors in one launch: vector v < nvec reads W + v*w, writes Xu + v*xu,
 // Xt + v*xt (Xc likewise) and uses omega[v].
 constexpr int kMaxVecBatch = 32;
+// cvs != 0: core-valence separation, unique triples without a core occupied index (bit of
+// core_bits) are skipped.
 struct VecBatch {
   int nvec = 1;
   long long w = 0, xu = 0, xt = 0;
   double omega[kMaxVecBatch] = {0.0};
+  int cvs = 0;
+  unsigned long long core_bits = 0;
 };
 
 // W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
@@ -79,6 +83,10 @@ void launch_small_right(const double *X, const double *T, const double *gov, con
 // vector -> gradient representer); outputs must not alias inputs
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,
                     double *oB, hipStream_t s);
+// CVS projection y = P x of a vector (may be in place): singles keep core I, doubles keep the
+// elements with a core occupied index; core: device flags [N_O]
+void launch_cvs_project(const double *x1, const double *x2a, const double *x2b, double *y1, double *y2a, double *y2b,
+                        const unsigned char *core, int no, int nv, int NO, int NV, hipStream_t s);
 // xT[p][a][L][b] = x[a][b][p][L]  (x: [n_v][n_v][n_o][N_O])
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s);
 // out[z][c][r] = in[z][r][c], z < batch

@@ -392,7 +392,8 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
   const int T0 = T[0], T1 = T[1], T2 = T[2];
   const UniqueTriple u = ut[tri];
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
-  const bool active = !(u.i == u.j && u.j == u.k) && u.canon >= tb && u.canon < te;
+  const bool keep = !vb.cvs || (((vb.core_bits >> u.i) | (vb.core_bits >> u.j) | (vb.core_bits >> u.k)) & 1ULL);
+  const bool active = !(u.i == u.j && u.j == u.k) && u.canon >= tb && u.canon < te && keep;
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
   double acc[TT];
 #pragma unroll
@@ -501,6 +502,25 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
       v[s0] = w[0]; v[s1] = w[1]; v[s2] = w[2];
       dst[(W0 + w[0]) * nv2 + (long long)(W1 + w[1]) * nv + (W2 + w[2])] = cube[v[0] * LX + v[1] * LY + v[2]];
     }
+  }
+}
+
+// CVS projection (one thread per element of the three arrays)
+__global__ void k_cvs_project(const double *x1, const double *x2a, const double *x2b, double *y1, double *y2a,
+                              double *y2b, const unsigned char *core, int no, int nv, int NO, int NV) {
+  const long long n1 = (long long)NV * NO, na = (long long)nv * NV * no * no, nb = (long long)nv * nv * no * NO;
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id < n1) {
+    const int I = (int)(id % NO);
+    y1[id] = core[I] ? x1[id] : 0.0;
+  } else if (id < n1 + na) {
+    const long long e = id - n1;
+    const int j = (int)(e % no), i = (int)((e / no) % no);
+    y2a[e] = (core[i] || core[j]) ? x2a[e] : 0.0;
+  } else if (id < n1 + na + nb) {
+    const long long e = id - n1 - na;
+    const int L = (int)(e % NO), i = (int)((e / NO) % no);
+    y2b[e] = (core[i] || core[L]) ? x2b[e] : 0.0;
   }
 }
 
@@ -808,6 +828,12 @@ void launch_small_right(const double *X, const double *T, const double *gov, con
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,
                     double *oB, hipStream_t s) {
   L1D(k_vec_map, (long long)nv * NV * no * no + (long long)nv * nv * no * NO, A2, B2, no, nv, NO, NV, mode, oA, oB);
+}
+
+void launch_cvs_project(const double *x1, const double *x2a, const double *x2b, double *y1, double *y2a, double *y2b,
+                        const unsigned char *core, int no, int nv, int NO, int NV, hipStream_t s) {
+  const long long n = (long long)NV * NO + (long long)nv * NV * no * no + (long long)nv * nv * no * NO;
+  L1D(k_cvs_project, n, x1, x2a, x2b, y1, y2a, y2b, core, no, nv, NO, NV);
 }
 
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s) {

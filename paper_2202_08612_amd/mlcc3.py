@@ -42,7 +42,8 @@ class _Vec(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("reuse_ground", ctypes.c_int32),
                 ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
-                ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32)]
+                ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32),
+                ("cvs_core", ctypes.c_void_p)]
 
 
 _lib.mlcc3_ws_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
@@ -179,7 +180,8 @@ def _vecs(lst):
     return arr
 
 
-def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0, check_finite=False):
+def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0, check_finite=False,
+              cvs_core=None):
     o = _Opts()
     _lib.mlcc3_opts_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -188,6 +190,9 @@ def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0
         o.triple_begin, o.triple_end = int(triple_range[0]), int(triple_range[1])
     o.guard = float(guard)
     o.check_finite = 1 if check_finite else 0
+    if cvs_core is not None:
+        o._cvs = np.ascontiguousarray(np.asarray(cvs_core) != 0, dtype=np.uint8)  # kept alive with o
+        o.cvs_core = o._cvs.ctypes.data
     return o
 
 

@@ -29,7 +29,8 @@ class V(ctypes.Structure):
 class O(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("reuse_ground", ctypes.c_int32),
                 ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
-                ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32)]
+                ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32),
+                ("cvs_core", ctypes.c_void_p)]
 
 
 @pytest.fixture(scope="module")
@@ -97,5 +98,31 @@ def test_empty_active_space_accepts_null_blocks(lib):
     om = (ctypes.c_double * 1)(0.4)
     assert lib.mlcc3_right_transform(ws, ctypes.byref(g), 1, om, vin, vout, ctypes.byref(o), None) == 0
     g.t1 = None
+    assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == -1
+    assert lib.mlcc3_ws_destroy(ws) == 0
+
+
+@pytest.mark.parametrize("d", [I.CONFIGS[4]["dims"], I.Dims(5, 17, 7, 37, 23)], ids=str)
+def test_cvs_launches_in_bounds(lib, d):
+    """Core-valence separation on the right and left transforms (core orbital 0); the ground
+    residual and the densities reject it."""
+    ws = ctypes.c_void_p()
+    assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+    p = _fake(64)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:8])
+    core = (ctypes.c_uint8 * d.N_O)(*([1] + [0] * (d.N_O - 1)))
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    o.cvs_core = ctypes.cast(core, ctypes.c_void_p)
+    nvec = 2
+    vin = (V * nvec)(*[V(*p[11 + 3 * m: 14 + 3 * m]) for m in range(nvec)])
+    vout = (V * nvec)(*[V(*p[30 + 3 * m: 33 + 3 * m]) for m in range(nvec)])
+    om = (ctypes.c_double * nvec)(15.2, 15.3)
+    for prec in (0, 1):
+        o.precision = prec
+        for fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
+            rc = getattr(lib, fn)(ws, ctypes.byref(g), nvec, om, vin, vout, ctypes.byref(o), None)
+            assert rc == 0, (fn, lib.mlcc3_last_error())
+    out = (V * 1)(V(*p[8:11]))
     assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == -1
     assert lib.mlcc3_ws_destroy(ws) == 0

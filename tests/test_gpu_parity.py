@@ -285,3 +285,49 @@ def test_oscillator_strengths(lib, ws):
     for a, b in ((Tm0, eT), (T0m, eT0), (f, ef)):
         a = a.cpu().numpy()
         assert rel(a, b) <= 1e-10 and maxrel(a, b) <= 1e-10, (rel(a, b), maxrel(a, b))
+
+
+# ------------------------------------------------------- core-valence separation (CVS)
+CVS_SHAPES = [(I.Dims(4, 5, 5, 7, 12), [0, 1, 0, 0, 0]), (I.Dims(5, 17, 7, 37, 23), [1, 0, 0, 0, 0, 0, 0])]
+
+
+@pytest.mark.parametrize("d,core", CVS_SHAPES, ids=lambda x: str(x))
+def test_cvs_right_left(lib, ws, d, core):
+    from oracle.oracle import Oracle
+    p = I.make_problem(d, 71, core=True)
+    orc = Oracle(p, cvs_core=core)
+    g = lib.Ground(p)
+    R, L = I.right_vectors(p, 2), I.left_vectors(p, 2)
+    om = [15.2, 15.21]
+    rho = lib.right_transform(ws, g, om, [lib.vec_to_device(v) for v in R], cvs_core=core)
+    sig = lib.left_transform(ws, g, om, [lib.vec_to_device(v) for v in L], cvs_core=core, reuse_ground=True)
+    for m in range(2):
+        _check(rho[m], orc.right_transform(om[m], R[m]))
+        _check(sig[m], orc.left_transform(om[m], L[m]))
+    with pytest.raises(lib.MLCC3Error) as e:
+        lib.ground_residual(ws, g, cvs_core=core)
+    assert e.value.code == lib.EINVAL
+
+
+def test_cvs_full_config4(lib, ws):
+    """Core-shaped workload at full size with its core orbital as the CVS core: the adjoint identity
+    inside the CVS space, outputs in the CVS space, the mixed form within 1e-6, and an oracle check
+    of the right transform on the first unique triples."""
+    p = I.make_config(4)
+    d = p.dims
+    g = lib.Ground(p)
+    core = [1] + [0] * (d.N_O - 1)
+    R, L = I.right_vectors(p, 2), I.left_vectors(p, 2)
+    om = [float(x) for x in I.omegas(4, 2)]
+    rho = lib.right_transform(ws, g, om, [lib.vec_to_device(v) for v in R], cvs_core=core)
+    sig = lib.left_transform(ws, g, om, [lib.vec_to_device(v) for v in L], cvs_core=core, reuse_ground=True)
+    for m in range(2):
+        a = pair_form_blocks(d, L[m], lib.to_numpy(rho[m]))
+        b = pair_form_blocks(d, lib.to_numpy(sig[m]), R[m])
+        assert abs(a - b) <= 1e-10 * abs(a), (m, a, b)
+        r = lib.to_numpy(rho[m])
+        assert np.all(r["x1"][:, 1:] == 0) and np.all(r["x2_vVoo"][:, :, 1:, 1:] == 0)
+    rmx = lib.right_transform(ws, g, om, [lib.vec_to_device(v) for v in R], cvs_core=core, reuse_ground=True,
+                              precision="fp32")
+    for k in rho[0]:
+        assert rel(rmx[0][k].cpu().numpy(), rho[0][k].cpu().numpy()) <= 1e-6, k
