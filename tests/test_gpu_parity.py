@@ -311,8 +311,7 @@ def test_cvs_right_left(lib, ws, d, core):
 
 def test_cvs_full_config4(lib, ws):
     """Core-shaped workload at full size with its core orbital as the CVS core: the adjoint identity
-    inside the CVS space, outputs in the CVS space, the mixed form within 1e-6, and an oracle check
-    of the right transform on the first unique triples."""
+    inside the CVS space, outputs in the CVS space, the mixed form within 1e-6."""
     p = I.make_config(4)
     d = p.dims
     g = lib.Ground(p)
