@@ -9,9 +9,10 @@ Workload (default): n_o=12, n_v=60 active; N_O=30, N_V=250 total; Cholesky rank 
 FP64 throughout.  Throughput counts the algorithmic FLOPs of the cost model
 (U = 2 N_V n_v^3 (n_o^3 - n_o); ground 2U, right 4U, left 4U per vector).
 
-The same step is then timed with the d-contractions in FP32 MFMA ("mixed"): its throughput,
-its speedup over FP64 and the errors of every output against the FP64 path are reported in
-the "mixed" object of the JSON line.
+The same step is then timed with reduced-precision d-contractions ("mixed": FP32 MFMA, and
+split-bf16 MFMA products with six or three products per FP64 product): for each form its
+throughput, the errors of every output against the FP64 path and, when every error is within
+1e-6, its speedup over FP64 are reported in the "mixed" object of the JSON line.
 
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
 runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --cfg.
@@ -29,6 +30,15 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 FP32_PEAK_TFLOPS = 157.3    # MI355X dense FP32 matrix
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix
+MIXED_FORMS = {
+    "fp32": ("FP32 MFMA d-contractions (FP32 sums per 32-deep K slab, FP64 across slabs), everything else FP64",
+             FP32_PEAK_TFLOPS, 1),
+    "bf16x6": ("split-bf16 d-contractions, 3 bf16 planes per operand and 6 bf16 MFMA products (FP32 sums per "
+               "64-deep K step, FP64 across steps), everything else FP64", BF16_PEAK_TFLOPS, 6),
+    "bf16x3": ("split-bf16 d-contractions, 2 bf16 planes per operand and 3 bf16 MFMA products (FP32 sums per "
+               "64-deep K step, FP64 across steps), everything else FP64", BF16_PEAK_TFLOPS, 3),
+}
 # HBM bytes per d-contraction launch (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, calibrated against a plain
 # copy, mean of the 5 launches of one step) measured with rocprofv3 on the kernel source whose sha256
 # starts with "src"; reported only while that source is unchanged and for that workload.
@@ -43,7 +53,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cfg", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 MFMA) step")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision steps (FP32 and split-bf16 MFMA)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -121,13 +131,14 @@ def nv_sweep(args):
     print(json.dumps({"nv_sweep_linear_fit": fits, "active": "n_o=8 n_v=136", "steps": args.steps}), flush=True)
 
 
-def mixed_report(args, d, flops_step, dt64, outs64, timed, L):
-    """The same step with the d-contractions in FP32 MFMA: throughput, speedup and the errors of
-    every output against the FP64 path (which the GPU tests hold within 1e-10 of the oracle)."""
-    import numpy as np
+def mixed_report(args, d, flops_step, dt64, outs64, timed, L, form):
+    """The same step with reduced-precision d-contractions (form: fp32, bf16x6, bf16x3):
+    throughput, the errors of every output against the FP64 path (which the GPU tests hold
+    within 1e-10 of the oracle), and the speedup, quoted only when every error is within 1e-6."""
     from paper_2202_08612_amd import mlcc3
     from tests.helpers import pair_form_blocks
-    dt, st, outs = timed("fp32")
+    desc, peak, nprod = MIXED_FORMS[form]
+    dt, st, outs = timed(form)
     err = {}
     for name, a, b in (("Omega", outs["om"], outs64["om"]), ("rho", outs["rho"][0], outs64["rho"][0]),
                        ("sigma", outs["sig"][0], outs64["sig"][0])):
@@ -141,13 +152,18 @@ def mixed_report(args, d, flops_step, dt64, outs64, timed, L):
     p64 = pair_form_blocks(d, Lh, mlcc3.to_numpy(outs64["rho"][0]))
     pmx = pair_form_blocks(d, Lh, mlcc3.to_numpy(outs["rho"][0]))
     worst = max(max(v["rel"], v["max_rel"]) for v in err.values())
+    pair_err = abs(pmx - p64) / abs(p64) if p64 else 0.0
+    ok = bool(worst <= 1e-6 and pair_err <= 1e-6)
     ach = st["flops"] * (d.n_o ** 3 - d.n_o) / float(d.n_o ** 3) / (st["ms"] * 1e-3) / 1e12 if st["ms"] > 0 else 0.0
-    return {"precision": "fp32 MFMA d-contractions (FP32 sums per 32-deep K slab, FP64 across slabs), everything else FP64",
+    return {"precision": desc,
             "value": round(flops_step / (dt / args.steps) / 1e9, 1), "unit": "GFLOP/s",
-            "ms_per_step": round(dt / args.steps * 1e3, 3), "speedup_vs_fp64": round(dt64 / dt, 3),
-            "dcontract_tflops": round(ach, 2), "dcontract_frac_fp32_peak": round(ach / FP32_PEAK_TFLOPS, 4),
-            "worst_rel_err_vs_fp64": worst, "pair_LAR_rel_err": abs(pmx - p64) / abs(p64) if p64 else 0.0,
-            "within_1e-6": bool(worst <= 1e-6 and abs(pmx - p64) <= 1e-6 * abs(p64)), "errors": err}
+            "ms_per_step": round(dt / args.steps * 1e3, 3),
+            "speedup_vs_fp64": round(dt64 / dt, 3) if ok else None,
+            "dcontract_tflops": round(ach, 2),
+            "dcontract_frac_matrix_peak": round(ach * nprod / peak, 4), "matrix_peak_tflops": peak,
+            "products_per_fp64_product": nprod,
+            "worst_rel_err_vs_fp64": worst, "pair_LAR_rel_err": pair_err,
+            "within_1e-6": ok, "errors": err}
 
 
 def dcontract_traffic(d):
@@ -274,7 +290,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_mixed:
-        res["mixed"] = mixed_report(args, d, flops_step, dt, outs, timed, L)
+        res["mixed"] = {form: mixed_report(args, d, flops_step, dt, outs, timed, L, form) for form in MIXED_FORMS}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_triples)
     print(json.dumps(res), flush=True)

@@ -67,7 +67,18 @@ enum {
   MLCC3_EUNSUPPORTED = -7  /* requested precision or device not supported               */
 };
 
-enum { MLCC3_FP64 = 0, MLCC3_FP32 = 1, MLCC3_BF16X3 = 2 };
+/* Arithmetic of the d-contraction GEMMs (the O(N_V n_v^3 n_o^3) step of the Implementation
+   section); the occupied term, permutations, denominators, back-contractions and every output
+   stay FP64 in all forms.
+   MLCC3_FP32:   FP32 MFMA on operands rounded to FP32, FP32 sums over 32-deep K slabs, FP64
+                 across slabs (about 1e-7 relative).
+   MLCC3_BF16X3: split-bf16 products (Henry, Tang and Heinecke, ARITH 2019): each operand is
+                 hi + lo in bf16, products hi*hi + hi*lo + lo*hi in bf16 MFMA with FP32 sums
+                 over 64-deep K steps, FP64 across steps (about 2^-16 = 1.5e-5 relative per
+                 product; expected to miss 1e-6 on random-sign data).
+   MLCC3_BF16X6: the same with a three-way split hi + mid + lo and the six products whose plane
+                 indices sum to at most 2 (about 2^-24 relative per product). */
+enum { MLCC3_FP64 = 0, MLCC3_FP32 = 1, MLCC3_BF16X3 = 2, MLCC3_BF16X6 = 3 };
 
 typedef struct {
   int32_t n_o, n_v, N_O, N_V, n_chol; /* 0 <= n_o <= N_O, 0 <= n_v <= N_V, n_chol >= 1 */
@@ -80,8 +91,9 @@ typedef struct { const double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_vec;
 typedef struct { double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_out;
 
 typedef struct {
-  int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3: arithmetic of the
-                             d-contraction GEMMs; denominators and accumulation stay FP64 */
+  int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3, MLCC3_BF16X6:
+                             arithmetic of the d-contraction GEMMs; denominators and
+                             accumulation stay FP64 */
   int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
                              since the last call on this workspace; reuse its prepared blocks */
   int64_t triple_begin;   /* half-open range over the canonical list of unique occupied     */
@@ -114,6 +126,25 @@ int64_t mlcc3_ws_bytes(mlcc3_ws ws);
  * their summed device time in ms and the FLOPs executed by those launches. */
 int mlcc3_ws_timing(mlcc3_ws ws, int32_t enable);
 int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *total_ms, double *flops);
+
+/* Launch-shape choices of a workspace (the knobs an autotuner times; none changes what is
+ * computed, only the launch shape, so results agree to rounding).  0 in a field = the
+ * library's size-based default.
+ *   dc_wg_per_cu: workgroups per CU of the persistent d-contraction grid (1..8), or -1 for one
+ *                 workgroup per tile;
+ *   back_ksplit:  K parts of the single-vector N_V-wide back-contraction GEMMs (1..8);
+ *   narrow_tile:  block tile of the generic FP64 GEMM in the N_O-wide back-contractions,
+ *                 10*TM + TN for a (32 TM) x (32 TN) tile, TM and TN in {1, 2, 4};
+ *   contra_form:  contravariant pass: 1 = one workgroup per 16^3 sub-cube, 2 = one per orbit
+ *                 of sub-cubes under the virtual permutations (used only when 16 divides n_v,
+ *                 else the per-sub-cube pass runs);
+ *   vec_group:    cap on the vectors that share one launch in the right and left transforms.
+ * mlcc3_ws_set_tuning(ws, NULL) restores the defaults; out-of-range values give MLCC3_EINVAL. */
+typedef struct {
+  int32_t dc_wg_per_cu, back_ksplit, narrow_tile, contra_form, vec_group;
+} mlcc3_tuning;
+int mlcc3_ws_set_tuning(mlcc3_ws ws, const mlcc3_tuning *t);
+int mlcc3_ws_get_tuning(mlcc3_ws ws, mlcc3_tuning *t);
 
 void mlcc3_opts_default(mlcc3_opts *o);
 

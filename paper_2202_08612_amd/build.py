@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "libmlcc3.so")
 ARCH = os.environ.get("MLCC3_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["gemm_f64.hip", "tile_gemm_f64.hip", "dcontract_mixed.hip", "triples_kernels.hip", "mlcc3_abi.hip"]
+SOURCES = ["gemm_f64.hip", "tile_gemm_f64.hip", "dcontract_mixed.hip", "dcontract_bf16.hip", "triples_kernels.hip", "mlcc3_abi.hip"]
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          # no packed-FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

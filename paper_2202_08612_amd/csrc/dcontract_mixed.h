@@ -1,8 +1,24 @@
-// Mixed-precision (FP32 MFMA) d-contraction of the triples intermediate.
+// Mixed-precision d-contractions of the triples intermediate: FP32 MFMA, and split-bf16
+// products (three or six bf16 MFMA products per FP64 product).
 #pragma once
+#include <stdint.h>
 #include "mlcc3_internal.h"
 
 namespace mlcc3 {
+
+// offset of row x under a two-level map: (x / d) s1 + (x % d) s0
+__device__ __forceinline__ long long mix_moff(const Idx2 &f, int x) {
+  const int q = x / f.d;
+  return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
+}
+
+// does a d-contraction tile (rows [m0, m1) of (p,q,a), batch r) touch a core occupied index?
+__device__ __forceinline__ bool mix_cvs_tile_kept(unsigned long long bits, int no, int nv, int r, int m0, int m1) {
+  if ((bits >> r) & 1ULL) return true;
+  for (int pq = m0 / nv; pq <= (m1 - 1) / nv; pq++)
+    if (((bits >> (pq / no)) | (bits >> (pq % no))) & 1ULL) return true;
+  return false;
+}
 
 // one product term: A[m][k] (FP32, row pitch lda) times B[z][k][n] (FP32, row pitch ldb,
 // batch pitch bbatch); k < Kp, where rows K <= k < Kp of B and columns of A are zero padding;
@@ -34,5 +50,43 @@ struct MixGemm {
 hipError_t dcontract_f32(const MixGemm &g, hipStream_t s);
 // dst[b][r][c] (b < nb, r < Rp, c < Cp) = FP32 of src[b][r][c] inside R x C, zero outside
 hipError_t pad_to_f32(const double *src, int nb, int R, int C, float *dst, int Rp, int Cp, hipStream_t s);
+
+// ---- split-bf16 form (Henry, Tang and Heinecke, ARITH 2019) ----
+// Every FP64 operand element is split into ns bf16 planes, x ~ x_0 + ... + x_{ns-1}, with
+// x_0 = bf16(x) and x_s = bf16 of the (exact, FP64) remainder after x_0..x_{s-1}.  The product
+// keeps the plane pairs (s, t) with s + t < ns: ns = 2 gives three products (about 2^-16
+// relative per product), ns = 3 six (about 2^-24).
+constexpr int BF_BM = 128, BF_BN = 64, BF_BK = 32;
+
+// one product term: A plane s at A + s*aplane, rows [m][k] with pitch Kp (Mp >= M rows, a
+// multiple of BF_BM, zero beyond M and K); B plane s at B + s*bplane, batch z at + z*bbatch,
+// stored TRANSPOSED as [n][k] with pitch Kp (Np >= N rows, a multiple of BF_BN, zero padded).
+// Kp a multiple of BF_BK; bases 16-byte aligned.  Vector v: A + v*avec, B + v*bvec.
+struct BfSeg {
+  const uint16_t *A = nullptr;
+  long long aplane = 0, avec = 0;
+  const uint16_t *B = nullptr;
+  long long bplane = 0, bbatch = 0, bvec = 0;
+  int Kp = 0;
+};
+
+// C[z*cbatch + cmap(m) + n] = sum_seg sum_(s,t) sum_k A_seg,s[m][k] B_seg,t[z][n][k] (bf16 MFMA,
+// FP32 sums over 64-deep K steps, added in FP64), for every vector v < nvec (C + v*cvec)
+struct BfGemm {
+  int M = 0, N = 0, nbatch = 1, nseg = 0, nvec = 1, ns = 2;
+  BfSeg seg[2];
+  double *C = nullptr;
+  Idx2 cmap;
+  long long cbatch = 0, cvec = 0;
+  int persist = 0;
+  int cvs = 0, cvs_no = 0, cvs_nv = 0;
+  unsigned long long cvs_bits = 0;
+};
+
+hipError_t dcontract_bf16(const BfGemm &g, hipStream_t s);
+// planes of src[b][r][c] (b < nb, inside R x C; zero outside) into dst + s*plane, layout
+// [b][Rp][Cp]; transpose = 1 writes [b][Cp][Rp] instead (src columns become rows)
+hipError_t split_bf16(const double *src, int nb, int R, int C, uint16_t *dst, int Rp, int Cp, long long plane,
+                      int ns, int transpose, hipStream_t s);
 
 }  // namespace mlcc3

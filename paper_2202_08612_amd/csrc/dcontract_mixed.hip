@@ -30,19 +30,6 @@ constexpr int PB = BN + 16;
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int GM = 8;
 
-__device__ __forceinline__ long long moff(const Idx2 &f, int x) {
-  const int q = x / f.d;
-  return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
-}
-
-// does a d-contraction tile (rows [m0, m1) of (p,q,a), batch r) touch a core occupied index?
-__device__ __forceinline__ bool cvs_tile_kept(unsigned long long bits, int no, int nv, int r, int m0, int m1) {
-  if ((bits >> r) & 1ULL) return true;
-  for (int pq = m0 / nv; pq <= (m1 - 1) / nv; pq++)
-    if (((bits >> (pq / no)) | (bits >> (pq % no))) & 1ULL) return true;
-  return false;
-}
-
 __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
   __shared__ float As[2][BM * PA];
   __shared__ float Bs[2][BK * PB];
@@ -59,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
     t -= grp * GM * nt;
     const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 32;
-    if (g.cvs && !cvs_tile_kept(g.cvs_bits, g.cvs_no, g.cvs_nv, z, m0, min(g.M, m0 + BM))) continue;
+    if (g.cvs && !mix_cvs_tile_kept(g.cvs_bits, g.cvs_no, g.cvs_nv, z, m0, min(g.M, m0 + BM))) continue;
 
     f4 acc[4][2];
     d4 acc64[4][2];
@@ -146,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
       for (int v = 0; v < 4; v++) {
         const int m = m0 + wm0 + 16 * i + 4 * (lane >> 4) + v;
         if (m >= g.M) continue;
-        double *crow = Cp + moff(g.cmap, m);
+        double *crow = Cp + mix_moff(g.cmap, m);
 #pragma unroll
         for (int j = 0; j < 2; j++) {
           const int n = n0 + wn0 + 16 * j + (lane & 15);

@@ -254,6 +254,10 @@ long long gemm_tiles(const Gemm &g) {
   while (blocks(tm, tn) < 512 && (tm > 2 || tn > 2)) {
     if (tm >= tn) tm /= 2; else tn /= 2;
   }
+  if (g.tm > 0 && g.tn > 0) {
+    tm = g.tm;
+    tn = g.tn;
+  }
   return blocks(tm, tn);
 }
 
@@ -272,6 +276,10 @@ hipError_t gemm_f64(const Gemm &g, hipStream_t s) {
   };
   while (blocks(tm, tn) < 512 && (tm > 2 || tn > 2)) {
     if (tm >= tn) tm /= 2; else tn /= 2;
+  }
+  if (g.tm > 0 && g.tn > 0) {  // caller's choice
+    tm = g.tm;
+    tn = g.tn;
   }
 #define MLCC3_TILE(a, b) \
   if (tm == a && tn == b) return launch_tiles<a, b>(g, s, akf, bnf);

@@ -84,9 +84,16 @@ struct mlcc3_ws_s {
   };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
+  mlcc3_tuning tune{};  // launch-shape choices (0 = default)
 };
 
 namespace {
+
+// launch-shape choices of the running call's workspace (all zero = defaults)
+const mlcc3_tuning &tune() {
+  static const mlcc3_tuning z{};
+  return t_ws ? t_ws->tune : z;
+}
 
 double *buf(mlcc3_ws ws, const std::string &name, size_t count, hipStream_t s) {
   auto &b = ws->bufs[name];
@@ -342,6 +349,7 @@ void tgemm(const TileGemm &g, hipStream_t s) {
         ks = k;
       }
     }
+    if (tune().back_ksplit > 0) ks = tune().back_ksplit;
     if (ks > 1 && ws) {
       TileGemm h = g;
       h.ksplit = ks;
@@ -622,24 +630,88 @@ struct DSeg {
   long long Gv = 0;
 };
 
-// persistent grid of the d-contraction: two workgroups per CU
-int persist_grid() {
-  static int n = 0;
-  if (n == 0) {
-    int dev = 0, cus = 0;
+// persistent grid of the d-contraction: per_cu workgroups per CU unless the workspace tuning
+// says otherwise; 0 = one workgroup per tile
+int persist_grid(int per_cu) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
     if (!g_dry && hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      n = 2 * cus;
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
     else
-      n = 512;
+      cus = 256;
   }
-  return n;
+  const int f = tune().dc_wg_per_cu;
+  if (f < 0) return 0;
+  return (f > 0 ? f : per_cu) * cus;
 }
 
 // W_v[p][q][r][a][b][c] = sum_seg sum_D x_seg,v[(p,q,a)][D] G_seg,v[r][D][(b,c)] for the nb vectors
 // of a group (W_v at W + v*|W|), one persistent launch for the whole group
 void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStream_t s) {
   const long long Wv = d.nord * d.nv3;
+  if (t_prec == MLCC3_BF16X3 || t_prec == MLCC3_BF16X6) {
+    // split-bf16 products on bf16 planes of the operands (B planes transposed, K-contiguous)
+    mlcc3_ws ws = t_ws;
+    const int ns = t_prec == MLCC3_BF16X3 ? 2 : 3;
+    BfGemm g;
+    g.M = d.no * d.no * d.nv;
+    g.N = (int)d.nv2;
+    g.nbatch = d.no;
+    g.nvec = nb;
+    g.ns = ns;
+    g.C = W;
+    g.cmap = split(d.nv, (long long)d.no * d.nv3, d.nv2);
+    g.cbatch = d.nv3;
+    g.cvec = Wv;
+    g.nseg = nseg;
+    // the six-product kernel holds one workgroup per CU (LDS), the three-product one two
+    g.persist = persist_grid(ns == 2 ? 2 : 1);
+    g.cvs = t_cvs;
+    g.cvs_bits = t_cvs_bits;
+    g.cvs_no = d.no;
+    g.cvs_nv = d.nv;
+    const int Kp = (d.NV + BF_BK - 1) / BF_BK * BF_BK;
+    const int Mp = (g.M + BF_BM - 1) / BF_BM * BF_BM, Np = (g.N + BF_BN - 1) / BF_BN * BF_BN;
+    static const char *an[2] = {"bf_A0", "bf_A1"}, *bn[2] = {"bf_B0", "bf_B1"};
+    for (int i = 0; i < nseg; i++) {
+      const int na_v = seg[i].xv ? nb : 1, nb_v = seg[i].Gv ? nb : 1;
+      const long long sa = (long long)Mp * Kp, sb = (long long)d.no * Np * Kp;  // one vector, one plane
+      const long long pa = sa * na_v, pb = sb * nb_v;                           // one plane
+      uint16_t *A = (uint16_t *)buf(ws, an[i], (size_t)(pa * ns + 3) / 4, s);
+      uint16_t *Bm = (uint16_t *)buf(ws, bn[i], (size_t)(pb * ns + 3) / 4, s);
+      check_range(seg[i].x, plain(d.NV), g.M, plain(1), d.NV, 0, 1, "A (d-contraction)", seg[i].xv, nb);
+      check_range(seg[i].G, plain(d.nv2), d.NV, plain(1), (int)d.nv2, (long long)d.NV * d.nv2, d.no,
+                  "B (d-contraction)", seg[i].Gv, nb);
+      check_bytes(A, (size_t)(pa * ns) * sizeof(uint16_t), "bf16 A planes (d-contraction)");
+      check_bytes(Bm, (size_t)(pb * ns) * sizeof(uint16_t), "bf16 B planes (d-contraction)");
+      for (int v = 0; v < na_v; v++)
+        HIPCHK(split_bf16(seg[i].x + v * seg[i].xv, 1, g.M, d.NV, A + v * sa, Mp, Kp, pa, ns, 0, s));
+      for (int v = 0; v < nb_v; v++)
+        HIPCHK(split_bf16(seg[i].G + v * seg[i].Gv, d.no, d.NV, (int)d.nv2, Bm + v * sb, Kp, Np, pb, ns, 1, s));
+      g.seg[i].A = A;
+      g.seg[i].aplane = pa;
+      g.seg[i].avec = seg[i].xv ? sa : 0;
+      g.seg[i].B = Bm;
+      g.seg[i].bplane = pb;
+      g.seg[i].bbatch = (long long)Np * Kp;
+      g.seg[i].bvec = seg[i].Gv ? sb : 0;
+      g.seg[i].Kp = Kp;
+    }
+    check_range(W, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (d-contraction)", g.cvec, nb);
+    if (!ws || !ws->timing || g_dry) {
+      HIPCHK(dcontract_bf16(g, s));
+      return;
+    }
+    const double fl = 2.0 * g.M * (double)g.N * d.NV * g.nbatch * nseg * nb;
+    mlcc3_ws_s::Mark mk{0, fl, pool_event(ws), pool_event(ws)};
+    HIPCHK(hipEventRecord(mk.a, s));
+    HIPCHK(dcontract_bf16(g, s));
+    HIPCHK(hipEventRecord(mk.b, s));
+    ws->marks.push_back(mk);
+    return;
+  }
   if (t_prec == MLCC3_FP32) {
     // FP32 MFMA on rounded, zero-padded copies of the operands; W and all later steps stay FP64
     mlcc3_ws ws = t_ws;
@@ -653,7 +725,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
     g.cbatch = d.nv3;
     g.cvec = Wv;
     g.nseg = nseg;
-    g.persist = persist_grid();
+    g.persist = persist_grid(2);
     g.cvs = t_cvs;
     g.cvs_bits = t_cvs_bits;
     g.cvs_no = d.no;
@@ -708,7 +780,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
   g.cvec = Wv;
   g.nseg = nseg;
   g.dcontract = 1;
-  g.persist = persist_grid();
+  g.persist = persist_grid(2);
   g.cvs = t_cvs;
   g.cvs_bits = t_cvs_bits;
   g.cvs_no = d.no;
@@ -765,7 +837,7 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
   check_bytes(Xt, sizeof(double) * Wv * nb, "X~ (permutation)");
   if (Xc) check_bytes(Xc, sizeof(double) * Wv * nb, "covariant X (permutation)");
   launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, vb,
-                       r.tb, r.te, lt, ot, s);
+                       r.tb, r.te, lt, ot, tune().contra_form, s);
   HIPRT(hipGetLastError());
 }
 
@@ -818,6 +890,15 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
   HIPRT(hipGetLastError());
 }
 
+// the workspace's tile choice for the N_O-wide back-contractions
+void narrow_tile(Gemm &g) {
+  const int t = tune().narrow_tile;
+  if (t > 0) {
+    g.tm = t / 10;
+    g.tn = t % 10;
+  }
+}
+
 // Y[i][(a,b)][L] = alpha * sum_{(j,k,c)} X~[i][j][k][a][b][c] G((j,k,c),L)   (+ second segment)
 Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2, double *Y, double alpha) {
   Gemm g;
@@ -834,6 +915,7 @@ Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2
   const long long xb = (long long)d.no * d.no * d.nv3;
   g.seg[0] = seg(X1, plain(d.nv), split(d.nv, d.nv3, 1), xb, G1.p, G1.row, G1.col, G1.batch, K);
   if (X2) g.seg[1] = seg(X2, plain(d.nv), split(d.nv, d.nv3, 1), xb, G2.p, G2.row, G2.col, G2.batch, K);
+  narrow_tile(g);
   return g;
 }
 // G stored [j][k][c][L]
@@ -854,6 +936,7 @@ void back_qrc(mlcc3_ws ws, const Dims &d, const double *X, const double *x, doub
   g.nseg = 1;
   g.seg[0] = seg(X, split(d.nv, d.nv3, 1), plain(d.nv), (long long)d.no * d.no * d.nv3, x,
                  plain((long long)d.no * d.NO), plain(1), d.NO, (int)d.nv2);
+  narrow_tile(g);
   gemm(g, s);
   launch_sum_rows(P, d.no, MN, Y, s);
   HIPRT(hipGetLastError());
@@ -915,8 +998,9 @@ mlcc3_opts opts_or_default(const mlcc3_opts *o) {
   mlcc3_opts r;
   mlcc3_opts_default(&r);
   if (o) r = *o;
-  check(r.precision == MLCC3_FP64 || r.precision == MLCC3_FP32 || r.precision == MLCC3_BF16X3, "bad precision");
-  if (r.precision == MLCC3_BF16X3) throw Status{MLCC3_EUNSUPPORTED, "MLCC3_BF16X3 is not implemented"};
+  check(r.precision == MLCC3_FP64 || r.precision == MLCC3_FP32 || r.precision == MLCC3_BF16X3 ||
+            r.precision == MLCC3_BF16X6,
+        "bad precision");
   t_prec = r.precision;
   t_cvs = 0;
   t_cvs_bits = 0;
@@ -1095,10 +1179,11 @@ void cvs_project_out(const Dims &d, const mlcc3_out &o, hipStream_t s) {
 
 // vectors per group: several vectors share one launch of the d-contraction and of the
 // permutation passes; a group holds two ordered-triple buffers (W, X~) per vector, kept within
-// 45% of device memory (environment MLCC3_VEC_BATCH caps the group size)
+// 45% of device memory (environment MLCC3_VEC_BATCH and the workspace tuning cap the group size)
 int group_size(mlcc3_ws ws, const Dims &d, int nvec) {
   int cap = kMaxVecBatch;
   if (const char *e = std::getenv("MLCC3_VEC_BATCH")) cap = std::max(1, std::min(cap, std::atoi(e)));
+  if (tune().vec_group > 0) cap = std::min(cap, tune().vec_group);
   size_t total = (size_t)256 << 30;
   if (!g_dry) {
     size_t fr = 0, tot = 0;
@@ -1233,6 +1318,32 @@ int mlcc3_ws_timing(mlcc3_ws ws, int32_t enable) {
         ws->pool.push_back(m.b);
       }
     ws->marks.clear();
+  });
+}
+
+int mlcc3_ws_set_tuning(mlcc3_ws ws, const mlcc3_tuning *t) {
+  return guarded([&] {
+    check(ws != nullptr, "ws is NULL");
+    mlcc3_tuning z{};
+    if (!t) {
+      ws->tune = z;
+      return;
+    }
+    check(t->dc_wg_per_cu == -1 || (t->dc_wg_per_cu >= 0 && t->dc_wg_per_cu <= 8), "dc_wg_per_cu out of range");
+    check(t->back_ksplit >= 0 && t->back_ksplit <= 8, "back_ksplit out of range");
+    const int tm = t->narrow_tile / 10, tn = t->narrow_tile % 10;
+    auto ok = [](int x) { return x == 1 || x == 2 || x == 4; };
+    check(t->narrow_tile == 0 || (t->narrow_tile < 100 && ok(tm) && ok(tn)), "narrow_tile must be 10*TM+TN, TM,TN in {1,2,4}");
+    check(t->contra_form >= 0 && t->contra_form <= 2, "contra_form out of range");
+    check(t->vec_group >= 0, "vec_group < 0");
+    ws->tune = *t;
+  });
+}
+
+int mlcc3_ws_get_tuning(mlcc3_ws ws, mlcc3_tuning *t) {
+  return guarded([&] {
+    check(ws != nullptr && t != nullptr, "NULL argument");
+    *t = ws->tune;
   });
 }
 

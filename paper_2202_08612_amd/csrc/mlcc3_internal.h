@@ -45,6 +45,8 @@ struct Gemm {
   // partial tiles go to P[batch][part][M][N] and a fixed-order reduction applies alpha/beta.
   int ksplit = 1;
   double *P = nullptr;
+  // block tile (32 tm) x (32 tn), tm, tn in {1, 2, 4}; 0 = chosen from the sizes
+  int tm = 0, tn = 0;
 };
 
 // FP64 MFMA GEMM (v_mfma_f64_16x16x4_f64), LDS-staged, 256 threads per block.

@@ -73,10 +73,12 @@ struct VecBatch {
 };
 
 // W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
-// (and, if Xc is not NULL, the covariant X to every ordering)
+// (and, if Xc is not NULL, the covariant X to every ordering); contra_form 1 forces the
+// per-sub-cube contravariant pass, otherwise the orbit pass runs when 16 divides n_v
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
-                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s);
+                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
+                          hipStream_t s);
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s);
 // pairing maps of the doubles blocks (mode 0 symmetrise, 1 gradient -> left vector, 2 left

@@ -919,14 +919,15 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
 
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
-                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, hipStream_t s) {
+                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
+                          hipStream_t s) {
   if (nu <= 0 || nv <= 0 || vb.nvec <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
   LocalTerms l = lt;
   if (!l.L1) l.L1v = l.LVv = 0;
   const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
   hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot, nu);
-  if (nv % TT == 0) {
+  if (nv % TT == 0 && contra_form != 1) {
     // rows of the ordered blocks are whole cache lines: one workgroup per orbit of tiles reads
     // each sub-cube of X_u once (measured 2.3 -> 1.8 ms at n_v = 80; at n_v = 60 the per-tile
     // kernel is as fast, its neighbouring tiles share the partial lines of a row in L2)

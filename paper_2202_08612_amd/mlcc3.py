@@ -22,8 +22,8 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ESINGULAR, ENOMEM, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -7
-FP64, FP32, BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -46,7 +46,16 @@ class _Opts(ctypes.Structure):
                 ("cvs_core", ctypes.c_void_p)]
 
 
+TUNING_FIELDS = ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group")
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in TUNING_FIELDS]
+
+
 _lib.mlcc3_ws_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+_lib.mlcc3_ws_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tuning)]
+_lib.mlcc3_ws_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tuning)]
 _lib.mlcc3_ws_destroy.argtypes = [ctypes.c_void_p]
 _lib.mlcc3_ws_bytes.argtypes = [ctypes.c_void_p]
 _lib.mlcc3_ws_bytes.restype = ctypes.c_int64
@@ -76,7 +85,8 @@ _lib.mlcc3_status_string.argtypes = [ctypes.c_int]
 _lib.mlcc3_status_string.restype = ctypes.c_char_p
 _lib.mlcc3_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_ws_timing", "mlcc3_ws_phase_stats", "mlcc3_opts_default",
+EXPORTED = ["mlcc3_ws_create", "mlcc3_ws_destroy", "mlcc3_ws_bytes", "mlcc3_ws_timing", "mlcc3_ws_phase_stats",
+            "mlcc3_ws_set_tuning", "mlcc3_ws_get_tuning", "mlcc3_opts_default",
             "mlcc3_num_triples", "mlcc3_ground_residual", "mlcc3_right_transform",
             "mlcc3_left_transform", "mlcc3_triples_densities", "mlcc3_vec_map", "mlcc3_oscillator_strengths", "mlcc3_flops",
             "mlcc3_status_string", "mlcc3_last_error"]
@@ -122,6 +132,23 @@ class Workspace:
         n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         _check(_lib.mlcc3_ws_phase_stats(self.h, phase, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
         return {"launches": int(n.value), "ms": float(ms.value), "flops": float(fl.value)}
+
+    def set_tuning(self, tuning=None):
+        """Launch-shape choices of this workspace (dict over TUNING_FIELDS, missing keys = 0 =
+        the library default); None restores all defaults."""
+        if tuning is None:
+            _check(_lib.mlcc3_ws_set_tuning(self.h, None))
+            return
+        bad = set(tuning) - set(TUNING_FIELDS)
+        if bad:
+            raise KeyError(f"unknown tuning fields {sorted(bad)}")
+        t = _Tuning(*[int(tuning.get(k, 0)) for k in TUNING_FIELDS])
+        _check(_lib.mlcc3_ws_set_tuning(self.h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = _Tuning()
+        _check(_lib.mlcc3_ws_get_tuning(self.h, ctypes.byref(t)))
+        return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
 
     def close(self):
         if self.h:

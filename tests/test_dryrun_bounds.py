@@ -52,7 +52,7 @@ def _fake(n):
 CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1), I.sweep_dims(5)]
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("d", CASES, ids=lambda d: f"{d.n_o}-{d.n_v}-{d.N_O}-{d.N_V}-{d.n_chol}")
 def test_all_launches_in_bounds(lib, d, prec):
     ws = ctypes.c_void_p()
@@ -118,11 +118,59 @@ def test_cvs_launches_in_bounds(lib, d):
     vin = (V * nvec)(*[V(*p[11 + 3 * m: 14 + 3 * m]) for m in range(nvec)])
     vout = (V * nvec)(*[V(*p[30 + 3 * m: 33 + 3 * m]) for m in range(nvec)])
     om = (ctypes.c_double * nvec)(15.2, 15.3)
-    for prec in (0, 1):
+    for prec in (0, 1, 2, 3):
         o.precision = prec
         for fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
             rc = getattr(lib, fn)(ws, ctypes.byref(g), nvec, om, vin, vout, ctypes.byref(o), None)
             assert rc == 0, (fn, lib.mlcc3_last_error())
     out = (V * 1)(V(*p[8:11]))
     assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == -1
+    assert lib.mlcc3_ws_destroy(ws) == 0
+
+
+class T(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group")]
+
+
+def test_tuning_validation(lib):
+    ws = ctypes.c_void_p()
+    assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+    t = T()
+    assert lib.mlcc3_ws_get_tuning(ws, ctypes.byref(t)) == 0
+    assert (t.dc_wg_per_cu, t.back_ksplit, t.narrow_tile, t.contra_form, t.vec_group) == (0, 0, 0, 0, 0)
+    for bad in (T(9, 0, 0, 0, 0), T(-2, 0, 0, 0, 0), T(0, 9, 0, 0, 0), T(0, 0, 43, 0, 0), T(0, 0, 3, 0, 0),
+                T(0, 0, 0, 3, 0), T(0, 0, 0, 0, -1)):
+        assert lib.mlcc3_ws_set_tuning(ws, ctypes.byref(bad)) == -1
+    good = T(-1, 8, 42, 1, 2)
+    assert lib.mlcc3_ws_set_tuning(ws, ctypes.byref(good)) == 0
+    assert lib.mlcc3_ws_get_tuning(ws, ctypes.byref(t)) == 0
+    assert (t.dc_wg_per_cu, t.back_ksplit, t.narrow_tile, t.contra_form, t.vec_group) == (-1, 8, 42, 1, 2)
+    assert lib.mlcc3_ws_set_tuning(ws, None) == 0
+    assert lib.mlcc3_ws_get_tuning(ws, ctypes.byref(t)) == 0 and t.back_ksplit == 0
+    assert lib.mlcc3_ws_destroy(ws) == 0
+
+
+@pytest.mark.parametrize("tune", [T(1, 1, 11, 1, 1), T(-1, 8, 44, 2, 2), T(4, 3, 14, 0, 0), T(3, 2, 41, 1, 3)],
+                         ids=["min", "max", "mixed", "odd"])
+@pytest.mark.parametrize("d", [I.CONFIGS[1]["dims"], I.CONFIGS[3]["dims"], I.Dims(5, 17, 7, 37, 23)], ids=str)
+def test_tuned_launches_in_bounds(lib, d, tune):
+    """Every launch-shape choice keeps all launches inside their buffers (all precisions)."""
+    ws = ctypes.c_void_p()
+    assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+    assert lib.mlcc3_ws_set_tuning(ws, ctypes.byref(tune)) == 0
+    p = _fake(64)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:8])
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    nvec = 3
+    vin = (V * nvec)(*[V(*p[11 + 3 * m: 14 + 3 * m]) for m in range(nvec)])
+    vout = (V * nvec)(*[V(*p[30 + 3 * m: 33 + 3 * m]) for m in range(nvec)])
+    om = (ctypes.c_double * nvec)(0.4, 0.5, 0.6)
+    for prec in (0, 1, 2, 3):
+        o.precision = prec
+        out = (V * 1)(V(*p[8:11]))
+        assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == 0, lib.mlcc3_last_error()
+        for fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
+            rc = getattr(lib, fn)(ws, ctypes.byref(g), nvec, om, vin, vout, ctypes.byref(o), None)
+            assert rc == 0, (fn, lib.mlcc3_last_error())
     assert lib.mlcc3_ws_destroy(ws) == 0
