@@ -11,8 +11,10 @@
 // 8 consecutive k of chunk l/16; result register v of lane l: row 4(l/16) + v, column l%16).
 // 256 threads in a 2x2 wave arrangement, 128x64 block tile, each wave 4x2 MFMA tiles.  Both
 // operands are staged K-contiguous (B planes are stored transposed, [n][k]), so every fragment
-// is one 16-byte LDS read; the row pitch of 80 bytes puts the 16 rows of a fragment read in 16
-// distinct groups of 4 banks.  LDS holds two slab buffers (double buffering, one barrier per slab).
+// is one 16-byte LDS read.  LDS rows are 64 bytes (32 k) with the four 16-byte chunks of row R
+// permuted by XOR with (R / 4) % 4, which puts the 16 rows of a fragment read in 16 distinct
+// groups of 4 banks without padding.  LDS holds two slab buffers (double buffering, one barrier
+// per slab): 48 KB for two planes, 72 KB for three, so two workgroups fit on a CU either way.
 #include "dcontract_mixed.h"
 
 namespace mlcc3 {
@@ -25,11 +27,14 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = BF_BM, BN = BF_BN, BK = BF_BK;
-constexpr int PW = BK / 2 + 4;  // LDS row pitch in 4-byte words
+constexpr int PW = BK / 2;      // LDS row pitch in 4-byte words (64 bytes)
 constexpr int GM = 8;           // M-tiles per group of the tile order
 constexpr int FLUSH = 2;        // K slabs summed in FP32 before the FP64 add
 
 __device__ __forceinline__ bf8 as_bf8(const u4 &x) { return __builtin_bit_cast(bf8, x); }
+
+// word offset of 16-byte chunk c (0..3) of LDS row r
+__device__ __forceinline__ int swz(int r, int c) { return r * PW + 4 * (c ^ ((r >> 2) & 3)); }
 
 // LDS word offsets of the A and B plane s of slab buffer b
 template <int NS>
@@ -42,7 +47,7 @@ __device__ __forceinline__ int b_off(int b, int s) {
 }
 
 template <int NS>
-__global__ __launch_bounds__(256, NS == 2 ? 2 : 1) void k_dcontract_bf16(const BfGemm g) {
+__global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
   __shared__ u4 lds[2 * NS * (BM + BN) * PW / 4];
   unsigned *ldw = (unsigned *)lds;
 
@@ -92,8 +97,8 @@ __global__ __launch_bounds__(256, NS == 2 ? 2 : 1) void k_dcontract_bf16(const B
 #pragma unroll
         for (int s = 0; s < NS; s++) {
 #pragma unroll
-          for (int u = 0; u < 2; u++) *(u4 *)&ldw[a_off<NS>(buf, s) + (sr + 64 * u) * PW + 4 * kc] = ra[s][u];
-          *(u4 *)&ldw[b_off<NS>(buf, s) + sr * PW + 4 * kc] = rb[s];
+          for (int u = 0; u < 2; u++) *(u4 *)&ldw[a_off<NS>(buf, s) + swz(sr + 64 * u, kc)] = ra[s][u];
+          *(u4 *)&ldw[b_off<NS>(buf, s) + swz(sr, kc)] = rb[s];
         }
       };
 
@@ -109,10 +114,10 @@ __global__ __launch_bounds__(256, NS == 2 ? 2 : 1) void k_dcontract_bf16(const B
         for (int s = 0; s < NS; s++) {
 #pragma unroll
           for (int i = 0; i < 4; i++)
-            af[s][i] = *(const u4 *)&ldw[a_off<NS>(cur, s) + (wm0 + 16 * i + (lane & 15)) * PW + 4 * (lane >> 4)];
+            af[s][i] = *(const u4 *)&ldw[a_off<NS>(cur, s) + swz(wm0 + 16 * i + (lane & 15), lane >> 4)];
 #pragma unroll
           for (int j = 0; j < 2; j++)
-            bq[s][j] = *(const u4 *)&ldw[b_off<NS>(cur, s) + (wn0 + 16 * j + (lane & 15)) * PW + 4 * (lane >> 4)];
+            bq[s][j] = *(const u4 *)&ldw[b_off<NS>(cur, s) + swz(wn0 + 16 * j + (lane & 15), lane >> 4)];
         }
         // plane pairs (sa, sb) with sa + sb = dg, smallest products first
 #pragma unroll

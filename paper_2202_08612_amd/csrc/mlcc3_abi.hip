@@ -666,8 +666,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
     g.cbatch = d.nv3;
     g.cvec = Wv;
     g.nseg = nseg;
-    // the six-product kernel holds one workgroup per CU (LDS), the three-product one two
-    g.persist = persist_grid(ns == 2 ? 2 : 1);
+    g.persist = persist_grid(2);
     g.cvs = t_cvs;
     g.cvs_bits = t_cvs_bits;
     g.cvs_no = d.no;
