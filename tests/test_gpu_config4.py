@@ -2,7 +2,9 @@
 n_v=60, N_O=90, N_V=1100, Cholesky rank 2500; 8 right and 8 left vectors; transition densities),
 checked by properties that hold at any size (the oracle is too slow at N_V=1100 for a test):
 batched calls equal single calls, the adjoint identity per block pairing, triple-range
-additivity, the density trace identities, and the mixed form within 1e-6 of FP64.
+additivity, the density trace identities, and the mixed forms against FP64 (FP32 and the
+six-product split-bf16 form within 1e-6, the three-product form within 2e-4), also with launch
+shapes picked by the autotuner.
 """
 import numpy as np
 import pytest
@@ -51,14 +53,44 @@ def test_config4_right_left_batched_adjoint_mixed(lib, ws, case):
         a = pair_form_blocks(d, Ls[m], lib.to_numpy(rho[m]))
         b = pair_form_blocks(d, lib.to_numpy(sig[m]), Rs[m])
         assert abs(a - b) <= 1e-10 * abs(a), (m, a, b)
-    rmx = lib.right_transform(ws, g, om, Rd, reuse_ground=True, precision="fp32")
-    smx = lib.left_transform(ws, g, om, Ld, reuse_ground=True, precision="fp32")
+    # mixed forms against FP64: FP32 and six-product split-bf16 at 1e-6, three-product at 2e-4
+    for prec, tol in (("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 2e-4)):
+        rmx = lib.right_transform(ws, g, om, Rd, reuse_ground=True, precision=prec)
+        smx = lib.left_transform(ws, g, om, Ld, reuse_ground=True, precision=prec)
+        for m in range(8):
+            for k in rho[m]:
+                x, y = rmx[m][k].cpu().numpy(), rho[m][k].cpu().numpy()
+                assert rel(x, y) <= tol, (prec, "rho", m, k, rel(x, y))
+                x, y = smx[m][k].cpu().numpy(), sig[m][k].cpu().numpy()
+                assert rel(x, y) <= tol, (prec, "sigma", m, k, rel(x, y))
+
+
+def test_config4_autotuned_mixed(lib, case, tmp_path):
+    """8 right and 8 left vectors in the six-product split-bf16 form with launch shapes picked by
+    the autotuner: within 1e-6 of the FP64 transforms of a default workspace."""
+    from paper_2202_08612_amd.autotune import autotune
+    p, g = case
+    om = [float(x) for x in I.omegas(4, 8)]
+    Rd = [lib.vec_to_device(r) for r in I.right_vectors(p, 8)]
+    Ld = [lib.vec_to_device(v) for v in I.left_vectors(p, 8)]
+    w64 = lib.Workspace(0)
+    try:
+        rho = lib.right_transform(w64, g, om, Rd)
+        sig = lib.left_transform(w64, g, om, Ld, reuse_ground=True)
+    finally:
+        w64.close()
+    wt = lib.Workspace(0)
+    try:
+        tuning, rep = autotune(wt, g, om, Rd, Ld, precision="bf16x6", cache=str(tmp_path / "tune.json"), reps=1)
+        assert wt.get_tuning() == tuning and rep["ms"] <= rep["default_ms"]
+        rmx = lib.right_transform(wt, g, om, Rd, reuse_ground=True, precision="bf16x6")
+        smx = lib.left_transform(wt, g, om, Ld, reuse_ground=True, precision="bf16x6")
+    finally:
+        wt.close()
     for m in range(8):
         for k in rho[m]:
-            x, y = rmx[m][k].cpu().numpy(), rho[m][k].cpu().numpy()
-            assert rel(x, y) <= 1e-6, ("rho", m, k, rel(x, y))
-            x, y = smx[m][k].cpu().numpy(), sig[m][k].cpu().numpy()
-            assert rel(x, y) <= 1e-6, ("sigma", m, k, rel(x, y))
+            assert rel(rmx[m][k].cpu().numpy(), rho[m][k].cpu().numpy()) <= 1e-6, ("rho", m, k)
+            assert rel(smx[m][k].cpu().numpy(), sig[m][k].cpu().numpy()) <= 1e-6, ("sigma", m, k)
 
 
 def test_config4_range_additivity(lib, ws, case):
@@ -82,12 +114,15 @@ def test_config4_densities_traces_and_mixed(lib, ws, case):
     Rs = [lib.vec_to_device(v) for v in I.right_vectors(p, 8)]
     lam = lib.vec_to_device(I.lambda_vector(p))
     Dm0, D0m, s = lib.triples_densities(ws, g, om, Ls, Rs, lam, p.t2_vVoO, p.t2_vVOo, reuse_ground=True)
-    Dm0x, D0mx, sx = lib.triples_densities(ws, g, om, Ls, Rs, lam, p.t2_vVoO, p.t2_vVOo, reuse_ground=True,
-                                           precision="fp32")
     for m in range(8):
         a, b = Dm0[m].cpu().numpy(), D0m[m].cpu().numpy()
         assert np.all(np.isfinite(a)) and np.all(np.isfinite(b))
         assert abs(np.trace(a)) <= 1e-10 * np.abs(a).sum(), m
         assert abs(np.trace(b) - 2 * d.N_O * float(s[m])) <= 1e-10 * np.abs(b).sum(), m
-        assert rel(Dm0x[m].cpu().numpy(), a) <= 1e-6 and rel(D0mx[m].cpu().numpy(), b) <= 1e-6, m
-        assert abs(float(sx[m]) - float(s[m])) <= 1e-6 * abs(float(s[m])), m
+    for prec in ("fp32", "bf16x6"):
+        Dm0x, D0mx, sx = lib.triples_densities(ws, g, om, Ls, Rs, lam, p.t2_vVoO, p.t2_vVOo, reuse_ground=True,
+                                               precision=prec)
+        for m in range(8):
+            a, b = Dm0[m].cpu().numpy(), D0m[m].cpu().numpy()
+            assert rel(Dm0x[m].cpu().numpy(), a) <= 1e-6 and rel(D0mx[m].cpu().numpy(), b) <= 1e-6, (prec, m)
+            assert abs(float(sx[m]) - float(s[m])) <= 1e-6 * abs(float(s[m])), (prec, m)
