@@ -12,14 +12,6 @@ __device__ __forceinline__ long long mix_moff(const Idx2 &f, int x) {
   return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
 }
 
-// does a d-contraction tile (rows [m0, m1) of (p,q,a), batch r) touch a core occupied index?
-__device__ __forceinline__ bool mix_cvs_tile_kept(unsigned long long bits, int no, int nv, int r, int m0, int m1) {
-  if ((bits >> r) & 1ULL) return true;
-  for (int pq = m0 / nv; pq <= (m1 - 1) / nv; pq++)
-    if (((bits >> (pq / no)) | (bits >> (pq % no))) & 1ULL) return true;
-  return false;
-}
-
 // one product term: A[m][k] (FP32, row pitch lda) times B[z][k][n] (FP32, row pitch ldb,
 // batch pitch bbatch); k < Kp, where rows K <= k < Kp of B and columns of A are zero padding;
 // B columns N <= n < Np are padding.  Kp, Np, lda, ldb, bbatch multiples of 4, bases 16-byte aligned.
@@ -42,9 +34,8 @@ struct MixGemm {
   Idx2 cmap;
   long long cbatch = 0, cvec = 0;
   int persist = 0;
-  // core-valence separation: skip tiles whose (p,q,r) are all valence (see TileGemm)
-  int cvs = 0, cvs_no = 0, cvs_nv = 0;
-  unsigned long long cvs_bits = 0;
+  // ordered triples the call does not need are skipped (see TileGemm)
+  TripleFilter tf;
 };
 
 hipError_t dcontract_f32(const MixGemm &g, hipStream_t s);
@@ -79,8 +70,7 @@ struct BfGemm {
   Idx2 cmap;
   long long cbatch = 0, cvec = 0;
   int persist = 0;
-  int cvs = 0, cvs_no = 0, cvs_nv = 0;
-  unsigned long long cvs_bits = 0;
+  TripleFilter tf;
 };
 
 hipError_t dcontract_bf16(const BfGemm &g, hipStream_t s);

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
     t -= grp * GM * nt;
     const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 32;
-    if (g.cvs && !mix_cvs_tile_kept(g.cvs_bits, g.cvs_no, g.cvs_nv, z, m0, min(g.M, m0 + BM))) continue;
+    if (g.tf.on && !tile_needed(g.tf, z, m0, min(g.M, m0 + BM))) continue;
 
     f4 acc[4][2];
     d4 acc64[4][2];
@@ -166,6 +166,7 @@ hipError_t pad_to_f32(const double *src, int nb, int R, int C, float *dst, int R
 
 hipError_t dcontract_f32(const MixGemm &g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g0.nvec <= 0 || g_dry) return hipSuccess;
+  if (g0.tf.on && (g0.tf.no < 1 || g0.tf.nv < 1)) return hipErrorInvalidValue;
   if (g0.nseg < 1 || g0.nseg > 2) return hipErrorInvalidValue;
   MixGemm g = g0;
   for (int i = 0; i < g.nseg; i++) {

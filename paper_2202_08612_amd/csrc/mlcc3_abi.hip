@@ -456,6 +456,87 @@ Seg asm_oovo_seg(const Dims &d, const double *A, const double *B) {
              split(d.no, d.NO, 1), 0, d.nc);
 }
 
+// --------------------------------------- one-index transformations of the Cholesky vectors
+// C[batch][M][N] = alpha * A B + beta * C for plain row-major operands (A: lda, B: ldb) with
+// per-batch strides (0 = shared)
+Gemm plain_gemm(int M, int N, int K, int nbatch, const double *A, long long lda, long long abatch, const double *B,
+                long long ldb, long long bbatch, double *C, long long ldc, long long cbatch, double alpha,
+                double beta) {
+  Gemm g;
+  g.M = M;
+  g.N = N;
+  g.nbatch = nbatch;
+  g.C = C;
+  g.crow = plain(ldc);
+  g.ccol = plain(1);
+  g.cbatch = cbatch;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.nseg = 1;
+  g.seg[0] = seg(A, plain(lda), plain(1), abatch, B, plain(ldb), plain(1), bbatch, K);
+  return g;
+}
+
+// T1 transform Lhat = (1 - T) L (1 + T) of the Cholesky vectors, T[N_O + A][I] = t^A_I
+// (SI, T1-transformed integrals), block by block as MFMA GEMMs batched over the Cholesky index J:
+//   Lhat_OO[J][I][K] = L_OO + sum_B L_OV[J][I][B] t[B][K]
+//   Lhat_vV[J][a][B] = L_vV - sum_I t[a][I] L_OV[J][I][B]
+//   Lhat_Vv[J][D][b] = L_vV[J][b][D] - sum_I t[D][I] L_OV[J][I][b]
+//   Lhat_vO[J][c][K] = L_OV[J][K][c] + sum_B L_vV[J][c][B] t[B][K] - sum_I t[c][I] Lhat_OO[J][I][K]
+void lhat_blocks(const Dims &d, const mlcc3_ground *g, double *LhOO, double *LhvV, double *LhVv, double *LhvO,
+                 hipStream_t s) {
+  const int nc = d.nc, NO = d.NO, NV = d.NV, nv = d.nv;
+  const double *LOV = g->L_OV, *t1 = g->t1;
+  check_bytes(LhOO, sizeof(double) * nc * NO * NO, "Lhat_OO");
+  if (!g_dry) HIPRT(hipMemcpyAsync(LhOO, g->L_OO, sizeof(double) * nc * NO * NO, hipMemcpyDeviceToDevice, s));
+  gemm(plain_gemm(nc * NO, NO, NV, 1, LOV, NV, 0, t1, NO, 0, LhOO, NO, 0, 1.0, 1.0), s);
+  if (nv <= 0) return;
+  const long long ov = (long long)NO * NV;
+  check_bytes(LhvV, sizeof(double) * nc * nv * NV, "Lhat_vV");
+  if (!g_dry) HIPRT(hipMemcpyAsync(LhvV, g->L_vV, sizeof(double) * nc * nv * NV, hipMemcpyDeviceToDevice, s));
+  gemm(plain_gemm(nv, NV, NO, nc, t1, NO, 0, LOV, NV, ov, LhvV, NV, (long long)nv * NV, -1.0, 1.0), s);
+  check_bytes(LhVv, sizeof(double) * nc * NV * nv, "Lhat_Vv");
+  launch_transpose(g->L_vV, LhVv, nc, nv, NV, s);
+  gemm(plain_gemm(NV, nv, NO, nc, t1, NO, 0, LOV, NV, ov, LhVv, nv, (long long)NV * nv, -1.0, 1.0), s);
+  check_bytes(LhvO, sizeof(double) * nc * nv * NO, "Lhat_vO");
+  launch_lhat_vO_init(LOV, nc, NO, NV, nv, LhvO, s);
+  gemm(plain_gemm(nc * nv, NO, NV, 1, g->L_vV, NV, 0, t1, NO, 0, LhvO, NO, 0, 1.0, 1.0), s);
+  gemm(plain_gemm(nv, NO, NO, nc, t1, NO, 0, LhOO, NO, (long long)NO * NO, LhvO, NO, (long long)nv * NO, -1.0, 1.0), s);
+  HIPRT(hipGetLastError());
+}
+
+// one-index transformation with a singles vector R, dLhat = Lhat R - R Lhat, as GEMMs:
+//   dOO[J][I][K] = sum_A L_OV[J][I][A] R[A][K]
+//   dvV[J][a][B] = -sum_I R[a][I] L_OV[J][I][B]
+//   dvO[J][c][K] = sum_B Lhat_vV[J][c][B] R[B][K] - sum_I R[c][I] Lhat_OO[J][I][K]
+void dlhat_blocks(const Dims &d, const double *LOV, const double *LhvV, const double *LhOO, const double *R1,
+                  double *dOO, double *dvV, double *dvO, hipStream_t s) {
+  const int nc = d.nc, NO = d.NO, NV = d.NV, nv = d.nv;
+  gemm(plain_gemm(nc * NO, NO, NV, 1, LOV, NV, 0, R1, NO, 0, dOO, NO, 0, 1.0, 0.0), s);
+  gemm(plain_gemm(nv, NV, NO, nc, R1, NO, 0, LOV, NV, (long long)NO * NV, dvV, NV, (long long)nv * NV, -1.0, 0.0), s);
+  gemm(plain_gemm(nc * nv, NO, NV, 1, LhvV, NV, 0, R1, NO, 0, dvO, NO, 0, 1.0, 0.0), s);
+  gemm(plain_gemm(nv, NO, NO, nc, R1, NO, 0, LhOO, NO, (long long)NO * NO, dvO, NO, (long long)nv * NO, -1.0, 1.0), s);
+}
+
+// X_kc = sum_LD (2 g_kcLD - g_kDLc) x^D_L from bare (ov|ov) = sum_J L_kc L_LD (active k, c):
+// s_J = sum_LD L^J_LD x^D_L, y^J_kL = sum_D L^J_kD x^D_L (MFMA GEMM), then
+// X_kc = sum_J (2 L^J_kc s_J - sum_L y^J_kL L^J_Lc) summed over J in a fixed order
+void fock_like(const Dims &d, const double *LOV, const double *x, double *tmp_s, double *tmp_y, double *tmp_z,
+               double *out, hipStream_t s) {
+  const int nc = d.nc, NO = d.NO, NV = d.NV, no = d.no, nv = d.nv;
+  launch_fock_s(LOV, x, nc, NO, NV, tmp_s, s);
+  Gemm g;
+  g.M = nc * no;
+  g.N = NO;
+  g.C = tmp_y;
+  g.crow = plain(NO);
+  g.ccol = plain(1);
+  g.nseg = 1;
+  g.seg[0] = seg(LOV, split(no, (long long)NO * NV, NV), plain(1), 0, x, plain(NO), plain(1), 0, NV);
+  gemm(g, s);
+  launch_fock_finish(LOV, tmp_s, tmp_y, nc, NO, NV, no, nv, tmp_z, out, s);
+}
+
 // -------------------------------------------------------------- ground prep
 bool same_ground(const mlcc3_ground &a, const mlcc3_ground &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
 
@@ -468,7 +549,7 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   double *LhvV = buf(ws, "LhvV", (size_t)nc * nv * NV, s);
   double *LhVv = buf(ws, "LhVv", (size_t)nc * NV * nv, s);
   double *LhvO = buf(ws, "LhvO", (size_t)nc * nv * NO, s);
-  launch_lhat(g->L_OO, g->L_OV, g->L_vV, g->t1, nc, NO, NV, nv, LhOO, LhvV, LhVv, LhvO, s);
+  lhat_blocks(d, g, LhOO, LhvV, LhVv, LhvO, s);
   HIPRT(hipGetLastError());
   const long long LOVs = (long long)NO * NV;
   // G1[k][D][b][c] = ghat_bDck
@@ -563,8 +644,8 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   HIPRT(hipGetLastError());
   // F_kc
   double *F = buf(ws, "F", (size_t)no * nv, s);
-  launch_fock_like(g->L_OV, g->t1, nc, NO, NV, no, nv, buf(ws, "fock_s", nc, s),
-                   buf(ws, "fock_y", (size_t)nc * no * NO, s), buf(ws, "fock_z", (size_t)nc * no * nv, s), F, s);
+  fock_like(d, g->L_OV, g->t1, buf(ws, "fock_s", nc, s), buf(ws, "fock_y", (size_t)nc * no * NO, s),
+            buf(ws, "fock_z", (size_t)nc * no * nv, s), F, s);
   // tA[p][q][a][D] = t^{aD}_{pq}
   launch_pack_vVoo(g->t2_vVoo, no, nv, NV, 0, buf(ws, "tA", (size_t)no * no * nv * NV, s), s);
   HIPRT(hipGetLastError());
@@ -578,6 +659,9 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
         u.i = i; u.j = j; u.k = k;
         const bool alleq = (i == j && j == k);
         u.canon = alleq ? -1 : canon++;
+        // the kernels' tile filters locate a triple by its closed-form position
+        if (!alleq && canon_index(i, j, k) != u.canon)
+          throw Status{MLCC3_EHIP, "internal check failed: canonical triple index"};
         static const int P[6][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {0, 2, 1}, {2, 0, 1}, {1, 2, 0}};
         const int o[3] = {i, j, k};
         int mask = 0;
@@ -647,9 +731,24 @@ int persist_grid(int per_cu) {
   return (f > 0 ? f : per_cu) * cus;
 }
 
+// the ordered triples a GEMM over rows (p,q,a) and batch r must produce for the call's triple
+// range and core-valence separation (off when every triple is needed)
+TripleFilter triple_filter(const Dims &d, const Range &r, bool zero) {
+  TripleFilter f;
+  f.on = (r.tb > 0 || r.te < mlcc3_num_triples(d.no) || t_cvs) ? 1 : 0;
+  f.no = d.no;
+  f.nv = d.nv;
+  f.zero = zero ? 1 : 0;
+  f.core = t_cvs ? t_cvs_bits : 0;
+  f.tb = r.tb;
+  f.te = r.te;
+  return f;
+}
+
 // W_v[p][q][r][a][b][c] = sum_seg sum_D x_seg,v[(p,q,a)][D] G_seg,v[r][D][(b,c)] for the nb vectors
-// of a group (W_v at W + v*|W|), one persistent launch for the whole group
-void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStream_t s) {
+// of a group (W_v at W + v*|W|), one persistent launch for the whole group; only the ordered
+// triples of the range r (and, under core-valence separation, with a core index) are formed
+void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, const Range &r, hipStream_t s) {
   const long long Wv = d.nord * d.nv3;
   if (t_prec == MLCC3_BF16X3 || t_prec == MLCC3_BF16X6) {
     // split-bf16 products on bf16 planes of the operands (B planes transposed, K-contiguous)
@@ -667,10 +766,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
     g.cvec = Wv;
     g.nseg = nseg;
     g.persist = persist_grid(2);
-    g.cvs = t_cvs;
-    g.cvs_bits = t_cvs_bits;
-    g.cvs_no = d.no;
-    g.cvs_nv = d.nv;
+    g.tf = triple_filter(d, r, false);
     const int Kp = (d.NV + BF_BK - 1) / BF_BK * BF_BK;
     const int Mp = (g.M + BF_BM - 1) / BF_BM * BF_BM, Np = (g.N + BF_BN - 1) / BF_BN * BF_BN;
     static const char *an[2] = {"bf_A0", "bf_A1"}, *bn[2] = {"bf_B0", "bf_B1"};
@@ -725,10 +821,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
     g.cvec = Wv;
     g.nseg = nseg;
     g.persist = persist_grid(2);
-    g.cvs = t_cvs;
-    g.cvs_bits = t_cvs_bits;
-    g.cvs_no = d.no;
-    g.cvs_nv = d.nv;
+    g.tf = triple_filter(d, r, false);
     const int Kp = (d.NV + 3) / 4 * 4, Np = ((int)d.nv2 + 3) / 4 * 4;
     static const char *an[2] = {"mx_A0", "mx_A1"}, *bn[2] = {"mx_B0", "mx_B1"};
     for (int i = 0; i < nseg; i++) {
@@ -780,10 +873,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, hipStr
   g.nseg = nseg;
   g.dcontract = 1;
   g.persist = persist_grid(2);
-  g.cvs = t_cvs;
-  g.cvs_bits = t_cvs_bits;
-  g.cvs_no = d.no;
-  g.cvs_nv = d.nv;
+  g.tf = triple_filter(d, r, false);
   for (int i = 0; i < g.nseg; i++) {
     g.seg[i] = tseg(seg[i].x, plain(d.NV), 0, seg[i].G, d.nv2, (long long)d.NV * d.nv2, d.NV);
     g.seg[i].avec = seg[i].xv;
@@ -847,7 +937,7 @@ void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
   DSeg sg;
   sg.x = B(ws, "tA");
   sg.G = B(ws, "G1");
-  w_dterm(d, W, 1, &sg, 1, s);
+  w_dterm(d, W, 1, &sg, 1, r, s);
   OccTerm ot;
   occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1);
   const double zero = 0.0;
@@ -856,7 +946,10 @@ void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
 
 // Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
 // writes one partial product per k into P[k][(i,j,a)][n] and a fixed-order sum reduces them.
-void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N, double *Y, hipStream_t s) {
+// X~ vanishes on the ordered triples outside the range r (and the all-valence ones under
+// core-valence separation): the wide GEMM writes zero partial tiles there without computing.
+void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N, double *Y, const Range &r,
+             hipStream_t s) {
   const long long MN = (long long)d.no * d.no * d.nv * N;
   double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
   const Idx2 xrow = split(d.nv, (long long)d.no * d.nv3, d.nv2);
@@ -870,6 +963,7 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     g.cbatch = MN;
     g.nseg = 1;
     g.seg[0] = tseg(X, xrow, d.nv3, G, N, d.nv2 * N, (int)d.nv2);
+    g.tf = triple_filter(d, r, true);
     tgemm(g, s);
   } else {
     // narrow N (N_O): the generic GEMM picks 32-wide tiles
@@ -1045,7 +1139,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
   double *dOO = buf(ws, "dOO", (size_t)nc * NO * NO, s);
   double *dvV = buf(ws, "dvV", (size_t)nc * nv * NV, s);
   double *dvO = buf(ws, "dvO", (size_t)nc * nv * NO, s);
-  launch_dlhat(g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R.x1, nc, NO, NV, nv, dOO, dvV, dvO, s);
+  dlhat_blocks(d, g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R.x1, dOO, dvV, dvO, s);
   HIPRT(hipGetLastError());
   double *U1 = buf(ws, "U1", (size_t)(z.U1 * nb), s) + slot * z.U1;
   {
@@ -1064,7 +1158,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
     gemm(gg, s);
   }
   double *Ukc = buf(ws, "Ukc", (size_t)(z.Ukc * nb), s) + slot * z.Ukc;
-  launch_fock_like(g->L_OV, R.x1, nc, NO, NV, no, nv, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc, s);
+  fock_like(d, g->L_OV, R.x1, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc, s);
   double *Xi = buf(ws, "Xi", (size_t)(z.Xi * nb), s) + slot * z.Xi;
   {
     Gemm gg;
@@ -1092,7 +1186,7 @@ void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   sg[1].x = B(ws, "tA");
   sg[1].G = B(ws, "U1");
   sg[1].Gv = z.U1;
-  w_dterm(d, W, nb, sg, 2, s);
+  w_dterm(d, W, nb, sg, 2, r, s);
   std::vector<const double *> rb(nb);
   for (int v = 0; v < nb; v++) rb[v] = B(ws, "RB") + v * z.RB;
   long long xv = 0;
@@ -1126,7 +1220,7 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   sg.x = LA;
   sg.xv = sLA;
   sg.G = B(ws, "GL1");
-  w_dterm(d, W, nb, &sg, 1, s);
+  w_dterm(d, W, nb, &sg, 1, r, s);
   long long xv = 0;
   const double *LBxT = occ_xT(ws, d, lb.data(), nb, "LBxT", &xv, s);
   OccTerm ot;
@@ -1450,7 +1544,7 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
     double *XT = B(ws, "XT");
     double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
     double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
-    back_vV(ws, d, XT, B(ws, "Gb1"), d.NV, YvV, s);
+    back_vV(ws, d, XT, B(ws, "Gb1"), d.NV, YvV, r, s);
     gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
     finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
   });
@@ -1494,7 +1588,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     tau_path(ws, g, d, r, s);
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, s);
+    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
     // vectors in groups: R3 of a whole group in one d-contraction launch and one launch per
     // permutation pass, then the back-contractions vector by vector
     const int ng = group_size(ws, d, nvec);
@@ -1511,7 +1605,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
         // back-contractions
         double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
         double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-        back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, s);
+        back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, r, s);
         {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
           Gemm gg;
           gg.M = no * no * nv;
@@ -1570,7 +1664,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     tau_path(ws, g, d, r, s);
     double *XT = B(ws, "XT");
     double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, s);
+    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
     // vectors in groups: L3 of a whole group in one d-contraction launch and one launch per
     // permutation pass, then the back-contractions vector by vector
@@ -1590,7 +1684,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
         // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
         double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
         double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
-        back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, s);
+        back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, r, s);
         gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
              s);
         // intermediates of the singles

@@ -49,6 +49,39 @@ struct Gemm {
   int tm = 0, tn = 0;
 };
 
+// Position of the unique occupied triple i >= j >= k (not all equal) in the canonical list
+// (i outer, k inner, the all-equal triples left out): the triples before it with first index
+// below i number C(i+2,3) - i, those with first index i and second below j number j(j+1)/2.
+__host__ __device__ __forceinline__ long long canon_index(int i, int j, int k) {
+  return (long long)i * (i + 1) * (i + 2) / 6 - i + (long long)j * (j + 1) / 2 + k;
+}
+
+// Which ordered occupied triples a GEMM over rows (p,q,a) (p*no + q pairs, nv values of a per
+// pair) and batch r has to produce: the triple (p,q,r) is needed when it is not all-equal, its
+// canonical position lies in [tb, te), and (core != 0) one of p, q, r is a core orbital (bit of
+// core).  A tile none of whose rows is needed is skipped; with zero set it writes zeros instead
+// (for outputs that are summed over the batch afterwards).
+struct TripleFilter {
+  int on = 0, no = 0, nv = 0, zero = 0;
+  unsigned long long core = 0;
+  long long tb = 0, te = 0;
+};
+
+__device__ __forceinline__ bool triple_needed(const TripleFilter &f, int p, int q, int r) {
+  if (p == q && q == r) return false;
+  if (f.core && !(((f.core >> p) | (f.core >> q) | (f.core >> r)) & 1ULL)) return false;
+  const int i = max(p, max(q, r)), k = min(p, min(q, r)), j = p + q + r - i - k;
+  const long long c = canon_index(i, j, k);
+  return c >= f.tb && c < f.te;
+}
+
+// is any row of [m0, m1) of batch r needed?
+__device__ __forceinline__ bool tile_needed(const TripleFilter &f, int r, int m0, int m1) {
+  for (int pq = m0 / f.nv; pq <= (m1 - 1) / f.nv; pq++)
+    if (triple_needed(f, pq / f.no, pq % f.no, r)) return true;
+  return false;
+}
+
 // FP64 MFMA GEMM (v_mfma_f64_16x16x4_f64), LDS-staged, 256 threads per block.
 hipError_t gemm_f64(const Gemm &g, hipStream_t s);
 // C = alpha * sum_{part < ksplit} P[batch][part][M][N] + beta * C through g's output maps

@@ -33,11 +33,10 @@ struct TileGemm {
   long long cpart = 0;
   // persistent launch: at most this many workgroups, each looping over tiles (0: one per tile)
   int persist = 0;
-  // d-contraction under core-valence separation: rows are (p,q,a) with cvs_nv values of a per
-  // pair, pairs (p,q) = p*cvs_no + q, batch z = r; a tile whose (p,q,r) are all valence (no bit
-  // of cvs_bits) is skipped (its W rows are never read)
-  int cvs = 0, cvs_no = 0, cvs_nv = 0;
-  unsigned long long cvs_bits = 0;
+  // rows (p,q,a), batch r: tiles of ordered triples the call does not need (outside its triple
+  // range, or all valence under core-valence separation) are skipped, or written as zeros
+  // (tf.zero; only without beta)
+  TripleFilter tf;
 };
 
 hipError_t tile_gemm_f64(const TileGemm &g, hipStream_t s);

@@ -40,14 +40,6 @@ __device__ __forceinline__ long long moff(const Idx2 &f, int x) {
   return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
 }
 
-// does a d-contraction tile (rows [m0, m1) of (p,q,a), batch r) touch a core occupied index?
-__device__ __forceinline__ bool cvs_tile_kept(unsigned long long bits, int no, int nv, int r, int m0, int m1) {
-  if ((bits >> r) & 1ULL) return true;
-  for (int pq = m0 / nv; pq <= (m1 - 1) / nv; pq++)
-    if (((bits >> (pq / no)) | (bits >> (pq % no))) & 1ULL) return true;
-  return false;
-}
-
 template <bool AK, bool VEC, bool BETA>
 __device__ __forceinline__ void tile_body(const TileGemm &g) {
   __shared__ double As[2][AK ? BM * PA : BK * PB];
@@ -67,7 +59,8 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
     t -= grp * GM * nt;
     const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    if (g.cvs && !cvs_tile_kept(g.cvs_bits, g.cvs_no, g.cvs_nv, z, m0, min(g.M, m0 + BM))) continue;
+    const bool skip = g.tf.on && !tile_needed(g.tf, z, m0, min(g.M, m0 + BM));  // uniform per workgroup
+    if (skip && !g.tf.zero) continue;
 
     d4 acc[4][4];
 #pragma unroll
@@ -81,7 +74,7 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
     const int np = tid & 63, kr = tid >> 6;
     d2 ra[4], rb[4];
 
-    for (int s = 0; s < g.nseg; s++) {
+    for (int s = 0; s < (skip ? 0 : g.nseg); s++) {
       const TgSeg &sg = g.seg[s];
       // K slice [kb, K) of this part
       const int chunk = ((sg.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
@@ -251,6 +244,7 @@ hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
   if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
   if (g.dcontract && !g.ak) return hipErrorInvalidValue;
   if (g.ksplit < 1 || (g.ksplit > 1 && g.beta != 0.0)) return hipErrorInvalidValue;
+  if (g.tf.on && (g.tf.no < 1 || g.tf.nv < 1 || (g.tf.zero && g.beta != 0.0))) return hipErrorInvalidValue;
   const long long T = tile_gemm_blocks(g);
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
   // 16-byte loads need even offsets of every loaded pair and 16-byte aligned bases

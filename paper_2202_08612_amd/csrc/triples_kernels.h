@@ -41,12 +41,13 @@ struct DoublesRaw {
   int no = 0, nv = 0, NO = 0, NV = 0, delta = 0;
 };
 
-void launch_lhat(const double *LOO, const double *LOV, const double *LvV, const double *t1, int nc, int NO,
-                 int NV, int nv, double *LhOO, double *LhvV, double *LhVv, double *LhvO, hipStream_t s);
-void launch_dlhat(const double *LOV, const double *LhvV, const double *LhOO, const double *R1, int nc, int NO,
-                  int NV, int nv, double *dOO, double *dvV, double *dvO, hipStream_t s);
-void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV, int no, int nv,
-                      double *tmp_s, double *tmp_y, double *tmp_z, double *out, hipStream_t s);
+// LhvO[J][c][K] = L_OV[J][K][c] (first term of the T1-transformed vO block)
+void launch_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, double *LhvO, hipStream_t s);
+// s_J = sum_LD L^J_LD x^D_L
+void launch_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *tmp_s, hipStream_t s);
+// X_kc = sum_J (2 L^J_kc s_J - sum_L y^J_kL L^J_Lc) (fixed order over J)
+void launch_fock_finish(const double *LOV, const double *tmp_s, const double *tmp_y, int nc, int NO, int NV, int no,
+                        int nv, double *tmp_z, double *out, hipStream_t s);
 void launch_pack_vVoo(const double *x, int no, int nv, int NV, int rbar, double *xA, hipStream_t s);
 void launch_rbar_vvoO(const double *x, int no, int nv, int NO, double *xB, hipStream_t s);
 void launch_pack_vvoo(const double *x, int no, int nv, int NV, int mode, double *xV, hipStream_t s);

@@ -11,89 +11,13 @@ namespace mlcc3 {
 static inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 // ---------------------------------------------------------------- T1 transform
-// Lhat = (1 - T) L (1 + T) with T[N_O+A, I] = t^A_I (T1-transformed Hamiltonian);
-// blocks: OO, active-virtual rows (a,B), active-virtual columns (D,b), (c,K).
-__global__ void k_lhat_oo(const double *LOO, const double *LOV, const double *t1, int nc, int NO,
-                          int NV, double *LhOO) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * NO * NO) return;
-  const int K = id % NO, I = (id / NO) % NO;
-  const long long J = id / ((long long)NO * NO);
-  const double *lov = LOV + (J * NO + I) * NV;
-  double s = LOO[id];
-  for (int B = 0; B < NV; B++) s += lov[B] * t1[(long long)B * NO + K];
-  LhOO[id] = s;
-}
-
-__global__ void k_lhat_vV(const double *LvV, const double *LOV, const double *t1, int nc, int NO,
-                          int NV, int nv, double *LhvV) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * nv * NV) return;
-  const int B = id % NV, a = (id / NV) % nv;
-  const long long J = id / ((long long)nv * NV);
-  double s = LvV[id];
-  for (int I = 0; I < NO; I++) s -= t1[(long long)a * NO + I] * LOV[(J * NO + I) * NV + B];
-  LhvV[id] = s;
-}
-
-__global__ void k_lhat_Vv(const double *LvV, const double *LOV, const double *t1, int nc, int NO,
-                          int NV, int nv, double *LhVv) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * NV * nv) return;
-  const int b = id % nv, D = (id / nv) % NV;
-  const long long J = id / ((long long)nv * NV);
-  double s = LvV[(J * nv + b) * NV + D];  // L_Db = L_bD
-  for (int I = 0; I < NO; I++) s -= t1[(long long)D * NO + I] * LOV[(J * NO + I) * NV + b];
-  LhVv[id] = s;
-}
-
-// Lhat_cK = L_cK + sum_B L_cB t^B_K - sum_I t^c_I Lhat_IK   (Lhat_IK = L_IK + sum_B L_IB t^B_K)
-__global__ void k_lhat_vO(const double *LvV, const double *LOV, const double *t1, const double *LhOO,
-                          int nc, int NO, int NV, int nv, double *LhvO) {
+// first term of Lhat_vO: LhvO[J][c][K] = L_OV[J][K][c] (the GEMMs add the rest)
+__global__ void k_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, double *LhvO) {
   long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (id >= (long long)nc * nv * NO) return;
   const int K = id % NO, c = (id / NO) % nv;
   const long long J = id / ((long long)nv * NO);
-  double s = LOV[(J * NO + K) * NV + c];
-  const double *lv = LvV + (J * nv + c) * NV;
-  for (int B = 0; B < NV; B++) s += lv[B] * t1[(long long)B * NO + K];
-  for (int I = 0; I < NO; I++) s -= t1[(long long)c * NO + I] * LhOO[(J * NO + I) * NO + K];
-  LhvO[id] = s;
-}
-
-// one-index transformation with a singles vector R: dLhat = Lhat R - R Lhat
-__global__ void k_dl_oo(const double *LOV, const double *R1, int nc, int NO, int NV, double *dOO) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * NO * NO) return;
-  const int K = id % NO, I = (id / NO) % NO;
-  const long long J = id / ((long long)NO * NO);
-  const double *lov = LOV + (J * NO + I) * NV;
-  double s = 0.0;
-  for (int A = 0; A < NV; A++) s += lov[A] * R1[(long long)A * NO + K];
-  dOO[id] = s;
-}
-
-__global__ void k_dl_vV(const double *LOV, const double *R1, int nc, int NO, int NV, int nv, double *dvV) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * nv * NV) return;
-  const int B = id % NV, a = (id / NV) % nv;
-  const long long J = id / ((long long)nv * NV);
-  double s = 0.0;
-  for (int I = 0; I < NO; I++) s -= R1[(long long)a * NO + I] * LOV[(J * NO + I) * NV + B];
-  dvV[id] = s;
-}
-
-__global__ void k_dl_vO(const double *LhvV, const double *LhOO, const double *R1, int nc, int NO, int NV,
-                        int nv, double *dvO) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * nv * NO) return;
-  const int K = id % NO, c = (id / NO) % nv;
-  const long long J = id / ((long long)nv * NO);
-  const double *lv = LhvV + (J * nv + c) * NV;
-  double s = 0.0;
-  for (int B = 0; B < NV; B++) s += lv[B] * R1[(long long)B * NO + K];
-  for (int I = 0; I < NO; I++) s -= R1[(long long)c * NO + I] * LhOO[(J * NO + I) * NO + K];
-  dvO[id] = s;
+  LhvO[id] = LOV[(J * NO + K) * NV + c];
 }
 
 // --------------------------------------------- X_kc = sum_LD (2 g_kcLD - g_kDLc) x^D_L
@@ -115,17 +39,6 @@ __global__ void k_fock_s(const double *LOV, const double *x, int nc, int NO, int
     __syncthreads();
   }
   if (threadIdx.x == 0) s[J] = red[0];
-}
-
-__global__ void k_fock_y(const double *LOV, const double *x, int nc, int NO, int NV, int no, double *y) {
-  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)nc * no * NO) return;
-  const int L = id % NO, k = (id / NO) % no;
-  const long long J = id / ((long long)no * NO);
-  const double *l = LOV + (J * NO + k) * NV;
-  double s = 0.0;
-  for (int D = 0; D < NV; D++) s += l[D] * x[(long long)D * NO + L];
-  y[id] = s;
 }
 
 __global__ void k_fock_z(const double *LOV, const double *s, const double *y, int nc, int NO, int NV, int no,
@@ -858,27 +771,16 @@ __global__ void k_transpose(const double *__restrict__ in, double *__restrict__ 
 #define L1D(kern, n, ...) \
   do { if (!g_dry && (n) > 0) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(256), 0, s, __VA_ARGS__); } while (0)
 
-void launch_lhat(const double *LOO, const double *LOV, const double *LvV, const double *t1, int nc, int NO,
-                 int NV, int nv, double *LhOO, double *LhvV, double *LhVv, double *LhvO, hipStream_t s) {
-  L1D(k_lhat_oo, (long long)nc * NO * NO, LOO, LOV, t1, nc, NO, NV, LhOO);
-  if (nv > 0) {
-    L1D(k_lhat_vV, (long long)nc * nv * NV, LvV, LOV, t1, nc, NO, NV, nv, LhvV);
-    L1D(k_lhat_Vv, (long long)nc * NV * nv, LvV, LOV, t1, nc, NO, NV, nv, LhVv);
-    L1D(k_lhat_vO, (long long)nc * nv * NO, LvV, LOV, t1, LhOO, nc, NO, NV, nv, LhvO);
-  }
+void launch_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, double *LhvO, hipStream_t s) {
+  L1D(k_lhat_vO_init, (long long)nc * nv * NO, LOV, nc, NO, NV, nv, LhvO);
 }
 
-void launch_dlhat(const double *LOV, const double *LhvV, const double *LhOO, const double *R1, int nc, int NO,
-                  int NV, int nv, double *dOO, double *dvV, double *dvO, hipStream_t s) {
-  L1D(k_dl_oo, (long long)nc * NO * NO, LOV, R1, nc, NO, NV, dOO);
-  L1D(k_dl_vV, (long long)nc * nv * NV, LOV, R1, nc, NO, NV, nv, dvV);
-  L1D(k_dl_vO, (long long)nc * nv * NO, LhvV, LhOO, R1, nc, NO, NV, nv, dvO);
+void launch_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *tmp_s, hipStream_t s) {
+  if (!g_dry && nc > 0) hipLaunchKernelGGL(k_fock_s, dim3(nc), dim3(256), 0, s, LOV, x, nc, NO, NV, tmp_s);
 }
 
-void launch_fock_like(const double *LOV, const double *x, int nc, int NO, int NV, int no, int nv,
-                      double *tmp_s, double *tmp_y, double *tmp_z, double *out, hipStream_t s) {
-  if (!g_dry) hipLaunchKernelGGL(k_fock_s, dim3(nc), dim3(256), 0, s, LOV, x, nc, NO, NV, tmp_s);
-  L1D(k_fock_y, (long long)nc * no * NO, LOV, x, nc, NO, NV, no, tmp_y);
+void launch_fock_finish(const double *LOV, const double *tmp_s, const double *tmp_y, int nc, int NO, int NV, int no,
+                        int nv, double *tmp_z, double *out, hipStream_t s) {
   L1D(k_fock_z, (long long)nc * no * nv, LOV, tmp_s, tmp_y, nc, NO, NV, no, nv, tmp_z);
   L1D(k_sum_rows, (long long)no * nv, tmp_z, (long long)nc, (long long)no * nv, out);
 }
