@@ -427,20 +427,6 @@ Seg seg(const double *A, Idx2 arow, Idx2 acol, long long abatch, const double *B
 }
 
 // ------------------------------------------------------ Cholesky assemblies
-// vVvo-kind: C[k][D][b][c] = sum_J A^J_bD B^J_ck  (A: [nc][nv][NV], B: [nc][nv][NO])
-Gemm asm_vVvo(const Dims &d, double *C) {
-  Gemm g;
-  g.M = d.nv * d.NV;  // m = b*NV + D
-  g.N = d.nv * d.no;  // n = c*no + k
-  g.crow = split(d.NV, d.nv, d.nv2);
-  g.ccol = split(d.no, 1, (long long)d.NV * d.nv2);
-  g.C = C;
-  return g;
-}
-Seg asm_vVvo_seg(const Dims &d, const double *A, const double *B) {
-  return seg(A, plain(1), plain((long long)d.nv * d.NV), 0, B, plain((long long)d.nv * d.NO), split(d.no, d.NO, 1),
-             0, d.nc);
-}
 // oovo-kind: C[L][j][k][c] = sum_J A^J_Lj B^J_ck  (A: [nc][NO][NO], B: [nc][nv][NO])
 Gemm asm_oovo(const Dims &d, double *C) {
   Gemm g;
@@ -537,6 +523,36 @@ void fock_like(const Dims &d, const double *LOV, const double *x, double *tmp_s,
   launch_fock_finish(LOV, tmp_s, tmp_y, nc, NO, NV, no, nv, tmp_z, out, s);
 }
 
+// vVvo-kind integral block C[k][D][b][c] = sum_J sum_seg A_seg[J][b][D] B_seg[J][c][k]
+// (A: [nc][nv][NV], B: [nc][nv][NO], active k < n_o) through the large-tile GEMM: the active
+// columns of B are packed to [nc][nv][n_o], the product (rows (b,D), columns (c,k), K = nc)
+// goes to a scratch block, which one pass then permutes into the [k][D][b][c] layout
+void vVvo_tiled(mlcc3_ws ws, const Dims &d, int nseg, const double *const *A, const double *const *Bfull, double *C,
+                hipStream_t s) {
+  const int nc = d.nc, nv = d.nv, NV = d.NV, NO = d.NO, no = d.no;
+  const long long M = (long long)nv * NV, N = (long long)nv * no;
+  if (M <= 0 || N <= 0) return;
+  static const char *pn[2] = {"vvvo_b0", "vvvo_b1"};
+  double *T = buf(ws, "vvvo_tmp", (size_t)(M * N), s);
+  TileGemm g;
+  g.M = (int)M;
+  g.N = (int)N;
+  g.nseg = nseg;
+  g.ak = 0;
+  g.C = T;
+  g.cmap = plain(N);
+  for (int i = 0; i < nseg; i++) {
+    double *Bp = buf(ws, pn[i], (size_t)nc * nv * no, s);
+    check_bytes(Bp, sizeof(double) * nc * nv * no, "packed B (vVvo)");
+    launch_pack_cols(Bfull[i], (long long)nc * nv, NO, no, Bp, s);
+    g.seg[i] = tseg(A[i], plain(M), 0, Bp, N, 0, nc);
+  }
+  tgemm(g, s);
+  check_bytes(C, sizeof(double) * M * N, "vVvo block");
+  launch_vvvo_permute(T, no, nv, NV, C, s);
+  HIPRT(hipGetLastError());
+}
+
 // -------------------------------------------------------------- ground prep
 bool same_ground(const mlcc3_ground &a, const mlcc3_ground &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
 
@@ -555,10 +571,8 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   // G1[k][D][b][c] = ghat_bDck
   double *G1 = buf(ws, "G1", (size_t)no * NV * d.nv2, s);
   {
-    Gemm gg = asm_vVvo(d, G1);
-    gg.nseg = 1;
-    gg.seg[0] = asm_vVvo_seg(d, LhvV, LhvO);
-    gemm(gg, s);
+    const double *A[1] = {LhvV}, *Bv[1] = {LhvO};
+    vVvo_tiled(ws, d, 1, A, Bv, G1, s);
   }
   // G2[L][j][k][c] = ghat_Ljck
   double *G2 = buf(ws, "G2", (size_t)NO * no * no * nv, s);
@@ -1143,11 +1157,8 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
   HIPRT(hipGetLastError());
   double *U1 = buf(ws, "U1", (size_t)(z.U1 * nb), s) + slot * z.U1;
   {
-    Gemm gg = asm_vVvo(d, U1);
-    gg.nseg = 2;
-    gg.seg[0] = asm_vVvo_seg(d, dvV, B(ws, "LhvO"));
-    gg.seg[1] = asm_vVvo_seg(d, B(ws, "LhvV"), dvO);
-    gemm(gg, s);
+    const double *A[2] = {dvV, B(ws, "LhvV")}, *Bv[2] = {B(ws, "LhvO"), dvO};
+    vVvo_tiled(ws, d, 2, A, Bv, U1, s);
   }
   double *Uo = buf(ws, "Uo", (size_t)(z.Uo * nb), s) + slot * z.Uo;
   {

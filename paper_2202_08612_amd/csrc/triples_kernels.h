@@ -41,6 +41,10 @@ struct DoublesRaw {
   int no = 0, nv = 0, NO = 0, NV = 0, delta = 0;
 };
 
+// dst[r][k] = src[r*ld + k] for k < nk (packs the first nk columns of each row)
+void launch_pack_cols(const double *src, long long rows, int ld, int nk, double *dst, hipStream_t s);
+// C[k][D][b][c] = T[(b*NV + D)][(c*no + k)]
+void launch_vvvo_permute(const double *T, int no, int nv, int NV, double *C, hipStream_t s);
 // LhvO[J][c][K] = L_OV[J][K][c] (first term of the T1-transformed vO block)
 void launch_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, double *LhvO, hipStream_t s);
 // s_J = sum_LD L^J_LD x^D_L

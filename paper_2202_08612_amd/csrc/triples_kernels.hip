@@ -28,9 +28,9 @@ __global__ void k_fock_s(const double *LOV, const double *x, int nc, int NO, int
   __shared__ double red[256];
   double acc = 0.0;
   const double *l = LOV + (long long)J * NO * NV;
-  for (int e = threadIdx.x; e < NO * NV; e += blockDim.x) {
-    const int L = e / NV, D = e % NV;
-    acc += l[e] * x[(long long)D * NO + L];
+  for (int L = 0; L < NO; L++) {
+    const double *row = l + (long long)L * NV;
+    for (int D = threadIdx.x; D < NV; D += 256) acc += row[D] * x[(long long)D * NO + L];
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -770,6 +770,33 @@ __global__ void k_transpose(const double *__restrict__ in, double *__restrict__ 
 // ------------------------------------------------------------- host launchers
 #define L1D(kern, n, ...) \
   do { if (!g_dry && (n) > 0) hipLaunchKernelGGL(kern, dim3(nblk(n)), dim3(256), 0, s, __VA_ARGS__); } while (0)
+
+// dst[r][k] = src[r][k] for k < nk of rows of length ld
+__global__ void k_pack_cols(const double *src, long long rows, int ld, int nk, double *dst) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= rows * nk) return;
+  const long long r = id / nk;
+  dst[id] = src[r * ld + (id - r * nk)];
+}
+
+// C[k][D][b][c] = T[(b*NV + D)][(c*no + k)]
+__global__ void k_vvvo_permute(const double *T, int no, int nv, int NV, double *C) {
+  long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long nv2 = (long long)nv * nv;
+  if (id >= (long long)no * NV * nv2) return;
+  const int c = id % nv, b = (id / nv) % nv;
+  const long long kD = id / nv2;
+  const int D = kD % NV, k = kD / NV;
+  C[id] = T[((long long)b * NV + D) * ((long long)nv * no) + (long long)c * no + k];
+}
+
+void launch_pack_cols(const double *src, long long rows, int ld, int nk, double *dst, hipStream_t s) {
+  L1D(k_pack_cols, rows * nk, src, rows, ld, nk, dst);
+}
+
+void launch_vvvo_permute(const double *T, int no, int nv, int NV, double *C, hipStream_t s) {
+  L1D(k_vvvo_permute, (long long)no * NV * nv * nv, T, no, nv, NV, C);
+}
 
 void launch_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, double *LhvO, hipStream_t s) {
   L1D(k_lhat_vO_init, (long long)nc * nv * NO, LOV, nc, NO, NV, nv, LhvO);
