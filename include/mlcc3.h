@@ -113,7 +113,10 @@ typedef struct {
 
 typedef struct mlcc3_ws_s *mlcc3_ws;
 
-/* Workspace: device scratch and the cached ground-state blocks, bound to `device`. */
+/* Workspace: device scratch and the cached ground-state blocks, bound to `device`.  Every
+ * compute entry point also accepts ws = NULL: the call then runs on a temporary workspace on
+ * the current device, prepares the ground-state blocks itself (reuse_ground has no effect) and
+ * waits for the device to finish before it returns and frees that workspace. */
 int mlcc3_ws_create(mlcc3_ws *ws, int device);
 int mlcc3_ws_destroy(mlcc3_ws ws);
 /* Bytes of device memory currently held by the workspace. */

@@ -1381,6 +1381,31 @@ int64_t mlcc3_num_triples(int32_t n_o) {
   return n * (n + 1) * (n + 2) / 6 - n;
 }
 
+// workspace of a call: the caller's, or (NULL) a temporary one on the current device that is
+// destroyed, after the device has finished the call's work, when the call returns
+struct CallWs {
+  mlcc3_ws ws = nullptr;
+  bool own = false;
+  explicit CallWs(mlcc3_ws w) {
+    if (w) {
+      ws = w;
+      return;
+    }
+    int dev = 0;
+    if (!g_dry) HIPRT(hipGetDevice(&dev));
+    ws = new mlcc3_ws_s();
+    ws->device = dev;
+    own = true;
+  }
+  ~CallWs() {
+    if (!own) return;
+    if (t_ws == ws) t_ws = nullptr;
+    (void)mlcc3_ws_destroy(ws);
+  }
+  CallWs(const CallWs &) = delete;
+  CallWs &operator=(const CallWs &) = delete;
+};
+
 int mlcc3_ws_create(mlcc3_ws *ws, int device) {
   return guarded([&] {
     check(ws != nullptr, "ws is NULL");
@@ -1475,7 +1500,8 @@ int mlcc3_oscillator_strengths(mlcc3_ws ws, int32_t N, int32_t ncomp, const doub
                                const double *omega, const double *D_m0, const double *D_0m, const double *D_00,
                                const double *s, double *T_m0, double *T_0m, double *f, void *stream) {
   return guarded([&] {
-    check(ws != nullptr, "ws is NULL");
+    CallWs call_ws(ws);  // NULL: a temporary workspace for this call
+    ws = call_ws.ws;
     check(N >= 1 && ncomp >= 1 && nstate >= 1, "need N, ncomp, nstate >= 1");
     check(A && omega && D_m0 && D_0m && D_00 && s && T_m0 && T_0m && f, "NULL argument");
     for (int m = 0; m < nstate; m++) check(std::isfinite(omega[m]), "omega must be finite");
@@ -1494,7 +1520,8 @@ int mlcc3_oscillator_strengths(mlcc3_ws ws, int32_t N, int32_t ncomp, const doub
 int mlcc3_vec_map(mlcc3_ws ws, const mlcc3_ground *g, int32_t mode, int32_t nvec, const mlcc3_vec *in,
                   mlcc3_out *out, void *stream) {
   return guarded([&] {
-    check(ws != nullptr, "ws is NULL");
+    CallWs call_ws(ws);  // NULL: a temporary workspace for this call
+    ws = call_ws.ws;
     check(g != nullptr, "ground is NULL");
     check(g->N_O >= 1 && g->N_V >= 1 && g->n_o >= 0 && g->n_o <= g->N_O && g->n_v >= 0 && g->n_v <= g->N_V,
           "bad dimensions");
@@ -1532,7 +1559,8 @@ double mlcc3_flops(const mlcc3_ground *g, int32_t which, int32_t nvec) {
 int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *opts, mlcc3_out *out,
                           void *stream) {
   return guarded([&] {
-    check(ws != nullptr, "ws is NULL");
+    CallWs call_ws(ws);  // NULL: a temporary workspace for this call
+    ws = call_ws.ws;
     t_ws = ws;
     t_stream = (hipStream_t)stream;
     validate_ground(g);
@@ -1564,7 +1592,8 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
 int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
                           const mlcc3_vec *R, mlcc3_out *rho, const mlcc3_opts *opts, void *stream) {
   return guarded([&] {
-    check(ws != nullptr, "ws is NULL");
+    CallWs call_ws(ws);  // NULL: a temporary workspace for this call
+    ws = call_ws.ws;
     t_ws = ws;
     t_stream = (hipStream_t)stream;
     validate_ground(g);
@@ -1641,7 +1670,8 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
 int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const double *omega,
                          const mlcc3_vec *L, mlcc3_out *sigma, const mlcc3_opts *opts, void *stream) {
   return guarded([&] {
-    check(ws != nullptr, "ws is NULL");
+    CallWs call_ws(ws);  // NULL: a temporary workspace for this call
+    ws = call_ws.ws;
     t_ws = ws;
     t_stream = (hipStream_t)stream;
     validate_ground(g);
@@ -1844,7 +1874,8 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
                             const mlcc3_vec *lambda, double *D_m0, double *D_0m, double *s_out,
                             const mlcc3_opts *opts, void *stream) {
   return guarded([&] {
-    check(ws != nullptr, "ws is NULL");
+    CallWs call_ws(ws);  // NULL: a temporary workspace for this call
+    ws = call_ws.ws;
     t_ws = ws;
     t_stream = (hipStream_t)stream;
     validate_ground(g);

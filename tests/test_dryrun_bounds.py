@@ -174,3 +174,19 @@ def test_tuned_launches_in_bounds(lib, d, tune):
             rc = getattr(lib, fn)(ws, ctypes.byref(g), nvec, om, vin, vout, ctypes.byref(o), None)
             assert rc == 0, (fn, lib.mlcc3_last_error())
     assert lib.mlcc3_ws_destroy(ws) == 0
+
+
+def test_null_workspace_runs_on_a_temporary_one(lib):
+    """A NULL workspace is accepted by the compute entry points (a temporary one is used)."""
+    d = I.Dims(5, 17, 7, 37, 23)
+    p = _fake(64)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:8])
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    out = (V * 1)(V(*p[8:11]))
+    assert lib.mlcc3_ground_residual(None, ctypes.byref(g), ctypes.byref(o), out, None) == 0, lib.mlcc3_last_error()
+    vin = (V * 2)(*[V(*p[11 + 3 * m: 14 + 3 * m]) for m in range(2)])
+    vout = (V * 2)(*[V(*p[30 + 3 * m: 33 + 3 * m]) for m in range(2)])
+    om = (ctypes.c_double * 2)(0.4, 0.5)
+    for fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
+        assert getattr(lib, fn)(None, ctypes.byref(g), 2, om, vin, vout, ctypes.byref(o), None) == 0, fn

@@ -310,6 +310,61 @@ def test_cvs_right_left(lib, ws, d, core):
     assert e.value.code == lib.EINVAL
 
 
+def test_null_workspace(lib, ws):
+    """A call without a workspace (NULL through the C-ABI) gives the same results as one with."""
+    import torch
+
+    class NoWorkspace:
+        h = None
+        device = torch.device("cuda", 0)
+
+    d = I.Dims(5, 17, 7, 37, 23)
+    p = I.make_problem(d, 77)
+    g = lib.Ground(p)
+    R = [lib.vec_to_device(v) for v in I.right_vectors(p, 2)]
+    om = I.omegas(False, 2)
+    a = lib.right_transform(ws, g, om, R)
+    b = lib.right_transform(NoWorkspace(), g, om, R)
+    c = lib.ground_residual(NoWorkspace(), g)
+    e = lib.ground_residual(ws, g, reuse_ground=True)
+    for m in range(2):
+        for k in a[m]:
+            assert torch.equal(a[m][k], b[m][k]), (m, k)
+    for k in c:
+        assert torch.equal(c[k], e[k]), k
+
+
+def test_cvs_with_triple_ranges(lib, ws):
+    """Core-valence separation combined with triple ranges (the d-contraction and N_V-wide
+    back-contraction tiles of unneeded ordered triples are skipped): each range against the
+    oracle over the same range, and the ranges add up to the whole CVS transform."""
+    from oracle.oracle import Oracle
+    d = I.Dims(5, 48, 7, 61, 19)
+    core = [0, 1, 0, 0, 0, 0, 0]
+    p = I.make_problem(d, 73, core=True)
+    orc = Oracle(p, cvs_core=core)
+    g = lib.Ground(p)
+    R, L = I.right_vectors(p, 1)[0], I.left_vectors(p, 1)[0]
+    w = 15.2
+    nt = lib.num_triples(d.n_o)
+    full_r = lib.right_transform(ws, g, [w], [lib.vec_to_device(R)], cvs_core=core)[0]
+    full_l = lib.left_transform(ws, g, [w], [lib.vec_to_device(L)], cvs_core=core, reuse_ground=True)[0]
+    parts_r, parts_l = [], []
+    for rng in ((0, 9), (9, 24), (24, nt)):
+        r = lib.right_transform(ws, g, [w], [lib.vec_to_device(R)], cvs_core=core, triple_range=rng,
+                                reuse_ground=True)[0]
+        l = lib.left_transform(ws, g, [w], [lib.vec_to_device(L)], cvs_core=core, triple_range=rng,
+                               reuse_ground=True)[0]
+        _check(r, orc.right_transform(w, R, *rng))
+        _check(l, orc.left_transform(w, L, *rng))
+        parts_r.append(r)
+        parts_l.append(l)
+    for full, parts in ((full_r, parts_r), (full_l, parts_l)):
+        for k in full:
+            tot = sum(x[k] for x in parts)
+            assert float((tot - full[k]).norm() / full[k].norm()) < 1e-12, k
+
+
 def test_cvs_full_config4(lib, ws):
     """Core-shaped workload at full size with its core orbital as the CVS core: the adjoint identity
     inside the CVS space, outputs in the CVS space, the mixed form within 1e-6."""
