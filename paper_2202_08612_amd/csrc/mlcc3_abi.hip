@@ -1623,7 +1623,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     cvs_setup(ws, g, o, nvec, R_in, &Rp, s);
     const mlcc3_vec *R = Rp.empty() ? R_in : Rp.data();
     prepare_ground(ws, g, o.reuse_ground != 0, s);
-    const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
+    const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
     // tau~ and Xtau[(i,j,a)][L] = sum tau~ g_Lbkc (shared by all vectors)
     tau_path(ws, g, d, r, s);
     double *XT = B(ws, "XT");

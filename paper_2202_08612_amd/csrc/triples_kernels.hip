@@ -35,7 +35,7 @@ __global__ void k_fock_s(const double *LOV, const double *x, int nc, int NO, int
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) s[J] = red[0];
@@ -108,7 +108,7 @@ __global__ void k_dot_partial(const double *a, const double *b, long long n, dou
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -140,7 +140,7 @@ __global__ void k_moments(const double *__restrict__ A, long long NN, int ncomp,
   r3[threadIdx.x] = s3;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       r1[threadIdx.x] += r1[threadIdx.x + w];
       r2[threadIdx.x] += r2[threadIdx.x + w];
       r3[threadIdx.x] += r3[threadIdx.x + w];
