@@ -58,6 +58,8 @@ def parse():
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
     ap.add_argument("--cpu-triples", type=int, default=48, help="unique triples in the CPU-baseline sample")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="time the guanine-shaped active spaces of the paper's core-state table (context)")
     ap.add_argument("--nv-sweep", action="store_true",
                     help="instead of the step: time the ground residual, right and left transforms and the "
                          "densities at a fixed active space (n_o=8, n_v=136) over six inactive-space sizes "
@@ -78,6 +80,62 @@ def unit_flops(d, tb, te):
                     n += len({(i, j, k), (j, i, k), (k, j, i), (i, k, j), (k, i, j), (j, k, i)})
                 t += 1
     return 2.0 * d.N_V * d.n_v ** 3 * n
+
+
+# Guanine core-state series of the paper (Table t:Gua_1state): full space N_O/N_V = 39/263,
+# times in seconds per call of the triples part on 2x Intel Xeon Gold 6138 (40 threads); R and
+# L with core-valence loop skipping.  Context only: real molecules, eT, precision not stated.
+PAPER_GUANINE = {(10, 100): {"right_transform": 1.72, "left_transform": 1.86, "ground_residual": 3.03,
+                             "densities": 3.68 + 7.29},
+                 (13, 130): {"right_transform": 4.82, "left_transform": 5.27, "ground_residual": 10.72}}
+
+
+def paper_shapes(args):
+    """The guanine-shaped active spaces of the paper's core-state table on synthetic inputs
+    (core-like orbital 0, Cholesky rank 3 (N_O + N_V)): time per call next to the paper's CPU
+    seconds.  R and L run with core-valence separation, as in the paper's core-state runs."""
+    import numpy as np
+    import torch
+    from paper_2202_08612_amd import inputs as I
+    from paper_2202_08612_amd import mlcc3
+    dev = torch.device("cuda", 0)
+    NO, NV = 39, 263
+    for (no, nv), paper in PAPER_GUANINE.items():
+        ws = mlcc3.Workspace(0)
+        d = I.Dims(no, nv, NO, NV, 3 * (NO + NV))
+        p = I.make_problem(d, 20220217 + 200 + no, core=True, with_density_blocks="densities" in paper)
+        g = mlcc3.Ground(p, dev)
+        R = [mlcc3.vec_to_device(I.right_vectors(p, 1)[0], dev)]
+        L = [mlcc3.vec_to_device(I.left_vectors(p, 1)[0], dev)]
+        w = float(I.omegas(True, 1)[0])
+        core = [1] + [0] * (NO - 1)
+        calls = {
+            "ground_residual": lambda: mlcc3.ground_residual(ws, g, reuse_ground=True),
+            "right_transform": lambda: mlcc3.right_transform(ws, g, [w], R, reuse_ground=True, cvs_core=core),
+            "left_transform": lambda: mlcc3.left_transform(ws, g, [w], L, reuse_ground=True, cvs_core=core),
+        }
+        if "densities" in paper:
+            lam = mlcc3.vec_to_device(I.lambda_vector(p), dev)
+            calls["densities"] = lambda: mlcc3.triples_densities(ws, g, [w], L, R, lam, p.t2_vVoO, p.t2_vVOo,
+                                                                 reuse_ground=True)
+        row = {"n_o": no, "n_v": nv, "N_O": NO, "N_V": NV, "n_chol": d.n_chol}
+        mlcc3.ground_residual(ws, g)  # prepares the ground-state blocks
+        for name, fn in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(max(1, args.steps)):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[name + "_s"] = round(float(np.median(ts)), 4)
+            row[name + "_paper_s"] = paper[name]
+        print(json.dumps({"paper_shapes": row, "paper_hardware": "2x Intel Xeon Gold 6138, 40 threads (context)"}),
+              flush=True)
+        ws.close()
+        del g, p, ws
+        torch.cuda.empty_cache()
 
 
 def nv_sweep(args):
@@ -207,6 +265,9 @@ def main():
               f"(the multi-GPU layout, sharding unique occupied triples, is design only)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.paper_shapes:
+        paper_shapes(args)
+        return
     if args.nv_sweep:
         nv_sweep(args)
         return
