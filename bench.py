@@ -224,6 +224,31 @@ def mixed_report(args, d, flops_step, dt64, outs64, timed, L, form):
             "within_1e-6": ok, "errors": err}
 
 
+def iteration_report(args, ws, g, w, R, L):
+    """One Davidson-style iteration of the FP64 path, right + left transform of the vector pair:
+    with the tau~ blocks formed inside each call (as in the timed step) and kept in HBM across
+    calls (opts.reuse_tau).  Time only: the second form does less work."""
+    import torch
+    from paper_2202_08612_amd import mlcc3
+
+    def run(reuse):
+        mlcc3.right_transform(ws, g, [w], R, reuse_ground=True, reuse_tau=reuse)
+        mlcc3.left_transform(ws, g, [w], L, reuse_ground=True, reuse_tau=reuse)
+
+    ms = {}
+    for reuse in (False, True):
+        run(reuse)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run(reuse)
+        torch.cuda.synchronize()
+        ms[reuse] = (time.perf_counter() - t0) / args.steps * 1e3
+    return {"right_left_ms": round(ms[False], 3), "right_left_reuse_tau_ms": round(ms[True], 3),
+            "speedup": round(ms[False] / ms[True], 3),
+            "note": "tau~ (3.0 GB at this size) kept in HBM across calls; not part of value"}
+
+
 def dcontract_traffic(d):
     import hashlib
     path = os.path.join(ROOT, "paper_2202_08612_amd", "csrc", "tile_gemm_f64.hip")
@@ -350,6 +375,7 @@ def main():
                      "launches": st["launches"], "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 4)},
         "cpu_baseline": None,
     }
+    res["iteration"] = iteration_report(args, ws, g, w, R, L)
     if not args.no_mixed:
         res["mixed"] = {form: mixed_report(args, d, flops_step, dt, outs, timed, L, form) for form in MIXED_FORMS}
     if not args.no_cpu_baseline:

@@ -109,6 +109,14 @@ typedef struct {
                              elements with at least one core occupied index; the d-contraction
                              skips its all-valence tiles.  Needs n_o <= 64.  The ground residual
                              and the densities reject it (MLCC3_EINVAL). */
+  int32_t reuse_tau;      /* nonzero (with reuse_ground): the ground residual and the right and
+                             left transforms reuse the tau~ blocks (ground-state triples
+                             amplitudes, contravariant, all ordered triples, kept in the
+                             workspace) that an earlier call on this workspace formed for the same
+                             ground state, triple range, core-valence setting and precision,
+                             instead of forming them again (the tau3 d-contraction and
+                             permutation passes are skipped; results are unchanged).  Any
+                             preparation of a new ground state discards them. */
 } mlcc3_opts;
 
 typedef struct mlcc3_ws_s *mlcc3_ws;

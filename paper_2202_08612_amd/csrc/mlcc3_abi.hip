@@ -85,6 +85,13 @@ struct mlcc3_ws_s {
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   mlcc3_tuning tune{};  // launch-shape choices (0 = default)
+  // what the tau~ blocks ("XT", and "Xtau" when xtau) were last formed for (opts.reuse_tau)
+  struct TauKey {
+    bool valid = false, xtau = false;
+    long long tb = 0, te = 0;
+    int prec = 0, cvs = 0;
+    unsigned long long core = 0;
+  } tau;
 };
 
 namespace {
@@ -559,6 +566,7 @@ bool same_ground(const mlcc3_ground &a, const mlcc3_ground &b) { return std::mem
 void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t s) {
   if (reuse && ws->prepared && same_ground(ws->key, *g)) return;
   ws->prepared = false;
+  ws->tau = mlcc3_ws_s::TauKey{};
   const Dims d = dims_of(g);
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
   double *LhOO = buf(ws, "LhOO", (size_t)nc * NO * NO, s);
@@ -944,8 +952,25 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
   HIPRT(hipGetLastError());
 }
 
-// tau~ for all ordered triples into "XT" (and covariant tau into Xc when given)
-void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s, double *Xc = nullptr) {
+// tau~ for all ordered triples into "XT" (and covariant tau into Xc when given).  With reuse,
+// the blocks an earlier call on this workspace formed for the same prepared ground state, triple
+// range, core-valence setting and precision are kept (returns true) instead of formed again.
+bool tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStream_t s, double *Xc = nullptr,
+              bool reuse = false) {
+  mlcc3_ws_s::TauKey key;
+  key.valid = true;
+  key.tb = r.tb;
+  key.te = r.te;
+  key.prec = t_prec;
+  key.cvs = t_cvs;
+  key.core = t_cvs ? t_cvs_bits : 0;
+  const mlcc3_ws_s::TauKey &k = ws->tau;
+  if (reuse && !Xc && k.valid && k.tb == key.tb && k.te == key.te && k.prec == key.prec && k.cvs == key.cvs &&
+      k.core == key.core) {
+    (void)buf(ws, "XT", (size_t)(d.nord * d.nv3), s);  // registers the kept buffer for the bounds checks
+    return true;
+  }
+  ws->tau = mlcc3_ws_s::TauKey{};
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
   double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
   DSeg sg;
@@ -956,7 +981,10 @@ void tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
   occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1);
   const double zero = 0.0;
   permute(ws, d, W, XT, g->eps_o, g->eps_v, &zero, 1, r, LocalTerms{}, ot, s, Xc);
+  ws->tau = key;
+  return false;
 }
+
 
 // Y[(i,j,a)][n] = sum_{k,bc} X~[i][j][k][a][b][c] G_k((b,c), n), split over k: the GEMM
 // writes one partial product per k into P[k][(i,j,a)][n] and a fixed-order sum reduces them.
@@ -995,6 +1023,16 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
   }
   launch_sum_rows(P, d.no, MN, Y, s);
   HIPRT(hipGetLastError());
+}
+
+// Xtau[(i,j,a)][L] = sum tau~ g_Lbkc, kept with the tau~ blocks it was formed from
+double *xtau_block(mlcc3_ws ws, const Dims &d, const double *XT, bool tau_kept, const Range &r, hipStream_t s) {
+  double *Xtau = buf(ws, "Xtau", (size_t)d.no * d.no * d.nv * d.NO, s);
+  if (!(tau_kept && ws->tau.xtau)) {
+    back_vV(ws, d, XT, B(ws, "gLb"), d.NO, Xtau, r, s);
+    ws->tau.xtau = true;
+  }
+  return Xtau;
 }
 
 // the workspace's tile choice for the N_O-wide back-contractions
@@ -1579,7 +1617,7 @@ int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
       return;
     }
     prepare_ground(ws, g, o.reuse_ground != 0, s);
-    tau_path(ws, g, d, r, s);
+    tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
     double *XT = B(ws, "XT");
     double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
     double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
@@ -1625,10 +1663,9 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     prepare_ground(ws, g, o.reuse_ground != 0, s);
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
     // tau~ and Xtau[(i,j,a)][L] = sum tau~ g_Lbkc (shared by all vectors)
-    tau_path(ws, g, d, r, s);
+    const bool tau_kept = tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
     double *XT = B(ws, "XT");
-    double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
+    double *Xtau = xtau_block(ws, d, XT, tau_kept, r, s);
     // vectors in groups: R3 of a whole group in one d-contraction launch and one launch per
     // permutation pass, then the back-contractions vector by vector
     const int ng = group_size(ws, d, nvec);
@@ -1702,10 +1739,9 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     const mlcc3_vec *L = Lp.empty() ? L_in : Lp.data();
     prepare_ground(ws, g, o.reuse_ground != 0, s);
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
-    tau_path(ws, g, d, r, s);
+    const bool tau_kept = tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
     double *XT = B(ws, "XT");
-    double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
-    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
+    double *Xtau = xtau_block(ws, d, XT, tau_kept, r, s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
     // vectors in groups: L3 of a whole group in one d-contraction launch and one launch per
     // permutation pass, then the back-contractions vector by vector

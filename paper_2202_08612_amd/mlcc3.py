@@ -43,7 +43,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("reuse_ground", ctypes.c_int32),
                 ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
                 ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32),
-                ("cvs_core", ctypes.c_void_p)]
+                ("cvs_core", ctypes.c_void_p), ("reuse_tau", ctypes.c_int32)]
 
 
 TUNING_FIELDS = ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group")
@@ -208,11 +208,12 @@ def _vecs(lst):
 
 
 def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0, check_finite=False,
-              cvs_core=None):
+              cvs_core=None, reuse_tau=False):
     o = _Opts()
     _lib.mlcc3_opts_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.reuse_ground = 1 if reuse_ground else 0
+    o.reuse_tau = 1 if reuse_tau else 0
     if triple_range is not None:
         o.triple_begin, o.triple_end = int(triple_range[0]), int(triple_range[1])
     o.guard = float(guard)

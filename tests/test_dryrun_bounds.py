@@ -30,7 +30,7 @@ class O(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("reuse_ground", ctypes.c_int32),
                 ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
                 ("guard", ctypes.c_double), ("check_finite", ctypes.c_int32),
-                ("cvs_core", ctypes.c_void_p)]
+                ("cvs_core", ctypes.c_void_p), ("reuse_tau", ctypes.c_int32)]
 
 
 @pytest.fixture(scope="module")
@@ -190,3 +190,26 @@ def test_null_workspace_runs_on_a_temporary_one(lib):
     om = (ctypes.c_double * 2)(0.4, 0.5)
     for fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
         assert getattr(lib, fn)(None, ctypes.byref(g), 2, om, vin, vout, ctypes.byref(o), None) == 0, fn
+
+
+def test_reuse_tau_launches_in_bounds(lib):
+    """Transforms that keep the tau~ blocks of an earlier call (opts.reuse_tau) stay in bounds."""
+    d = I.CONFIGS[1]["dims"]
+    ws = ctypes.c_void_p()
+    assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+    p = _fake(64)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *p[:8])
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    out = (V * 1)(V(*p[8:11]))
+    assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == 0
+    o.reuse_ground = 1
+    o.reuse_tau = 1
+    vin = (V * 1)(V(*p[11:14]))
+    vout = (V * 1)(V(*p[30:33]))
+    om = (ctypes.c_double * 1)(0.4)
+    for fn in ("mlcc3_right_transform", "mlcc3_left_transform", "mlcc3_right_transform"):
+        rc = getattr(lib, fn)(ws, ctypes.byref(g), 1, om, vin, vout, ctypes.byref(o), None)
+        assert rc == 0, (fn, lib.mlcc3_last_error())
+    assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == 0
+    assert lib.mlcc3_ws_destroy(ws) == 0

@@ -310,6 +310,42 @@ def test_cvs_right_left(lib, ws, d, core):
     assert e.value.code == lib.EINVAL
 
 
+def test_reuse_tau(lib):
+    """opts.reuse_tau: transforms after a ground-residual call on the same workspace reuse its
+    tau~ blocks and give exactly the results of fresh calls; a different ground state, triple
+    range or precision forms them again."""
+    import torch
+    d = I.Dims(5, 17, 7, 37, 23)
+    p1, p2 = I.make_problem(d, 81), I.make_problem(d, 82)
+    g1, g2 = lib.Ground(p1), lib.Ground(p2)
+    R = [lib.vec_to_device(v) for v in I.right_vectors(p1, 2)]
+    L = [lib.vec_to_device(v) for v in I.left_vectors(p1, 2)]
+    om = I.omegas(False, 2)
+    wf, wt = lib.Workspace(0), lib.Workspace(0)
+    try:
+        ref_r1 = lib.right_transform(wf, g1, om, R)
+        ref_l1 = lib.left_transform(wf, g1, om, L, reuse_ground=True)
+        ref_rng = lib.right_transform(wf, g1, om, R, reuse_ground=True, triple_range=(3, 17))
+        ref_r2 = lib.right_transform(wf, g2, om, R)
+        ref_mx = lib.right_transform(wf, g2, om, R, reuse_ground=True, precision="fp32")
+
+        def same(a, b):
+            for m in range(len(b)):
+                for k in b[m]:
+                    assert torch.equal(a[m][k], b[m][k]), (m, k)
+
+        lib.ground_residual(wt, g1)
+        same(lib.right_transform(wt, g1, om, R, reuse_ground=True, reuse_tau=True), ref_r1)
+        same(lib.left_transform(wt, g1, om, L, reuse_ground=True, reuse_tau=True), ref_l1)
+        same(lib.right_transform(wt, g1, om, R, reuse_ground=True, reuse_tau=True, triple_range=(3, 17)), ref_rng)
+        same(lib.right_transform(wt, g1, om, R, reuse_ground=True, reuse_tau=True), ref_r1)
+        same(lib.right_transform(wt, g2, om, R, reuse_ground=True, reuse_tau=True), ref_r2)
+        same(lib.right_transform(wt, g2, om, R, reuse_ground=True, reuse_tau=True, precision="fp32"), ref_mx)
+    finally:
+        wf.close()
+        wt.close()
+
+
 def test_null_workspace(lib, ws):
     """A call without a workspace (NULL through the C-ABI) gives the same results as one with."""
     import torch
