@@ -646,39 +646,44 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// ρ-type small contractions over ordered blocks, one wave per (p,q,a):
+// ρ-type small contractions over ordered blocks, one workgroup per (p,q,a):
 //   part1[p][q][a]   = sum_{r,b,c} X~^{abc}_{pqr} g_qbrc
 //   Yvv[p][q][a][b]  = sum_{r,c} (X~^{abc}_{pqr} F_rc + T~^{abc}_{pqr} U_rc)
-__global__ __launch_bounds__(64) void k_small_right(const double *__restrict__ X, const double *__restrict__ T,
-                                                    const double *gov, const double *F, const double *U,
-                                                    int no, int nv, double *part1, double *Yvv) {
+// Each of the four waves takes every fourth row b and runs the r sum inside the row, so a row
+// costs one cross-lane reduction and its n_o loads per lane are independent of each other.
+template <bool HAS_T>
+__global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ X, const double *__restrict__ T,
+                                                     const double *__restrict__ gov, const double *__restrict__ F,
+                                                     const double *__restrict__ U, int no, int nv,
+                                                     double *__restrict__ part1, double *__restrict__ Yvv) {
   const int id = blockIdx.x;
   const int a = id % nv, q = (id / nv) % no, p = id / (nv * no);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
-  extern __shared__ double ysum[];
-  for (int b = lane; b < nv; b += 64) ysum[b] = 0.0;
-  __syncthreads();
+  const long long off = ((long long)p * no + q) * no * nv3 + (long long)a * nv2;  // r = 0
+  const double *x0 = X + off;
+  const double *g0 = gov + (long long)q * no * nv2;
+  __shared__ double rpart[4];
   double racc = 0.0;
-  for (int r = 0; r < no; r++) {
-    const long long base = (((long long)p * no + q) * no + r) * nv3 + (long long)a * nv2;
-    const double *g = gov + ((long long)q * no + r) * nv2;
-    for (int b = 0; b < nv; b++) {
-      double yb = 0.0;
-      for (int c = lane; c < nv; c += 64) {
-        const double x = X[base + (long long)b * nv + c];
-        racc += x * g[(long long)b * nv + c];
-        yb += x * F[(long long)r * nv + c];
-        if (T) yb += T[base + (long long)b * nv + c] * U[(long long)r * nv + c];
+  for (int b = wv; b < nv; b += 4) {
+    double yb = 0.0;
+    for (int c = lane; c < nv; c += 64) {
+      const long long e = (long long)b * nv + c;
+#pragma unroll 4
+      for (int r = 0; r < no; r++) {
+        const double x = x0[r * nv3 + e];
+        racc += x * g0[r * nv2 + e];
+        yb += x * F[r * nv + c];
+        if (HAS_T) yb += T[off + r * nv3 + e] * U[r * nv + c];
       }
-      yb = wave_sum(yb);
-      if (lane == 0) ysum[b] += yb;
     }
+    yb = wave_sum(yb);
+    if (lane == 0) Yvv[(((long long)p * no + q) * nv + a) * nv + b] = yb;
   }
   racc = wave_sum(racc);
+  if (lane == 0) rpart[wv] = racc;
   __syncthreads();
-  if (lane == 0) part1[((long long)p * no + q) * nv + a] = racc;
-  for (int b = lane; b < nv; b += 64) Yvv[(((long long)p * no + q) * nv + a) * nv + b] = ysum[b];
+  if (threadIdx.x == 0) part1[((long long)p * no + q) * nv + a] = (rpart[0] + rpart[1]) + (rpart[2] + rpart[3]);
 }
 
 // x1[A][I] = sum_q part1[I][q][A] on the active block, 0 elsewhere
@@ -873,8 +878,11 @@ void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, c
 void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
                         int no, int nv, double *part1, double *Yvv, hipStream_t s) {
   if (no <= 0 || nv <= 0 || g_dry) return;
-  hipLaunchKernelGGL(k_small_right, dim3(no * no * nv), dim3(64), nv * sizeof(double), s, X, T, gov, F, U,
-                     no, nv, part1, Yvv);
+  if (T)
+    hipLaunchKernelGGL(k_small_right<true>, dim3(no * no * nv), dim3(256), 0, s, X, T, gov, F, U, no, nv, part1, Yvv);
+  else
+    hipLaunchKernelGGL(k_small_right<false>, dim3(no * no * nv), dim3(256), 0, s, X, T, gov, F, U, no, nv, part1,
+                       Yvv);
 }
 
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,
