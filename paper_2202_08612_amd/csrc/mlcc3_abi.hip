@@ -85,6 +85,7 @@ struct mlcc3_ws_s {
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   mlcc3_tuning tune{};  // launch-shape choices (0 = default)
+  bool gle = false;     // "gLE" (left-transform integral block) formed for the prepared ground
   // what the tau~ blocks ("XT", and "Xtau" when xtau) were last formed for (opts.reuse_tau)
   struct TauKey {
     bool valid = false, xtau = false;
@@ -566,6 +567,7 @@ bool same_ground(const mlcc3_ground &a, const mlcc3_ground &b) { return std::mem
 void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t s) {
   if (reuse && ws->prepared && same_ground(ws->key, *g)) return;
   ws->prepared = false;
+  ws->gle = false;
   ws->tau = mlcc3_ws_s::TauKey{};
   const Dims d = dims_of(g);
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
@@ -1097,6 +1099,22 @@ Gemm gemm_plain(int M, int N, double *C, Idx2 crow, Idx2 ccol, double alpha, dou
   g.alpha = alpha;
   g.beta = beta;
   return g;
+}
+
+// gLE[k][c][L][E] = sum_J Lh_ck L_LE = ghat_ckLE, the integral block through which the left
+// transform's sigma^d_L term contracts Bq: formed once per prepared ground state
+double *gle_block(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, hipStream_t s) {
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+  double *gLE = buf(ws, "gLE", (size_t)no * nv * NO * NV, s);
+  if (ws->gle) return gLE;
+  // rows (k,c) of LhvO[J][c][k]; columns (L,E) of L_OV[J][L][E], unit stride along E
+  Gemm gg = gemm_plain(no * nv, NO * NV, gLE, plain((long long)NO * NV), plain(1), 1.0, 0.0);
+  gg.nseg = 1;
+  gg.seg[0] = seg(B(ws, "LhvO"), split(nv, 1, NO), plain((long long)nv * NO), 0, g->L_OV, plain((long long)NO * NV),
+                  plain(1), 0, d.nc);
+  gemm(gg, s);
+  ws->gle = true;
+  return gLE;
 }
 
 void zero_out(const Dims &d, const mlcc3_out *o, hipStream_t s) {
@@ -1743,6 +1761,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     double *XT = B(ws, "XT");
     double *Xtau = xtau_block(ws, d, XT, tau_kept, r, s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
+    const double *gLE = gle_block(ws, g, d, s);
     // vectors in groups: L3 of a whole group in one d-contraction launch and one launch per
     // permutation pass, then the back-contractions vector by vector
     const int ng = group_size(ws, d, nvec);
@@ -1864,11 +1883,12 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
           g5.seg[0] = seg(g->L_OV, plain(1), plain(NV), 0, H3, plain(1), plain((long long)nc * NO), 0, nc * NO);
           gemm(g5, s);
         }
-        // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE He[J][d][E]
+        // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE sum_{(k,c)} Lh_ck Bq[k][d][c][E];
+        //     the second term is taken as sum_{(k,c,E)} Bq[k][d][c][E] ghat_ckLE (gLE, formed once
+        //     per ground state) instead of through the rank x n_v N_V intermediate
         {
           double *Am = buf(ws, "Am", (size_t)no * nc * no * nv, s);
           double *Z = buf(ws, "Zl", (size_t)nc * no * nv, s);
-          double *He = buf(ws, "He", (size_t)nc * nv * NV, s);
           // Am[j][J][(k,d)] = sum_M Lh_Mj Aq[j][k][d][M]
           Gemm g1 = gemm_plain(nc, no * nv, Am, plain((long long)no * nv), plain(1), 1.0, 0.0);
           g1.nbatch = no;
@@ -1879,18 +1899,12 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
           gemm(g1, s);
           launch_left_Z(Am, Hp, nc, no, nv, Z, s);
           HIPRT(hipGetLastError());
-          // He[J][(d,E)] = sum_{(k,c)} Lh_ck Bq[k][d][c][E]
-          Gemm g2 = gemm_plain(nc, nv * NV, He, plain((long long)nv * NV), plain(1), 1.0, 0.0);
-          g2.nseg = 1;
-          g2.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Bq, split(nv, d.nv2 * NV, NV),
-                          split(NV, (long long)nv * NV, 1), 0, no * nv);
-          gemm(g2, s);
-          // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(J,E)} He[J][d][E] L_LE
+          // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(k,c,E)} Bq[k][d][c][E] gLE[k][c][L][E]
           Gemm g3 = gemm_plain(nv, NO, s1, plain(NO), plain(1), 1.0, 1.0);
           g3.nseg = 2;
           g3.seg[0] = seg(Z, plain(1), plain(nv), 0, LhOO, split(no, (long long)NO * NO, 1), plain(NO), 0, nc * no);
-          g3.seg[1] = seg(He, plain(NV), split(NV, (long long)nv * NV, 1), 0, g->L_OV, split(NV, (long long)NO * NV, 1),
-                          plain(NV), 0, nc * NV, -1.0);
+          g3.seg[1] = seg(Bq, plain((long long)nv * NV), split(nv * NV, d.nv2 * NV, 1), 0, gLE,
+                          split(NV, (long long)NO * NV, 1), plain(NV), 0, no * nv * NV, -1.0);
           gemm(g3, s);
         }
         DoublesRaw y;
