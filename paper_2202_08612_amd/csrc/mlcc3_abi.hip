@@ -515,10 +515,10 @@ void dlhat_blocks(const Dims &d, const double *LOV, const double *LhvV, const do
 // X_kc = sum_LD (2 g_kcLD - g_kDLc) x^D_L from bare (ov|ov) = sum_J L_kc L_LD (active k, c):
 // s_J = sum_LD L^J_LD x^D_L, y^J_kL = sum_D L^J_kD x^D_L (MFMA GEMM), then
 // X_kc = sum_J (2 L^J_kc s_J - sum_L y^J_kL L^J_Lc) summed over J in a fixed order
-void fock_like(const Dims &d, const double *LOV, const double *x, double *tmp_s, double *tmp_y, double *tmp_z,
-               double *out, hipStream_t s) {
+void fock_like(const Dims &d, const double *LOV, const double *x, double *tmp_x, double *tmp_s, double *tmp_y,
+               double *tmp_z, double *out, hipStream_t s) {
   const int nc = d.nc, NO = d.NO, NV = d.NV, no = d.no, nv = d.nv;
-  launch_fock_s(LOV, x, nc, NO, NV, tmp_s, s);
+  launch_fock_s(LOV, x, nc, NO, NV, tmp_x, tmp_s, s);
   Gemm g;
   g.M = nc * no;
   g.N = NO;
@@ -668,7 +668,8 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   HIPRT(hipGetLastError());
   // F_kc
   double *F = buf(ws, "F", (size_t)no * nv, s);
-  fock_like(d, g->L_OV, g->t1, buf(ws, "fock_s", nc, s), buf(ws, "fock_y", (size_t)nc * no * NO, s),
+  fock_like(d, g->L_OV, g->t1, buf(ws, "fock_xT", (size_t)NO * NV, s), buf(ws, "fock_s", nc, s),
+            buf(ws, "fock_y", (size_t)nc * no * NO, s),
             buf(ws, "fock_z", (size_t)nc * no * nv, s), F, s);
   // tA[p][q][a][D] = t^{aD}_{pq}
   launch_pack_vVoo(g->t2_vVoo, no, nv, NV, 0, buf(ws, "tA", (size_t)no * no * nv * NV, s), s);
@@ -1225,7 +1226,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
     gemm(gg, s);
   }
   double *Ukc = buf(ws, "Ukc", (size_t)(z.Ukc * nb), s) + slot * z.Ukc;
-  fock_like(d, g->L_OV, R.x1, B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc, s);
+  fock_like(d, g->L_OV, R.x1, B(ws, "fock_xT"), B(ws, "fock_s"), B(ws, "fock_y"), B(ws, "fock_z"), Ukc, s);
   double *Xi = buf(ws, "Xi", (size_t)(z.Xi * nb), s) + slot * z.Xi;
   {
     Gemm gg;

@@ -48,7 +48,9 @@ void launch_vvvo_permute(const double *T, int no, int nv, int NV, double *C, hip
 // LhvO[J][c][K] = L_OV[J][K][c] (first term of the T1-transformed vO block)
 void launch_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, double *LhvO, hipStream_t s);
 // s_J = sum_LD L^J_LD x^D_L
-void launch_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *tmp_s, hipStream_t s);
+// s_J = sum_LD L^J_LD x^D_L (x as [N_V][N_O]; tmp_xT holds its [N_O][N_V] transpose)
+void launch_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *tmp_xT, double *tmp_s,
+                   hipStream_t s);
 // X_kc = sum_J (2 L^J_kc s_J - sum_L y^J_kL L^J_Lc) (fixed order over J)
 void launch_fock_finish(const double *LOV, const double *tmp_s, const double *tmp_y, int nc, int NO, int NV, int no,
                         int nv, double *tmp_z, double *out, hipStream_t s);

@@ -23,15 +23,15 @@ __global__ void k_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv
 // --------------------------------------------- X_kc = sum_LD (2 g_kcLD - g_kDLc) x^D_L
 // with bare (ov|ov) = sum_J L_kc L_LD:  s_J = sum_LD L^J_LD x^D_L,
 // y^J_kL = sum_D L^J_kD x^D_L,  X_kc = sum_J (2 L^J_kc s_J - sum_L y^J_kL L^J_Lc)
-__global__ void k_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *s) {
+// s_J as a dot product of the contiguous block L^J [L][D] with xT[L][D] = x^D_L
+__global__ void k_fock_s(const double *__restrict__ LOV, const double *__restrict__ xT, int nc, int NO, int NV,
+                         double *s) {
   const int J = blockIdx.x;
   __shared__ double red[256];
   double acc = 0.0;
-  const double *l = LOV + (long long)J * NO * NV;
-  for (int L = 0; L < NO; L++) {
-    const double *row = l + (long long)L * NV;
-    for (int D = threadIdx.x; D < NV; D += 256) acc += row[D] * x[(long long)D * NO + L];
-  }
+  const long long n = (long long)NO * NV;
+  const double *l = LOV + (long long)J * n;
+  for (long long e = threadIdx.x; e < n; e += 256) acc += l[e] * xT[e];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -807,8 +807,11 @@ void launch_lhat_vO_init(const double *LOV, int nc, int NO, int NV, int nv, doub
   L1D(k_lhat_vO_init, (long long)nc * nv * NO, LOV, nc, NO, NV, nv, LhvO);
 }
 
-void launch_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *tmp_s, hipStream_t s) {
-  if (!g_dry && nc > 0) hipLaunchKernelGGL(k_fock_s, dim3(nc), dim3(256), 0, s, LOV, x, nc, NO, NV, tmp_s);
+void launch_fock_s(const double *LOV, const double *x, int nc, int NO, int NV, double *tmp_xT, double *tmp_s,
+                   hipStream_t s) {
+  if (g_dry || nc <= 0) return;
+  launch_transpose(x, tmp_xT, 1, NV, NO, s);
+  hipLaunchKernelGGL(k_fock_s, dim3(nc), dim3(256), 0, s, LOV, tmp_xT, nc, NO, NV, tmp_s);
 }
 
 void launch_fock_finish(const double *LOV, const double *tmp_s, const double *tmp_y, int nc, int NO, int NV, int no,
