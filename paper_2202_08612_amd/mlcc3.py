@@ -166,11 +166,31 @@ GROUND_KEYS = ("eps_o", "eps_v", "L_OO", "L_OV", "L_vV", "t1", "t2_vVoo", "t2_vv
 VEC_KEYS = ("x1", "x2_vVoo", "x2_vvoO")
 
 
-def _dev(x, device):
+def ground_sizes(d):
+    """Element counts of the ground-state arrays (layouts in include/mlcc3.h)."""
+    no, nv, NO, NV, nc = d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol
+    return {"eps_o": NO, "eps_v": NV, "L_OO": nc * NO * NO, "L_OV": nc * NO * NV, "L_vV": nc * nv * NV,
+            "t1": NV * NO, "t2_vVoo": nv * NV * no * no, "t2_vvoO": nv * nv * no * NO}
+
+
+def vec_sizes(d):
+    """Element counts of the blocks of a trial vector or output."""
+    no, nv, NO, NV = d.n_o, d.n_v, d.N_O, d.N_V
+    return {"x1": NV * NO, "x2_vVoo": nv * NV * no * no, "x2_vvoO": nv * nv * no * NO}
+
+
+def _dev(x, device, n=None, what="array"):
+    """FP64 contiguous copy (or view) of x on device.  The library takes bare pointers and reads
+    the element counts its sizes imply, so every array is checked here: a missing one or one of
+    the wrong size would be read out of bounds on the device."""
+    if x is None:
+        raise ValueError(f"{what}: missing")
     if isinstance(x, torch.Tensor):
         t = x.to(device=device, dtype=torch.float64)
     else:
         t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {n}")
     return t.contiguous()
 
 
@@ -180,7 +200,8 @@ class Ground:
     def __init__(self, prob, device="cuda"):
         d = prob.dims
         self.dims = d
-        self.t = {k: _dev(getattr(prob, k), device) for k in GROUND_KEYS}
+        n = ground_sizes(d)
+        self.t = {k: _dev(getattr(prob, k), device, n[k], k) for k in GROUND_KEYS}
         self.c = _Ground(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol,
                          *[self.t[k].data_ptr() for k in GROUND_KEYS])
 
@@ -198,13 +219,30 @@ def empty_out(d, device="cuda"):
             "x2_vvoO": torch.empty((d.n_v, d.n_v, d.n_o, d.N_O), dtype=torch.float64, device=device)}
 
 
-def _vecs(lst):
+def _vecs(lst, d, device):
+    """C array of vector descriptors; every block must be a contiguous FP64 tensor of the size
+    the dimensions give, on the workspace's device."""
+    n = vec_sizes(d)
+    dev = torch.device(device)
     arr = (_Vec * len(lst))()
     for m, v in enumerate(lst):
         for k in VEC_KEYS:
-            assert v[k].is_contiguous() and v[k].dtype == torch.float64
+            t = v[k]
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError(f"vector {m} block {k}: not a contiguous float64 tensor")
+            if t.device.type != dev.type or (dev.index is not None and t.device.index != dev.index):
+                raise ValueError(f"vector {m} block {k}: on {t.device}, expected {dev}")
+            if t.numel() != n[k]:
+                raise ValueError(f"vector {m} block {k}: {t.numel()} elements, expected {n[k]}")
         arr[m] = _Vec(v["x1"].data_ptr(), v["x2_vVoo"].data_ptr(), v["x2_vvoO"].data_ptr())
     return arr
+
+
+def _check_ground(ws, ground):
+    dev = torch.device(ws.device)
+    for k, t in ground.t.items():
+        if t.device.type != dev.type or (dev.index is not None and t.device.index != dev.index):
+            raise ValueError(f"ground array {k}: on {t.device}, expected {dev}")
 
 
 def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0, check_finite=False,
@@ -227,7 +265,8 @@ def make_opts(precision="fp64", reuse_ground=False, triple_range=None, guard=0.0
 def ground_residual(ws, ground, out=None, **kw):
     out = empty_out(ground.dims, ws.device) if out is None else out
     o = make_opts(**kw)
-    arr = _vecs([out])
+    _check_ground(ws, ground)
+    arr = _vecs([out], ground.dims, ws.device)
     _check(_lib.mlcc3_ground_residual(ws.h, ctypes.byref(ground.c), ctypes.byref(o), arr, _stream(ws.device)))
     return out
 
@@ -237,8 +276,9 @@ def _transform(fn, ws, ground, omegas, vecs, outs=None, **kw):
     outs = [empty_out(ground.dims, ws.device) for _ in range(n)] if outs is None else outs
     om = (ctypes.c_double * n)(*[float(w) for w in omegas])
     o = make_opts(**kw)
-    _check(fn(ws.h, ctypes.byref(ground.c), n, om, _vecs(vecs), _vecs(outs), ctypes.byref(o),
-              _stream(ws.device)))
+    _check_ground(ws, ground)
+    vin, vout = _vecs(vecs, ground.dims, ws.device), _vecs(outs, ground.dims, ws.device)
+    _check(fn(ws.h, ctypes.byref(ground.c), n, om, vin, vout, ctypes.byref(o), _stream(ws.device)))
     return outs
 
 
@@ -246,10 +286,16 @@ def oscillator_strengths(ws, A, omegas, D_m0, D_0m, D_00, s):
     """Transition moments T_m0, T_0m ([nstate][ncomp]) and oscillator strengths f ([nstate]) from
     densities D_m0, D_0m ([nstate][N][N]), D_00 ([N][N]), s ([nstate]) and operator A ([ncomp][N][N])."""
     dev = ws.device
-    A = _dev(A, dev)
+    A = _dev(A, dev, what="A")
+    if A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError(f"A: shape {tuple(A.shape)}, expected [ncomp][N][N]")
     ncomp, N = A.shape[0], A.shape[1]
-    D_m0, D_0m, D_00, sv = _dev(D_m0, dev), _dev(D_0m, dev), _dev(D_00, dev), _dev(s, dev)
-    n = D_m0.shape[0]
+    D_m0, D_0m = _dev(D_m0, dev, what="D_m0"), _dev(D_0m, dev, what="D_0m")
+    n = D_m0.shape[0] if D_m0.dim() == 3 else -1
+    D_m0, D_0m = _dev(D_m0, dev, n * N * N, "D_m0"), _dev(D_0m, dev, n * N * N, "D_0m")
+    D_00, sv = _dev(D_00, dev, N * N, "D_00"), _dev(s, dev, n, "s")
+    if len(omegas) != n:
+        raise ValueError(f"{len(omegas)} omegas for {n} states")
     Tm0 = torch.empty((n, ncomp), dtype=torch.float64, device=dev)
     T0m = torch.empty((n, ncomp), dtype=torch.float64, device=dev)
     f = torch.empty((n,), dtype=torch.float64, device=dev)
@@ -264,8 +310,8 @@ def vec_map(ws, ground, mode, vecs, outs=None):
     """Pairing maps of trial vectors (MAP_SYMMETRIZE, MAP_GRAD_TO_LEFT, MAP_LEFT_TO_GRAD)."""
     n = len(vecs)
     outs = [empty_out(ground.dims, ws.device) for _ in range(n)] if outs is None else outs
-    _check(_lib.mlcc3_vec_map(ws.h, ctypes.byref(ground.c), int(mode), n, _vecs(vecs), _vecs(outs),
-                              _stream(ws.device)))
+    vin, vout = _vecs(vecs, ground.dims, ws.device), _vecs(outs, ground.dims, ws.device)
+    _check(_lib.mlcc3_vec_map(ws.h, ctypes.byref(ground.c), int(mode), n, vin, vout, _stream(ws.device)))
     return outs
 
 
@@ -285,16 +331,20 @@ def triples_densities(ws, ground, omegas, Lvecs, Rvecs, lam, t2_vVoO, t2_vVOo, *
     """Triples terms of D^{m-0}, D^{0-m} ([nstate][N][N]) and s ([nstate]) on the device."""
     d = ground.dims
     n = len(Lvecs)
-    assert len(Rvecs) == n
+    if len(Rvecs) != n:
+        raise ValueError(f"{n} left and {len(Rvecs)} right vectors")
     N = d.N_O + d.N_V
+    nt2 = d.n_v * d.N_V * d.n_o * d.N_O
+    a = _dev(t2_vVoO, ws.device, nt2, "t2_vVoO")
+    b = _dev(t2_vVOo, ws.device, nt2, "t2_vVOo")
+    _check_ground(ws, ground)
+    vl, vr, vlam = _vecs(Lvecs, d, ws.device), _vecs(Rvecs, d, ws.device), _vecs([lam], d, ws.device)
     Dm0 = torch.empty((n, N, N), dtype=torch.float64, device=ws.device)
     D0m = torch.empty((n, N, N), dtype=torch.float64, device=ws.device)
     sv = torch.empty((n,), dtype=torch.float64, device=ws.device)
-    a = _dev(t2_vVoO, ws.device)
-    b = _dev(t2_vVOo, ws.device)
     om = (ctypes.c_double * n)(*[float(w) for w in omegas])
     o = make_opts(**kw)
     _check(_lib.mlcc3_triples_densities(ws.h, ctypes.byref(ground.c), a.data_ptr(), b.data_ptr(), n, om,
-                                        _vecs(Lvecs), _vecs(Rvecs), _vecs([lam]), Dm0.data_ptr(),
-                                        D0m.data_ptr(), sv.data_ptr(), ctypes.byref(o), _stream(ws.device)))
+                                        vl, vr, vlam, Dm0.data_ptr(), D0m.data_ptr(), sv.data_ptr(),
+                                        ctypes.byref(o), _stream(ws.device)))
     return Dm0, D0m, sv

@@ -313,10 +313,10 @@ def test_cvs_right_left(lib, ws, d, core):
 def test_reuse_tau(lib):
     """opts.reuse_tau: transforms after a ground-residual call on the same workspace reuse its
     tau~ blocks and give exactly the results of fresh calls; a different ground state, triple
-    range or precision forms them again."""
+    range or precision forms them again, and so does a densities call in between."""
     import torch
     d = I.Dims(5, 17, 7, 37, 23)
-    p1, p2 = I.make_problem(d, 81), I.make_problem(d, 82)
+    p1, p2 = I.make_problem(d, 81), I.make_problem(d, 82, with_density_blocks=True)
     g1, g2 = lib.Ground(p1), lib.Ground(p2)
     R = [lib.vec_to_device(v) for v in I.right_vectors(p1, 2)]
     L = [lib.vec_to_device(v) for v in I.left_vectors(p1, 2)]
@@ -328,6 +328,7 @@ def test_reuse_tau(lib):
         ref_rng = lib.right_transform(wf, g1, om, R, reuse_ground=True, triple_range=(3, 17))
         ref_r2 = lib.right_transform(wf, g2, om, R)
         ref_mx = lib.right_transform(wf, g2, om, R, reuse_ground=True, precision="fp32")
+        ref_l2 = lib.left_transform(wf, g2, om, L, reuse_ground=True)
 
         def same(a, b):
             for m in range(len(b)):
@@ -341,6 +342,11 @@ def test_reuse_tau(lib):
         same(lib.right_transform(wt, g1, om, R, reuse_ground=True, reuse_tau=True), ref_r1)
         same(lib.right_transform(wt, g2, om, R, reuse_ground=True, reuse_tau=True), ref_r2)
         same(lib.right_transform(wt, g2, om, R, reuse_ground=True, reuse_tau=True, precision="fp32"), ref_mx)
+        # the densities form tau~ (with its covariant form) again on this workspace
+        lam = lib.vec_to_device(I.lambda_vector(p2))
+        lib.triples_densities(wt, g2, om, L, R, lam, p2.t2_vVoO, p2.t2_vVOo, reuse_ground=True)
+        same(lib.left_transform(wt, g2, om, L, reuse_ground=True, reuse_tau=True), ref_l2)
+        same(lib.right_transform(wt, g2, om, R, reuse_ground=True, reuse_tau=True), ref_r2)
     finally:
         wf.close()
         wt.close()
