@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
-    ap.add_argument("--cpu-triples", type=int, default=48, help="unique triples in the CPU-baseline sample")
+    ap.add_argument("--cpu-triples", type=int, default=120, help="unique triples in the CPU-baseline sample")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="time the guanine-shaped active spaces of the paper's core-state table (context)")
     ap.add_argument("--nv-sweep", action="store_true",
