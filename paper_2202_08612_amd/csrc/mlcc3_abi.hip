@@ -1360,6 +1360,21 @@ int group_size(mlcc3_ws ws, const Dims &d, int nvec) {
 // C[k][l] = alpha sum_{(i,j),(abc)} X1[i][j][k][abc] X2[i][j][l][abc] + beta C
 void g_kl(const Dims &d, const double *X1, const double *X2, double *C, long long ldc, double alpha, double beta,
           hipStream_t s) {
+  if (d.no <= 16 && t_ws) {
+    // small occupied output, K = n_o^2 n_v^3: the streaming MFMA Gram kernel
+    int nch;
+    long long chunk;
+    gram_kl_shape(d.no, d.nv3, nch, chunk);
+    const long long np = (long long)d.no * d.no * nch * d.no * d.no;
+    double *P = buf(t_ws, "gram_part", (size_t)np, s);
+    const size_t xb = sizeof(double) * (size_t)(d.nord * d.nv3);
+    check_bytes(X1, xb, "X1 (occupied Gram)");
+    check_bytes(X2, xb, "X2 (occupied Gram)");
+    check_range(C, plain(ldc), d.no, plain(1), d.no, 0, 1, "C (occupied Gram)");
+    launch_gram_kl(X1, X2, d.no, d.nv3, P, alpha, beta, C, ldc, s);
+    HIPRT(hipGetLastError());
+    return;
+  }
   Gemm g = gemm_plain(d.no, d.no, C, plain(ldc), plain(1), alpha, beta);
   g.nseg = 1;
   g.seg[0] = seg(X1, plain(d.nv3), split((int)d.nv3, (long long)d.no * d.nv3, 1), 0, X2,

@@ -101,6 +101,12 @@ void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStrea
 // out[z][c][r] = in[z][r][c], z < batch
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s);
 // out[i] = sum_r P[r][i], r = 0..rows-1 (fixed order)
+// C[k][l] = alpha sum_{(i,j),e} X1[i][j][k][e] X2[i][j][l][e] + beta C[k][l] for ordered-triple
+// buffers with ne = n_v^3 values per triple, n_o <= 16; P holds the per-workgroup partials
+// (gram_kl_shape gives their count: no * no * nch blocks of no * no doubles)
+void gram_kl_shape(int no, long long ne, int &nch, long long &chunk);
+void launch_gram_kl(const double *X1, const double *X2, int no, long long ne, double *P, double alpha, double beta,
+                    double *C, long long ldc, hipStream_t s);
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s);
 void launch_diag_sum(const double *Q, int no, int nv, int NO, double *V, hipStream_t s);
 void launch_left_Z(const double *Am, const double *Hp, int nc, int no, int nv, double *Z, hipStream_t s);

@@ -686,6 +686,60 @@ __global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ 
   if (threadIdx.x == 0) part1[((long long)p * no + q) * nv + a] = (rpart[0] + rpart[1]) + (rpart[2] + rpart[3]);
 }
 
+// Occupied Gram block of two ordered-triple buffers (n_o <= 16), one partial per workgroup:
+//   P[w][k][l] = sum_{e in chunk} X1[i][j][k][e] X2[i][j][l][e],  w = (i n_o + j) nch + chunk,
+// e running over the n_v^3 virtual triples.  Each wave accumulates one 16x16 tile with
+// v_mfma_f64_16x16x4_f64: lane l holds row l%16 (k of X1 as the A operand, l of X2 as the B
+// operand) at four consecutive e, so the four lanes of a row read 128 contiguous bytes and the
+// k index of each MFMA is a set of four e values shared by both operands.  Rows k >= n_o and
+// positions past the chunk load zeros.  The four waves' tiles are summed in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_gram_kl(const double *__restrict__ X1, const double *__restrict__ X2, int no,
+                                                long long ne, long long chunk, int nch, double *__restrict__ P) {
+  __shared__ double red[4][16][17];
+  const int w = blockIdx.x;
+  const int ij = w / nch, ch = w - ij * nch;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, q = lane >> 4;
+  const long long e0 = (long long)ch * chunk, e1 = min(ne, e0 + chunk);
+  const bool valid = row < no;
+  const long long roff = ((long long)ij * no + (valid ? row : 0)) * ne;
+  const double *x1 = X1 + roff, *x2 = X2 + roff;
+  d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+  // the trip count is uniform over the wave (the MFMA reads every lane's operands whatever the
+  // exec mask): positions past the chunk load zeros
+  for (long long eb = e0 + 16 * wave; eb < e1; eb += 64) {
+    const long long e = eb + 4 * q;
+    double a[4], b[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const bool in = valid && e + c < e1;
+      a[c] = in ? x1[e + c] : 0.0;
+      b[c] = in ? x2[e + c] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], b[c], acc, 0, 0, 0);
+  }
+  // lane l, register v: row l/16 + 4v, column l%16
+#pragma unroll
+  for (int v = 0; v < 4; v++) red[wave][q + 4 * v][row] = acc[v];
+  __syncthreads();
+  const int k = threadIdx.x >> 4, l = threadIdx.x & 15;
+  if (k < no && l < no)
+    P[((long long)w * no + k) * no + l] = (red[0][k][l] + red[1][k][l]) + (red[2][k][l] + red[3][k][l]);
+}
+
+// C[k][l] = alpha sum_w P[w][k][l] + beta C[k][l] (row stride ldc), w in order
+__global__ void k_gram_reduce(const double *__restrict__ P, int nw, int no, double alpha, double beta, double *C,
+                              long long ldc) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= no * no) return;
+  const int k = id / no, l = id - k * no;
+  double s = 0.0;
+  for (int w = 0; w < nw; w++) s += P[(long long)w * no * no + id];
+  double *c = C + (long long)k * ldc + l;
+  *c = alpha * s + (beta != 0.0 ? beta * *c : 0.0);
+}
+
 // x1[A][I] = sum_q part1[I][q][A] on the active block, 0 elsewhere
 __global__ void k_singles_out(const double *part1, int no, int nv, int NO, int NV, double *x1) {
   int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -906,6 +960,26 @@ void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStrea
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s) {
   if (g_dry || batch <= 0 || R <= 0 || C <= 0) return;
   hipLaunchKernelGGL(k_transpose, dim3((C + 31) / 32, (R + 31) / 32, batch), dim3(256), 0, s, in, out, R, C);
+}
+
+void gram_kl_shape(int no, long long ne, int &nch, long long &chunk) {
+  const int nij = no * no;
+  nch = std::max(1, (3072 + nij - 1) / nij);
+  chunk = (ne + nch - 1) / nch;
+  chunk = (chunk + 63) / 64 * 64;
+  nch = (int)((ne + chunk - 1) / chunk);
+}
+
+void launch_gram_kl(const double *X1, const double *X2, int no, long long ne, double *P, double alpha, double beta,
+                    double *C, long long ldc, hipStream_t s) {
+  if (g_dry || no <= 0 || ne <= 0) return;
+  int nch;
+  long long chunk;
+  gram_kl_shape(no, ne, nch, chunk);
+  const int nw = no * no * nch;
+  hipLaunchKernelGGL(k_gram_kl, dim3((unsigned)nw), dim3(256), 0, s, X1, X2, no, ne, chunk, nch, P);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((no * no + 255) / 256)), dim3(256), 0, s, P, nw, no, alpha, beta,
+                     C, ldc);
 }
 
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s) {
