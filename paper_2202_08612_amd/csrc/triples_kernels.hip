@@ -728,16 +728,25 @@ __global__ __launch_bounds__(256) void k_gram_kl(const double *__restrict__ X1, 
     P[((long long)w * no + k) * no + l] = (red[0][k][l] + red[1][k][l]) + (red[2][k][l] + red[3][k][l]);
 }
 
-// C[k][l] = alpha sum_w P[w][k][l] + beta C[k][l] (row stride ldc), w in order
-__global__ void k_gram_reduce(const double *__restrict__ P, int nw, int no, double alpha, double beta, double *C,
-                              long long ldc) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= no * no) return;
-  const int k = id / no, l = id - k * no;
+// C[k][l] = alpha sum_w P[w][k][l] + beta C[k][l] (row stride ldc): one workgroup per (k,l),
+// thread t sums w = t, t+256, ... and a fixed tree adds the 256 partial sums
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ P, int nw, int no, double alpha,
+                                                     double beta, double *C, long long ldc) {
+  __shared__ double red[256];
+  const int id = blockIdx.x, k = id / no, l = id - k * no;
+  const long long n2 = (long long)no * no;
   double s = 0.0;
-  for (int w = 0; w < nw; w++) s += P[(long long)w * no * no + id];
-  double *c = C + (long long)k * ldc + l;
-  *c = alpha * s + (beta != 0.0 ? beta * *c : 0.0);
+  for (int w = threadIdx.x; w < nw; w += 256) s += P[w * n2 + id];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *c = C + (long long)k * ldc + l;
+    *c = alpha * red[0] + (beta != 0.0 ? beta * *c : 0.0);
+  }
 }
 
 // x1[A][I] = sum_q part1[I][q][A] on the active block, 0 elsewhere
@@ -978,8 +987,7 @@ void launch_gram_kl(const double *X1, const double *X2, int no, long long ne, do
   gram_kl_shape(no, ne, nch, chunk);
   const int nw = no * no * nch;
   hipLaunchKernelGGL(k_gram_kl, dim3((unsigned)nw), dim3(256), 0, s, X1, X2, no, ne, chunk, nch, P);
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((no * no + 255) / 256)), dim3(256), 0, s, P, nw, no, alpha, beta,
-                     C, ldc);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(no * no)), dim3(256), 0, s, P, nw, no, alpha, beta, C, ldc);
 }
 
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s) {
