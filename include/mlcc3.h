@@ -147,8 +147,8 @@ int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *
  *   narrow_tile:  block tile of the generic FP64 GEMM in the N_O-wide back-contractions,
  *                 10*TM + TN for a (32 TM) x (32 TN) tile, TM and TN in {1, 2, 4};
  *   contra_form:  contravariant pass: 1 = one workgroup per 16^3 sub-cube, 2 = one per orbit
- *                 of sub-cubes under the virtual permutations (used only when 16 divides n_v,
- *                 else the per-sub-cube pass runs);
+ *                 of sub-cubes under the virtual permutations (any n_v); the default takes the
+ *                 orbit pass when 16 divides n_v or n_v > 64;
  *   vec_group:    cap on the vectors that share one launch in the right and left transforms.
  * mlcc3_ws_set_tuning(ws, NULL) restores the defaults; out-of-range values give MLCC3_EINVAL. */
 typedef struct {

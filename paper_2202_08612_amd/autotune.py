@@ -25,7 +25,7 @@ CANDIDATES = {
     "dc_wg_per_cu": [0, 1, 3, 4, -1],
     "back_ksplit": [0, 1, 2, 4, 8],
     "narrow_tile": [0, 41, 21, 42, 22, 44, 12],
-    "contra_form": [0, 1],
+    "contra_form": [0, 1, 2],
     "vec_group": [0, 1, 2, 4, 8, 16],
 }
 
@@ -48,8 +48,8 @@ def cache_key(dims, nvec, precision, arch):
 def candidates(dims, nvec):
     """Candidate values that can make a difference at these sizes."""
     c = {k: list(v) for k, v in CANDIDATES.items()}
-    if dims.n_v % 16:
-        c["contra_form"] = [0]           # the orbit pass needs 16 | n_v
+    # the default is the orbit pass when 16 | n_v or n_v > 64, else the per-sub-cube pass
+    c["contra_form"] = [0, 1] if (dims.n_v % 16 == 0 or dims.n_v > 64) else [0, 2]
     c["vec_group"] = [v for v in c["vec_group"] if v == 0 or v < nvec]
     return c
 

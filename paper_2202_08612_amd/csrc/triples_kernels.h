@@ -80,8 +80,9 @@ struct VecBatch {
 };
 
 // W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
-// (and, if Xc is not NULL, the covariant X to every ordering); contra_form 1 forces the
-// per-sub-cube contravariant pass, otherwise the orbit pass runs when 16 divides n_v
+// (and, if Xc is not NULL, the covariant X to every ordering); contravariant pass per
+// sub-cube (contra_form 1), per orbit of sub-cubes (2), or by the size rule (0: per orbit
+// when 16 divides n_v or n_v > 64)
 void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
                           long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,

@@ -927,10 +927,12 @@ void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, c
   if (!l.L1) l.L1v = l.LVv = 0;
   const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
   hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot, nu);
-  if (nv % TT == 0 && contra_form != 1) {
-    // rows of the ordered blocks are whole cache lines: one workgroup per orbit of tiles reads
-    // each sub-cube of X_u once (measured 2.3 -> 1.8 ms at n_v = 80; at n_v = 60 the per-tile
-    // kernel is as fast, its neighbouring tiles share the partial lines of a row in L2)
+  if (contra_form == 2 || (contra_form == 0 && (nv % TT == 0 || nv > 4 * TT))) {
+    // one workgroup per orbit of tiles reads each sub-cube of X_u once (measured 2.3 -> 1.8 ms
+    // per launch at n_v = 80, right + left transform 174.6 -> 168.3 ms at n_v = 136; at n_v = 60
+    // the per-tile kernel is as fast, its neighbouring tiles share the partial lines of a row in
+    // L2).  Ragged tiles are exact: a member tile loads zeros past n_v, a permuted read of an
+    // output inside n_v stays inside n_v, and writes stop at n_v.
     const int norb = nt * (nt + 1) * (nt + 2) / 6;
     hipLaunchKernelGGL(k_contra_orbit, dim3((unsigned)((long long)vb.nvec * nu * norb)), dim3(256), 0, s, Xu, Xt, ut,
                        no, nv, nu, vb.nvec, vb.xu, vb.xt);

@@ -106,3 +106,35 @@ def test_autotune_picks_caches_and_matches_oracle(lib, tmp_path):
                 assert rel(l[m][k], ref_l[k]) <= TOL, ("left", m, k, rel(l[m][k], ref_l[k]))
     finally:
         w2.close()
+
+
+@pytest.mark.parametrize("dims", [I.Dims(3, 20, 5, 30, 11), I.Dims(5, 17, 7, 37, 23)], ids=str)
+def test_orbit_pass_on_ragged_sub_cubes(lib, ws, dims):
+    """The orbit form of the contravariant pass (contra_form 2) on a virtual space that 16 does
+    not divide: the oracle's results at the FP64 bar, and the per-sub-cube form's to rounding."""
+    from oracle.oracle import Oracle
+    p = I.make_problem(dims, 9)
+    orc = Oracle(p)
+    g = lib.Ground(p)
+    Rh, Lh = I.right_vectors(p, 2), I.left_vectors(p, 2)
+    R = [lib.vec_to_device(v) for v in Rh]
+    L = [lib.vec_to_device(v) for v in Lh]
+    om = I.omegas(False, 2)
+    out = {}
+    try:
+        for form in (1, 2):
+            ws.set_tuning({"contra_form": form})
+            out[form] = (_host(lib, lib.right_transform(ws, g, om, R)),
+                         _host(lib, lib.left_transform(ws, g, om, L, reuse_ground=True)),
+                         lib.to_numpy(lib.ground_residual(ws, g, reuse_ground=True)))
+    finally:
+        ws.set_tuning(None)
+    _same(out[2][0], out[1][0], 1e-12, "right")
+    _same(out[2][1], out[1][1], 1e-12, "left")
+    _same([out[2][2]], [out[1][2]], 1e-12, "ground")
+    for m in range(2):
+        ref_r = orc.right_transform(om[m], Rh[m])
+        ref_l = orc.left_transform(om[m], Lh[m])
+        for k in ref_r:
+            assert rel(out[2][0][m][k], ref_r[k]) <= TOL, ("right", m, k)
+            assert rel(out[2][1][m][k], ref_l[k]) <= TOL, ("left", m, k)
