@@ -15,7 +15,8 @@ throughput, the errors of every output against the FP64 path and, when every err
 1e-6, its speedup over FP64 are reported in the "mixed" object of the JSON line.
 
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
-runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --cfg.
+runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --cfg;
+--copy-mib, --paper-shapes, --nv-sweep and --config4 run other reports instead of the step.
 """
 from __future__ import annotations
 
@@ -62,6 +63,11 @@ def parse():
     ap.add_argument("--cpu-triples", type=int, default=120, help="unique triples in the CPU-baseline sample")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="time the guanine-shaped active spaces of the paper's core-state table (context)")
+    ap.add_argument("--config4", action="store_true",
+                    help="instead of the step: the core-shaped case n_o=8, n_v=60, N_O=90, N_V=1100, rank 2500 with "
+                         "8 right and 8 left vectors and 8 density states, FP64 (with and without core-valence "
+                         "separation) and each reduced-precision form on an autotuned workspace, with its errors "
+                         "against FP64; one JSON line per form")
     ap.add_argument("--nv-sweep", action="store_true",
                     help="instead of the step: time the ground residual, right and left transforms and the "
                          "densities at a fixed active space (n_o=8, n_v=136) over six inactive-space sizes "
@@ -138,6 +144,90 @@ def paper_shapes(args):
         ws.close()
         del g, p, ws
         torch.cuda.empty_cache()
+
+
+def config4_report(args):
+    """Core-shaped case: 8 right and 8 left vectors and 8 density states in FP64 and in each
+    reduced-precision form with autotuned launch shapes; time per call (median) and the errors
+    of every output against the FP64 results."""
+    import os
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_2202_08612_amd import inputs as I
+    from paper_2202_08612_amd import mlcc3
+    from paper_2202_08612_amd.autotune import autotune
+    dev = torch.device("cuda", 0)
+    p = I.make_config(4, with_density_blocks=True)
+    d = p.dims
+    g = mlcc3.Ground(p, dev)
+    n = 8
+    om = [float(x) for x in I.omegas(4, n)]
+    R = [mlcc3.vec_to_device(v, dev) for v in I.right_vectors(p, n)]
+    L = [mlcc3.vec_to_device(v, dev) for v in I.left_vectors(p, n)]
+    lam = mlcc3.vec_to_device(I.lambda_vector(p), dev)
+    core = [1] + [0] * (d.N_O - 1)
+
+    def timed(fn):
+        out = fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return out, round(float(np.median(ts)) * 1e3, 2)
+
+    def run(ws, **kw):
+        res = {}
+        mlcc3.right_transform(ws, g, om, R, **kw)  # prepares the ground-state blocks
+        kw = dict(kw, reuse_ground=True)
+        out = {}
+        out["rho"], res["right_ms"] = timed(lambda: mlcc3.right_transform(ws, g, om, R, **kw))
+        out["sigma"], res["left_ms"] = timed(lambda: mlcc3.left_transform(ws, g, om, L, **kw))
+        kd = {k: v for k, v in kw.items() if k != "cvs_core"}
+        out["dens"], res["densities_ms"] = timed(
+            lambda: mlcc3.triples_densities(ws, g, om, L, R, lam, p.t2_vVoO, p.t2_vVOo, **kd))
+        return out, res
+
+    def errors(a, b):
+        worst_rel, worst_maxrel = 0.0, 0.0
+        for key in ("rho", "sigma"):
+            for m in range(n):
+                for k in a[key][m]:
+                    x, y = a[key][m][k].double(), b[key][m][k].double()
+                    ny = float(y.norm())
+                    if ny > 0:
+                        worst_rel = max(worst_rel, float((x - y).norm()) / ny)
+                        worst_maxrel = max(worst_maxrel, float((x - y).abs().max() / y.abs().max()))
+        dens = 0.0
+        for x, y in zip(a["dens"], b["dens"]):
+            ny = float(y.norm())
+            if ny > 0:
+                dens = max(dens, float((x - y).norm()) / ny)
+        return {"transforms_worst_rel": worst_rel, "transforms_worst_max_rel": worst_maxrel,
+                "densities_worst_rel": dens}
+
+    base = {"n_o": d.n_o, "n_v": d.n_v, "N_O": d.N_O, "N_V": d.N_V, "n_chol": d.n_chol, "vectors": n}
+    ws = mlcc3.Workspace(0)
+    ref, r64 = run(ws)
+    print(json.dumps({"config4": dict(base, precision="fp64", tuning="default", **r64)}), flush=True)
+    _, rc = run(ws, cvs_core=core)
+    rc.pop("densities_ms")
+    print(json.dumps({"config4": dict(base, precision="fp64", tuning="default", cvs="core orbital 0", **rc)}),
+          flush=True)
+    ws.close()
+    with tempfile.TemporaryDirectory() as tmp:
+        for form in ("fp64", "fp32", "bf16x6", "bf16x3"):
+            ws = mlcc3.Workspace(0)
+            tuning, rep = autotune(ws, g, om, R, L, precision=form, cache=os.path.join(tmp, "tune.json"), reps=1)
+            out, res = run(ws, precision=form)
+            err = errors(out, ref)
+            row = dict(base, precision=form, tuning=tuning, autotune_trials=len(rep["trials"]), **res, **err)
+            row["speedup_right_left"] = round((r64["right_ms"] + r64["left_ms"]) / (res["right_ms"] + res["left_ms"]), 3)
+            print(json.dumps({"config4": row}), flush=True)
+            ws.close()
 
 
 def nv_sweep(args):
@@ -297,6 +387,9 @@ def main():
         return
     if args.nv_sweep:
         nv_sweep(args)
+        return
+    if args.config4:
+        config4_report(args)
         return
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 8
