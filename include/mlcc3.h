@@ -38,7 +38,9 @@
  * rho_2 additionally carries Delta^{-1}, Delta_{ai,bj} = 1 + delta_ij delta_ab (SI).
  *
  * Pointers in mlcc3_ground / mlcc3_vec / mlcc3_out are DEVICE pointers on the
- * device the workspace was created for; omega arrays are HOST arrays.  The
+ * device the workspace was created for; omega arrays are HOST arrays.  Every array must
+ * hold at least the element count its layout and the sizes imply: the library checks
+ * pointers for NULL but cannot see allocation sizes, and reads past a short array.  The
  * caller owns all buffers; the library never frees or retains them beyond the
  * call.  Work is enqueued on `stream` (a hipStream_t, NULL = default stream)
  * and the call returns after enqueue; outputs are valid once the stream has
