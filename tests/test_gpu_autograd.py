@@ -147,3 +147,23 @@ def test_config3_batched_vectors_adjoint_fd_oracle(lib, ws):
     ref = Oracle(p).left_transform(om[0], map_grad_to_left(d, gout), *rng_t)
     for k in sig:
         assert rel(sig[k], ref[k]) <= 1e-10, (k, rel(sig[k], ref[k]))
+
+
+@pytest.mark.parametrize("case", ["tiny-full", "config0-fast"])
+def test_gradcheck(lib, ws, case):
+    """torch.autograd.gradcheck of the right transform: the full numerical Jacobian (central
+    differences, FP64) against the backward at a tiny shape, and torch's fast mode (random
+    projections) at the config-0 shape."""
+    import torch
+    from paper_2202_08612_amd import autograd as AD
+    d = I.Dims(2, 3, 3, 4, 5) if case == "tiny-full" else I.CONFIGS[0]["dims"]
+    p = I.make_problem(d, 41)
+    g = lib.Ground(p)
+    lib.ground_residual(ws, g)  # prepares the ground-state blocks that the forward reuses
+    R = _leaf(lib, _rand(d, np.random.default_rng(3)))
+
+    def f(x1, x2a, x2b):
+        return AD.right_transform(ws, g, 0.43, x1, x2a, x2b)
+
+    assert torch.autograd.gradcheck(f, (R["x1"], R["x2_vVoo"], R["x2_vvoO"]), eps=1e-6, atol=1e-7, rtol=1e-5,
+                                    fast_mode=(case != "tiny-full"))

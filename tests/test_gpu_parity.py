@@ -428,3 +428,30 @@ def test_cvs_full_config4(lib, ws):
                               precision="fp32")
     for k in rho[0]:
         assert rel(rmx[0][k].cpu().numpy(), rho[0][k].cpu().numpy()) <= 1e-6, k
+
+
+def test_executed_dcontract_flops_match_the_cost_model(lib, ws):
+    """The d-contraction launches execute exactly the model's O(N_V n_v^3 n_o^3) work: per product
+    term 2 N_V n_v^3 over all n_o^3 ordered triples (the n_o diagonal ones are formed and left
+    out of the algorithmic count U = 2 N_V n_v^3 (n_o^3 - n_o)); tau3 once per call, two terms
+    per right vector, one per left vector."""
+    d = I.Dims(5, 17, 7, 37, 23)
+    p = I.make_problem(d, 5)
+    g = lib.Ground(p)
+    R = [lib.vec_to_device(v) for v in I.right_vectors(p, 3)]
+    L = [lib.vec_to_device(v) for v in I.left_vectors(p, 3)]
+    om = I.omegas(False, 3)
+    T = 2.0 * d.N_V * d.n_v ** 3 * d.n_o ** 3
+    U = 2.0 * d.N_V * d.n_v ** 3 * (d.n_o ** 3 - d.n_o)
+    for name, call, terms, model in (
+            ("ground", lambda: lib.ground_residual(ws, g), 1, 2 * U),
+            ("right", lambda: lib.right_transform(ws, g, om, R, reuse_ground=True), 1 + 2 * 3, (1 + 3 * 3) * U),
+            ("left", lambda: lib.left_transform(ws, g, om, L, reuse_ground=True), 1 + 3, (1 + 3 * 3) * U)):
+        lib.right_transform(ws, g, om[:1], R[:1])  # prepared ground, warm buffers
+        ws.timing(True)
+        call()
+        st = ws.phase_stats(0)
+        ws.timing(False)
+        assert st["flops"] == terms * T, (name, st["flops"], terms * T)
+        fl = g.flops({"ground": 0, "right": 1, "left": 2}[name], 3)
+        assert fl == model, (name, fl, model)
