@@ -210,8 +210,20 @@ def config4_report(args):
                 "densities_worst_rel": dens}
 
     base = {"n_o": d.n_o, "n_v": d.n_v, "N_O": d.N_O, "N_V": d.N_V, "n_chol": d.n_chol, "vectors": n}
+    # algorithmic FLOPs: U = 2 N_V n_v^3 (n_o^3 - n_o); transforms (1 + 3 n) U each; densities of
+    # n states (2 + 2n) U for D^{m-0} and (2 + 4n) U + 2 U (lambda3) for D^{0-m}
+    U = 2.0 * d.N_V * d.n_v ** 3 * (d.n_o ** 3 - d.n_o)
+    f_tr, f_dens = (1 + 3 * n) * U, ((2 + 2 * n) + (2 + 4 * n) + 2) * U
+
+    def rates(res):
+        out = {"right_gflops": round(f_tr / res["right_ms"] / 1e6, 1), "left_gflops": round(f_tr / res["left_ms"] / 1e6, 1)}
+        if "densities_ms" in res:
+            out["densities_gflops"] = round(f_dens / res["densities_ms"] / 1e6, 1)
+        return out
+
     ws = mlcc3.Workspace(0)
     ref, r64 = run(ws)
+    r64.update(rates(r64))
     print(json.dumps({"config4": dict(base, precision="fp64", tuning="default", **r64)}), flush=True)
     _, rc = run(ws, cvs_core=core)
     rc.pop("densities_ms")
@@ -223,6 +235,7 @@ def config4_report(args):
             ws = mlcc3.Workspace(0)
             tuning, rep = autotune(ws, g, om, R, L, precision=form, cache=os.path.join(tmp, "tune.json"), reps=1)
             out, res = run(ws, precision=form)
+            res.update(rates(res))
             err = errors(out, ref)
             row = dict(base, precision=form, tuning=tuning, autotune_trials=len(rep["trials"]), **res, **err)
             row["speedup_right_left"] = round((r64["right_ms"] + r64["left_ms"]) / (res["right_ms"] + res["left_ms"]), 3)
@@ -316,6 +329,31 @@ def mixed_report(args, d, flops_step, dt64, outs64, timed, L, form):
             "within_1e-6": ok, "errors": err}
 
 
+def per_call_report(args, ws, g, w, R, L):
+    """FP64 time, GFLOP/s and fraction of the FP64 and FP32 matrix peaks of each call of the
+    step separately (ground residual, right and left transform of one vector), each call on its
+    own with the ground-state blocks already prepared (outside value)."""
+    import torch
+    from paper_2202_08612_amd import mlcc3
+    calls = {"ground_residual": (lambda: mlcc3.ground_residual(ws, g, reuse_ground=True), g.flops(0)),
+             "right_transform": (lambda: mlcc3.right_transform(ws, g, [w], R, reuse_ground=True), g.flops(1, 1)),
+             "left_transform": (lambda: mlcc3.left_transform(ws, g, [w], L, reuse_ground=True), g.flops(2, 1))}
+    out = {}
+    for name, (fn, fl) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        gf = fl / dt / 1e9
+        out[name] = {"ms": round(dt * 1e3, 3), "gflops": round(gf, 1),
+                     "pct_fp64_peak": round(100 * gf / 1e3 / FP64_PEAK_TFLOPS, 2),
+                     "pct_fp32_peak": round(100 * gf / 1e3 / FP32_PEAK_TFLOPS, 2)}
+    return out
+
+
 def iteration_report(args, ws, g, w, R, L):
     """One Davidson-style iteration of the FP64 path, right + left transform of the vector pair:
     with the tau~ blocks formed inside each call (as in the timed step) and kept in HBM across
@@ -369,7 +407,13 @@ def cpu_baseline(prob, ntrip):
     orc.left_transform(w, L, tb, te)
     dt = time.perf_counter() - t0
     fl = 10.0 * unit_flops(d, tb, te)
-    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(num_threads()), "kind": "oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(num_threads()), "kind": "oracle", "host_cpu": model,
             "sample": f"FP64 C oracle (restricted i>=j>=k loop, OpenMP), ground residual + right + left "
                       f"transform on unique triples [{tb},{te}) of {nt} at the full workload shape, "
                       f"integral preparation included; {dt:.1f} s"}
@@ -470,6 +514,7 @@ def main():
                      "launches": st["launches"], "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 4)},
         "cpu_baseline": None,
     }
+    res["per_call"] = per_call_report(args, ws, g, w, R, L)
     if not args.no_iteration:
         res["iteration"] = iteration_report(args, ws, g, w, R, L)
     if not args.no_mixed:
