@@ -14,7 +14,7 @@ from tests.helpers import rel
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
-# 16 divides n_v, so both forms of the contravariant pass run
+# 16 divides n_v: the default is the orbit form, contra_form 1 the per-sub-cube one
 D = I.Dims(4, 32, 6, 47, 19)
 
 
