@@ -49,7 +49,9 @@ def _fake(n):
     return [base + (i << 38) for i in range(n)]
 
 
-CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1), I.sweep_dims(5)]
+# I.Dims(17, 3, 18, 5, 7): more than 16 active occupied orbitals (generic occupied Gram blocks)
+CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1), I.sweep_dims(5),
+                                                   I.Dims(17, 3, 18, 5, 7)]
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x6"])

@@ -15,7 +15,7 @@ TOL = 1e-10
 
 SMALL = [I.Dims(3, 4, 4, 6, 10), I.Dims(4, 5, 5, 7, 12), I.CONFIGS[0]["dims"], I.Dims(4, 6, 4, 6, 9),
          I.Dims(2, 3, 4, 5, 8), I.Dims(5, 17, 7, 37, 23), I.Dims(6, 9, 6, 140, 33), I.Dims(4, 16, 5, 23, 17),
-         I.Dims(3, 32, 4, 41, 11)]
+         I.Dims(3, 32, 4, 41, 11), I.Dims(17, 3, 18, 5, 7)]  # the last: n_o > 16 (generic occupied Gram blocks)
 
 
 @pytest.fixture(scope="module")
