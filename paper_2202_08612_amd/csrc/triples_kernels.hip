@@ -649,8 +649,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ρ-type small contractions over ordered blocks, one workgroup per (p,q,a):
 //   part1[p][q][a]   = sum_{r,b,c} X~^{abc}_{pqr} g_qbrc
 //   Yvv[p][q][a][b]  = sum_{r,c} (X~^{abc}_{pqr} F_rc + T~^{abc}_{pqr} U_rc)
-// Each of the four waves takes every fourth row b and runs the r sum inside the row, so a row
-// costs one cross-lane reduction and its n_o loads per lane are independent of each other.
+// Each of the four waves takes every fourth row b; its lanes run over the n_o n_v pairs (r, c)
+// of the row, 64 at a time, so every pass but the last is a full wave of independent loads and
+// a row costs one cross-lane reduction.
 template <bool HAS_T>
 __global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ X, const double *__restrict__ T,
                                                      const double *__restrict__ gov, const double *__restrict__ F,
@@ -660,21 +661,29 @@ __global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ 
   const int a = id % nv, q = (id / nv) % no, p = id / (nv * no);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
-  const long long off = ((long long)p * no + q) * no * nv3 + (long long)a * nv2;  // r = 0
+  const long long off = ((long long)p * no + q) * no * nv3 + (long long)a * nv2;  // r = 0, b = 0
   const double *x0 = X + off;
   const double *g0 = gov + (long long)q * no * nv2;
+  const int nrc = no * nv;
+  const int r0 = lane / nv, c0 = lane - r0 * nv;  // (r, c) of position e = lane
   __shared__ double rpart[4];
   double racc = 0.0;
   for (int b = wv; b < nv; b += 4) {
+    const long long bo = (long long)b * nv;
     double yb = 0.0;
-    for (int c = lane; c < nv; c += 64) {
-      const long long e = (long long)b * nv + c;
+    int r = r0, c = c0;
 #pragma unroll 4
-      for (int r = 0; r < no; r++) {
-        const double x = x0[r * nv3 + e];
-        racc += x * g0[r * nv2 + e];
-        yb += x * F[r * nv + c];
-        if (HAS_T) yb += T[off + r * nv3 + e] * U[r * nv + c];
+    for (int e = lane; e < nrc; e += 64) {
+      const long long o = (long long)r * nv3 + bo + c;
+      const double x = x0[o];
+      racc += x * g0[(long long)r * nv2 + bo + c];
+      yb += x * F[r * nv + c];
+      if (HAS_T) yb += T[off + o] * U[r * nv + c];
+      // advance the position by 64: c += 64 with the carry into r
+      c += 64;
+      while (c >= nv) {
+        c -= nv;
+        r++;
       }
     }
     yb = wave_sum(yb);
