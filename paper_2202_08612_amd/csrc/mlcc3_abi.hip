@@ -1384,6 +1384,19 @@ void g_kl(const Dims &d, const double *X1, const double *X2, double *C, long lon
 // C[c][d] = alpha sum_{(ijk,ab)} X1[ijk][ab][c] X2[ijk][ab][d] + beta C
 void g_cd(const Dims &d, const double *X1, const double *X2, double *C, long long ldc, double alpha, double beta,
           hipStream_t s) {
+  if (d.nv > 64 && d.nv <= 160 && t_ws) {
+    // the whole n_v x n_v output per workgroup (the generic tiles would be half padding)
+    const long long nrows = d.nord * d.nv2;
+    const int nw = gram_cd_chunks(nrows);
+    double *P = buf(t_ws, "gram_part", (size_t)nw * d.nv * d.nv, s);
+    const size_t xb = sizeof(double) * (size_t)(d.nord * d.nv3);
+    check_bytes(X1, xb, "X1 (virtual Gram)");
+    check_bytes(X2, xb, "X2 (virtual Gram)");
+    check_range(C, plain(ldc), d.nv, plain(1), d.nv, 0, 1, "C (virtual Gram)");
+    launch_gram_cd(X1, X2, d.nv, nrows, P, alpha, beta, C, ldc, s);
+    HIPRT(hipGetLastError());
+    return;
+  }
   Gemm g = gemm_plain(d.nv, d.nv, C, plain(ldc), plain(1), alpha, beta);
   g.nseg = 1;
   g.seg[0] = seg(X1, plain(1), plain(d.nv), 0, X2, plain(d.nv), plain(1), 0, (int)(d.nord * d.nv2));

@@ -108,6 +108,11 @@ void launch_transpose(const double *in, double *out, int batch, int R, int C, hi
 void gram_kl_shape(int no, long long ne, int &nch, long long &chunk);
 void launch_gram_kl(const double *X1, const double *X2, int no, long long ne, double *P, double alpha, double beta,
                     double *C, long long ldc, hipStream_t s);
+// C[c][d] = alpha sum_k X1[k][c] X2[k][d] + beta C[c][d] over nrows rows of n contiguous values,
+// for 64 < n <= 160; P holds gram_cd_chunks(nrows) partial n x n blocks
+int gram_cd_chunks(long long nrows);
+void launch_gram_cd(const double *X1, const double *X2, int n, long long nrows, double *P, double alpha, double beta,
+                    double *C, long long ldc, hipStream_t s);
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s);
 void launch_diag_sum(const double *Q, int no, int nv, int NO, double *V, hipStream_t s);
 void launch_left_Z(const double *Am, const double *Hp, int nc, int no, int nv, double *Z, hipStream_t s);

@@ -737,6 +737,99 @@ __global__ __launch_bounds__(256) void k_gram_kl(const double *__restrict__ X1, 
     P[((long long)w * no + k) * no + l] = (red[0][k][l] + red[1][k][l]) + (red[2][k][l] + red[3][k][l]);
 }
 
+// Virtual Gram block of two ordered-triple buffers seen as row sets, for 64 < n <= 160:
+//   P[w][c][d] = sum_{k in chunk w} X1[k][c] X2[k][d],  rows k of n contiguous values
+// (n = n_v, k running over (i,j,k,a,b)).  The whole n x n output lives in one workgroup: 8 waves
+// share its 16x16 v_mfma_f64_16x16x4_f64 tiles (tile t = wave + 8 j), so each slab of 16 rows
+// (a contiguous block of 16 n values per operand) is read from HBM once and staged in LDS.
+constexpr int GCD_TMAX = 10;                          // 16-wide tiles per dimension (n <= 160)
+constexpr int GCD_LDP = 16 * GCD_TMAX + 4;            // LDS row pitch (doubles)
+constexpr int GCD_SLOTS = (GCD_TMAX * GCD_TMAX + 7) / 8;  // tiles per wave
+__global__ __launch_bounds__(512, 1) void k_gram_cd(const double *__restrict__ X1, const double *__restrict__ X2,
+                                                   int n, long long nrows, long long chunk,
+                                                   double *__restrict__ P) {
+  __shared__ double As[2][16][GCD_LDP];
+  __shared__ double Bs[2][16][GCD_LDP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = (n + 15) / 16, ntile = nt * nt;
+  const long long k0 = (long long)blockIdx.x * chunk, k1 = min(nrows, k0 + chunk);
+  const int nslab = (int)((k1 - k0 + 15) / 16);
+  const int sn = 16 * n;  // values per slab and operand
+  // zero both buffers once: the columns n .. 16 nt - 1 stay zero
+  for (int e = tid; e < 2 * 16 * GCD_LDP; e += 512) {
+    (&As[0][0][0])[e] = 0.0;
+    (&Bs[0][0][0])[e] = 0.0;
+  }
+  constexpr int PER = (16 * 16 * GCD_TMAX + 511) / 512;  // staged values per thread and operand
+  double ra[PER], rb[PER];
+  auto load = [&](int sl) {
+    const long long base = (k0 + 16LL * sl) * n;
+    const long long lim = (k1 - k0 - 16LL * sl) * n;  // values of this slab inside the chunk
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 512 * u;
+      const bool in = e < sn && e < lim;
+      ra[u] = in ? X1[base + e] : 0.0;
+      rb[u] = in ? X2[base + e] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 512 * u;
+      if (e < sn) {
+        const int r = e / n, c = e - (e / n) * n;
+        As[buf][r][c] = ra[u];
+        Bs[buf][r][c] = rb[u];
+      }
+    }
+  };
+  d4v acc[GCD_SLOTS];
+#pragma unroll
+  for (int j = 0; j < GCD_SLOTS; j++) acc[j] = d4v{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  if (nslab > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int sl = 0; sl < nslab; sl++) {
+    const int cur = sl & 1;
+    if (sl + 1 < nslab) load(sl + 1);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < GCD_SLOTS; j++) {
+        const int t = wave + 8 * j;
+        if (t < ntile) {  // uniform over the wave
+          const int ti = t / nt, tj = t - (t / nt) * nt;
+          const double a = As[cur][kr][16 * ti + (lane & 15)];
+          const double b = Bs[cur][kr][16 * tj + (lane & 15)];
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+    if (sl + 1 < nslab) store(cur ^ 1);
+    __syncthreads();
+  }
+  // lane l, register v: row (c) 16 ti + l/16 + 4 v, column (d) 16 tj + l%16
+  double *Pw = P + (long long)blockIdx.x * n * n;
+#pragma unroll
+  for (int j = 0; j < GCD_SLOTS; j++) {
+    const int t = wave + 8 * j;
+    if (t < ntile) {
+      const int ti = t / nt, tj = t - (t / nt) * nt;
+      const int d = 16 * tj + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int c = 16 * ti + (lane >> 4) + 4 * v;
+        if (c < n && d < n) Pw[(long long)c * n + d] = acc[j][v];
+      }
+    }
+  }
+}
+
 // C[k][l] = alpha sum_w P[w][k][l] + beta C[k][l] (row stride ldc): one workgroup per (k,l),
 // thread t sums w = t, t+256, ... and a fixed tree adds the 256 partial sums
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ P, int nw, int no, double alpha,
@@ -999,6 +1092,22 @@ void launch_gram_kl(const double *X1, const double *X2, int no, long long ne, do
   const int nw = no * no * nch;
   hipLaunchKernelGGL(k_gram_kl, dim3((unsigned)nw), dim3(256), 0, s, X1, X2, no, ne, chunk, nch, P);
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(no * no)), dim3(256), 0, s, P, nw, no, alpha, beta, C, ldc);
+}
+
+int gram_cd_chunks(long long nrows) {
+  const long long nslab = (nrows + 15) / 16;
+  return (int)std::max(1LL, std::min(512LL, nslab / 4));
+}
+
+void launch_gram_cd(const double *X1, const double *X2, int n, long long nrows, double *P, double alpha, double beta,
+                    double *C, long long ldc, hipStream_t s) {
+  if (g_dry || n <= 0 || nrows <= 0) return;
+  const int nw = gram_cd_chunks(nrows);
+  long long chunk = (nrows + nw - 1) / nw;
+  chunk = (chunk + 15) / 16 * 16;
+  const int nwu = (int)((nrows + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_gram_cd, dim3((unsigned)nwu), dim3(512), 0, s, X1, X2, n, nrows, chunk, P);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(n * n)), dim3(256), 0, s, P, nwu, n, alpha, beta, C, ldc);
 }
 
 void launch_sum_rows(const double *P, long long rows, long long n, double *out, hipStream_t s) {

@@ -455,3 +455,16 @@ def test_executed_dcontract_flops_match_the_cost_model(lib, ws):
         assert st["flops"] == terms * T, (name, st["flops"], terms * T)
         fl = g.flops({"ground": 0, "right": 1, "left": 2}[name], 3)
         assert fl == model, (name, fl, model)
+
+
+@pytest.mark.parametrize("d", [I.Dims(2, 70, 3, 75, 10), I.Dims(3, 66, 4, 71, 9)], ids=str)
+def test_densities_wide_virtual_space(lib, ws, d):
+    """64 < n_v <= 160: the virtual Gram blocks (D_cd) take the whole-output MFMA kernel."""
+    p, orc, g = _dens_case(lib, d, 37)
+    Ls, Rs = I.left_vectors(p, 1), I.right_vectors(p, 1)
+    lam = I.lambda_vector(p)
+    om = I.omegas(False, 1)
+    got = lib.triples_densities(ws, g, om, [lib.vec_to_device(v) for v in Ls], [lib.vec_to_device(v) for v in Rs],
+                                lib.vec_to_device(lam), p.t2_vVoO, p.t2_vVOo)
+    ref = orc.densities(om[0], Ls[0], Rs[0], lam, p.t2_vVoO, p.t2_vVOo)
+    _check_dens((got[0][0], got[1][0], got[2][0]), ref)
