@@ -15,7 +15,7 @@ throughput, the errors of every output against the FP64 path and, when every err
 1e-6, its speedup over FP64 are reported in the "mixed" object of the JSON line.
 
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
-runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --cfg;
+runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --no-per-call, --cfg;
 --copy-mib, --paper-shapes, --nv-sweep and --config4 run other reports instead of the step.
 """
 from __future__ import annotations
@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision steps (FP32 and split-bf16 MFMA)")
     ap.add_argument("--no-iteration", action="store_true",
                     help="skip the right + left iteration timing with and without kept tau~ blocks")
+    ap.add_argument("--no-per-call", action="store_true",
+                    help="skip the separate timing of the ground residual, right and left transform")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
@@ -514,7 +516,8 @@ def main():
                      "launches": st["launches"], "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 4)},
         "cpu_baseline": None,
     }
-    res["per_call"] = per_call_report(args, ws, g, w, R, L)
+    if not args.no_per_call:
+        res["per_call"] = per_call_report(args, ws, g, w, R, L)
     if not args.no_iteration:
         res["iteration"] = iteration_report(args, ws, g, w, R, L)
     if not args.no_mixed:
