@@ -330,7 +330,8 @@ hipEvent_t pool_event(mlcc3_ws ws) {
 
 // large-tile GEMM launch with the bounds self-check of its operands; the d-contraction is
 // recorded under timing phase 0 when the workspace timer is on
-void tgemm(const TileGemm &g, hipStream_t s) {
+// whole_k: never split K (each output then sums its K terms in the same order whatever N is)
+void tgemm(const TileGemm &g, hipStream_t s, bool whole_k = false) {
   if (g.M <= 0 || g.N <= 0) return;
   for (int i = 0; i < g.nseg; i++) {
     const TgSeg &sg = g.seg[i];
@@ -341,7 +342,7 @@ void tgemm(const TileGemm &g, hipStream_t s) {
   }
   check_range(g.C, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (tile GEMM)", g.cvec, g.nvec);
   mlcc3_ws ws = t_ws;
-  if (!g.dcontract && g.nvec == 1) {
+  if (!g.dcontract && g.nvec == 1 && !whole_k) {
     // split K when the 128x128 tiles fill the 512 workgroup slots (two per CU) in few, ragged
     // rounds: the part count with the best filled fraction of the last round (>= 256 K each)
     const long long tiles = tile_gemm_blocks(g);
@@ -445,9 +446,12 @@ Gemm asm_oovo(const Dims &d, double *C) {
   g.C = C;
   return g;
 }
-Seg asm_oovo_seg(const Dims &d, const double *A, const double *B) {
-  return seg(A, split(d.no, d.NO, 1), plain((long long)d.NO * d.NO), 0, B, plain((long long)d.nv * d.NO),
-             split(d.no, d.NO, 1), 0, d.nc);
+// A [nc][NO][row pitch pa], B [nc][nv][row pitch pb] (pitch 0: N_O)
+Seg asm_oovo_seg(const Dims &d, const double *A, const double *B, long long pa = 0, long long pb = 0) {
+  if (pa <= 0) pa = d.NO;
+  if (pb <= 0) pb = d.NO;
+  return seg(A, split(d.no, pa, 1), plain((long long)d.NO * pa), 0, B, plain((long long)d.nv * pb), split(d.no, pb, 1),
+             0, d.nc);
 }
 
 // --------------------------------------- one-index transformations of the Cholesky vectors
@@ -503,13 +507,16 @@ void lhat_blocks(const Dims &d, const mlcc3_ground *g, double *LhOO, double *Lhv
 //   dOO[J][I][K] = sum_A L_OV[J][I][A] R[A][K]
 //   dvV[J][a][B] = -sum_I R[a][I] L_OV[J][I][B]
 //   dvO[J][c][K] = sum_B Lhat_vV[J][c][B] R[B][K] - sum_I R[c][I] Lhat_OO[J][I][K]
-void dlhat_blocks(const Dims &d, const double *LOV, const double *LhvV, const double *LhOO, const double *R1,
-                  double *dOO, double *dvV, double *dvO, hipStream_t s) {
+// The two products over the full N_V (dOO and the first term of dvO) are formed for the whole
+// group of vectors at once (group_dlhat, rows of pitch nb N_O with vector v at column v N_O);
+// the rest per vector (dlhat_rest, on vector v's columns).
+void dlhat_rest(const Dims &d, const double *LOV, const double *LhOO, const double *R1, double *dvV, double *dvO,
+                long long pitch, hipStream_t s) {
   const int nc = d.nc, NO = d.NO, NV = d.NV, nv = d.nv;
-  gemm(plain_gemm(nc * NO, NO, NV, 1, LOV, NV, 0, R1, NO, 0, dOO, NO, 0, 1.0, 0.0), s);
   gemm(plain_gemm(nv, NV, NO, nc, R1, NO, 0, LOV, NV, (long long)NO * NV, dvV, NV, (long long)nv * NV, -1.0, 0.0), s);
-  gemm(plain_gemm(nc * nv, NO, NV, 1, LhvV, NV, 0, R1, NO, 0, dvO, NO, 0, 1.0, 0.0), s);
-  gemm(plain_gemm(nv, NO, NO, nc, R1, NO, 0, LhOO, NO, (long long)NO * NO, dvO, NO, (long long)nv * NO, -1.0, 1.0), s);
+  gemm(plain_gemm(nv, NO, NO, nc, R1, NO, 0, LhOO, NO, (long long)NO * NO, dvO, pitch, (long long)nv * pitch, -1.0,
+                  1.0),
+       s);
 }
 
 // X_kc = sum_LD (2 g_kcLD - g_kDLc) x^D_L from bare (ov|ov) = sum_J L_kc L_LD (active k, c):
@@ -536,7 +543,7 @@ void fock_like(const Dims &d, const double *LOV, const double *x, double *tmp_x,
 // columns of B are packed to [nc][nv][n_o], the product (rows (b,D), columns (c,k), K = nc)
 // goes to a scratch block, which one pass then permutes into the [k][D][b][c] layout
 void vVvo_tiled(mlcc3_ws ws, const Dims &d, int nseg, const double *const *A, const double *const *Bfull, double *C,
-                hipStream_t s) {
+                hipStream_t s, const long long *bpitch = nullptr) {
   const int nc = d.nc, nv = d.nv, NV = d.NV, NO = d.NO, no = d.no;
   const long long M = (long long)nv * NV, N = (long long)nv * no;
   if (M <= 0 || N <= 0) return;
@@ -552,7 +559,9 @@ void vVvo_tiled(mlcc3_ws ws, const Dims &d, int nseg, const double *const *A, co
   for (int i = 0; i < nseg; i++) {
     double *Bp = buf(ws, pn[i], (size_t)nc * nv * no, s);
     check_bytes(Bp, sizeof(double) * nc * nv * no, "packed B (vVvo)");
-    launch_pack_cols(Bfull[i], (long long)nc * nv, NO, no, Bp, s);
+    const long long ld = bpitch ? bpitch[i] : NO;
+    check_bytes(Bfull[i], sizeof(double) * (size_t)(((long long)nc * nv - 1) * ld + no), "B (vVvo)");
+    launch_pack_cols(Bfull[i], (long long)nc * nv, (int)ld, no, Bp, s);
     g.seg[i] = tseg(A[i], plain(M), 0, Bp, N, 0, nc);
   }
   tgemm(g, s);
@@ -1199,6 +1208,35 @@ RightSizes right_sizes(const Dims &d) {
 // one-index transformed blocks of right vector `slot` of a group of nb: Rbar packs "RA"
 // [p][q][a][D] and "RB" [a][b][p][L], Upsilon_bDck "U1", Upsilon_Ljck "Uo", Upsilon_kc "Ukc",
 // Xi_jLkc "Xi"; each buffer holds nb blocks, this vector's at slot * size
+void group_dlhat(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *R, int nb, hipStream_t s) {
+  const int nc = d.nc, NO = d.NO, NV = d.NV, nv = d.nv;
+  const long long pitch = (long long)nb * NO;
+  double *R1s = buf(ws, "R1s", (size_t)(NV * pitch), s);
+  for (int v = 0; v < nb; v++) {
+    check_bytes(R[v].x1, sizeof(double) * (size_t)NV * NO, "R1 (group)");
+    check_bytes(R1s + v * NO, sizeof(double) * (size_t)((NV - 1) * pitch + NO), "stacked R1");
+    if (!g_dry)
+      HIPRT(hipMemcpy2DAsync(R1s + v * NO, sizeof(double) * pitch, R[v].x1, sizeof(double) * NO, sizeof(double) * NO,
+                             NV, hipMemcpyDeviceToDevice, s));
+  }
+  double *dOO = buf(ws, "dOO", (size_t)((long long)nc * NO * pitch), s);
+  double *dvO = buf(ws, "dvO", (size_t)((long long)nc * nv * pitch), s);
+  const double *A[2] = {g->L_OV, B(ws, "LhvV")};
+  double *C[2] = {dOO, dvO};
+  const int M[2] = {nc * NO, nc * nv};
+  for (int i = 0; i < 2; i++) {
+    TileGemm tg;
+    tg.M = M[i];
+    tg.N = (int)pitch;
+    tg.nseg = 1;
+    tg.ak = 1;
+    tg.C = C[i];
+    tg.cmap = plain(pitch);
+    tg.seg[0] = tseg(A[i], plain(NV), 0, R1s, pitch, 0, NV);
+    tgemm(tg, s, true);  // whole K: the same sums for any group size
+  }
+}
+
 void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &R, int slot, int nb,
                        hipStream_t s) {
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
@@ -1207,22 +1245,25 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
   double *RB = buf(ws, "RB", (size_t)(z.RB * nb), s) + slot * z.RB;
   launch_pack_vVoo(R.x2_vVoo, no, nv, NV, 1, RA, s);
   launch_rbar_vvoO(R.x2_vvoO, no, nv, NO, RB, s);
-  double *dOO = buf(ws, "dOO", (size_t)nc * NO * NO, s);
+  // this vector's columns of the group's dOO and dvO (group_dlhat), row pitch nb N_O
+  const long long pitch = (long long)nb * NO;
+  const double *dOO = B(ws, "dOO") + slot * NO;
+  double *dvO = B(ws, "dvO") + slot * NO;
   double *dvV = buf(ws, "dvV", (size_t)nc * nv * NV, s);
-  double *dvO = buf(ws, "dvO", (size_t)nc * nv * NO, s);
-  dlhat_blocks(d, g->L_OV, B(ws, "LhvV"), B(ws, "LhOO"), R.x1, dOO, dvV, dvO, s);
+  dlhat_rest(d, g->L_OV, B(ws, "LhOO"), R.x1, dvV, dvO, pitch, s);
   HIPRT(hipGetLastError());
   double *U1 = buf(ws, "U1", (size_t)(z.U1 * nb), s) + slot * z.U1;
   {
     const double *A[2] = {dvV, B(ws, "LhvV")}, *Bv[2] = {B(ws, "LhvO"), dvO};
-    vVvo_tiled(ws, d, 2, A, Bv, U1, s);
+    const long long bp[2] = {NO, pitch};
+    vVvo_tiled(ws, d, 2, A, Bv, U1, s, bp);
   }
   double *Uo = buf(ws, "Uo", (size_t)(z.Uo * nb), s) + slot * z.Uo;
   {
     Gemm gg = asm_oovo(d, Uo);
     gg.nseg = 2;
-    gg.seg[0] = asm_oovo_seg(d, dOO, B(ws, "LhvO"));
-    gg.seg[1] = asm_oovo_seg(d, B(ws, "LhOO"), dvO);
+    gg.seg[0] = asm_oovo_seg(d, dOO, B(ws, "LhvO"), pitch, 0);
+    gg.seg[1] = asm_oovo_seg(d, B(ws, "LhOO"), dvO, 0, pitch);
     gemm(gg, s);
   }
   double *Ukc = buf(ws, "Ukc", (size_t)(z.Ukc * nb), s) + slot * z.Ukc;
@@ -1720,6 +1761,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     for (int m0 = 0; m0 < nvec; m0 += ng) {
       const int nb = std::min(ng, nvec - m0);
       double *XRg = buf(ws, "XR", (size_t)(d.nord * d.nv3 * nb), s);
+      group_dlhat(ws, g, d, R + m0, nb, s);
       for (int v = 0; v < nb; v++) right_vector_prep(ws, g, d, R[m0 + v], v, nb, s);
       build_R3(ws, g, d, R + m0, omega + m0, nb, r, XRg, nullptr, s);
       for (int v = 0; v < nb; v++) {
@@ -2025,6 +2067,7 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     for (int m = 0; m < nstate; m++) {
       double *Dm = D_m0 + (long long)m * N * N, *D0 = D_0m + (long long)m * N * N;
       build_L3(ws, g, d, L + m, omega + m, 1, r, XL, "LA", "LV", s);
+      group_dlhat(ws, g, d, R + m, 1, s);
       right_vector_prep(ws, g, d, R[m], 0, 1, s);
       build_R3(ws, g, d, R + m, omega + m, 1, r, XRt, XRc, s);
       // ---- D^{m-0} (SI left density) ----
