@@ -629,7 +629,7 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   }
   // Gb3L[L][j][k][c] (the occupied term of L3 reads G with L outermost); t2xT[i][a][L][b] = t^{ab}_{iL}
   launch_transpose(Gb3, buf(ws, "Gb3L", (size_t)no * no * nv * NO, s), 1, no * no * nv, NO, s);
-  launch_occ_xT(g->t2_vvoO, no, nv, NO, buf(ws, "t2xT", (size_t)no * nv * NO * nv, s), s);
+  launch_occ_xT(g->t2_vvoO, no, nv, NO, buf(ws, "t2xT", (size_t)no * nv * NO * occ_pitch(nv), s), s);
   HIPRT(hipGetLastError());
   // gov[j][k][b][c] = g_jbkc (bare)
   double *gov = buf(ws, "gov", (size_t)no * no * d.nv2, s);
@@ -726,7 +726,7 @@ double *B(mlcc3_ws ws, const char *name) {
 // the occupied-term operands read inside the permutation kernel: x [n_v][n_v][n_o][N_O] and a
 // G block of n_o^2 n_v N_O elements (either layout)
 void reg_check_occ(const Dims &d, const double *x, const double *G) {
-  const long long nx = (long long)d.nv * d.nv * d.no * d.NO, ng = (long long)d.no * d.no * d.nv * d.NO;
+  const long long nx = (long long)d.nv * occ_pitch(d.nv) * d.no * d.NO, ng = (long long)d.no * d.no * d.nv * d.NO;
   check_range(x, plain(1), (int)nx, plain(0), 1, 0, 1, "occupied-term x");
   check_range(G, plain(1), (int)ng, plain(0), 1, 0, 1, "occupied-term G");
 }
@@ -932,7 +932,7 @@ void occ_add(OccTerm &ot, const Dims &d, const double *xT, long long xv, const d
 // buffer `name`, stacked with the stride returned in *stride
 const double *occ_xT(mlcc3_ws ws, const Dims &d, const double *const *x, int nb, const char *name, long long *stride,
                      hipStream_t s) {
-  const long long n = (long long)d.no * d.nv * d.NO * d.nv;
+  const long long n = (long long)d.no * d.nv * d.NO * occ_pitch(d.nv);
   double *xT = buf(ws, name, (size_t)(n * nb), s);
   for (int v = 0; v < nb; v++) launch_occ_xT(x[v], d.no, d.nv, d.NO, xT + v * n, s);
   HIPRT(hipGetLastError());

@@ -97,7 +97,10 @@ void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, 
 // elements with a core occupied index; core: device flags [N_O]
 void launch_cvs_project(const double *x1, const double *x2a, const double *x2b, double *y1, double *y2a, double *y2b,
                         const unsigned char *core, int no, int nv, int NO, int NV, hipStream_t s);
-// xT[p][a][L][b] = x[a][b][p][L]  (x: [n_v][n_v][n_o][N_O])
+// xT[p][a][L][b] = x[a][b][p][L]  (x: [n_v][n_v][n_o][N_O]); the b rows have the pitch
+// occ_pitch(n_v) (padding zero), so that the 16-wide segments the MFMA operand loads read
+// are whole 128-byte lines
+__host__ __device__ inline int occ_pitch(int nv) { return (nv + 15) / 16 * 16; }
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s);
 // out[z][c][r] = in[z][r][c], z < batch
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s);

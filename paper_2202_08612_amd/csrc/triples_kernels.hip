@@ -238,7 +238,8 @@ __device__ __forceinline__ void cube_store(const double (&v)[TT], double *lds) {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-// cube[x][y][z] -= sum_L xT[p][X0+x][L][Y0+y] G[L][q][r][Z0+z] for the sub-cube in LDS; wave w
+// cube[x][y][z] -= sum_L xT[p][X0+x][L][Y0+y] G[L][q][r][Z0+z] for the sub-cube in LDS (xT rows of
+// pitch occ_pitch(n_v)); wave w
 // takes the x-slices w, w+4, w+8, w+12, each a 16x16 (y,z) tile of v_mfma_f64_16x16x4_f64
 // (operand lane l: A row y = l%16, k = l/16; B k = l/16, column z = l%16; result row
 // l/16 + 4v, column l%16).
@@ -248,6 +249,7 @@ __device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int vec, int no
   const int ly = lane & 15, lk = lane >> 4;
   const int NO = ot.NO;
   const int gy = Y0 + ly, gz = Z0 + ly;
+  const int nvp = occ_pitch(nv);  // b pitch of xT
   constexpr int KC = 4;  // k-steps per chunk (16 values of L)
   constexpr int XS = TT / 4;  // x-slices per wave: w, w+4, w+8, w+12, taken two at a time
   const long long qr = (long long)no * no * nv;  // L stride of G
@@ -268,11 +270,11 @@ __device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int vec, int no
 #pragma unroll
         for (int e = 0; e < 2; e++) {
           const int gx = X0 + wave + 4 * (h + e);
-          const double *xa = ot.x[sg] + vec * ot.xv[sg] + ((long long)p * nv + gx) * NO * nv + gy;
+          const double *xa = ot.x[sg] + vec * ot.xv[sg] + ((long long)p * nv + gx) * NO * nvp + gy;
 #pragma unroll
           for (int u = 0; u < KC; u++) {
             const int L = k0 + 4 * u + lk;
-            a[e][u] = (L < NO && gy < nv && gx < nv) ? xa[L * nv] : 0.0;
+            a[e][u] = (L < NO && gy < nv && gx < nv) ? xa[L * nvp] : 0.0;
           }
         }
 #pragma unroll
@@ -439,15 +441,16 @@ __global__ void k_cvs_project(const double *x1, const double *x2a, const double 
 
 // xT[p][a][L][b] = x[a][b][p][L]
 __global__ void k_occ_xT(const double *__restrict__ x, int no, int nv, int NO, double *__restrict__ xT) {
-  const long long n = (long long)no * nv * NO * nv;
+  const int nvp = occ_pitch(nv);
+  const long long n = (long long)no * nv * NO * nvp;
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (id >= n) return;
-  const int b = (int)(id % nv);
-  long long t = id / nv;
+  const int b = (int)(id % nvp);
+  long long t = id / nvp;
   const int L = (int)(t % NO);
   t /= NO;
   const int a = (int)(t % nv), p = (int)(t / nv);
-  xT[id] = x[(((long long)a * nv + b) * no + p) * NO + L];
+  xT[id] = b < nv ? x[(((long long)a * nv + b) * no + p) * NO + L] : 0.0;
 }
 
 // ------------------------------------------------- pairing maps of doubles vectors
@@ -1067,7 +1070,7 @@ void launch_cvs_project(const double *x1, const double *x2a, const double *x2b, 
 }
 
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s) {
-  L1D(k_occ_xT, (long long)no * nv * NO * nv, x, no, nv, NO, xT);
+  L1D(k_occ_xT, (long long)no * nv * NO * occ_pitch(nv), x, no, nv, NO, xT);
 }
 
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s) {
