@@ -946,7 +946,8 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
              const double *omega, int nb, Range r, const LocalTerms &lt, const OccTerm &ot, hipStream_t s,
              double *Xc = nullptr) {
   check(nb >= 1 && nb <= kMaxVecBatch, "vector group too large");
-  const long long Wv = d.nord * d.nv3, Xuv = (long long)ws->nu * d.nv3;
+  // unique-triple blocks Xu[u][a][b][c] with rows of pitch occ_pitch(n_v) (whole 128-byte lines)
+  const long long Wv = d.nord * d.nv3, Xuv = (long long)ws->nu * d.nv2 * occ_pitch(d.nv);
   double *Xu = buf(ws, "Xu", (size_t)(Xuv * nb), s);
   VecBatch vb;
   vb.nvec = nb;

@@ -79,7 +79,8 @@ struct VecBatch {
   unsigned long long core_bits = 0;
 };
 
-// W -> Xu (covariant unique-triple blocks [u][a][b][c]) -> Xt (contravariant, all orderings)
+// W -> Xu (covariant unique-triple blocks [u][a][b][c], rows of pitch occ_pitch(n_v)) -> Xt
+// (contravariant, all orderings)
 // (and, if Xc is not NULL, the covariant X to every ordering); contravariant pass per
 // sub-cube (contra_form 1), per orbit of sub-cubes (2), or by the size rule (0: per orbit
 // when 16 divides n_v or n_v > 64)

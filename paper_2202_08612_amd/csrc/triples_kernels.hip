@@ -216,15 +216,16 @@ __device__ __forceinline__ void pass_item(int nvec, int nu, int nt, int &vec, in
 constexpr int LY = TT + 1, LX = (TT + 1) * (TT + 1);  // odd strides (in doubles) against bank conflicts
 constexpr int SUB = TT * LX;
 
-// sub-cube of block src starting at (X0,Y0,Z0): thread (y,z) = (tid/16, tid%16) loads the
-// 16 x-values of its (y,z) line into registers; cube_store puts them at lds[x*LX + y*LY + z]
-__device__ __forceinline__ void cube_load(const double *__restrict__ src, int nv, int X0, int Y0, int Z0,
+// sub-cube of block src (rows of pitch rp >= n_v) starting at (X0,Y0,Z0): thread (y,z) =
+// (tid/16, tid%16) loads the 16 x-values of its (y,z) line into registers; cube_store puts them
+// at lds[x*LX + y*LY + z]
+__device__ __forceinline__ void cube_load(const double *__restrict__ src, int nv, int rp, int X0, int Y0, int Z0,
                                           double (&v)[TT]) {
   const int tid = threadIdx.x;
   const int y = tid >> 4, z = tid & 15;
-  const long long nv2 = (long long)nv * nv;
+  const long long nv2 = (long long)nv * rp;
   const bool yz = (Y0 + y) < nv && (Z0 + z) < nv;
-  const double *row = src + (long long)(Y0 + y) * nv + (Z0 + z);
+  const double *row = src + (long long)(Y0 + y) * rp + (Z0 + z);
 #pragma unroll
   for (int x = 0; x < TT; x++) v[x] = (yz && X0 + x < nv) ? row[(X0 + x) * nv2] : 0.0;
 }
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
       const int X0 = TT * sel3(T0, T1, T2, s0), Y0 = TT * sel3(T0, T1, T2, s1), Z0 = TT * sel3(T0, T1, T2, s2);
       {
         double v[TT];
-        cube_load(W + ((long long)(p * no + q) * no + rr) * nv3, nv, X0, Y0, Z0, v);
+        cube_load(W + ((long long)(p * no + q) * no + rr) * nv3, nv, nv, X0, Y0, Z0, v);
         __syncthreads();
         cube_store(v, cube);
       }
@@ -350,7 +351,8 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
     }
   }
   const double eocc = eps_o[u.i] + eps_o[u.j] + eps_o[u.k];
-  double *dst = Xu + (long long)tri * nv3;
+  const int up = occ_pitch(nv);  // row pitch of the unique-triple blocks
+  double *dst = Xu + (long long)tri * nv * nv * up;
   const int gb = TT * T1 + lb, gc = TT * T2 + lc;
   if (gb >= nv || gc >= nv) return;
 #pragma unroll
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
     const int ga = TT * T0 + r;
     if (ga >= nv) break;
     const double den = eps_v[ga] + eps_v[gb] + eps_v[gc] - eocc - omega;
-    dst[ga * nv2 + (long long)gb * nv + gc] = active ? -acc[r] / den : 0.0;
+    dst[((long long)ga * nv + gb) * up + gc] = active ? -acc[r] / den : 0.0;
   }
 }
 
@@ -375,21 +377,22 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
-  const double *src = Xu + (long long)tri * nv3;
+  const int up = occ_pitch(nv);  // row pitch of the unique-triple blocks
+  const double *src = Xu + (long long)tri * nv * nv * up;
   double acc[TT];
 #pragma unroll
   for (int r = 0; r < TT; r++) acc[r] = 0.0;
   const int nterm = covariant ? 1 : 6;  // covariant mode copies X itself to every ordering
   // the sub-cube of term t+1 is loaded into registers while term t is gathered
   double nxt[TT];
-  cube_load(src, nv, TT * T[0], TT * T[1], TT * T[2], nxt);
+  cube_load(src, nv, up, TT * T[0], TT * T[1], TT * T[2], nxt);
   for (int t = 0; t < nterm; t++) {
     const int t0 = c_perm[t][0], t1 = c_perm[t][1], t2 = c_perm[t][2];
     __syncthreads();
     cube_store(nxt, cube);
     if (t + 1 < nterm) {
       const int u0 = c_perm[t + 1][0], u1 = c_perm[t + 1][1], u2 = c_perm[t + 1][2];
-      cube_load(src, nv, TT * T[u0], TT * T[u1], TT * T[u2], nxt);
+      cube_load(src, nv, up, TT * T[u0], TT * T[u1], TT * T[u2], nxt);
     }
     __syncthreads();
     const double cf = covariant ? 1.0 : c_coef[t];
@@ -576,7 +579,8 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
-  const double *src = Xu + vec * xuv + (long long)tri * nv3;
+  const int up = occ_pitch(nv);  // row pitch of the unique-triple blocks
+  const double *src = Xu + vec * xuv + (long long)tri * nv * nv * up;
   Xt += vec * xtv;
   double acc[6][TT];
 #pragma unroll
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
     const int J = mem[j];
     const int J0 = J / (nt * nt), J1 = (J / nt) % nt, J2 = J % nt;
     double v[TT];
-    cube_load(src, nv, TT * J0, TT * J1, TT * J2, v);
+    cube_load(src, nv, up, TT * J0, TT * J1, TT * J2, v);
     __syncthreads();
     cube_store(v, cube);
     __syncthreads();
