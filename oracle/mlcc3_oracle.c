@@ -88,23 +88,32 @@ static void ov_fock_like(const ctx *c, const double *x, double *out) {
   const int no = c->no, nv = c->nv, NO = c->NO, NV = c->NV, nc = c->nc;
   const double *LOV = c->P->L_OV;
   memset(out, 0, sizeof(double) * no * nv);
+  double *sJ = zalloc(nc); /* s_J = sum_LD L_LD x^D_L */
+#pragma omp parallel for schedule(static)
   for (int J = 0; J < nc; J++) {
     const double *Lov = LOV + (size_t)J * NO * NV;
     double s = 0.0;
     for (int L = 0; L < NO; L++)
       for (int D = 0; D < NV; D++) s += Lov[L * NV + D] * x[D * NO + L];
-    for (int cc = 0; cc < nv; cc++) {
-      double *u = zalloc(NV); /* u_D = sum_L L_Lc x^D_L */
+    sJ[J] = s;
+  }
+#pragma omp parallel for schedule(static)
+  for (int cc = 0; cc < nv; cc++) {
+    double *u = zalloc(NV); /* u_D = sum_L L_Lc x^D_L */
+    for (int J = 0; J < nc; J++) {
+      const double *Lov = LOV + (size_t)J * NO * NV;
+      memset(u, 0, sizeof(double) * NV);
       for (int D = 0; D < NV; D++)
         for (int L = 0; L < NO; L++) u[D] += Lov[L * NV + cc] * x[D * NO + L];
       for (int k = 0; k < no; k++) {
         double e = 0.0;
         for (int D = 0; D < NV; D++) e += Lov[k * NV + D] * u[D];
-        out[k * nv + cc] += 2.0 * Lov[k * NV + cc] * s - e;
+        out[k * nv + cc] += 2.0 * Lov[k * NV + cc] * sJ[J] - e;
       }
-      free(u);
     }
+    free(u);
   }
+  free(sJ);
 }
 
 static void ctx_init(ctx *c, const orc_problem *P) {
@@ -139,13 +148,13 @@ static void ctx_init(ctx *c, const orc_problem *P) {
         for (int I = 0; I < NO; I++) s -= t1[D * NO + I] * Lov[I * NV + b];
         c->Lh_Vv[((size_t)J * NV + D) * nv + b] = s;
       }
+    /* Lhat_cK = [(1 - T) M]_cK with M = L (1 + T): M_cK = L_cK + sum_B L_cB t_BK, and the
+       occupied rows of M are M_IK = hOO[I][K] (formed above) */
     for (int cc = 0; cc < nv; cc++)
       for (int K = 0; K < NO; K++) {
         double s = Lov[K * NV + cc]; /* L_cK = L_Kc */
-        for (int I = 0; I < NO; I++) s -= t1[cc * NO + I] * Loo[I * NO + K];
         for (int B = 0; B < NV; B++) s += Lvv[cc * NV + B] * t1[B * NO + K];
-        for (int I = 0; I < NO; I++)
-          for (int B = 0; B < NV; B++) s -= t1[cc * NO + I] * Lov[I * NV + B] * t1[B * NO + K];
+        for (int I = 0; I < NO; I++) s -= t1[cc * NO + I] * hOO[I * NO + K];
         c->Lh_vO[((size_t)J * nv + cc) * NO + K] = s;
       }
   }
@@ -153,26 +162,34 @@ static void ctx_init(ctx *c, const orc_problem *P) {
   /* ghat_bDck and ghat_Ljck: accumulate over J with c innermost */
   c->G1 = zalloc((size_t)no * NV * nv * nv);
   c->Go = zalloc((size_t)no * no * NO * nv);
-#pragma omp parallel for schedule(static)
-  for (int k = 0; k < no; k++) {
-    double *w = zalloc(nv);
-    for (int J = 0; J < nc; J++) {
-      for (int cc = 0; cc < nv; cc++) w[cc] = c->Lh_vO[((size_t)J * nv + cc) * NO + k];
-      for (int D = 0; D < NV; D++)
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < no; k++)
+    for (int D = 0; D < NV; D++) {
+      double *w = zalloc(nv);
+      for (int J = 0; J < nc; J++) {
+        for (int cc = 0; cc < nv; cc++) w[cc] = c->Lh_vO[((size_t)J * nv + cc) * NO + k];
         for (int b = 0; b < nv; b++) {
           const double f = c->Lh_vV[((size_t)J * nv + b) * NV + D];
           double *g = c->G1 + IDX4(k, D, b, 0, NV, nv, nv);
           for (int cc = 0; cc < nv; cc++) g[cc] += f * w[cc];
         }
-      for (int j = 0; j < no; j++)
+      }
+      free(w);
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < no; k++)
+    for (int j = 0; j < no; j++) {
+      double *w = zalloc(nv);
+      for (int J = 0; J < nc; J++) {
+        for (int cc = 0; cc < nv; cc++) w[cc] = c->Lh_vO[((size_t)J * nv + cc) * NO + k];
         for (int L = 0; L < NO; L++) {
           const double f = c->LhOO[((size_t)J * NO + L) * NO + j];
           double *g = c->Go + IDX4(j, k, L, 0, no, NO, nv);
           for (int cc = 0; cc < nv; cc++) g[cc] += f * w[cc];
         }
+      }
+      free(w);
     }
-    free(w);
-  }
   c->gov = zalloc((size_t)no * no * nv * nv);
   c->gOL = zalloc((size_t)no * no * nv * NO);
 #pragma omp parallel for collapse(2) schedule(static)
@@ -288,29 +305,40 @@ static void rvec_init(const ctx *c, rvec *v, const double *R1, const double *R2a
   /* Upsilon_bDck = sum_J (dL_bD Lh_ck + Lh_bD dL_ck), Upsilon_Ljck likewise */
   v->U1 = zalloc((size_t)no * NV * nv * nv);
   v->Uo = zalloc((size_t)no * no * NO * nv);
-#pragma omp parallel for schedule(static)
-  for (int k = 0; k < no; k++) {
-    double *w = zalloc(nv), *dw = zalloc(nv);
-    for (int J = 0; J < nc; J++) {
-      for (int cc = 0; cc < nv; cc++) {
-        w[cc] = c->Lh_vO[((size_t)J * nv + cc) * NO + k];
-        dw[cc] = dvO[((size_t)J * nv + cc) * NO + k];
-      }
-      for (int D = 0; D < NV; D++)
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < no; k++)
+    for (int D = 0; D < NV; D++) {
+      double *w = zalloc(nv), *dw = zalloc(nv);
+      for (int J = 0; J < nc; J++) {
+        for (int cc = 0; cc < nv; cc++) {
+          w[cc] = c->Lh_vO[((size_t)J * nv + cc) * NO + k];
+          dw[cc] = dvO[((size_t)J * nv + cc) * NO + k];
+        }
         for (int b = 0; b < nv; b++) {
           const double f = dvV[((size_t)J * nv + b) * NV + D], h = c->Lh_vV[((size_t)J * nv + b) * NV + D];
           double *g = v->U1 + IDX4(k, D, b, 0, NV, nv, nv);
           for (int cc = 0; cc < nv; cc++) g[cc] += f * w[cc] + h * dw[cc];
         }
-      for (int j = 0; j < no; j++)
+      }
+      free(w); free(dw);
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < no; k++)
+    for (int j = 0; j < no; j++) {
+      double *w = zalloc(nv), *dw = zalloc(nv);
+      for (int J = 0; J < nc; J++) {
+        for (int cc = 0; cc < nv; cc++) {
+          w[cc] = c->Lh_vO[((size_t)J * nv + cc) * NO + k];
+          dw[cc] = dvO[((size_t)J * nv + cc) * NO + k];
+        }
         for (int L = 0; L < NO; L++) {
           const double f = dOO[((size_t)J * NO + L) * NO + j], h = c->LhOO[((size_t)J * NO + L) * NO + j];
           double *g = v->Uo + IDX4(j, k, L, 0, no, NO, nv);
           for (int cc = 0; cc < nv; cc++) g[cc] += f * w[cc] + h * dw[cc];
         }
+      }
+      free(w); free(dw);
     }
-    free(w); free(dw);
-  }
   v->Ukc = zalloc((size_t)no * nv);
   ov_fock_like(c, R1, v->Ukc);
   /* Xi_jLkc = sum_D g_jDkc R^D_L with g_jDkc = sum_J L_jD L_kc (bare) */
