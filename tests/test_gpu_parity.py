@@ -457,7 +457,8 @@ def test_executed_dcontract_flops_match_the_cost_model(lib, ws):
         assert fl == model, (name, fl, model)
 
 
-@pytest.mark.parametrize("d", [I.Dims(2, 70, 3, 75, 10), I.Dims(3, 66, 4, 71, 9)], ids=str)
+@pytest.mark.parametrize("d", [I.Dims(2, 70, 3, 75, 10), I.Dims(3, 66, 4, 71, 9), I.Dims(2, 136, 3, 140, 9),
+                               I.Dims(2, 160, 3, 163, 9)], ids=str)
 def test_densities_wide_virtual_space(lib, ws, d):
     """64 < n_v <= 160: the virtual Gram blocks (D_cd) take the whole-output MFMA kernel."""
     p, orc, g = _dens_case(lib, d, 37)
