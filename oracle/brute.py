@@ -154,11 +154,13 @@ class Brute:
     def tau3(self):
         return self.triples(self.W(self.t2, self.g), 0.0)
 
-    def ground_residual(self):
-        """Triples contributions to Omega_1 and Omega_2 (SI ground-state residual)."""
+    def ground_residual(self, tau=None):
+        """Triples contributions to Omega_1 and Omega_2 (SI ground-state residual).
+        Test hook: `tau` replaces the triples amplitudes (the residual is linear in them), and
+        the attribute F (the occupied-virtual Fock block F_kc) may be overwritten."""
         o, v = self.o, self.v
         g = self.g
-        tt = tilde3(self.tau3())
+        tt = tilde3(self.tau3() if tau is None else tau)
         om1 = np.einsum("abcijk,jbkc->ai", tt, g[o, v, o, v])
         Y = (np.einsum("abcijk,kc->abij", tt, self.F)
              - np.einsum("abcijk,jlkc->abil", tt, g[o, o, o, v])
@@ -176,18 +178,19 @@ class Brute:
         Rb = self.Delta * R2
         return self.triples(self.W(Rb, self.g) + self.W(self.t2, self.upsilon(R1)), omega)
 
-    def right_transform(self, R1, R2, omega):
-        """Triples contributions to rho = J R (SI right Jacobian transformation)."""
+    def right_transform(self, R1, R2, omega, R3=None):
+        """Triples contributions to rho = J R (SI right Jacobian transformation).  Test hook:
+        `R3` replaces the right triples amplitudes (rho is linear in them)."""
         if self.cvs is not None:
             R1, R2 = self.cvs_project(R1, R2)
-            return self.cvs_project(*self._right(R1, R2, omega))
-        return self._right(R1, R2, omega)
+            return self.cvs_project(*self._right(R1, R2, omega, R3))
+        return self._right(R1, R2, omega, R3)
 
-    def _right(self, R1, R2, omega):
+    def _right(self, R1, R2, omega, R3=None):
         o, v = self.o, self.v
         g = self.g
         tt = tilde3(self.tau3())
-        Rt = tilde3(self.R3(R1, R2, omega))
+        Rt = tilde3(self.R3(R1, R2, omega) if R3 is None else R3)
         rho1 = np.einsum("abcijk,jbkc->ai", Rt, g[o, v, o, v])
         Y = (np.einsum("abcijk,kc->abij", Rt, self.F)
              + np.einsum("abcijk,kc->abij", tt, self.upsilon_kc(R1))
@@ -242,25 +245,30 @@ class Brute:
         """lambda3 from the L3 recipe with (lambda1, lambda2) at omega = 0 (ground-state multipliers)."""
         return self.L3(lam1, lam2, 0.0)
 
-    def density_m0(self, L1, L2, omega):
+    def density_m0(self, L1, L2, omega, terms=False):
         """Triples terms of the left transition density D^{m-0} (SI left density), D[p][q]
-        multiplies A_pq; occupied orbitals first."""
+        multiplies A_pq; occupied orbitals first.  terms=True returns the N x N contribution of
+        each printed term by name instead of their sum."""
         o, v = self.o, self.v
         t2 = self.t2
         tau = self.tau3()
         tt = tilde3(tau)
         Lt = tilde3(self.L3(L1, L2, omega))
-        D = np.zeros((self.N, self.N))
-        D[o, o] -= 0.5 * np.einsum("abcijl,abcijk->kl", Lt, tau)
-        D[o, v] += np.einsum("abij,abdijl->ld", L2, tt)
-        D[o, v] -= np.einsum("abcijk,acil,bdjk->ld", Lt, t2, t2)
-        D[v, v] += 0.5 * np.einsum("abcijk,abdijk->cd", Lt, tau)
-        return D
+        T = {k: np.zeros((self.N, self.N)) for k in ("kl", "ld", "LD", "cd")}
+        T["kl"][o, o] -= 0.5 * np.einsum("abcijl,abcijk->kl", Lt, tau)
+        T["ld"][o, v] += np.einsum("abij,abdijl->ld", L2, tt)
+        T["LD"][o, v] -= np.einsum("abcijk,acil,bdjk->ld", Lt, t2, t2)
+        T["cd"][v, v] += 0.5 * np.einsum("abcijk,abdijk->cd", Lt, tau)
+        if terms:
+            return T
+        return T["kl"] + T["ld"] + T["LD"] + T["cd"]
 
-    def density_0m(self, lam1, lam2, R1, R2, omega):
+    def density_0m(self, lam1, lam2, R1, R2, omega, terms=False):
         """Triples terms of the right transition density D^{0-m} (SI right density) and the
         triples overlap s = (1/6) sum lambda~3 R3.  The occupied diagonal carries 2s; the
-        -s D^{0-0} term is left to the caller.  Doubles of R enter as Rbar = Delta R."""
+        -s D^{0-0} term is left to the caller.  Doubles of R enter as Rbar = Delta R; the doubles
+        multipliers of the D_ld term enter plain (printed with a tilde).
+        terms=True returns ({name: N x N contribution of each printed term}, s)."""
         o, v = self.o, self.v
         t2 = self.t2
         tau = self.tau3()
@@ -268,24 +276,31 @@ class Brute:
         R3 = self.R3(R1, R2, omega)
         Rt = tilde3(R3)
         Rb = self.Delta * R2
-        l2t = 2.0 * lam2 - np.einsum("baij->abij", lam2)
-        D = np.zeros((self.N, self.N))
-        D[o, o] -= np.einsum("abcijl,ai,bcjk->kl", lt, R1, t2)
-        D[o, o] -= 0.5 * np.einsum("abcijl,abcijk->kl", lt, R3)
-        D[o, v] += (np.einsum("abcijk,ai,bcdjkl->ld", lt, R1, tau)
-                    - np.einsum("abcijk,ai,bcdjlk->ld", lt, R1, tau)
-                    + np.einsum("abij,abdijl->ld", l2t, Rt))
-        D[o, v] += 0.5 * (2.0 * np.einsum("abcijk,abij,cdkl->ld", lt, Rb, t2)
-                          - np.einsum("abcijk,abij,cdlk->ld", lt, Rb, t2))
-        D[o, v] -= (np.einsum("abcijk,acil,bdjk->ld", lt, Rb, t2)
-                    + np.einsum("abcijk,adik,bcjl->ld", lt, Rb, t2))
-        D[o, v] -= 0.5 * np.einsum("abcijk,abcijl,dk->ld", lt, tau, R1)
-        D[o, v] -= 0.5 * np.einsum("abcijk,abdijk,cl->ld", lt, tau, R1)
-        D[v, o] += 0.5 * np.einsum("abcijk,abij->ck", lt, Rb)
-        D[v, v] += np.einsum("abcijk,ai,bdjk->cd", lt, R1, t2)
-        D[v, v] += 0.5 * np.einsum("abcijk,abdijk->cd", lt, R3)
+        names = ("Kl", "kl", "ld_R1tau", "ld_l2Rt", "LD_Rbt", "LD_Rbt2", "lD", "Ld", "ck", "cD", "cd", "LL")
+        T = {k: np.zeros((self.N, self.N)) for k in names}
+        T["Kl"][o, o] -= np.einsum("abcijl,ai,bcjk->kl", lt, R1, t2)
+        T["kl"][o, o] -= 0.5 * np.einsum("abcijl,abcijk->kl", lt, R3)
+        T["ld_R1tau"][o, v] += (np.einsum("abcijk,ai,bcdjkl->ld", lt, R1, tau)
+                                - np.einsum("abcijk,ai,bcdjlk->ld", lt, R1, tau))
+        # the printed lambda~^{ab}_{ij} read as the plain multipliers lambda^{ab}_{ij}: the term is
+        # the multiplier analog of the left density's L^{ab}_{ij} tau~^{abd}_{ijl} term
+        T["ld_l2Rt"][o, v] += np.einsum("abij,abdijl->ld", lam2, Rt)
+        T["LD_Rbt"][o, v] += 0.5 * (2.0 * np.einsum("abcijk,abij,cdkl->ld", lt, Rb, t2)
+                                    - np.einsum("abcijk,abij,cdlk->ld", lt, Rb, t2))
+        T["LD_Rbt2"][o, v] -= (np.einsum("abcijk,acil,bdjk->ld", lt, Rb, t2)
+                               + np.einsum("abcijk,adik,bcjl->ld", lt, Rb, t2))
+        T["lD"][o, v] -= 0.5 * np.einsum("abcijk,abcijl,dk->ld", lt, tau, R1)
+        T["Ld"][o, v] -= 0.5 * np.einsum("abcijk,abdijk,cl->ld", lt, tau, R1)
+        T["ck"][v, o] += 0.5 * np.einsum("abcijk,abij->ck", lt, Rb)
+        T["cD"][v, v] += np.einsum("abcijk,ai,bdjk->cd", lt, R1, t2)
+        T["cd"][v, v] += 0.5 * np.einsum("abcijk,abdijk->cd", lt, R3)
         s = float(np.sum(lt * R3)) / 6.0
-        D[o, o] += 2.0 * s * np.eye(self.NO)
+        T["LL"][o, o] += 2.0 * s * np.eye(self.NO)
+        if terms:
+            return T, s
+        D = np.zeros((self.N, self.N))
+        for k in names:
+            D += T[k]
         return D, s
 
 

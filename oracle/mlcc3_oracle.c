@@ -1168,7 +1168,9 @@ int orc_densities(const orc_problem *P, const double *t2_vVoO, const double *t2_
       D0m[k * N + l] -= 0.5 * acc;
       Zt[k * no + l] = z;
     }
-  /* D_ld += sum X^{bc}_{jk} (tau^{bcd}_{jkl} - tau^{bcd}_{jlk}) + sum lambda~^{ab}_{ij} R~^{abd}_{ijl} */
+  /* D_ld += sum X^{bc}_{jk} (tau^{bcd}_{jkl} - tau^{bcd}_{jlk}) + sum lambda^{ab}_{ij} R~^{abd}_{ijl}
+     (the SI prints the doubles multipliers with a tilde; read as the plain lambda^{ab}_{ij}, the
+     multiplier analog of the left density's L^{ab}_{ij} tau~^{abd}_{ijl}) */
   for (int l = 0; l < no; l++)
     for (int d = 0; d < nv; d++) {
       double acc = 0.0;
@@ -1182,8 +1184,7 @@ int orc_densities(const orc_problem *P, const double *t2_vVoO, const double *t2_
         for (int j = 0; j < no; j++)
           for (int a = 0; a < nv; a++)
             for (int b = 0; b < nv; b++) {
-              const double lt = 2.0 * l2a[IDX4(a, b, i, j, NV, no, no)] - l2a[IDX4(b, a, i, j, NV, no, no)];
-              acc += lt * BLK(R3t, i, j, l)[E3(a, b, d)];
+              acc += l2a[IDX4(a, b, i, j, NV, no, no)] * BLK(R3t, i, j, l)[E3(a, b, d)];
             }
       D0m[l * N + NO + d] += acc;
     }

@@ -2052,8 +2052,8 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     double *XLam = buf(ws, "XLam", nbig, s);
     const double zero = 0.0;
     build_L3(ws, g, d, lambda, &zero, 1, r, XLam, "LAlam", "LVlam", s);   // lambda3: L3 recipe at omega = 0
-    double *lam2t = buf(ws, "lam2t", (size_t)no * no * d.nv2, s);
-    launch_pack_vvoo(lambda->x2_vVoo, no, nv, NV, 2, lam2t, s);
+    double *lam2a = buf(ws, "lam2a", (size_t)no * no * d.nv2, s);   // lambda^{ab}_{ij}, [i][j][a][b]
+    launch_pack_vvoo(lambda->x2_vVoo, no, nv, NV, 0, lam2a, s);
     double *XL = buf(ws, "XR", nbig, s);
     double *XRt = buf(ws, "XRt", nbig, s);
     double *XRc = buf(ws, "XRc", nbig, s);
@@ -2108,7 +2108,7 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
                         (long long)no * no * d.nv3, Xl, plain(1), plain(1), (long long)no * d.nv2, no * (int)d.nv2);
         gemm_sumz(ws, gg, s);
       }
-      g_ld(d, XRt, lam2t, D0 + NO, split(nv, N, 1), 1.0, 1.0, s);    // D_ld += lambda~^{ab}_{ij} R~^{abd}_{ijl}
+      g_ld(d, XRt, lam2a, D0 + NO, split(nv, N, 1), 1.0, 1.0, s);    // D_ld += lambda^{ab}_{ij} R~^{abd}_{ijl}
       launch_pack_vvoo(R[m].x2_vVoo, no, nv, NV, 1, Rbv, s);           // Rbar^{ab}_{ij}
       g_ld(d, XLam, Rbv, Yc, plain(1), 1.0, 0.0, s);                   // Y_kc = sum lambda~^{abc}_{ijk} Rbar^{ab}_{ij}
       {  // D_LD += 1/2 sum Y_kc (2 t^{cD}_{kL} - t^{cD}_{Lk})

@@ -10,13 +10,18 @@
   (Results: one active occupied orbital reproduces CCSD);
 * pair-permutation symmetry of the triples blocks, the omega closed form of the
   denominator, linearity in the trial vector, and covariance under rotations of
-  the inactive orbitals (the D and L sums span the full space, eq. tau3).
+  the inactive orbitals (the D and L sums span the full space, eq. tau3);
+* density terms as derivatives: a one-electron perturbation of the Hamiltonian
+  (Theory section: densities contracted with one-electron operators) differentiated
+  through the residual and the right transform reproduces the left-density terms
+  and five right-density terms; the oscillator-strength formula on the hydrogen
+  atom's 1s -> 2p transition.
 """
 import numpy as np
 import pytest
 
 from paper_2202_08612_amd import inputs as I
-from oracle.brute import Brute, blocks2, delta2, pair_form
+from oracle.brute import Brute, blocks2, delta2, pair_form, tilde3
 from oracle.oracle import Oracle
 from tests.helpers import compare_out, pair_form_blocks, rbar_blocks, rel, vec_lin
 
@@ -385,6 +390,181 @@ def test_density_inactive_rotation_covariance():
     D0, s0 = b.density_0m(l1, l2, R1, R2, 0.4)
     D1, s1 = b2.density_0m(r1(l1), r2(l2), r1(R1), r2(R2), 0.4)
     assert rel(D1, C.T @ D0 @ C) < 1e-12 and abs(s1 - s0) < 1e-12 * abs(s0)
+
+
+# ------------------------------------------- density terms as derivatives (field identities)
+def _one_electron(N, seed):
+    """A random symmetric one-electron operator V[p][q] (occupied orbitals first)."""
+    V = np.random.default_rng(seed).standard_normal((N, N))
+    return V + V.T
+
+
+def _vact(X, V, NO):
+    """Action of a one-electron operator on a triples amplitude, from [E_pq, E_ai] =
+    delta_qa E_pi - delta_ip E_aq:  sum_d (V_ad X^{dbc} + V_bd X^{adc} + V_cd X^{abd})
+    - sum_l (V_li X_{ljk} + V_lj X_{ilk} + V_lk X_{ijl})  (full-space X[a,b,c,i,j,k])."""
+    Vvv, Voo = V[NO:, NO:], V[:NO, :NO]
+    return (np.einsum("ad,dbcijk->abcijk", Vvv, X) + np.einsum("bd,adcijk->abcijk", Vvv, X)
+            + np.einsum("cd,abdijk->abcijk", Vvv, X) - np.einsum("li,abcljk->abcijk", Voo, X)
+            - np.einsum("lj,abcilk->abcijk", Voo, X) - np.einsum("lk,abcijl->abcijk", Voo, X))
+
+
+FIELD = [I.Dims(3, 4, 4, 6, 10), I.Dims(2, 3, 4, 5, 8), I.Dims(3, 3, 3, 3, 5)]
+
+
+@pytest.mark.parametrize("d", FIELD)
+def test_left_density_is_the_field_derivative_of_the_residual_pairing(d):
+    """Theory section (densities contracted with a one-electron operator) and SI left density.
+    Add eps V (a symmetric one-electron operator, T1 basis) to the Hamiltonian with V of zeroth
+    order: the triples equation gains eps [V, T3] (the orbital-energy denominators become
+    eps3 + eps V acting on the triples) and the doubles residual's F_kc becomes F_kc + eps V_kc.
+    At omega = 0, L3 is -eps3^{-1} times the transpose couplings, so the chain rule gives
+        sum_pq (D_kl + D_ld + D_cd)_pq V_pq = d/d eps G(L, (Omega_1, Delta^{-1} Omega_2)),
+    with the residual linear in tau3 and in F.  This pins the occupied-occupied and
+    virtual-virtual terms (their 1/2 factors and index placement) and the L^{ab}_{ij} tau~ term;
+    the t2 t2 term D_LD has no counterpart in the residual (separated by name)."""
+    seed = 23
+    p, b = _dens_inputs(d, seed)
+    N, NO = d.N, d.N_O
+    o, v = slice(0, NO), slice(NO, N)
+    L1, L2 = I.full_vector(seed, d, 64)
+    V = _one_electron(N, 5)
+    T = b.density_m0(L1, L2, 0.0, terms=True)
+    lhs = sum(float(np.sum(T[k] * V)) for k in ("kl", "ld", "cd"))
+    tau = b.tau3()
+    dtau = -b.mask * _vact(tau, V, NO) / b.eps3
+    F0 = b.F.copy()
+    Om_dtau = b.ground_residual(tau=dtau)
+    b.F = V[o, v].copy()
+    Om_V = b.ground_residual(tau=tau)
+    b.F = np.zeros_like(F0)
+    Om_0 = b.ground_residual(tau=tau)
+    b.F = F0
+    dO1 = Om_dtau[0] + Om_V[0] - Om_0[0]
+    dO2 = Om_dtau[1] + Om_V[1] - Om_0[1]
+    rhs = pair_form(d, L1, L2, dO1, dO2 / delta2(d.N_V, d.N_O))
+    assert abs(lhs) > 1e-8
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs), (lhs, rhs)
+    # each block separately: V restricted to the occupied-virtual block gives the L tau~ term alone
+    Vov = np.zeros_like(V)
+    Vov[o, v] = V[o, v]
+    b.F = Vov[o, v].copy()
+    a = b.ground_residual(tau=tau)
+    b.F = np.zeros_like(F0)
+    z = b.ground_residual(tau=tau)
+    b.F = F0
+    ov = pair_form(d, L1, L2, a[0] - z[0], (a[1] - z[1]) / delta2(d.N_V, d.N_O))
+    assert abs(float(np.sum(T["ld"] * Vov)) - ov) <= 1e-12 * abs(ov)
+
+
+@pytest.mark.parametrize("d", FIELD)
+@pytest.mark.parametrize("omega", [0.0, 0.45])
+def test_right_density_terms_against_the_right_transform(d, omega):
+    """SI right density against the SI right transformation, by the same one-electron
+    perturbation V:
+    * D_kl, D_cd (the lambda~ R3 terms): the R3 denominators eps3 - omega gain eps V acting on
+      the triples; lambda3 (omega = 0) is -eps3^{-1} times the transpose couplings, so
+      sum (D_kl + D_cd) V = G(lambda, rho restricted to its R3 terms at X3 = -eps3^{-1} V.R3);
+    * D_ld second term: F_kc enters rho_2 only through sum R~ F_kc and R3 does not depend on F,
+      so the term equals d G(lambda, rho)/d F_ld (this fixes the plain multipliers lambda^{ab}_{ij}
+      there; the printed tilde form fails it);
+    * D_lD + D_Ld: the triples projection of [[V, R1], T3], i.e. the one-electron operator
+      [V_ov, R1] (occupied block sum_c V_kc R^c_i, virtual block -sum_k R^a_k V_kc) acting on
+      tau3, paired with lambda~3 / 6."""
+    seed = 31
+    p, b = _dens_inputs(d, seed)
+    N, NO = d.N, d.N_O
+    o, v = slice(0, NO), slice(NO, N)
+    R1, R2 = I.full_vector(seed, d, 0)
+    l1, l2 = I.full_vector(seed, d, 128, normalise=False, sigma1=0.01, sigma2=0.02)
+    V = _one_electron(N, 9)
+    T, s = b.density_0m(l1, l2, R1, R2, omega, terms=True)
+    dot = {k: float(np.sum(T[k] * V)) for k in T}
+    # (1) occupied-occupied and virtual-virtual terms
+    R3 = b.R3(R1, R2, omega)
+    ra = b.right_transform(R1, R2, omega, R3=-b.mask * _vact(R3, V, NO) / b.eps3)
+    rz = b.right_transform(R1, R2, omega, R3=np.zeros_like(R3))
+    g = pair_form(d, l1, l2, ra[0] - rz[0], ra[1] - rz[1])
+    assert abs(dot["kl"] + dot["cd"] - g) <= 1e-12 * abs(g), (dot["kl"] + dot["cd"], g)
+    # (2) the doubles-multiplier term of D_ld
+    F0 = b.F.copy()
+    b.F = V[o, v].copy()
+    rV = b.right_transform(R1, R2, omega)
+    b.F = np.zeros_like(F0)
+    r0 = b.right_transform(R1, R2, omega)
+    b.F = F0
+    zero1 = np.zeros_like(l1)
+    gF = pair_form(d, zero1, l2, rV[0] - r0[0], rV[1] - r0[1])
+    assert abs(dot["ld_l2Rt"] - gF) <= 1e-12 * abs(gF), (dot["ld_l2Rt"], gF)
+    l2t = 2.0 * l2 - np.einsum("baij->abij", l2)
+    assert abs(pair_form(d, zero1, l2t, rV[0] - r0[0], rV[1] - r0[1]) - gF) > 0.1 * abs(gF)
+    # (3) the lambda~3 tau R1 terms
+    Vp = np.zeros_like(V)
+    Vp[o, o] = np.einsum("kc,ci->ki", V[o, v], R1)
+    Vp[v, v] = -np.einsum("ak,kc->ac", R1, V[o, v])
+    lt = tilde3(b.lambda3(l1, l2))
+    x = float(np.sum(lt * _vact(b.tau3(), Vp, NO))) / 6.0
+    assert abs(dot["lD"] + dot["Ld"] - x) <= 1e-12 * abs(x), (dot["lD"] + dot["Ld"], x)
+
+
+def test_right_density_Rbar_t2_terms_linearise_the_left_density_t2t2_term():
+    """SI densities: the two lambda~3 (Rbar t2) terms of D^{0-m}_LD are the first-order change of
+    the left density's t2 t2 term D^{m-0}_LD when t2 -> t2 + h Rbar2 (with L~3 -> lambda~3): the
+    projection of [[V, R2], T2] is the linearisation of (1/2)[[V, T2], T2].  Relates two
+    transcriptions of the SI text (neither term is pinned absolutely)."""
+    d = I.Dims(3, 4, 4, 6, 10)
+    seed = 13
+    p, b = _dens_inputs(d, seed)
+    R1, R2 = I.full_vector(seed, d, 0)
+    l1, l2 = I.full_vector(seed, d, 128, normalise=False, sigma1=0.01, sigma2=0.02)
+    T, s = b.density_0m(l1, l2, R1, R2, 0.3, terms=True)
+    lt = tilde3(b.lambda3(l1, l2))
+    Rb = b.Delta * R2
+    h = 1.0
+
+    def ld_t2t2(X2):
+        return -np.einsum("abcijk,acil,bdjk->ld", lt, X2, X2)
+    lin = 0.5 * (ld_t2t2(b.t2 + h * Rb) - ld_t2t2(b.t2 - h * Rb)) / h
+    o, v = slice(0, d.N_O), slice(d.N_O, d.N)
+    assert rel(T["LD_Rbt2"][o, v], lin) < 1e-12
+
+
+def _hydrogen_dipoles():
+    """<p| x_c |q> for p, q in (1s, 2p_x, 2p_y, 2p_z) of the hydrogen atom (atomic units), by
+    numerical quadrature of the wavefunctions psi_1s = exp(-r)/sqrt(pi),
+    psi_2p_c = r exp(-r/2) (x_c/r) / sqrt(32 pi): radial and angular integrals separately."""
+    from scipy import integrate
+    rad = integrate.quad(lambda r: np.exp(-r) * r * np.exp(-r / 2) * r * r * r, 0, np.inf)[0]
+    norm = 1.0 / np.sqrt(np.pi) / np.sqrt(32 * np.pi)
+
+    def unit(c, th, ph):
+        return (np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th))[c]
+    A = np.zeros((3, 4, 4))
+    for comp in range(3):
+        for m in range(3):
+            ang = integrate.dblquad(lambda th, ph: unit(comp, th, ph) * unit(m, th, ph) * np.sin(th),
+                                    0, 2 * np.pi, 0, np.pi)[0]
+            A[comp, 0, 1 + m] = A[comp, 1 + m, 0] = norm * rad * ang
+    return A
+
+
+def test_oscillator_strength_formula_hydrogen_lyman_alpha():
+    """f = (2/3) omega sum_x T^{0m}_x T^{m0}_x (length-gauge oscillator strength of EOM-CC; for
+    exact states T^{0m} = T^{m0} = <0|x|m> and f = (2/3) omega |<0|r|m>|^2, Stanton and Bartlett,
+    J. Chem. Phys. 98, 7029 (1993)).  Pinned on the hydrogen atom: 1s -> 2p at omega = 3/8
+    hartree, dipole integrals by quadrature, the three 2p states summed give the textbook
+    absorption oscillator strength 0.4162 (Bethe and Salpeter, Quantum Mechanics of One- and
+    Two-Electron Atoms, 1957).  Unit transition densities D^{m-0} = E_{m,0}, D^{0-m} = E_{0,m}."""
+    from oracle.oracle import oscillator_strengths
+    A = _hydrogen_dipoles()
+    Dm0 = np.zeros((3, 4, 4))
+    D0m = np.zeros((3, 4, 4))
+    for m in range(3):
+        Dm0[m, 1 + m, 0] = 1.0
+        D0m[m, 0, 1 + m] = 1.0
+    Tm0, T0m, f = oscillator_strengths(A, [0.375] * 3, Dm0, D0m, np.zeros((4, 4)), [0.0] * 3)
+    assert abs(Tm0[2, 2] - 0.7449) < 1e-4          # <1s|z|2p_z> = 2^7 sqrt(2) / 3^5
+    assert np.allclose(f, f[0]) and abs(float(np.sum(f)) - 0.4162) < 1e-4, f
 
 
 # ------------------------------------------------ transition moments / oscillator strengths
