@@ -170,6 +170,24 @@ int64_t mlcc3_num_triples(int32_t n_o);
 int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *opts,
                           mlcc3_out *omega_T, void *stream);
 
+/* The ground residual without any device allocation, for callers that cannot allocate (code
+ * that runs under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same inputs, outputs and results as mlcc3_ground_residual with a fresh workspace (opts may
+ * be NULL; reuse_ground and reuse_tau must be 0, there is no workspace to reuse), but every
+ * intermediate lives in one fixed scratch array in device memory, linked into the library:
+ * mlcc3_noalloc_scratch_bytes() bytes (128 MiB) on each device the call runs on, held until the
+ * process ends.  The call first sizes the intermediates on the host without touching the
+ * device; a problem that needs more scratch than that returns MLCC3_EINVAL (the text names the
+ * bytes needed) with no work enqueued.  It never calls hipMalloc or hipFree.  Runs on the
+ * current device.  All calls on one device share that device's scratch: calls that overlap in
+ * time on one device (different streams or host threads) race and give wrong results; calls
+ * ordered on one stream are safe.  The scratch keeps the previous call's contents; everything
+ * the call reads from it is written first within the call.  Like the other entry points it
+ * returns after enqueue, except that preparing the integral blocks waits for the stream once. */
+int mlcc3_ground_residual_noalloc(const mlcc3_ground *g, const mlcc3_opts *opts, mlcc3_out *omega_T,
+                                  void *stream);
+int64_t mlcc3_noalloc_scratch_bytes(void);
+
 /* Triples contribution to rho_m = J(omega_m) R_m for nvec trial vectors (eq. R3 and
  * the SI right-transformation terms).  R and rho are host arrays of nvec descriptors
  * holding device pointers; omega[nvec] is a host array. */

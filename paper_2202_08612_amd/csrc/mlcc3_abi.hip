@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,14 @@
 #include "triples_kernels.h"
 
 using namespace mlcc3;
+
+// Fixed device scratch of mlcc3_ground_residual_noalloc (one copy per device, held until the
+// process ends).  In host code `scratch` only names the symbol: its device address on the current
+// device comes from hipGetSymbolAddress, taken once per device (scratch_address); kernels only
+// ever receive that address.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -85,6 +94,11 @@ struct mlcc3_ws_s {
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   mlcc3_tuning tune{};  // launch-shape choices (0 = default)
+  // arena mode (mlcc3_ground_residual_noalloc): buffers are carved from one preallocated range
+  // [arena_base, arena_base + arena_cap) and never allocated or freed
+  bool arena = false;
+  uintptr_t arena_base = 0;
+  size_t arena_cap = 0, arena_used = 0;
   bool gle = false;     // "gLE" (left-transform integral block) formed for the prepared ground
   // what the tau~ blocks ("XT", and "Xtau" when xtau) were last formed for (opts.reuse_tau)
   struct TauKey {
@@ -108,6 +122,16 @@ double *buf(mlcc3_ws ws, const std::string &name, size_t count, hipStream_t s) {
   size_t bytes = std::max<size_t>(count * sizeof(double), 256);
   if (b.second >= bytes) {
     reg(b.first, (long long)(b.second / sizeof(double)), "ws");
+    return (double *)b.first;
+  }
+  if (ws->arena) {  // a new 256-byte aligned range of the arena (a smaller earlier one is abandoned)
+    const size_t off = (ws->arena_used + 255) & ~(size_t)255;
+    if (off > ws->arena_cap || bytes > ws->arena_cap - off)
+      throw Status{MLCC3_EINVAL, "scratch exhausted at buffer '" + name + "'"};
+    b = {(void *)(ws->arena_base + off), bytes};
+    ws->arena_used = off + bytes;
+    ws->total += bytes;
+    reg(b.first, (long long)(bytes / sizeof(double)), "ws");
     return (double *)b.first;
   }
   if (g_dry) {
@@ -1683,36 +1707,116 @@ double mlcc3_flops(const mlcc3_ground *g, int32_t which, int32_t nvec) {
   return (1.0 + 3.0 * std::max(nvec, 1)) * U;
 }
 
+namespace {
+
+// the ground residual on workspace ws (the caller's, a temporary one, or an arena)
+void ground_residual_call(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *opts, mlcc3_out *out, void *stream) {
+  t_ws = ws;
+  t_stream = (hipStream_t)stream;
+  validate_ground(g);
+  validate_out(g, out);
+  reg_ground(g);
+  reg_vec(g, out->x1, out->x2_vVoo, out->x2_vvoO);
+  const mlcc3_opts o = opts_or_default(opts);
+  check(!o.cvs_core, "core-valence separation applies to the right and left transforms only");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ws->device);
+  const Dims d = dims_of(g);
+  const Range r = range_of(o, mlcc3_num_triples(d.no));
+  if (o.check_finite) ground_finite(ws, g, s);
+  if (d.no < 2 || d.nv < 2 || r.tb == r.te) {  // CCSD reduction: triples terms vanish
+    zero_out(d, out, s);
+    return;
+  }
+  prepare_ground(ws, g, o.reuse_ground != 0, s);
+  tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
+  double *XT = B(ws, "XT");
+  double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
+  double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
+  back_vV(ws, d, XT, B(ws, "Gb1"), d.NV, YvV, r, s);
+  gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
+  finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
+}
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// device address of this device's scratch (the device must be current)
+void *scratch_address(int dev) {
+  check(dev >= 0 && dev < kMaxDevices, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    check(p != nullptr, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
+}  // namespace
+
 int mlcc3_ground_residual(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *opts, mlcc3_out *out,
                           void *stream) {
   return guarded([&] {
     CallWs call_ws(ws);  // NULL: a temporary workspace for this call
-    ws = call_ws.ws;
-    t_ws = ws;
-    t_stream = (hipStream_t)stream;
+    ground_residual_call(call_ws.ws, g, opts, out, stream);
+  });
+}
+
+int64_t mlcc3_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
+
+int mlcc3_ground_residual_noalloc(const mlcc3_ground *g, const mlcc3_opts *opts, mlcc3_out *out, void *stream) {
+  return guarded([&] {
     validate_ground(g);
     validate_out(g, out);
-    reg_ground(g);
-    reg_vec(g, out->x1, out->x2_vVoo, out->x2_vvoO);
-    const mlcc3_opts o = opts_or_default(opts);
-    check(!o.cvs_core, "core-valence separation applies to the right and left transforms only");
-    hipStream_t s = (hipStream_t)stream;
-    DeviceGuard dg(ws->device);
-    const Dims d = dims_of(g);
-    const Range r = range_of(o, mlcc3_num_triples(d.no));
-    if (o.check_finite) ground_finite(ws, g, s);
-    if (d.no < 2 || d.nv < 2 || r.tb == r.te) {  // CCSD reduction: triples terms vanish
-      zero_out(d, out, s);
-      return;
+    check(!opts || !opts->reuse_ground, "reuse_ground needs a workspace");
+    check(!opts || !opts->reuse_tau, "reuse_tau needs a workspace");
+    int dev = 0;
+    if (!g_dry) HIPCHK(hipGetDevice(&dev));
+    // 1. size: the same orchestration with no device work, carving fake addresses
+    size_t need = 0;
+    {
+      const bool dry = g_dry;
+      mlcc3_ws_s probe;
+      probe.device = dev;
+      probe.arena = true;
+      probe.arena_base = (uintptr_t)1 << 44;
+      probe.arena_cap = (size_t)1 << 42;
+      g_dry = true;
+      try {
+        ground_residual_call(&probe, g, opts, out, stream);
+      } catch (...) {
+        g_dry = dry;
+        t_ws = nullptr;
+        throw;
+      }
+      g_dry = dry;
+      t_ws = nullptr;
+      need = probe.arena_used;
     }
-    prepare_ground(ws, g, o.reuse_ground != 0, s);
-    tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
-    double *XT = B(ws, "XT");
-    double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
-    double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
-    back_vV(ws, d, XT, B(ws, "Gb1"), d.NV, YvV, r, s);
-    gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
-    finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
+    if (need > kScratchBytes)
+      throw Status{MLCC3_EINVAL, "problem needs " + std::to_string(need) + " bytes of scratch; the fixed scratch of "
+                                     "mlcc3_ground_residual_noalloc holds " + std::to_string(kScratchBytes)};
+    // 2. run on the device's fixed scratch
+    t_ext.clear();
+    mlcc3_ws_s ws;
+    ws.device = dev;
+    ws.arena = true;
+    ws.arena_cap = kScratchBytes;
+    if (g_dry) {
+      ws.arena_base = (uintptr_t)1 << 44;
+    } else {
+      DeviceGuard dg(dev);
+      ws.arena_base = (uintptr_t)scratch_address(dev);
+    }
+    try {
+      ground_residual_call(&ws, g, opts, out, stream);
+    } catch (...) {
+      t_ws = nullptr;
+      throw;
+    }
+    t_ws = nullptr;
   });
 }
 

@@ -67,6 +67,9 @@ _lib.mlcc3_num_triples.restype = ctypes.c_int64
 _lib.mlcc3_opts_default.argtypes = [ctypes.POINTER(_Opts)]
 _lib.mlcc3_ground_residual.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.POINTER(_Opts),
                                        ctypes.POINTER(_Vec), ctypes.c_void_p]
+_lib.mlcc3_ground_residual_noalloc.argtypes = [ctypes.POINTER(_Ground), ctypes.POINTER(_Opts), ctypes.POINTER(_Vec),
+                                               ctypes.c_void_p]
+_lib.mlcc3_noalloc_scratch_bytes.restype = ctypes.c_int64
 for _fn in ("mlcc3_right_transform", "mlcc3_left_transform"):
     getattr(_lib, _fn).argtypes = [ctypes.c_void_p, ctypes.POINTER(_Ground), ctypes.c_int32, _dp,
                                    ctypes.POINTER(_Vec), ctypes.POINTER(_Vec), ctypes.POINTER(_Opts),
@@ -268,6 +271,24 @@ def ground_residual(ws, ground, out=None, **kw):
     _check_ground(ws, ground)
     arr = _vecs([out], ground.dims, ws.device)
     _check(_lib.mlcc3_ground_residual(ws.h, ctypes.byref(ground.c), ctypes.byref(o), arr, _stream(ws.device)))
+    return out
+
+
+def noalloc_scratch_bytes():
+    return int(_lib.mlcc3_noalloc_scratch_bytes())
+
+
+def ground_residual_noalloc(ground, out, device="cuda", **kw):
+    """mlcc3_ground_residual_noalloc on `device` (made current for the call): no device allocation
+    inside the library; `out` (e.g. from empty_out) is filled."""
+    dev = torch.device(device)
+    o = make_opts(**kw)
+    for k, t in ground.t.items():
+        if t.device.type != dev.type or (dev.index is not None and t.device.index != dev.index):
+            raise ValueError(f"ground array {k}: on {t.device}, expected {dev}")
+    arr = _vecs([out], ground.dims, dev)
+    with torch.cuda.device(dev):
+        _check(_lib.mlcc3_ground_residual_noalloc(ctypes.byref(ground.c), ctypes.byref(o), arr, _stream(dev)))
     return out
 
 

@@ -215,3 +215,26 @@ def test_reuse_tau_launches_in_bounds(lib):
         assert rc == 0, (fn, lib.mlcc3_last_error())
     assert lib.mlcc3_ground_residual(ws, ctypes.byref(g), ctypes.byref(o), out, None) == 0
     assert lib.mlcc3_ws_destroy(ws) == 0
+
+
+@pytest.mark.parametrize("d,ok", [(I.CONFIGS[0]["dims"], True), (I.Dims(6, 24, 10, 48, 120), True),
+                                  (I.CONFIGS[1]["dims"], False)], ids=["config0", "6-24-10-48", "config1"])
+def test_noalloc_ground_residual_sizing(lib, d, ok):
+    """mlcc3_ground_residual_noalloc sizes its intermediates on the host first: a problem that fits
+    the fixed scratch runs its whole orchestration (bounds-checked, fake addresses); a larger one
+    returns MLCC3_EINVAL naming the bytes it needs, before any work."""
+    lib.mlcc3_noalloc_scratch_bytes.restype = ctypes.c_int64
+    assert lib.mlcc3_noalloc_scratch_bytes() == 128 << 20
+    f = _fake(12)
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *f[:8])
+    out = V(*f[8:11])
+    rc = lib.mlcc3_ground_residual_noalloc(ctypes.byref(g), None, ctypes.byref(out), None)
+    msg = lib.mlcc3_last_error().decode()
+    if ok:
+        assert rc == 0, msg
+    else:
+        assert rc == -1 and "bytes of scratch" in msg, (rc, msg)
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    o.reuse_ground = 1
+    assert lib.mlcc3_ground_residual_noalloc(ctypes.byref(g), ctypes.byref(o), ctypes.byref(out), None) == -1
