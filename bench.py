@@ -11,8 +11,10 @@ FP64 throughout.  Throughput counts the algorithmic FLOPs of the cost model
 
 The same step is then timed with reduced-precision d-contractions ("mixed": FP32 MFMA, and
 split-bf16 MFMA products with six or three products per FP64 product): for each form its
-throughput, the errors of every output against the FP64 path and, when every error is within
-1e-6, its speedup over FP64 are reported in the "mixed" object of the JSON line.
+throughput, the errors of every output against the FP64 oracle (run over the whole workload in
+the CPU-baseline leg; against the FP64 GPU path when that leg is skipped or sampled) and, when
+every error is within 1e-6, its speedup over FP64 are reported in the "mixed" object of the
+JSON line; "fp64_vs_oracle" holds the FP64 path's own errors.
 
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
 runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --no-per-call, --cfg;
@@ -62,7 +64,9 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 plain device copies (out = 1.0 * in) of this many MiB, for calibrating "
                          "the FETCH_SIZE / WRITE_SIZE counters, and exit")
-    ap.add_argument("--cpu-triples", type=int, default=120, help="unique triples in the CPU-baseline sample")
+    ap.add_argument("--cpu-triples", type=int, default=0,
+                    help="unique triples in the CPU-baseline sample (0 = all: the oracle's outputs then serve as "
+                         "the reference of the error report)")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="time the guanine-shaped active spaces of the paper's core-state table (context)")
     ap.add_argument("--config4", action="store_true",
@@ -296,28 +300,53 @@ def nv_sweep(args):
     print(json.dumps({"nv_sweep_linear_fit": fits, "active": "n_o=8 n_v=136", "steps": args.steps}), flush=True)
 
 
-def mixed_report(args, d, flops_step, dt64, outs64, timed, L, form):
+def pair_form_blocks(d, X, Y):
+    """G(X, Y) = sum X1 Y1 + sum_{(AI)>=(BJ)} X~2 Y2 over the union of the two doubles blocks
+    (host numpy; X~^{AB}_{IJ} = 2 X^{AB}_{IJ} - X^{BA}_{IJ}): the scalar <L|A R> of the metric."""
+    import numpy as np
+    a = np.arange(d.n_v)[:, None, None, None]
+    D = np.arange(d.N_V)[None, :, None, None]
+    i = np.arange(d.n_o)[None, None, :, None]
+    j = np.arange(d.n_o)[None, None, None, :]
+    m1 = (D >= d.n_v) | (a * d.N_O + i >= D * d.N_O + j)
+    m2 = np.broadcast_to(np.arange(d.N_O)[None, None, None, :] >= d.n_o, (d.n_v, d.n_v, d.n_o, d.N_O))
+    A, Bv = X["x2_vVoo"], X["x2_vvoO"]
+    sa = np.einsum("adji->adij", A)              # X^{Da}_{ij} for inactive D (pair symmetry)
+    sa[:, :d.n_v] = np.einsum("daij->adij", A[:, :d.n_v])
+    sb = np.einsum("bail->abil", Bv)
+    return float(np.sum(X["x1"] * Y["x1"]) + np.sum(np.where(m1, (2.0 * A - sa) * Y["x2_vVoo"], 0.0))
+                 + np.sum(np.where(m2, (2.0 * Bv - sb) * Y["x2_vvoO"], 0.0)))
+
+
+def output_errors(outs, ref, L, d):
+    """Errors of the step's outputs (Omega, rho, sigma blocks; torch tensors) against a
+    reference (numpy dicts), and of the scalar <L|A R> = G(L, rho)."""
+    import numpy as np
+    err = {}
+    for name in ("Omega", "rho", "sigma"):
+        for k in ("x1", "x2_vVoo", "x2_vvoO"):
+            x = outs[name][k].double().cpu().numpy()
+            y = ref[name][k]
+            ny = float(np.linalg.norm(y))
+            err[f"{name}.{k}"] = {"rel": float(np.linalg.norm(x - y)) / ny if ny > 0 else 0.0,
+                                  "max_abs": float(np.abs(x - y).max()),
+                                  "max_rel": float(np.abs(x - y).max() / np.abs(y).max()) if ny > 0 else 0.0}
+    rho = {k: v.double().cpu().numpy() for k, v in outs["rho"].items()}
+    p_ref = pair_form_blocks(d, L, ref["rho"])
+    p = pair_form_blocks(d, L, rho)
+    worst = max(max(v["rel"], v["max_rel"]) for v in err.values())
+    return worst, (abs(p - p_ref) / abs(p_ref) if p_ref else 0.0), err
+
+
+def mixed_report(args, d, flops_step, dt64, ref, ref_kind, timed, Lh, form):
     """The same step with reduced-precision d-contractions (form: fp32, bf16x6, bf16x3):
-    throughput, the errors of every output against the FP64 path (which the GPU tests hold
-    within 1e-10 of the oracle), and the speedup, quoted only when every error is within 1e-6."""
-    from paper_2202_08612_amd import mlcc3
-    from tests.helpers import pair_form_blocks
+    throughput, the errors of every output against `ref` (the FP64 oracle's outputs when the
+    CPU-baseline leg ran, else the FP64 GPU path), and the speedup, quoted only when every error
+    is within 1e-6."""
     desc, peak, nprod = MIXED_FORMS[form]
     dt, st, outs = timed(form)
-    err = {}
-    for name, a, b in (("Omega", outs["om"], outs64["om"]), ("rho", outs["rho"][0], outs64["rho"][0]),
-                       ("sigma", outs["sig"][0], outs64["sig"][0])):
-        for k in ("x1", "x2_vVoo", "x2_vvoO"):
-            x, y = a[k].double(), b[k].double()
-            ny = float(y.norm())
-            err[f"{name}.{k}"] = {"rel": float((x - y).norm()) / ny if ny > 0 else 0.0,
-                                  "max_abs": float((x - y).abs().max()),
-                                  "max_rel": float((x - y).abs().max() / y.abs().max()) if ny > 0 else 0.0}
-    Lh = mlcc3.to_numpy(L[0])
-    p64 = pair_form_blocks(d, Lh, mlcc3.to_numpy(outs64["rho"][0]))
-    pmx = pair_form_blocks(d, Lh, mlcc3.to_numpy(outs["rho"][0]))
-    worst = max(max(v["rel"], v["max_rel"]) for v in err.values())
-    pair_err = abs(pmx - p64) / abs(p64) if p64 else 0.0
+    worst, pair_err, err = output_errors({"Omega": outs["om"], "rho": outs["rho"][0], "sigma": outs["sig"][0]},
+                                         ref, Lh, d)
     ok = bool(worst <= 1e-6 and pair_err <= 1e-6)
     ach = st["flops"] * (d.n_o ** 3 - d.n_o) / float(d.n_o ** 3) / (st["ms"] * 1e-3) / 1e12 if st["ms"] > 0 else 0.0
     return {"precision": desc,
@@ -327,7 +356,8 @@ def mixed_report(args, d, flops_step, dt64, outs64, timed, L, form):
             "dcontract_tflops": round(ach, 2),
             "dcontract_frac_matrix_peak": round(ach * nprod / peak, 4), "matrix_peak_tflops": peak,
             "products_per_fp64_product": nprod,
-            "worst_rel_err_vs_fp64": worst, "pair_LAR_rel_err": pair_err,
+            "errors_against": ref_kind,
+            "worst_rel_err": worst, "pair_LAR_rel_err": pair_err,
             "within_1e-6": ok, "errors": err}
 
 
@@ -393,20 +423,24 @@ def dcontract_traffic(d):
 
 
 def cpu_baseline(prob, ntrip):
+    """The FP64 C oracle on the host cores, ground residual + right + left transform of the step's
+    vectors on `ntrip` unique triples (all of them when ntrip <= 0 or beyond the list), integral
+    preparation included.  Returns the baseline record and, when the whole list ran, the
+    oracle's outputs (the reference of the error report)."""
     from oracle.oracle import Oracle, num_threads
     from paper_2202_08612_amd import inputs as I
     d = prob.dims
     orc = Oracle(prob)
     nt = orc.num_triples()
-    tb = max(0, nt // 3)
-    te = min(nt, tb + ntrip)
+    full = ntrip <= 0 or ntrip >= nt
+    tb = 0 if full else max(0, nt // 3)
+    te = nt if full else min(nt, tb + ntrip)
     R = I.right_vectors(prob, 1)[0]
     L = I.left_vectors(prob, 1)[0]
     w = float(I.omegas(False, 1)[0])
     t0 = time.perf_counter()
-    orc.ground_residual(tb, te)
-    orc.right_transform(w, R, tb, te)
-    orc.left_transform(w, L, tb, te)
+    out = {"Omega": orc.ground_residual(tb, te), "rho": orc.right_transform(w, R, tb, te),
+           "sigma": orc.left_transform(w, L, tb, te)}
     dt = time.perf_counter() - t0
     fl = 10.0 * unit_flops(d, tb, te)
     model = ""
@@ -415,10 +449,11 @@ def cpu_baseline(prob, ntrip):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(num_threads()), "kind": "oracle", "host_cpu": model,
-            "sample": f"FP64 C oracle (restricted i>=j>=k loop, OpenMP), ground residual + right + left "
-                      f"transform on unique triples [{tb},{te}) of {nt} at the full workload shape, "
-                      f"integral preparation included; {dt:.1f} s"}
+    rec = {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(num_threads()), "kind": "oracle", "host_cpu": model,
+           "sample": f"FP64 C oracle (restricted i>=j>=k loop, OpenMP), ground residual + right + left "
+                     f"transform on unique triples [{tb},{te}) of {nt} at the full workload shape, "
+                     f"integral preparation included; {dt:.1f} s"}
+    return rec, (out if full else None)
 
 
 def main():
@@ -458,7 +493,8 @@ def main():
     g = mlcc3.Ground(prob, dev)
     w = float(I.omegas(cfg, 1)[0])
     R = [mlcc3.vec_to_device(I.right_vectors(prob, 1)[0], dev)]
-    L = [mlcc3.vec_to_device(I.left_vectors(prob, 1)[0], dev)]
+    Lh = I.left_vectors(prob, 1)[0]
+    L = [mlcc3.vec_to_device(Lh, dev)]
     def new_outs():
         return {"om": mlcc3.empty_out(d, dev), "rho": [mlcc3.empty_out(d, dev)], "sig": [mlcc3.empty_out(d, dev)]}
 
@@ -520,10 +556,21 @@ def main():
         res["per_call"] = per_call_report(args, ws, g, w, R, L)
     if not args.no_iteration:
         res["iteration"] = iteration_report(args, ws, g, w, R, L)
-    if not args.no_mixed:
-        res["mixed"] = {form: mixed_report(args, d, flops_step, dt, outs, timed, L, form) for form in MIXED_FORMS}
+    ref, ref_kind = None, "FP64 GPU path"
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(prob, args.cpu_triples)
+        res["cpu_baseline"], ref = cpu_baseline(prob, args.cpu_triples)
+    if ref is not None:
+        ref_kind = "FP64 oracle (all unique triples)"
+        worst, pair_err, _ = output_errors({"Omega": outs["om"], "rho": outs["rho"][0], "sigma": outs["sig"][0]},
+                                           ref, Lh, d)
+        res["fp64_vs_oracle"] = {"worst_rel_err": worst, "pair_LAR_rel_err": pair_err, "within_1e-10": bool(
+            worst <= 1e-10 and pair_err <= 1e-10)}
+    else:
+        ref = {"Omega": mlcc3.to_numpy(outs["om"]), "rho": mlcc3.to_numpy(outs["rho"][0]),
+               "sigma": mlcc3.to_numpy(outs["sig"][0])}
+    if not args.no_mixed:
+        res["mixed"] = {form: mixed_report(args, d, flops_step, dt, ref, ref_kind, timed, Lh, form)
+                        for form in MIXED_FORMS}
     print(json.dumps(res), flush=True)
 
 

@@ -66,6 +66,8 @@ enum {
   MLCC3_ENOMEM = -3,       /* device allocation failed                                  */
   MLCC3_EHIP = -4,         /* HIP runtime error (text in mlcc3_status_string / last_error) */
   MLCC3_ENONFINITE = -5,   /* NaN/Inf found in an input (only with opts.check_finite)   */
+  MLCC3_ESTATE = -6,       /* reuse_ground: the ground-state inputs changed since the workspace
+                              prepared its blocks (no work enqueued)                      */
   MLCC3_EUNSUPPORTED = -7  /* requested precision or device not supported               */
 };
 
@@ -97,7 +99,10 @@ typedef struct {
                              arithmetic of the d-contraction GEMMs; denominators and
                              accumulation stay FP64 */
   int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
-                             since the last call on this workspace; reuse its prepared blocks */
+                             since the last call on this workspace; reuse its prepared blocks.
+                             The call checks that: a 64-bit fingerprint of the inputs' contents
+                             (one read of them and one wait for the stream) must equal the one
+                             taken when the blocks were prepared, else MLCC3_ESTATE */
   int64_t triple_begin;   /* half-open range over the canonical list of unique occupied     */
   int64_t triple_end;     /* triples (i>=j>=k, not all equal; i outer, k inner); end < 0 = all.
                              Outputs are the partial sums over that range.                 */

@@ -15,16 +15,24 @@ _SO = os.path.join(_HERE, "libmlcc3_oracle.so")
 _lib = None
 
 
-def build(verbose=False):
-    """Compile the oracle with gcc (plain C, OpenMP, no BLAS)."""
+_SO_SANITIZE = os.path.join(_HERE, "libmlcc3_oracle_san.so")
+
+
+def build(verbose=False, sanitize=False):
+    """Compile the oracle with gcc (plain C, OpenMP, no BLAS).  sanitize=True builds
+    libmlcc3_oracle_san.so with AddressSanitizer and UndefinedBehaviorSanitizer (load it with
+    gcc's libasan preloaded)."""
+    so = _SO_SANITIZE if sanitize else _SO
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"] \
+        if sanitize else []
     cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           "-Wall", "-Wno-unused-variable", "-o", _SO + ".tmp",
+           "-Wall", "-Wno-unused-variable", *san, "-o", so + ".tmp",
            os.path.join(_HERE, "mlcc3_oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(_SO + ".tmp", _SO)
-    return _SO
+    os.replace(so + ".tmp", so)
+    return so
 
 
 class _Problem(ctypes.Structure):
@@ -38,9 +46,10 @@ class _Problem(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        so = os.environ.get("MLCC3_ORACLE_SO", _SO)   # the sanitizer build, under the CPU checks
+        if so == _SO and not os.path.exists(_SO):
             build()
-        L = ctypes.CDLL(_SO)
+        L = ctypes.CDLL(so)
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_triples.restype = ctypes.c_int64
         L.orc_num_triples.argtypes = [ctypes.c_int]
@@ -134,8 +143,9 @@ def oscillator_strengths(A, omega, Dm0, D0m, D00, s):
     """Transition moments and oscillator strengths of states m (plain definition):
     T^{m0}_x = sum_pq D^{m-0}_pq A^x_pq (Theory section: densities contracted with a one-electron
     operator), T^{0m}_x = sum_pq (D^{0-m} - s D^{0-0})_pq A^x_pq (the -s D^{0-0} term the SI right
-    density leaves out), f = (2/3) omega sum_x T^{0m}_x T^{m0}_x (the EOM-CC oscillator strength,
-    used but not printed in the paper).  A [ncomp][N][N], Dm0/D0m [nstate][N][N], D00 [N][N]."""
+    density leaves out), f = (2/3) omega sum_x T^{0m}_x T^{m0}_x (the length-gauge EOM-CC oscillator
+    strength, Stanton and Bartlett, J. Chem. Phys. 98, 7029 (1993); used but not printed in the
+    paper).  A [ncomp][N][N], Dm0/D0m [nstate][N][N], D00 [N][N]."""
     A = np.asarray(A, dtype=np.float64)
     Dm0 = np.asarray(Dm0, dtype=np.float64)
     D0m = np.asarray(D0m, dtype=np.float64)

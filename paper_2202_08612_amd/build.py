@@ -18,14 +18,25 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wno-unused-result"]
 
 
-def build(verbose=False):
+# host-side sanitizer build (CPU checks of the orchestration in dry-run mode): every sanitizer
+# flag applies to the host compilation only, the device code is built as usual
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+SO_SANITIZE = os.path.join(PKG, "libmlcc3_hostsan.so")
+
+
+def build(verbose=False, sanitize=False, out=None):
+    """Compile libmlcc3.so; sanitize=True builds libmlcc3_hostsan.so with AddressSanitizer and
+    UndefinedBehaviorSanitizer in the host code (load it with the clang ASan runtime preloaded)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    so = out or (SO_SANITIZE if sanitize else SO)
+    extra = SANITIZE_FLAGS if sanitize else []
     with tempfile.TemporaryDirectory() as td:
         procs, objs = [], []
         for s in srcs:
             obj = os.path.join(td, s.replace(".hip", ".o"))
-            cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, s), "-o", obj]
+            cmd = [hipcc, *FLAGS, *extra, "-c", os.path.join(CSRC, s), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -41,11 +52,11 @@ def build(verbose=False):
                 print("\n".join(lines))
         if failed:
             raise RuntimeError(f"hipcc failed for {failed}")
-        tmp = SO + ".tmp"
-        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        tmp = so + ".tmp"
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, "-o", tmp, *objs]
         subprocess.check_call(cmd)
-        os.replace(tmp, SO)
-    return SO
+        os.replace(tmp, so)
+    return so
 
 
 if __name__ == "__main__":

@@ -9,6 +9,7 @@
 //   back          Y^{aD}_{ij} (K = n_o n_v^2), Y^{ab}_{iL} (K = n_o^2 n_v) GEMMs, small terms
 //   out           Delta^{-1}, pair symmetrisation, contravariant -> covariant, block gather
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -62,12 +63,73 @@ struct Extent {
 thread_local std::vector<Extent> t_ext;
 
 thread_local mlcc3_ws t_ws = nullptr;   // workspace of the running call (timing, split-K scratch)
+// test hook MLCC3_TEST_FAIL_ALLOC=<n>: the n-th new workspace allocation of a call fails (ENOMEM)
+thread_local long long t_alloc_fail_at = 0, t_alloc_count = 0;
 thread_local hipStream_t t_stream = nullptr;
 thread_local int t_prec = MLCC3_FP64;   // arithmetic of the d-contractions of the running call
 // core-valence separation of the running call: on/off, active core orbitals as bits, device flags [N_O]
 thread_local int t_cvs = 0;
 thread_local unsigned long long t_cvs_bits = 0;
 thread_local const unsigned char *t_cvs_dev = nullptr;
+
+// MLCC3_LOG=1: one line per compute call on stderr with the device time of its phases, from HIP
+// events recorded on the call's stream at the end of each phase (the call then waits for its
+// stream before returning)
+struct CallLog {
+  bool on = false;
+  std::string what;
+  hipStream_t s = nullptr;
+  std::vector<std::pair<std::string, hipEvent_t>> ev;
+};
+thread_local CallLog t_log;
+
+void log_phase(const char *name) {
+  if (!t_log.on || t_log.what.empty() || g_dry) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  if (hipEventRecord(e, t_log.s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return;
+  }
+  t_log.ev.push_back({name, e});
+}
+
+void log_begin(const char *call, hipStream_t s, int no, int nv, int NO, int NV, int nc, int nvec, int prec) {
+  if (!t_log.on) return;
+  char b[256];
+  std::snprintf(b, sizeof b, "%s n_o=%d n_v=%d N_O=%d N_V=%d rank=%d nvec=%d precision=%d", call, no, nv, NO, NV, nc,
+                nvec, prec);
+  t_log.what = b;
+  t_log.s = s;
+  log_phase("start");
+}
+
+void log_end(int rc) {
+  if (!t_log.on || t_log.what.empty()) return;
+  std::string line = "mlcc3: " + t_log.what + " status=" + std::to_string(rc);
+  if (g_dry) line += " (dry run)";
+  if (rc == MLCC3_OK && t_log.ev.size() > 0) {
+    log_phase("other");
+    if (hipEventSynchronize(t_log.ev.back().second) == hipSuccess) {
+      float tot = 0.0f;
+      char b[96];
+      for (size_t i = 1; i < t_log.ev.size(); i++) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, t_log.ev[i - 1].second, t_log.ev[i].second);
+        tot += ms;
+        std::snprintf(b, sizeof b, " | %s %.3f", t_log.ev[i].first.c_str(), ms);
+        line += b;
+      }
+      std::snprintf(b, sizeof b, " | total %.3f ms", tot);
+      line += b;
+    }
+  }
+  std::fprintf(stderr, "%s\n", line.c_str());
+  std::fflush(stderr);
+  for (auto &e : t_log.ev) (void)hipEventDestroy(e.second);
+  t_log.ev.clear();
+  t_log.what.clear();
+}
 
 void reg(const void *p, long long count, const char *name) {
   if (!p || count <= 0) return;
@@ -82,6 +144,7 @@ struct mlcc3_ws_s {
   long long total = 0;
   bool prepared = false;
   mlcc3_ground key{};
+  unsigned long long fingerprint = 0;  // content fingerprint of the prepared ground-state inputs
   int nu = 0;
   uintptr_t fake_next = (uintptr_t)1 << 44;  // dry-run address space
   // optional per-phase timing (HIP events on the call's stream)
@@ -124,6 +187,8 @@ double *buf(mlcc3_ws ws, const std::string &name, size_t count, hipStream_t s) {
     reg(b.first, (long long)(b.second / sizeof(double)), "ws");
     return (double *)b.first;
   }
+  if (t_alloc_fail_at > 0 && !ws->arena && ++t_alloc_count == t_alloc_fail_at)
+    throw Status{MLCC3_ENOMEM, "injected allocation failure (MLCC3_TEST_FAIL_ALLOC) at buffer '" + name + "'"};
   if (ws->arena) {  // a new 256-byte aligned range of the arena (a smaller earlier one is abandoned)
     const size_t off = (ws->arena_used + 255) & ~(size_t)255;
     if (off > ws->arena_cap || bytes > ws->arena_cap - off)
@@ -264,6 +329,54 @@ void finite_check(mlcc3_ws ws, std::vector<std::pair<const double *, long long>>
   HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (h) throw Status{MLCC3_ENONFINITE, "NaN or Inf in an input array"};
+}
+
+// 64-bit content fingerprint of the ground-state inputs: the sum modulo 2^64 over all elements of
+// mix(bits(x) ^ (tag * golden + index)), with mix the SplitMix64 finaliser (Steele, Lea and Flood,
+// 2014).  The sum is order-independent, so the parallel reduction is deterministic.
+__device__ __forceinline__ unsigned long long fp_mix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_fingerprint(const double *x, long long n, unsigned long long tag, unsigned long long *out) {
+  __shared__ unsigned long long red[256];
+  unsigned long long acc = 0;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n; id += (long long)gridDim.x * blockDim.x)
+    acc += fp_mix((unsigned long long)__double_as_longlong(x[id]) ^ (tag * 0x9E3779B97F4A7C15ULL + (unsigned long long)id));
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// enqueue the fingerprint of every ground-state input array into the workspace word "fingerprint"
+// and its copy to *host (valid after the stream has synchronised)
+void ground_fingerprint(mlcc3_ws ws, const mlcc3_ground *g, unsigned long long *host, hipStream_t s) {
+  *host = 0;
+  if (g_dry) return;
+  const Dims d = dims_of(g);
+  unsigned long long *w = (unsigned long long *)buf(ws, "fingerprint", 1, s);
+  HIPCHK(hipMemsetAsync(w, 0, sizeof(unsigned long long), s));
+  const std::pair<const double *, long long> arrs[] = {{g->eps_o, d.NO},
+                                                       {g->eps_v, d.NV},
+                                                       {g->L_OO, (long long)d.nc * d.NO * d.NO},
+                                                       {g->L_OV, (long long)d.nc * d.NO * d.NV},
+                                                       {g->L_vV, (long long)d.nc * d.nv * d.NV},
+                                                       {g->t1, (long long)d.NV * d.NO},
+                                                       {g->t2_vVoo, (long long)d.nv * d.NV * d.no * d.no},
+                                                       {g->t2_vvoO, (long long)d.nv * d.nv * d.no * d.NO}};
+  unsigned long long tag = 1;
+  for (auto &a : arrs) {
+    if (a.second > 0) hipLaunchKernelGGL(k_fingerprint, dim3(1024), dim3(256), 0, s, a.first, a.second, tag, w);
+    tag++;
+  }
+  HIPRT(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(host, w, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
 }
 
 void ground_finite(mlcc3_ws ws, const mlcc3_ground *g, hipStream_t s) {
@@ -598,7 +711,16 @@ void vVvo_tiled(mlcc3_ws ws, const Dims &d, int nseg, const double *const *A, co
 bool same_ground(const mlcc3_ground &a, const mlcc3_ground &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
 
 void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t s) {
-  if (reuse && ws->prepared && same_ground(ws->key, *g)) return;
+  if (reuse && ws->prepared && same_ground(ws->key, *g)) {
+    // the prepared blocks are reused only if the inputs' contents are those they were made from
+    unsigned long long now = 0;
+    ground_fingerprint(ws, g, &now, s);
+    HIPRT(hipStreamSynchronize(s));
+    if (now != ws->fingerprint)
+      throw Status{MLCC3_ESTATE, "reuse_ground: the ground-state inputs changed since this workspace prepared its "
+                                 "blocks (same pointers, new contents); call with reuse_ground = 0"};
+    return;
+  }
   ws->prepared = false;
   ws->gle = false;
   ws->tau = mlcc3_ws_s::TauKey{};
@@ -735,7 +857,10 @@ void prepare_ground(mlcc3_ws ws, const mlcc3_ground *g, bool reuse, hipStream_t 
   ws->nu = (int)ut.size();
   void *dut = buf(ws, "utriples", ut.size() * sizeof(UniqueTriple) / sizeof(double) + 1, s);
   HIPRT(hipMemcpyAsync(dut, ut.data(), ut.size() * sizeof(UniqueTriple), hipMemcpyHostToDevice, s));
-  HIPRT(hipStreamSynchronize(s));  // the host vector goes out of scope
+  unsigned long long fp = 0;
+  ground_fingerprint(ws, g, &fp, s);
+  HIPRT(hipStreamSynchronize(s));  // the host vector goes out of scope; fp is valid
+  ws->fingerprint = fp;
   ws->key = *g;
   ws->prepared = true;
 }
@@ -1177,17 +1302,27 @@ int guarded(F &&f) {
     g_last_error.clear();
     const char *dr = std::getenv("MLCC3_DRYRUN");
     g_dry = dr && dr[0] == '1';
+    const char *fa = std::getenv("MLCC3_TEST_FAIL_ALLOC");
+    t_alloc_fail_at = fa ? std::atoll(fa) : 0;
+    t_alloc_count = 0;
+    const char *lg = std::getenv("MLCC3_LOG");
+    t_log.on = lg && lg[0] == '1';
+    t_log.what.clear();
     t_ext.clear();
     f();
+    log_end(MLCC3_OK);
     return MLCC3_OK;
   } catch (const Status &st) {
     g_last_error = st.msg;
+    log_end(st.code);
     return st.code;
   } catch (const std::exception &e) {
     g_last_error = e.what();
+    log_end(MLCC3_EHIP);
     return MLCC3_EHIP;
   } catch (...) {
     g_last_error = "unknown error";
+    log_end(MLCC3_EHIP);
     return MLCC3_EHIP;
   }
 }
@@ -1722,6 +1857,7 @@ void ground_residual_call(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ws->device);
   const Dims d = dims_of(g);
+  log_begin("ground_residual", s, d.no, d.nv, d.NO, d.NV, d.nc, 0, o.precision);
   const Range r = range_of(o, mlcc3_num_triples(d.no));
   if (o.check_finite) ground_finite(ws, g, s);
   if (d.no < 2 || d.nv < 2 || r.tb == r.te) {  // CCSD reduction: triples terms vanish
@@ -1729,13 +1865,17 @@ void ground_residual_call(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
     return;
   }
   prepare_ground(ws, g, o.reuse_ground != 0, s);
+  log_phase("prep");
   tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
+  log_phase("tau3");
   double *XT = B(ws, "XT");
   double *YvV = buf(ws, "YvV", (size_t)d.no * d.no * d.nv * d.NV, s);
   double *YvO = buf(ws, "YvO", (size_t)d.no * d.nv2 * d.NO, s);
   back_vV(ws, d, XT, B(ws, "Gb1"), d.NV, YvV, r, s);
+  log_phase("back");
   gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
   finish_right_like(ws, d, XT, nullptr, nullptr, YvV, YvO, 0, out, s);
+  log_phase("out");
 }
 
 std::mutex g_scratch_mu;
@@ -1838,6 +1978,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ws->device);
     const Dims d = dims_of(g);
+    log_begin("right_transform", s, d.no, d.nv, d.NO, d.NV, d.nc, nvec, o.precision);
     const Range r = range_of(o, mlcc3_num_triples(d.no));
     if (o.check_finite) {
       ground_finite(ws, g, s);
@@ -1854,9 +1995,11 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     cvs_setup(ws, g, o, nvec, R_in, &Rp, s);
     const mlcc3_vec *R = Rp.empty() ? R_in : Rp.data();
     prepare_ground(ws, g, o.reuse_ground != 0, s);
+    log_phase("prep");
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
     // tau~ and Xtau[(i,j,a)][L] = sum tau~ g_Lbkc (shared by all vectors)
     const bool tau_kept = tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
+    log_phase("tau3");
     double *XT = B(ws, "XT");
     double *Xtau = xtau_block(ws, d, XT, tau_kept, r, s);
     // vectors in groups: R3 of a whole group in one d-contraction launch and one launch per
@@ -1869,6 +2012,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
       group_dlhat(ws, g, d, R + m0, nb, s);
       for (int v = 0; v < nb; v++) right_vector_prep(ws, g, d, R[m0 + v], v, nb, s);
       build_R3(ws, g, d, R + m0, omega + m0, nb, r, XRg, nullptr, s);
+      log_phase("R3");
       for (int v = 0; v < nb; v++) {
         const int m = m0 + v;
         double *XR = XRg + v * d.nord * d.nv3;
@@ -1877,6 +2021,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
         double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
         double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
         back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, r, s);
+        log_phase("back");
         {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
           Gemm gg;
           gg.M = no * no * nv;
@@ -1892,6 +2037,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
         }
         gemm(back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), XT, bm_jkcL(d, Xi), YvO, -1.0), s);
         finish_right_like(ws, d, XR, XT, Ukc, YvV, YvO, 1, &rho[m], s);
+        log_phase("out");
         cvs_project_out(d, rho[m], s);
       }
     }
@@ -1916,6 +2062,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ws->device);
     const Dims d = dims_of(g);
+    log_begin("left_transform", s, d.no, d.nv, d.NO, d.NV, d.nc, nvec, o.precision);
     const Range r = range_of(o, mlcc3_num_triples(d.no));
     if (o.check_finite) {
       ground_finite(ws, g, s);
@@ -1932,8 +2079,10 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     cvs_setup(ws, g, o, nvec, L_in, &Lp, s);
     const mlcc3_vec *L = Lp.empty() ? L_in : Lp.data();
     prepare_ground(ws, g, o.reuse_ground != 0, s);
+    log_phase("prep");
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
     const bool tau_kept = tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
+    log_phase("tau3");
     double *XT = B(ws, "XT");
     double *Xtau = xtau_block(ws, d, XT, tau_kept, r, s);
     double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
@@ -1948,6 +2097,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
       // L3 (SI transpose transformation, exact-transpose index placement):
       //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc + local terms
       build_L3(ws, g, d, L + m0, omega + m0, nb, r, XLg, "LA", "LV", s);
+      log_phase("L3");
       for (int v = 0; v < nb; v++) {
         const int m = m0 + v;
         const double *L2b = L[m].x2_vvoO;
@@ -1957,6 +2107,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
         double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
         double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
         back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, r, s);
+        log_phase("back");
         gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
              s);
         // intermediates of the singles
@@ -2133,6 +2284,7 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     check(!o.cvs_core, "core-valence separation applies to the right and left transforms only");
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ws->device);
+    log_begin("triples_densities", s, d.no, d.nv, d.NO, d.NV, d.nc, nstate, o.precision);
     const Range r = range_of(o, mlcc3_num_triples(d.no));
     if (o.check_finite) {
       ground_finite(ws, g, s);
@@ -2148,10 +2300,12 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     HIPRT(hipMemsetAsync(s_out, 0, sizeof(double) * nstate, s));
     if (d.no < 2 || d.nv < 2 || r.tb == r.te) return;  // no triples: the triples terms vanish
     prepare_ground(ws, g, o.reuse_ground != 0, s);
+    log_phase("prep");
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
     const size_t nbig = (size_t)(d.nord * d.nv3);
     double *XTc = buf(ws, "XTc", nbig, s);
     tau_path(ws, g, d, r, s, XTc);
+    log_phase("tau3");
     double *XT = B(ws, "XT");
     double *XLam = buf(ws, "XLam", nbig, s);
     const double zero = 0.0;
@@ -2172,9 +2326,11 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     for (int m = 0; m < nstate; m++) {
       double *Dm = D_m0 + (long long)m * N * N, *D0 = D_0m + (long long)m * N * N;
       build_L3(ws, g, d, L + m, omega + m, 1, r, XL, "LA", "LV", s);
+      log_phase("L3");
       group_dlhat(ws, g, d, R + m, 1, s);
       right_vector_prep(ws, g, d, R[m], 0, 1, s);
       build_R3(ws, g, d, R + m, omega + m, 1, r, XRt, XRc, s);
+      log_phase("R3");
       // ---- D^{m-0} (SI left density) ----
       g_kl(d, XTc, XL, Dm, N, -0.5, 1.0, s);                          // D_kl -= 1/2 L~_{ijl} tau_{ijk}
       g_cd(d, XL, XTc, Dm + NO * N + NO, N, 0.5, 1.0, s);             // D_cd += 1/2 L~^{abc} tau^{abd}
@@ -2274,6 +2430,7 @@ const char *mlcc3_status_string(int status) {
     case MLCC3_ENOMEM: return "device allocation failed";
     case MLCC3_EHIP: return "HIP runtime error";
     case MLCC3_ENONFINITE: return "non-finite input";
+    case MLCC3_ESTATE: return "stale workspace (ground-state inputs changed under reuse_ground)";
     case MLCC3_EUNSUPPORTED: return "unsupported request";
     default: return "unknown status";
   }

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, EINVAL, ESINGULAR, ENOMEM, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -7
+OK, EINVAL, ESINGULAR, ENOMEM, EHIP, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 

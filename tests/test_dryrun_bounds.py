@@ -13,7 +13,9 @@ import pytest
 from paper_2202_08612_amd import inputs as I
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SO = os.path.join(ROOT, "paper_2202_08612_amd", "libmlcc3.so")
+# MLCC3_HOST_LIB: another build of the same sources (the host-sanitizer build, under
+# tests/test_host_sanitizers.py)
+SO = os.environ.get("MLCC3_HOST_LIB", os.path.join(ROOT, "paper_2202_08612_amd", "libmlcc3.so"))
 
 
 class G(ctypes.Structure):
@@ -238,3 +240,40 @@ def test_noalloc_ground_residual_sizing(lib, d, ok):
     lib.mlcc3_opts_default(ctypes.byref(o))
     o.reuse_ground = 1
     assert lib.mlcc3_ground_residual_noalloc(ctypes.byref(g), ctypes.byref(o), ctypes.byref(out), None) == -1
+
+
+def _call_right(lib, ws, d, f):
+    g = G(d.n_o, d.n_v, d.N_O, d.N_V, d.n_chol, *f[:8])
+    vin = (V * 1)(V(*f[8:11]))
+    vout = (V * 1)(V(*f[11:14]))
+    om = (ctypes.c_double * 1)(0.4)
+    o = O()
+    lib.mlcc3_opts_default(ctypes.byref(o))
+    return lib.mlcc3_right_transform(ws, ctypes.byref(g), 1, om, vin, vout, ctypes.byref(o), None)
+
+
+def test_injected_allocation_failures_return_enomem(lib):
+    """MLCC3_TEST_FAIL_ALLOC=n makes the n-th new workspace allocation of a call fail: every
+    such failure of a right transform on a fresh workspace returns MLCC3_ENOMEM with the
+    buffer named, leaves the workspace usable (the same call then succeeds on it), and past the
+    last allocation the call succeeds."""
+    d = I.CONFIGS[0]["dims"]
+    f = _fake(16)
+    failures = 0
+    for n in range(1, 200):
+        ws = ctypes.c_void_p()
+        assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
+        os.environ["MLCC3_TEST_FAIL_ALLOC"] = str(n)
+        try:
+            rc = _call_right(lib, ws, d, f)
+            msg = lib.mlcc3_last_error().decode()
+        finally:
+            os.environ.pop("MLCC3_TEST_FAIL_ALLOC", None)
+        if rc == 0:
+            assert lib.mlcc3_ws_destroy(ws) == 0
+            break
+        assert rc == -3 and "injected allocation failure" in msg, (n, rc, msg)
+        failures += 1
+        assert _call_right(lib, ws, d, f) == 0, lib.mlcc3_last_error()
+        assert lib.mlcc3_ws_destroy(ws) == 0
+    assert failures >= 20, failures
