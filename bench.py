@@ -18,7 +18,7 @@ JSON line; "fp64_vs_oracle" holds the FP64 path's own errors.
 
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
 runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --no-per-call, --cfg;
---copy-mib, --paper-shapes, --nv-sweep and --config4 run other reports instead of the step.
+--copy-mib, --paper-shapes, --nv-sweep, --config3 and --config4 run other reports instead of the step.
 """
 from __future__ import annotations
 
@@ -74,6 +74,10 @@ def parse():
                          "8 right and 8 left vectors and 8 density states, FP64 (with and without core-valence "
                          "separation) and each reduced-precision form on an autotuned workspace, with its errors "
                          "against FP64; one JSON line per form")
+    ap.add_argument("--config3", action="store_true",
+                    help="instead of the step: the batched case n_o=16, n_v=80, N_O=40, N_V=400, rank 1000, right and "
+                         "left transform of 4 vectors in one call each, FP64: time, GFLOP/s and fraction of the FP64 "
+                         "peak per call, d-contraction rate; one JSON line")
     ap.add_argument("--nv-sweep", action="store_true",
                     help="instead of the step: time the ground residual, right and left transforms and the "
                          "densities at a fixed active space (n_o=8, n_v=136) over six inactive-space sizes "
@@ -247,6 +251,48 @@ def config4_report(args):
             row["speedup_right_left"] = round((r64["right_ms"] + r64["left_ms"]) / (res["right_ms"] + res["left_ms"]), 3)
             print(json.dumps({"config4": row}), flush=True)
             ws.close()
+
+
+def config3_report(args):
+    """Config 3 (n_o=16, n_v=80, N_O=40, N_V=400, rank 1000): the right and the left transform of
+    4 trial vectors, one call each (vectors batched in one persistent launch per pass), FP64,
+    ground-state blocks prepared; median of `steps` timed calls after `warmup`."""
+    import numpy as np
+    import torch
+    from paper_2202_08612_amd import inputs as I
+    from paper_2202_08612_amd import mlcc3
+    prob = I.make_config(3)
+    d = prob.dims
+    ws = mlcc3.Workspace(0)
+    g = mlcc3.Ground(prob)
+    om = [float(x) for x in I.omegas(3, 4)]
+    R = [mlcc3.vec_to_device(v) for v in I.right_vectors(prob, 4)]
+    L = [mlcc3.vec_to_device(v) for v in I.left_vectors(prob, 4)]
+    mlcc3.ground_residual(ws, g)
+    calls = {"right_transform": (lambda: mlcc3.right_transform(ws, g, om, R, reuse_ground=True), g.flops(1, 4)),
+             "left_transform": (lambda: mlcc3.left_transform(ws, g, om, L, reuse_ground=True), g.flops(2, 4))}
+    out = {}
+    for name, (fn, fl) in calls.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        ws.timing(True)
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        st = ws.phase_stats(0)
+        ws.timing(False)
+        dt = float(np.median(ts))
+        ach = st["flops"] * (d.n_o ** 3 - d.n_o) / float(d.n_o ** 3) / (st["ms"] * 1e-3) / 1e12 if st["ms"] > 0 else 0.0
+        out[name] = {"ms": round(dt * 1e3, 2), "gflops": round(fl / dt / 1e9, 1),
+                     "pct_fp64_peak": round(100 * fl / dt / 1e12 / FP64_PEAK_TFLOPS, 2),
+                     "dcontract_tflops": round(ach, 2), "dcontract_launches": st["launches"]}
+    ws.close()
+    print(json.dumps({"report": "config3", "workload": f"n_o={d.n_o} n_v={d.n_v} N_O={d.N_O} N_V={d.N_V} "
+                      f"rank {d.n_chol}, 4 vectors per call, FP64", "steps": args.steps, "calls": out}), flush=True)
 
 
 def nv_sweep(args):
@@ -471,6 +517,9 @@ def main():
         return
     if args.config4:
         config4_report(args)
+        return
+    if args.config3:
+        config3_report(args)
         return
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 8

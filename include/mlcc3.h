@@ -71,9 +71,12 @@ enum {
   MLCC3_EUNSUPPORTED = -7  /* requested precision or device not supported               */
 };
 
-/* Arithmetic of the d-contraction GEMMs (the O(N_V n_v^3 n_o^3) step of the Implementation
-   section); the occupied term, permutations, denominators, back-contractions and every output
-   stay FP64 in all forms.
+/* Arithmetic of the O(N_V n_v^3 n_o^3) GEMMs of the Implementation section: the d-contractions
+   that build the triples intermediates in every reduced form, and in the split-bf16 forms also
+   the N_V-wide back-contractions of the contravariant triples (rho^{aD}_{ij}, sigma^{aD}_{ij},
+   Omega^{aD}_{ij}; their FP64 triples operand is split while it is staged).  The occupied
+   (N_O-sized) terms, permutations, denominators, the N_O-wide back-contractions and every
+   output stay FP64 in all forms.
    MLCC3_FP32:   FP32 MFMA on operands rounded to FP32, FP32 sums over 32-deep K slabs, FP64
                  across slabs (about 1e-7 relative).
    MLCC3_BF16X3: split-bf16 products (Henry, Tang and Heinecke, ARITH 2019): each operand is
@@ -96,7 +99,8 @@ typedef struct { double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_out;
 
 typedef struct {
   int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3, MLCC3_BF16X6:
-                             arithmetic of the d-contraction GEMMs; denominators and
+                             arithmetic of the d-contraction GEMMs (and, in the split-bf16
+                             forms, of the N_V-wide back-contractions); denominators and
                              accumulation stay FP64 */
   int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
                              since the last call on this workspace; reuse its prepared blocks.

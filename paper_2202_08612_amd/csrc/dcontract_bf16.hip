@@ -46,7 +46,39 @@ __device__ __forceinline__ int b_off(int b, int s) {
   return 2 * NS * BM * PW + (b * NS + s) * BN * PW;
 }
 
+// round-to-nearest-even FP32 -> bf16 (finite inputs)
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double bf16_value(uint16_t h) { return (double)__uint_as_float((unsigned)h << 16); }
+
+// x = x_0 + ... + x_{ns-1} + remainder; each remainder is exact in FP64
 template <int NS>
+__device__ __forceinline__ void split_planes(double x, uint16_t *o) {
+#pragma unroll
+  for (int s = 0; s < NS; s++) {
+    o[s] = bf16_rne((float)x);
+    x -= bf16_value(o[s]);
+  }
+}
+
+// eight FP64 values as the 16-byte chunks (eight bf16) of the NS planes
+template <int NS>
+__device__ __forceinline__ void split8(const double (&x)[8], u4 (&o)[NS]) {
+#pragma unroll
+  for (int w = 0; w < 4; w++) {
+    uint16_t lo[NS], hi[NS];
+    split_planes<NS>(x[2 * w], lo);
+    split_planes<NS>(x[2 * w + 1], hi);
+#pragma unroll
+    for (int s = 0; s < NS; s++) o[s][w] = (unsigned)lo[s] | ((unsigned)hi[s] << 16);
+  }
+}
+
+// BF64: the B operand of every segment is read in FP64 (BfSeg::B64) and split while staged
+template <int NS, bool BF64>
 __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
   __shared__ u4 lds[2 * NS * (BM + BN) * PW / 4];
   unsigned *ldw = (unsigned *)lds;
@@ -63,7 +95,9 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
     t -= grp * GM * nt;
     const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 32;
-    if (g.tf.on && !tile_needed(g.tf, z, m0, min(g.M, m0 + BM))) continue;
+    const bool skip = g.tf.on && (BF64 ? !tile_needed(g.tf, z, n0, min(g.N, n0 + BN))
+                                       : !tile_needed(g.tf, z, m0, min(g.M, m0 + BM)));  // uniform per workgroup
+    if (skip && !g.tf.zero) continue;
 
     f4 acc[4][2];
     d4 acc64[4][2];
@@ -78,22 +112,44 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
     // staging: 16-byte chunk kc (8 k values) of rows sr and sr + 64 (A) and of row sr (B)
     const int kc = tid & 3, sr = tid >> 2;
     u4 ra[NS][2], rb[NS];
+    double xb[8];
 
-    for (int sg_i = 0; sg_i < g.nseg; sg_i++) {
+    for (int sg_i = 0; sg_i < (skip ? 0 : g.nseg); sg_i++) {
       const BfSeg &sg = g.seg[sg_i];
       const int Kp = sg.Kp, nkt = Kp / BK;
-      const uint16_t *Ap = sg.A + vv * sg.avec + (long long)m0 * Kp;
-      const uint16_t *Bp = sg.B + vv * sg.bvec + (long long)z * sg.bbatch + (long long)n0 * Kp;
+      const uint16_t *Ap = sg.A + vv * sg.avec + (long long)z * sg.abatch + (long long)m0 * Kp;
+      const uint16_t *Bp = BF64 ? nullptr : sg.B + vv * sg.bvec + (long long)z * sg.bbatch + (long long)n0 * Kp;
+      const double *B64 = BF64 ? sg.B64 + vv * sg.bvec + (long long)z * sg.bbatch : nullptr;
+      long long brow = -1;
+      if (BF64) {
+        const int n = n0 + sr;
+        brow = n < g.N ? mix_moff(sg.bmap, n) : -1;
+      }
       auto load = [&](int kt) {
         const int k = kt * BK + 8 * kc;
+        if (BF64) {
+          if (brow >= 0 && k + 8 <= sg.K && ((brow + k) & 1) == 0) {  // four 16-byte loads
+            const double2 *q = (const double2 *)(B64 + brow + k);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+              const double2 v = q[e];
+              xb[2 * e] = v.x;
+              xb[2 * e + 1] = v.y;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++) xb[e] = (brow >= 0 && k + e < sg.K) ? B64[brow + k + e] : 0.0;
+          }
+        }
 #pragma unroll
         for (int s = 0; s < NS; s++) {
 #pragma unroll
           for (int u = 0; u < 2; u++) ra[s][u] = *(const u4 *)(Ap + s * sg.aplane + (long long)(sr + 64 * u) * Kp + k);
-          rb[s] = *(const u4 *)(Bp + s * sg.bplane + (long long)sr * Kp + k);
+          if (!BF64) rb[s] = *(const u4 *)(Bp + s * sg.bplane + (long long)sr * Kp + k);
         }
       };
       auto store = [&](int buf) {
+        if (BF64) split8<NS>(xb, rb);
 #pragma unroll
         for (int s = 0; s < NS; s++) {
 #pragma unroll
@@ -160,24 +216,6 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
         }
       }
   }  // tiles of a persistent workgroup
-}
-
-// round-to-nearest-even FP32 -> bf16 (finite inputs)
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ double bf16_value(uint16_t h) { return (double)__uint_as_float((unsigned)h << 16); }
-
-// x = x_0 + ... + x_{ns-1} + remainder; each remainder is exact in FP64
-template <int NS>
-__device__ __forceinline__ void split_planes(double x, uint16_t *o) {
-#pragma unroll
-  for (int s = 0; s < NS; s++) {
-    o[s] = bf16_rne((float)x);
-    x -= bf16_value(o[s]);
-  }
 }
 
 // planes of src[b][r][c] into dst[s*plane + (b*Rp + r)*Cp + c], zero outside R x C
@@ -253,9 +291,10 @@ hipError_t dcontract_bf16(const BfGemm &g0, hipStream_t s) {
   BfGemm g = g0;
   for (int i = 0; i < g.nseg; i++) {
     const BfSeg &sg = g.seg[i];
-    if (sg.Kp <= 0 || sg.Kp % BK || sg.aplane % 8 || sg.bplane % 8 || sg.bbatch % 8 || sg.avec % 8 || sg.bvec % 8 ||
-        (uintptr_t)sg.A % 16 || (uintptr_t)sg.B % 16)
+    if (sg.Kp <= 0 || sg.Kp % BK || sg.aplane % 8 || sg.avec % 8 || sg.abatch % 8 || (uintptr_t)sg.A % 16)
       return hipErrorInvalidValue;
+    if (!sg.B64 && (sg.bplane % 8 || sg.bbatch % 8 || sg.bvec % 8 || (uintptr_t)sg.B % 16)) return hipErrorInvalidValue;
+    if (sg.B64 && (uintptr_t)sg.B64 % 16) return hipErrorInvalidValue;  // the 16-byte loads test offset parity only
   }
   if (g.cmap.d <= 0) {
     g.cmap.d = 0x7fffffff;
@@ -264,10 +303,25 @@ hipError_t dcontract_bf16(const BfGemm &g0, hipStream_t s) {
   const long long T = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.nvec;
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(g.persist > 0 && g.persist < T ? g.persist : T));
-  if (g.ns == 2)
-    hipLaunchKernelGGL(k_dcontract_bf16<2>, grid, dim3(256), 0, s, g);
-  else
-    hipLaunchKernelGGL(k_dcontract_bf16<3>, grid, dim3(256), 0, s, g);
+  const bool bf64 = g.seg[0].B64 != nullptr;
+  for (int i = 0; i < g.nseg; i++)
+    if ((g.seg[i].B64 != nullptr) != bf64 || (bf64 && (g.seg[i].K <= 0 || g.seg[i].K > g.seg[i].Kp)))
+      return hipErrorInvalidValue;
+  if (bf64) {
+    for (int i = 0; i < g.nseg; i++)
+      if (g.seg[i].bmap.d <= 0) {
+        g.seg[i].bmap.d = 0x7fffffff;
+        g.seg[i].bmap.s1 = 0;
+      }
+    if (g.ns == 2)
+      hipLaunchKernelGGL((k_dcontract_bf16<2, true>), grid, dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((k_dcontract_bf16<3, true>), grid, dim3(256), 0, s, g);
+  } else if (g.ns == 2) {
+    hipLaunchKernelGGL((k_dcontract_bf16<2, false>), grid, dim3(256), 0, s, g);
+  } else {
+    hipLaunchKernelGGL((k_dcontract_bf16<3, false>), grid, dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }
 

@@ -59,6 +59,12 @@ struct BfSeg {
   const uint16_t *B = nullptr;
   long long bplane = 0, bbatch = 0, bvec = 0;
   int Kp = 0;
+  long long abatch = 0;  // batch z of the A planes at + z*abatch (0: shared by all batches)
+  // B given in FP64 instead (B64 != NULL): row n, k < K at B64 + v*bvec + z*bbatch + bmap(n) + k
+  // (zero for k >= K or n >= N), split into planes while it is staged; B and bplane unused
+  const double *B64 = nullptr;
+  Idx2 bmap;
+  int K = 0;
 };
 
 // C[z*cbatch + cmap(m) + n] = sum_seg sum_(s,t) sum_k A_seg,s[m][k] B_seg,t[z][n][k] (bf16 MFMA,
@@ -70,6 +76,8 @@ struct BfGemm {
   Idx2 cmap;
   long long cbatch = 0, cvec = 0;
   int persist = 0;
+  // ordered triples the call does not need: the filter applies to the rows (p,q,a) with batch r,
+  // or, with B in FP64, to the columns; tf.zero writes the skipped tiles as zeros
   TripleFilter tf;
 };
 

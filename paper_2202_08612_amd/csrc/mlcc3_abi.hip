@@ -340,8 +340,17 @@ __device__ __forceinline__ unsigned long long fp_mix(unsigned long long z) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_fingerprint(const double *x, long long n, unsigned long long tag, unsigned long long *out) {
+struct FpArrays {
+  const double *x[8];
+  long long n[8];
+};
+
+// array blockIdx.y (tag blockIdx.y + 1) of the list
+__global__ void k_fingerprint(FpArrays a, unsigned long long *out) {
   __shared__ unsigned long long red[256];
+  const double *x = a.x[blockIdx.y];
+  const long long n = a.n[blockIdx.y];
+  const unsigned long long tag = blockIdx.y + 1;
   unsigned long long acc = 0;
   for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n; id += (long long)gridDim.x * blockDim.x)
     acc += fp_mix((unsigned long long)__double_as_longlong(x[id]) ^ (tag * 0x9E3779B97F4A7C15ULL + (unsigned long long)id));
@@ -370,11 +379,12 @@ void ground_fingerprint(mlcc3_ws ws, const mlcc3_ground *g, unsigned long long *
                                                        {g->t1, (long long)d.NV * d.NO},
                                                        {g->t2_vVoo, (long long)d.nv * d.NV * d.no * d.no},
                                                        {g->t2_vvoO, (long long)d.nv * d.nv * d.no * d.NO}};
-  unsigned long long tag = 1;
-  for (auto &a : arrs) {
-    if (a.second > 0) hipLaunchKernelGGL(k_fingerprint, dim3(1024), dim3(256), 0, s, a.first, a.second, tag, w);
-    tag++;
+  FpArrays fa;
+  for (int i = 0; i < 8; i++) {
+    fa.x[i] = arrs[i].first;
+    fa.n[i] = arrs[i].second > 0 ? arrs[i].second : 0;
   }
+  hipLaunchKernelGGL(k_fingerprint, dim3(512, 8), dim3(256), 0, s, fa, w);   // one launch for all eight
   HIPRT(hipGetLastError());
   HIPCHK(hipMemcpyAsync(host, w, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
 }
@@ -1157,7 +1167,47 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
   const long long MN = (long long)d.no * d.no * d.nv * N;
   double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
   const Idx2 xrow = split(d.nv, (long long)d.no * d.nv3, d.nv2);
-  if (N >= 96) {
+  if (N >= 96 && (t_prec == MLCC3_BF16X3 || t_prec == MLCC3_BF16X6)) {
+    // split-bf16 products on the transposed product P^T[k][n][(i,j,a)] = G_k^T X~_k^T: the
+    // N_V x n_v^2 integral block (A, split once per call into planes [k][n][(b,c)]) is shared by
+    // all column tiles, the triples block (B, FP64, split into planes while it is staged) is read
+    // by ceil(N / 128) row tiles; FP32 sums over 64-deep K steps, FP64 across steps
+    const int ns = t_prec == MLCC3_BF16X3 ? 2 : 3;
+    const int M2 = d.no * d.no * d.nv;
+    const int Kp = ((int)d.nv2 + BF_BK - 1) / BF_BK * BF_BK, Mp = (N + BF_BM - 1) / BF_BM * BF_BM;
+    const long long pa = (long long)d.no * Mp * Kp;  // one plane
+    uint16_t *Am = (uint16_t *)buf(ws, "bk_A", (size_t)(pa * ns + 3) / 4, s);
+    double *PT = buf(ws, "bk_PT", (size_t)(MN * d.no), s);
+    check_range(G, plain(N), (int)d.nv2, plain(1), N, d.nv2 * N, d.no, "G (back-contraction)");
+    check_bytes(Am, (size_t)(pa * ns) * sizeof(uint16_t), "bf16 G planes (back-contraction)");
+    HIPCHK(split_bf16(G, d.no, (int)d.nv2, N, Am, Kp, Mp, pa, ns, 1, s));
+    BfGemm g;
+    g.M = N;
+    g.N = M2;
+    g.nbatch = d.no;
+    g.ns = ns;
+    g.C = PT;
+    g.cmap = plain(M2);
+    g.cbatch = MN;
+    g.nseg = 1;
+    g.tf = triple_filter(d, r, true);
+    g.seg[0].A = Am;
+    g.seg[0].aplane = pa;
+    g.seg[0].abatch = (long long)Mp * Kp;
+    g.seg[0].B64 = X;
+    g.seg[0].bmap = xrow;
+    g.seg[0].bbatch = d.nv3;
+    g.seg[0].K = (int)d.nv2;
+    g.seg[0].Kp = Kp;
+    check_range(X, xrow, M2, plain(1), (int)d.nv2, d.nv3, d.no, "X~ (back-contraction)");
+    check_range(PT, plain(M2), N, plain(1), M2, MN, d.no, "C (back-contraction)");
+    HIPCHK(dcontract_bf16(g, s));
+    // Y[(i,j,a)][n] = sum_k P^T[k][n][(i,j,a)]: fixed-order sum over k, then one transpose
+    launch_sum_rows(PT, d.no, MN, P, s);
+    launch_transpose(P, Y, 1, N, M2, s);
+    HIPRT(hipGetLastError());
+    return;
+  } else if (N >= 96) {
     TileGemm g;
     g.M = d.no * d.no * d.nv;
     g.N = N;
