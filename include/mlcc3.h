@@ -74,8 +74,11 @@ enum {
 /* Arithmetic of the O(N_V n_v^3 n_o^3) GEMMs of the Implementation section: the d-contractions
    that build the triples intermediates in every reduced form, and in the split-bf16 forms also
    the N_V-wide back-contractions of the contravariant triples (rho^{aD}_{ij}, sigma^{aD}_{ij},
-   Omega^{aD}_{ij}; their FP64 triples operand is split while it is staged).  The occupied
-   (N_O-sized) terms, permutations, denominators, the N_O-wide back-contractions and every
+   Omega^{aD}_{ij}; their triples operand is split while it is staged).  In the reduced forms
+   of the ground residual and the right and left transforms, the contravariant triples blocks
+   (tau~, R~, L~; formed in FP64) are stored in FP32 and widened to FP64 where they are read
+   (about 6e-8 relative per element); the densities keep them in FP64.  The occupied (N_O-sized)
+   terms, permutations, denominators, the arithmetic of the N_O-wide back-contractions and every
    output stay FP64 in all forms.
    MLCC3_FP32:   FP32 MFMA on operands rounded to FP32, FP32 sums over 32-deep K slabs, FP64
                  across slabs (about 1e-7 relative).
@@ -100,8 +103,9 @@ typedef struct { double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_out;
 typedef struct {
   int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3, MLCC3_BF16X6:
                              arithmetic of the d-contraction GEMMs (and, in the split-bf16
-                             forms, of the N_V-wide back-contractions); denominators and
-                             accumulation stay FP64 */
+                             forms, of the N_V-wide back-contractions) and storage of the
+                             contravariant triples blocks (FP32 in the reduced forms, except in
+                             the densities); denominators and accumulation stay FP64 */
   int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
                              since the last call on this workspace; reuse its prepared blocks.
                              The call checks that: a 64-bit fingerprint of the inputs' contents

@@ -77,9 +77,11 @@ __device__ __forceinline__ void split8(const double (&x)[8], u4 (&o)[NS]) {
   }
 }
 
-// BF64: the B operand of every segment is read in FP64 (BfSeg::B64) and split while staged
-template <int NS, bool BF64>
+// BMODE 0: B given as bf16 planes; 1: the B operand of every segment is read in FP64
+// (BfSeg::B64), 2: in FP32 (BfSeg::B32), and split into planes while staged
+template <int NS, int BMODE>
 __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
+  constexpr bool BF64 = BMODE != 0;
   __shared__ u4 lds[2 * NS * (BM + BN) * PW / 4];
   unsigned *ldw = (unsigned *)lds;
 
@@ -113,13 +115,15 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
     const int kc = tid & 3, sr = tid >> 2;
     u4 ra[NS][2], rb[NS];
     double xb[8];
+    float xf[8];  // B32 elements as loaded
 
     for (int sg_i = 0; sg_i < (skip ? 0 : g.nseg); sg_i++) {
       const BfSeg &sg = g.seg[sg_i];
       const int Kp = sg.Kp, nkt = Kp / BK;
       const uint16_t *Ap = sg.A + vv * sg.avec + (long long)z * sg.abatch + (long long)m0 * Kp;
       const uint16_t *Bp = BF64 ? nullptr : sg.B + vv * sg.bvec + (long long)z * sg.bbatch + (long long)n0 * Kp;
-      const double *B64 = BF64 ? sg.B64 + vv * sg.bvec + (long long)z * sg.bbatch : nullptr;
+      const double *B64 = BMODE == 1 ? sg.B64 + vv * sg.bvec + (long long)z * sg.bbatch : nullptr;
+      const float *B32 = BMODE == 2 ? sg.B32 + vv * sg.bvec + (long long)z * sg.bbatch : nullptr;
       long long brow = -1;
       if (BF64) {
         const int n = n0 + sr;
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
       }
       auto load = [&](int kt) {
         const int k = kt * BK + 8 * kc;
-        if (BF64) {
+        if (BMODE == 1) {
           if (brow >= 0 && k + 8 <= sg.K && ((brow + k) & 1) == 0) {  // four 16-byte loads
             const double2 *q = (const double2 *)(B64 + brow + k);
 #pragma unroll
@@ -140,6 +144,22 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
 #pragma unroll
             for (int e = 0; e < 8; e++) xb[e] = (brow >= 0 && k + e < sg.K) ? B64[brow + k + e] : 0.0;
           }
+        } else if (BMODE == 2) {
+          // kept as float until the store: a conversion here would wait for the loads
+          if (brow >= 0 && k + 8 <= sg.K && ((brow + k) & 3) == 0) {  // two 16-byte loads
+            const float4 *q = (const float4 *)(B32 + brow + k);
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+              const float4 v = q[e];
+              xf[4 * e] = v.x;
+              xf[4 * e + 1] = v.y;
+              xf[4 * e + 2] = v.z;
+              xf[4 * e + 3] = v.w;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++) xf[e] = (brow >= 0 && k + e < sg.K) ? B32[brow + k + e] : 0.0f;
+          }
         }
 #pragma unroll
         for (int s = 0; s < NS; s++) {
@@ -149,6 +169,9 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
         }
       };
       auto store = [&](int buf) {
+        if (BMODE == 2)
+#pragma unroll
+          for (int e = 0; e < 8; e++) xb[e] = (double)xf[e];
         if (BF64) split8<NS>(xb, rb);
 #pragma unroll
         for (int s = 0; s < NS; s++) {
@@ -285,7 +308,7 @@ hipError_t split_bf16(const double *src, int nb, int R, int C, uint16_t *dst, in
 }
 
 hipError_t dcontract_bf16(const BfGemm &g0, hipStream_t s) {
-  if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g0.nvec <= 0 || g_dry) return hipSuccess;
+  if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g0.nvec <= 0) return hipSuccess;
   if (g0.tf.on && (g0.tf.no < 1 || g0.tf.nv < 1)) return hipErrorInvalidValue;
   if (g0.nseg < 1 || g0.nseg > 2 || (g0.ns != 2 && g0.ns != 3)) return hipErrorInvalidValue;
   BfGemm g = g0;
@@ -293,8 +316,10 @@ hipError_t dcontract_bf16(const BfGemm &g0, hipStream_t s) {
     const BfSeg &sg = g.seg[i];
     if (sg.Kp <= 0 || sg.Kp % BK || sg.aplane % 8 || sg.avec % 8 || sg.abatch % 8 || (uintptr_t)sg.A % 16)
       return hipErrorInvalidValue;
-    if (!sg.B64 && (sg.bplane % 8 || sg.bbatch % 8 || sg.bvec % 8 || (uintptr_t)sg.B % 16)) return hipErrorInvalidValue;
-    if (sg.B64 && (uintptr_t)sg.B64 % 16) return hipErrorInvalidValue;  // the 16-byte loads test offset parity only
+    if (!sg.B64 && !sg.B32 && (sg.bplane % 8 || sg.bbatch % 8 || sg.bvec % 8 || (uintptr_t)sg.B % 16))
+      return hipErrorInvalidValue;
+    // the 16-byte loads test the alignment of the element offset only
+    if ((sg.B64 && (uintptr_t)sg.B64 % 16) || (sg.B32 && (uintptr_t)sg.B32 % 16)) return hipErrorInvalidValue;
   }
   if (g.cmap.d <= 0) {
     g.cmap.d = 0x7fffffff;
@@ -303,25 +328,25 @@ hipError_t dcontract_bf16(const BfGemm &g0, hipStream_t s) {
   const long long T = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.nvec;
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(g.persist > 0 && g.persist < T ? g.persist : T));
-  const bool bf64 = g.seg[0].B64 != nullptr;
-  for (int i = 0; i < g.nseg; i++)
-    if ((g.seg[i].B64 != nullptr) != bf64 || (bf64 && (g.seg[i].K <= 0 || g.seg[i].K > g.seg[i].Kp)))
+  const int bmode = g.seg[0].B64 ? 1 : (g.seg[0].B32 ? 2 : 0);
+  for (int i = 0; i < g.nseg; i++) {
+    const BfSeg &sg = g.seg[i];
+    if ((sg.B64 ? 1 : (sg.B32 ? 2 : 0)) != bmode || (sg.B64 && sg.B32) ||
+        (bmode && (sg.K <= 0 || sg.K > sg.Kp)))
       return hipErrorInvalidValue;
-  if (bf64) {
+  }
+  if (g_dry) return hipSuccess;  // host sizing run: arguments checked, nothing launched
+  if (bmode) {
     for (int i = 0; i < g.nseg; i++)
       if (g.seg[i].bmap.d <= 0) {
         g.seg[i].bmap.d = 0x7fffffff;
         g.seg[i].bmap.s1 = 0;
       }
-    if (g.ns == 2)
-      hipLaunchKernelGGL((k_dcontract_bf16<2, true>), grid, dim3(256), 0, s, g);
-    else
-      hipLaunchKernelGGL((k_dcontract_bf16<3, true>), grid, dim3(256), 0, s, g);
-  } else if (g.ns == 2) {
-    hipLaunchKernelGGL((k_dcontract_bf16<2, false>), grid, dim3(256), 0, s, g);
-  } else {
-    hipLaunchKernelGGL((k_dcontract_bf16<3, false>), grid, dim3(256), 0, s, g);
   }
+#define MLCC3_BF(NS_, M_) \
+  if (g.ns == NS_ && bmode == M_) hipLaunchKernelGGL((k_dcontract_bf16<NS_, M_>), grid, dim3(256), 0, s, g);
+  MLCC3_BF(2, 0) MLCC3_BF(3, 0) MLCC3_BF(2, 1) MLCC3_BF(3, 1) MLCC3_BF(2, 2) MLCC3_BF(3, 2)
+#undef MLCC3_BF
   return hipGetLastError();
 }
 

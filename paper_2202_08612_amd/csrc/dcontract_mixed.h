@@ -63,6 +63,7 @@ struct BfSeg {
   // B given in FP64 instead (B64 != NULL): row n, k < K at B64 + v*bvec + z*bbatch + bmap(n) + k
   // (zero for k >= K or n >= N), split into planes while it is staged; B and bplane unused
   const double *B64 = nullptr;
+  const float *B32 = nullptr;  // instead of B64: float elements at the same offsets
   Idx2 bmap;
   int K = 0;
 };

@@ -165,7 +165,7 @@ hipError_t pad_to_f32(const double *src, int nb, int R, int C, float *dst, int R
 }
 
 hipError_t dcontract_f32(const MixGemm &g0, hipStream_t s) {
-  if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g0.nvec <= 0 || g_dry) return hipSuccess;
+  if (g0.M <= 0 || g0.N <= 0 || g0.nbatch <= 0 || g0.nvec <= 0) return hipSuccess;
   if (g0.tf.on && (g0.tf.no < 1 || g0.tf.nv < 1)) return hipErrorInvalidValue;
   if (g0.nseg < 1 || g0.nseg > 2) return hipErrorInvalidValue;
   MixGemm g = g0;
@@ -181,6 +181,7 @@ hipError_t dcontract_f32(const MixGemm &g0, hipStream_t s) {
   }
   const long long T = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.nbatch * g.nvec;
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (g_dry) return hipSuccess;  // host sizing run: arguments checked, nothing launched
   hipLaunchKernelGGL(k_dcontract_f32, dim3((unsigned)(g.persist > 0 && g.persist < T ? g.persist : T)), dim3(256), 0,
                      s, g);
   return hipGetLastError();

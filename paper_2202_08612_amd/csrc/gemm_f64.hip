@@ -15,7 +15,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;
 
-template <int TM, int TN, bool AKF, bool BNF>
+// AF: the A operand of every segment holds float elements (Operand::pf), widened when staged
+template <int TM, int TN, bool AKF, bool BNF, bool AF>
 __device__ __forceinline__ void gemm_body(const Gemm &g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   constexpr int PA = BM + 2, PB = BN + 2;
@@ -35,6 +36,8 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
     for (int j = 0; j < TN; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   double ra[NA], rb[NB];
+  // float A stays as loaded until the LDS store (a conversion at the load would wait for it)
+  float raf[NA];
 
   for (int s = 0; s < g.nseg; s++) {
     const Seg &sg = g.seg[s];
@@ -43,7 +46,8 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
     const int kbeg = part * chunk;
     const int K = min(sg.K, kbeg + chunk);
     if (kbeg >= K) continue;
-    const double *Ap = sg.A.p + (long long)z * sg.A.batch;
+    const double *Ap = AF ? nullptr : sg.A.p + (long long)z * sg.A.batch;
+    const float *Af = AF ? sg.A.pf + (long long)z * sg.A.batch : nullptr;
     const double *Bp = sg.B.p + (long long)z * sg.B.batch;
     const double scale = sg.scale;
     // hoisted offsets of the fixed (non-K) index of each staged element
@@ -69,12 +73,16 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
         const bool kin = k < K;
         const long long ko = kin ? ioff(sg.A.col, k) : 0;
 #pragma unroll
-        for (int u = 0; u < NA; u++) ra[u] = (kin && aok[u]) ? Ap[aoff[u] + ko] : 0.0;
+        for (int u = 0; u < NA; u++) {
+          if (AF) raf[u] = (kin && aok[u]) ? Af[aoff[u] + ko] : 0.0f;
+          else ra[u] = (kin && aok[u]) ? Ap[aoff[u] + ko] : 0.0;
+        }
       } else {
 #pragma unroll
         for (int u = 0; u < NA; u++) {
           const int k = kb + tid / BM + u * (256 / BM);
-          ra[u] = (k < K && aok[u]) ? Ap[aoff[u] + ioff(sg.A.col, k)] : 0.0;
+          if (AF) raf[u] = (k < K && aok[u]) ? Af[aoff[u] + ioff(sg.A.col, k)] : 0.0f;
+          else ra[u] = (k < K && aok[u]) ? Ap[aoff[u] + ioff(sg.A.col, k)] : 0.0;
         }
       }
       if (BNF) {
@@ -94,8 +102,9 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
     auto store = [&](int buf) {
 #pragma unroll
       for (int u = 0; u < NA; u++) {
-        if (AKF) As[buf][tid % BK][tid / BK + u * (256 / BK)] = ra[u] * scale;
-        else As[buf][tid / BM + u * (256 / BM)][tid % BM] = ra[u] * scale;
+        const double av = AF ? (double)raf[u] : ra[u];
+        if (AKF) As[buf][tid % BK][tid / BK + u * (256 / BK)] = av * scale;
+        else As[buf][tid / BM + u * (256 / BM)][tid % BM] = av * scale;
       }
 #pragma unroll
       for (int u = 0; u < NB; u++) {
@@ -192,9 +201,9 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
   }
 }
 
-template <int TM, int TN, bool AKF, bool BNF>
+template <int TM, int TN, bool AKF, bool BNF, bool AF = false>
 __global__ __launch_bounds__(256) void k_gemm_f64(const Gemm g) {
-  gemm_body<TM, TN, AKF, BNF>(g);
+  gemm_body<TM, TN, AKF, BNF, AF>(g);
 }
 
 // C = alpha * sum_part P[batch][part] + beta * C through the output maps (fixed order)
@@ -215,9 +224,14 @@ __global__ void k_splitk_reduce(const Gemm g) {
 }
 
 template <int TM, int TN>
-static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf) {
+static hipError_t launch_tiles(const Gemm &g, hipStream_t s, bool akf, bool bnf, bool af) {
   dim3 grid((g.N + 32 * TN - 1) / (32 * TN), (g.M + 32 * TM - 1) / (32 * TM), g.nbatch * g.ksplit);
-  if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true>), grid, dim3(256), 0, s, g);
+  if (af) {  // float A (contravariant triples of the reduced-precision forms)
+    if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true, true>), grid, dim3(256), 0, s, g);
+    else if (akf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, false, true>), grid, dim3(256), 0, s, g);
+    else if (bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, true, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, false, true>), grid, dim3(256), 0, s, g);
+  } else if (akf && bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, true>), grid, dim3(256), 0, s, g);
   else if (akf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, true, false>), grid, dim3(256), 0, s, g);
   else if (bnf) hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, true>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((k_gemm_f64<TM, TN, false, false>), grid, dim3(256), 0, s, g);
@@ -262,10 +276,13 @@ long long gemm_tiles(const Gemm &g) {
 }
 
 hipError_t gemm_f64(const Gemm &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g_dry) return hipSuccess;
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
   if (g.nseg < 1 || g.nseg > 2 || g.ksplit < 1 || (g.ksplit > 1 && !g.P)) return hipErrorInvalidValue;
   const bool akf = unit(g.seg[0].A.col);
   const bool bnf = unit(g.seg[0].B.col);
+  const bool af = g.seg[0].A.pf != nullptr;
+  for (int i = 0; i < g.nseg; i++)
+    if ((g.seg[i].A.pf != nullptr) != af) return hipErrorInvalidValue;
   int tm = pick(g.M), tn = pick(g.N);
   long long ktot = 0;
   for (int i = 0; i < g.nseg; i++) ktot += g.seg[i].K;
@@ -281,8 +298,9 @@ hipError_t gemm_f64(const Gemm &g, hipStream_t s) {
     tm = g.tm;
     tn = g.tn;
   }
+  if (g_dry) return hipSuccess;  // host sizing run: arguments checked, nothing launched
 #define MLCC3_TILE(a, b) \
-  if (tm == a && tn == b) return launch_tiles<a, b>(g, s, akf, bnf);
+  if (tm == a && tn == b) return launch_tiles<a, b>(g, s, akf, bnf, af);
   MLCC3_TILE(4, 4) MLCC3_TILE(4, 2) MLCC3_TILE(4, 1) MLCC3_TILE(2, 4) MLCC3_TILE(2, 2) MLCC3_TILE(2, 1)
   MLCC3_TILE(1, 4) MLCC3_TILE(1, 2) MLCC3_TILE(1, 1)
 #undef MLCC3_TILE

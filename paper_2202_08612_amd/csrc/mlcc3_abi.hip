@@ -67,6 +67,9 @@ thread_local mlcc3_ws t_ws = nullptr;   // workspace of the running call (timing
 thread_local long long t_alloc_fail_at = 0, t_alloc_count = 0;
 thread_local hipStream_t t_stream = nullptr;
 thread_local int t_prec = MLCC3_FP64;   // arithmetic of the d-contractions of the running call
+// the contravariant ordered-triple blocks (tau~, R~, L~) of the running call hold float elements
+// (the reduced-precision forms of the ground residual and the transforms; never in the densities)
+thread_local bool t_xf32 = false;
 // core-valence separation of the running call: on/off, active core orbitals as bits, device flags [N_O]
 thread_local int t_cvs = 0;
 thread_local unsigned long long t_cvs_bits = 0;
@@ -167,7 +170,7 @@ struct mlcc3_ws_s {
   struct TauKey {
     bool valid = false, xtau = false;
     long long tb = 0, te = 0;
-    int prec = 0, cvs = 0;
+    int prec = 0, cvs = 0, xf32 = 0;
     unsigned long long core = 0;
   } tau;
 };
@@ -420,12 +423,11 @@ long long max_off(const Idx2 &f, int X) {
   return best;
 }
 
-void check_range(const double *p, const Idx2 &row, int R, const Idx2 &col, int Cc, long long batch, int nb,
-                 const char *what, long long vstride = 0, int nvec = 1) {
+void check_range(const void *p, const Idx2 &row, int R, const Idx2 &col, int Cc, long long batch, int nb,
+                 const char *what, long long vstride = 0, int nvec = 1, size_t esz = sizeof(double)) {
   const uintptr_t lo = (uintptr_t)p;
   const uintptr_t hi =
-      lo + (uintptr_t)(max_off(row, R) + max_off(col, Cc) + batch * (nb - 1) + vstride * (nvec - 1) + 1) *
-               sizeof(double);
+      lo + (uintptr_t)(max_off(row, R) + max_off(col, Cc) + batch * (nb - 1) + vstride * (nvec - 1) + 1) * esz;
   for (const Extent &e : t_ext)
     if (e.lo <= lo && hi <= e.hi) return;
   throw Status{MLCC3_EHIP, std::string("internal bounds check failed for GEMM operand ") + what};
@@ -443,7 +445,8 @@ void gemm(const Gemm &g, hipStream_t s) {
   for (int i = 0; i < g.nseg; i++) {
     const Seg &sg = g.seg[i];
     if (sg.K <= 0) continue;
-    check_range(sg.A.p, sg.A.row, g.M, sg.A.col, sg.K, sg.A.batch, g.nbatch, "A");
+    if (sg.A.pf) check_range(sg.A.pf, sg.A.row, g.M, sg.A.col, sg.K, sg.A.batch, g.nbatch, "A", 0, 1, sizeof(float));
+    else check_range(sg.A.p, sg.A.row, g.M, sg.A.col, sg.K, sg.A.batch, g.nbatch, "A");
     check_range(sg.B.p, sg.B.row, sg.K, sg.B.col, g.N, sg.B.batch, g.nbatch, "B");
   }
   check_range(g.C, g.crow, g.M, g.ccol, g.N, g.cbatch, g.nbatch, "C");
@@ -483,8 +486,10 @@ void tgemm(const TileGemm &g, hipStream_t s, bool whole_k = false) {
   for (int i = 0; i < g.nseg; i++) {
     const TgSeg &sg = g.seg[i];
     if (sg.K <= 0) continue;
-    if (g.ak) check_range(sg.A, sg.amap, g.M, plain(1), sg.K, sg.abatch, g.nbatch, "A (tile GEMM)", sg.avec, g.nvec);
-    else check_range(sg.A, sg.amap, sg.K, plain(1), g.M, sg.abatch, g.nbatch, "A (tile GEMM)", sg.avec, g.nvec);
+    const void *ap = sg.Af ? (const void *)sg.Af : (const void *)sg.A;
+    const size_t ae = sg.Af ? sizeof(float) : sizeof(double);
+    if (g.ak) check_range(ap, sg.amap, g.M, plain(1), sg.K, sg.abatch, g.nbatch, "A (tile GEMM)", sg.avec, g.nvec, ae);
+    else check_range(ap, sg.amap, sg.K, plain(1), g.M, sg.abatch, g.nbatch, "A (tile GEMM)", sg.avec, g.nvec, ae);
     check_range(sg.B, plain(sg.ldb), sg.K, plain(1), g.N, sg.bbatch, g.nbatch, "B (tile GEMM)", sg.bvec, g.nvec);
   }
   check_range(g.C, g.cmap, g.M, plain(1), g.N, g.cbatch, g.nbatch, "C (tile GEMM)", g.cvec, g.nvec);
@@ -570,6 +575,26 @@ void reg_vec(const mlcc3_ground *g, const double *x1, const double *a, const dou
   reg(x1, NV * NO, "x1");
   reg(a, nv * NV * no * no, "x2_vVoo");
   reg(b, nv * nv * no * NO, "x2_vvoO");
+}
+
+// element count of an ordered-triple buffer of n values in the running call's element type, as
+// the double count buf() takes, and the sub-buffer starting e elements in
+size_t xcount(long long n) { return t_xf32 ? (size_t)((n + 1) / 2) : (size_t)n; }
+double *xsub(double *base, long long e) { return t_xf32 ? (double *)((float *)base + e) : base + e; }
+size_t xesz() { return t_xf32 ? sizeof(float) : sizeof(double); }
+// element pitch of the vectors of a group in the contravariant buffers: float blocks start on
+// 256-byte boundaries (the 16-byte loads of the split-bf16 staging need 16-byte aligned bases)
+long long xpitch(long long n) { return t_xf32 ? (n + 63) / 64 * 64 : n; }
+// the A operand of a segment reads the running call's contravariant blocks (float when t_xf32)
+void xa(Seg &sg) {
+  if (!t_xf32) return;
+  sg.A.pf = (const float *)sg.A.p;
+  sg.A.p = nullptr;
+}
+void xa(TgSeg &sg) {
+  if (!t_xf32) return;
+  sg.Af = (const float *)sg.A;
+  sg.A = nullptr;
 }
 
 Seg seg(const double *A, Idx2 arow, Idx2 acol, long long abatch, const double *B, Idx2 brow, Idx2 bcol,
@@ -1100,7 +1125,8 @@ const double *occ_xT(mlcc3_ws ws, const Dims &d, const double *const *x, int nb,
 }
 
 // symmetrise, divide and convert the W blocks of nb vectors (W_v at W + v*|W|) into X~_v at
-// Xt + v*|W| (and covariant X into Xc likewise); one launch per pass for the whole group
+// Xt + v*pitch (pitch |W|, padded to 64 elements for float blocks; covariant X into Xc at
+// + v*|W|); one launch per pass for the whole group
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
              const double *omega, int nb, Range r, const LocalTerms &lt, const OccTerm &ot, hipStream_t s,
              double *Xc = nullptr) {
@@ -1112,15 +1138,15 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
   vb.nvec = nb;
   vb.w = Wv;
   vb.xu = Xuv;
-  vb.xt = Wv;
+  vb.xt = xpitch(Wv);
   for (int v = 0; v < nb; v++) vb.omega[v] = omega[v];
   vb.cvs = t_cvs;
   vb.core_bits = t_cvs_bits;
   check_bytes(W, sizeof(double) * Wv * nb, "W (permutation)");
-  check_bytes(Xt, sizeof(double) * Wv * nb, "X~ (permutation)");
+  check_bytes(Xt, xesz() * vb.xt * nb, "X~ (permutation)");
   if (Xc) check_bytes(Xc, sizeof(double) * Wv * nb, "covariant X (permutation)");
   launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, vb,
-                       r.tb, r.te, lt, ot, tune().contra_form, s);
+                       r.tb, r.te, lt, ot, tune().contra_form, s, t_xf32);
   HIPRT(hipGetLastError());
 }
 
@@ -1136,15 +1162,16 @@ bool tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
   key.prec = t_prec;
   key.cvs = t_cvs;
   key.core = t_cvs ? t_cvs_bits : 0;
+  key.xf32 = t_xf32;
   const mlcc3_ws_s::TauKey &k = ws->tau;
   if (reuse && !Xc && k.valid && k.tb == key.tb && k.te == key.te && k.prec == key.prec && k.cvs == key.cvs &&
-      k.core == key.core) {
-    (void)buf(ws, "XT", (size_t)(d.nord * d.nv3), s);  // registers the kept buffer for the bounds checks
+      k.core == key.core && k.xf32 == key.xf32) {
+    (void)buf(ws, "XT", xcount(xpitch(d.nord * d.nv3)), s);  // registers the kept buffer for the bounds checks
     return true;
   }
   ws->tau = mlcc3_ws_s::TauKey{};
   double *W = buf(ws, "W", (size_t)(d.nord * d.nv3), s);
-  double *XT = buf(ws, "XT", (size_t)(d.nord * d.nv3), s);
+  double *XT = buf(ws, "XT", xcount(xpitch(d.nord * d.nv3)), s);
   DSeg sg;
   sg.x = B(ws, "tA");
   sg.G = B(ws, "G1");
@@ -1194,12 +1221,13 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     g.seg[0].A = Am;
     g.seg[0].aplane = pa;
     g.seg[0].abatch = (long long)Mp * Kp;
-    g.seg[0].B64 = X;
+    if (t_xf32) g.seg[0].B32 = (const float *)X;
+    else g.seg[0].B64 = X;
     g.seg[0].bmap = xrow;
     g.seg[0].bbatch = d.nv3;
     g.seg[0].K = (int)d.nv2;
     g.seg[0].Kp = Kp;
-    check_range(X, xrow, M2, plain(1), (int)d.nv2, d.nv3, d.no, "X~ (back-contraction)");
+    check_range(X, xrow, M2, plain(1), (int)d.nv2, d.nv3, d.no, "X~ (back-contraction)", 0, 1, xesz());
     check_range(PT, plain(M2), N, plain(1), M2, MN, d.no, "C (back-contraction)");
     HIPCHK(dcontract_bf16(g, s));
     // Y[(i,j,a)][n] = sum_k P^T[k][n][(i,j,a)]: fixed-order sum over k, then one transpose
@@ -1217,6 +1245,7 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     g.cbatch = MN;
     g.nseg = 1;
     g.seg[0] = tseg(X, xrow, d.nv3, G, N, d.nv2 * N, (int)d.nv2);
+    xa(g.seg[0]);
     g.tf = triple_filter(d, r, true);
     tgemm(g, s);
   } else {
@@ -1231,6 +1260,7 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     g.cbatch = MN;
     g.nseg = 1;
     g.seg[0] = seg(X, xrow, plain(1), d.nv3, G, plain(N), plain(1), d.nv2 * N, (int)d.nv2);
+    xa(g.seg[0]);
     gemm(g, s);
   }
   launch_sum_rows(P, d.no, MN, Y, s);
@@ -1271,7 +1301,11 @@ Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2
   const int K = d.no * d.no * d.nv;
   const long long xb = (long long)d.no * d.no * d.nv3;
   g.seg[0] = seg(X1, plain(d.nv), split(d.nv, d.nv3, 1), xb, G1.p, G1.row, G1.col, G1.batch, K);
-  if (X2) g.seg[1] = seg(X2, plain(d.nv), split(d.nv, d.nv3, 1), xb, G2.p, G2.row, G2.col, G2.batch, K);
+  xa(g.seg[0]);
+  if (X2) {
+    g.seg[1] = seg(X2, plain(d.nv), split(d.nv, d.nv3, 1), xb, G2.p, G2.row, G2.col, G2.batch, K);
+    xa(g.seg[1]);
+  }
   narrow_tile(g);
   return g;
 }
@@ -1293,6 +1327,7 @@ void back_qrc(mlcc3_ws ws, const Dims &d, const double *X, const double *x, doub
   g.nseg = 1;
   g.seg[0] = seg(X, split(d.nv, d.nv3, 1), plain(d.nv), (long long)d.no * d.no * d.nv3, x,
                  plain((long long)d.no * d.NO), plain(1), d.NO, (int)d.nv2);
+  xa(g.seg[0]);
   narrow_tile(g);
   gemm(g, s);
   launch_sum_rows(P, d.no, MN, Y, s);
@@ -1385,6 +1420,7 @@ mlcc3_opts opts_or_default(const mlcc3_opts *o) {
             r.precision == MLCC3_BF16X6,
         "bad precision");
   t_prec = r.precision;
+  t_xf32 = r.precision != MLCC3_FP64;
   t_cvs = 0;
   t_cvs_bits = 0;
   t_cvs_dev = nullptr;
@@ -1396,7 +1432,7 @@ void finish_right_like(mlcc3_ws ws, const Dims &d, const double *X, const double
                        const double *YvV, const double *YvO, int delta, const mlcc3_out *out, hipStream_t s) {
   double *part1 = buf(ws, "part1", (size_t)d.no * d.no * d.nv, s);
   double *Yvv = buf(ws, "Yvv", (size_t)d.no * d.no * d.nv2, s);
-  launch_small_right(X, T, B(ws, "gov"), B(ws, "F"), U, d.no, d.nv, part1, Yvv, s);
+  launch_small_right(X, T, B(ws, "gov"), B(ws, "F"), U, d.no, d.nv, part1, Yvv, s, t_xf32);
   launch_singles_out(part1, d.no, d.nv, d.NO, d.NV, out->x1, s);
   DoublesRaw y;
   y.YvV = YvV; y.YvO = YvO; y.Yvv = Yvv;
@@ -1493,7 +1529,7 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
 }
 
 // R3 of the nb prepared right vectors of a group (slots 0..nb-1 of the prep buffers):
-// contravariant into Xt_v = Xt + v*|W|, covariant into Xc (optional)
+// contravariant into the vector pitch of Xt (see permute), covariant into Xc (optional)
 void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *R, const double *omega, int nb,
               Range r, double *Xt, double *Xc, hipStream_t s) {
   const RightSizes z = right_sizes(d);
@@ -1517,7 +1553,7 @@ void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, LocalTerms{}, ot, s, Xc);
 }
 
-// L3 (transpose-transformation recipe) of nb left-type vectors into Xt_v = Xt + v*|W|; packs
+// L3 (transpose-transformation recipe) of nb left-type vectors into Xt (vector pitch as in permute); packs
 // LA/LV (stacked, under the given names) and the singles copy "L1s"
 void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *L, const double *omega, int nb,
               Range r, double *Xt, const char *laname, const char *lvname, hipStream_t s) {
@@ -2058,14 +2094,14 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     const RightSizes z = right_sizes(d);
     for (int m0 = 0; m0 < nvec; m0 += ng) {
       const int nb = std::min(ng, nvec - m0);
-      double *XRg = buf(ws, "XR", (size_t)(d.nord * d.nv3 * nb), s);
+      double *XRg = buf(ws, "XR", xcount(xpitch(d.nord * d.nv3) * nb), s);
       group_dlhat(ws, g, d, R + m0, nb, s);
       for (int v = 0; v < nb; v++) right_vector_prep(ws, g, d, R[m0 + v], v, nb, s);
       build_R3(ws, g, d, R + m0, omega + m0, nb, r, XRg, nullptr, s);
       log_phase("R3");
       for (int v = 0; v < nb; v++) {
         const int m = m0 + v;
-        double *XR = XRg + v * d.nord * d.nv3;
+        double *XR = xsub(XRg, v * xpitch(d.nord * d.nv3));
         double *Ukc = B(ws, "Ukc") + v * z.Ukc, *Xi = B(ws, "Xi") + v * z.Xi;
         // back-contractions
         double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
@@ -2143,7 +2179,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     const long long sLA = (long long)no * no * nv * NV;
     for (int m0 = 0; m0 < nvec; m0 += ng) {
       const int nb = std::min(ng, nvec - m0);
-      double *XLg = buf(ws, "XR", (size_t)(d.nord * d.nv3 * nb), s);
+      double *XLg = buf(ws, "XR", xcount(xpitch(d.nord * d.nv3) * nb), s);
       // L3 (SI transpose transformation, exact-transpose index placement):
       //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc + local terms
       build_L3(ws, g, d, L + m0, omega + m0, nb, r, XLg, "LA", "LV", s);
@@ -2151,7 +2187,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
       for (int v = 0; v < nb; v++) {
         const int m = m0 + v;
         const double *L2b = L[m].x2_vvoO;
-        double *XL = XLg + v * d.nord * d.nv3;
+        double *XL = xsub(XLg, v * xpitch(d.nord * d.nv3));
         double *LA = B(ws, "LA") + v * sLA;
         // doubles: sigma^{aD}_{ij} <- sum L~ g_bDck ; sigma^{ab}_{iL} <- -sum L~ g_Ljck
         double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
@@ -2174,6 +2210,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
           gg.cbatch = d.nv2 * NV;
           gg.nseg = 1;
           gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), NV, 0, no * no * nv);
+          xa(gg.seg[0]);
           tgemm(gg, s);
         }
         // Aq[(q,r,c)][M] = sum L~[p][q][r][a][b][c] t^{ab}_{pM};  Qtau likewise with tau~ and L^{ab}_{pL}
@@ -2331,6 +2368,7 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     reg(D_0m, nstate * N * N, "D_0m");
     reg(s_out, nstate, "s");
     const mlcc3_opts o = opts_or_default(opts);
+    t_xf32 = false;  // the densities read the contravariant blocks in FP64 in every form
     check(!o.cvs_core, "core-valence separation applies to the right and left transforms only");
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(ws->device);

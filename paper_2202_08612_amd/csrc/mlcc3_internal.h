@@ -26,6 +26,7 @@ struct Operand {
   const double *p = nullptr;
   Idx2 row, col;
   long long batch = 0;
+  const float *pf = nullptr;  // A operands only: float elements at the same offsets instead of p
 };
 
 struct Seg {

@@ -9,6 +9,7 @@ namespace mlcc3 {
 // A(m,k) = A[v*avec + z*abatch + amap(m) + k] when TileGemm::ak, else A[... + amap(k) + m]
 struct TgSeg {
   const double *A = nullptr;
+  const float *Af = nullptr;  // A of float elements at the same offsets instead of A (then A unused)
   Idx2 amap;
   long long abatch = 0, avec = 0;
   const double *B = nullptr;

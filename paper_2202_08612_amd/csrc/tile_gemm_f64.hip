@@ -40,7 +40,8 @@ __device__ __forceinline__ long long moff(const Idx2 &f, int x) {
   return (long long)q * f.s1 + (long long)(x - q * f.d) * f.s0;
 }
 
-template <bool AK, bool VEC, bool BETA>
+// AF: the A operand of every segment holds float elements (TgSeg::Af), widened when staged
+template <bool AK, bool VEC, bool BETA, bool AF = false>
 __device__ __forceinline__ void tile_body(const TileGemm &g) {
   __shared__ double As[2][AK ? BM * PA : BK * PB];
   __shared__ double Bs[2][BK * PB];
@@ -73,6 +74,9 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
     const int akp = tid & 7, ar = tid >> 3;
     const int np = tid & 63, kr = tid >> 6;
     d2 ra[4], rb[4];
+    // float A is kept as loaded until the LDS store: a conversion at the load would wait for
+    // the load there and take the next K-step's prefetch out of the shadow of the MFMAs
+    float2 raf[4];
 
     for (int s = 0; s < (skip ? 0 : g.nseg); s++) {
       const TgSeg &sg = g.seg[s];
@@ -81,7 +85,8 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
       const int kb = part * chunk;
       const int K = min(sg.K, kb + chunk);
       if (kb >= K) continue;  // uniform over the workgroup
-      const double *Ap = sg.A + vv * sg.avec + (long long)z * sg.abatch;
+      const double *Ap = AF ? nullptr : sg.A + vv * sg.avec + (long long)z * sg.abatch;
+      const float *Afp = AF ? sg.Af + vv * sg.avec + (long long)z * sg.abatch : nullptr;
       const double *Bp = sg.B + vv * sg.bvec + (long long)z * sg.bbatch;
       const int nkt = (K - kb + BK - 1) / BK;
       long long aoff[4];
@@ -99,16 +104,28 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
 #pragma unroll
           for (int u = 0; u < 4; u++) {
             d2 v = d2{0.0, 0.0};
+            float2 f = make_float2(0.0f, 0.0f);
             if (aoff[u] >= 0) {
-              const double *p = Ap + aoff[u] + k;
-              if (VEC && k + 1 < K) {
-                v = *(const d2 *)p;
+              if (AF) {
+                const float *p = Afp + aoff[u] + k;
+                if (VEC && k + 1 < K) {
+                  f = *(const float2 *)p;
+                } else {
+                  if (k < K) f.x = p[0];
+                  if (k + 1 < K) f.y = p[1];
+                }
               } else {
-                if (k < K) v.x = p[0];
-                if (k + 1 < K) v.y = p[1];
+                const double *p = Ap + aoff[u] + k;
+                if (VEC && k + 1 < K) {
+                  v = *(const d2 *)p;
+                } else {
+                  if (k < K) v.x = p[0];
+                  if (k + 1 < K) v.y = p[1];
+                }
               }
             }
-            ra[u] = v;
+            if (AF) raf[u] = f;
+            else ra[u] = v;
           }
         } else {
           const int m = m0 + 2 * np;
@@ -116,16 +133,28 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
           for (int u = 0; u < 4; u++) {
             const int k = kb + kt * BK + kr + 4 * u;
             d2 v = d2{0.0, 0.0};
+            float2 f = make_float2(0.0f, 0.0f);
             if (k < K) {
-              const double *p = Ap + moff(sg.amap, k) + m;
-              if (VEC && m + 1 < g.M) {
-                v = *(const d2 *)p;
+              if (AF) {
+                const float *p = Afp + moff(sg.amap, k) + m;
+                if (VEC && m + 1 < g.M) {
+                  f = *(const float2 *)p;
+                } else {
+                  if (m < g.M) f.x = p[0];
+                  if (m + 1 < g.M) f.y = p[1];
+                }
               } else {
-                if (m < g.M) v.x = p[0];
-                if (m + 1 < g.M) v.y = p[1];
+                const double *p = Ap + moff(sg.amap, k) + m;
+                if (VEC && m + 1 < g.M) {
+                  v = *(const d2 *)p;
+                } else {
+                  if (m < g.M) v.x = p[0];
+                  if (m + 1 < g.M) v.y = p[1];
+                }
               }
             }
-            ra[u] = v;
+            if (AF) raf[u] = f;
+            else ra[u] = v;
           }
         }
         const int n = n0 + 2 * np;
@@ -148,12 +177,13 @@ __device__ __forceinline__ void tile_body(const TileGemm &g) {
       auto store = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
+          const d2 av = AF ? d2{(double)raf[u].x, (double)raf[u].y} : ra[u];
           if (AK) {
             double *pa = &As[buf][(ar + 32 * u) * PA + 2 * akp];
-            pa[0] = ra[u].x;
-            pa[1] = ra[u].y;
+            pa[0] = av.x;
+            pa[1] = av.y;
           } else {
-            *(d2 *)&As[buf][(kr + 4 * u) * PB + 2 * np] = ra[u];
+            *(d2 *)&As[buf][(kr + 4 * u) * PB + 2 * np] = av;
           }
         }
 #pragma unroll
@@ -217,9 +247,9 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f64(const TileGemm g) {
   tile_body<true, VEC, false>(g);
 }
 
-template <bool AK, bool VEC, bool BETA>
+template <bool AK, bool VEC, bool BETA, bool AF = false>
 __global__ __launch_bounds__(256, 2) void k_tile_gemm_f64(const TileGemm g) {
-  tile_body<AK, VEC, BETA>(g);
+  tile_body<AK, VEC, BETA, AF>(g);
 }
 
 bool even_map(const Idx2 &f) { return f.s0 % 2 == 0 && (f.d <= 0 || f.s1 % 2 == 0); }
@@ -240,22 +270,29 @@ long long tile_gemm_blocks(const TileGemm &g) {
 
 hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
   TileGemm g = g0;
-  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g.nvec <= 0 || g_dry) return hipSuccess;
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0 || g.nvec <= 0) return hipSuccess;
   if (g.nseg < 1 || g.nseg > 2) return hipErrorInvalidValue;
   if (g.dcontract && !g.ak) return hipErrorInvalidValue;
   if (g.ksplit < 1 || (g.ksplit > 1 && g.beta != 0.0)) return hipErrorInvalidValue;
   if (g.tf.on && (g.tf.no < 1 || g.tf.nv < 1 || (g.tf.zero && g.beta != 0.0))) return hipErrorInvalidValue;
   const long long T = tile_gemm_blocks(g);
   if (T > 0x7fffffffLL) return hipErrorInvalidValue;
-  // 16-byte loads need even offsets of every loaded pair and 16-byte aligned bases
+  // 16-byte loads need even offsets of every loaded pair and 16-byte aligned bases (8-byte ones
+  // for a float A)
+  const bool af = g.seg[0].Af != nullptr;
   bool vec = g.N % 2 == 0;
   for (int i = 0; i < g.nseg; i++) {
     const TgSeg &sg = g.seg[i];
+    if ((sg.Af != nullptr) != af) return hipErrorInvalidValue;
+    const bool abase = af ? (uintptr_t)sg.Af % 8 == 0 : (uintptr_t)sg.A % 16 == 0;
     vec = vec && even_map(sg.amap) && sg.ldb % 2 == 0 && sg.abatch % 2 == 0 && sg.bbatch % 2 == 0 &&
-          sg.avec % 2 == 0 && sg.bvec % 2 == 0 && (uintptr_t)sg.A % 16 == 0 && (uintptr_t)sg.B % 16 == 0;
+          sg.avec % 2 == 0 && sg.bvec % 2 == 0 && abase && (uintptr_t)sg.B % 16 == 0;
   }
+  if (af && (g.dcontract || g.beta != 0.0)) return hipErrorInvalidValue;
   for (int i = 0; i < g.nseg; i++) g.seg[i].amap = branchless(g.seg[i].amap);
   g.cmap = branchless(g.cmap);
+  if (g.dcontract && g.beta != 0.0) return hipErrorInvalidValue;
+  if (g_dry) return hipSuccess;  // host sizing run: arguments checked, nothing launched
   const dim3 grid((unsigned)(g.persist > 0 && g.persist < T ? g.persist : T)), block(256);
   const bool beta = g.beta != 0.0;
   if (g.dcontract) {
@@ -263,12 +300,14 @@ hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
     if (vec) hipLaunchKernelGGL(k_dcontract_f64<true>, grid, block, 0, s, g);
     else hipLaunchKernelGGL(k_dcontract_f64<false>, grid, block, 0, s, g);
   }
-#define MLCC3_TG(A_, V_, B_) \
-  else if ((g.ak != 0) == A_ && vec == V_ && beta == B_) \
-    hipLaunchKernelGGL((k_tile_gemm_f64<A_, V_, B_>), grid, block, 0, s, g);
-  MLCC3_TG(true, true, false) MLCC3_TG(true, true, true) MLCC3_TG(true, false, false) MLCC3_TG(true, false, true)
-  MLCC3_TG(false, true, false) MLCC3_TG(false, true, true) MLCC3_TG(false, false, false)
-  MLCC3_TG(false, false, true)
+#define MLCC3_TG(A_, V_, B_, F_) \
+  else if ((g.ak != 0) == A_ && vec == V_ && beta == B_ && af == F_) \
+    hipLaunchKernelGGL((k_tile_gemm_f64<A_, V_, B_, F_>), grid, block, 0, s, g);
+  MLCC3_TG(true, true, false, false) MLCC3_TG(true, true, true, false) MLCC3_TG(true, false, false, false)
+  MLCC3_TG(true, false, true, false) MLCC3_TG(false, true, false, false) MLCC3_TG(false, true, true, false)
+  MLCC3_TG(false, false, false, false) MLCC3_TG(false, false, true, false)
+  MLCC3_TG(true, true, false, true) MLCC3_TG(true, false, false, true) MLCC3_TG(false, true, false, true)
+  MLCC3_TG(false, false, false, true)
 #undef MLCC3_TG
   return hipGetLastError();
 }

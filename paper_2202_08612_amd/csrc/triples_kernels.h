@@ -84,12 +84,14 @@ struct VecBatch {
 // (and, if Xc is not NULL, the covariant X to every ordering); contravariant pass per
 // sub-cube (contra_form 1), per orbit of sub-cubes (2), or by the size rule (0: per orbit
 // when 16 divides n_v or n_v > 64)
-void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
+// (xt_f32: Xt holds float elements; the covariant copy Xc is always double)
+void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
                           long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
-                          hipStream_t s);
-void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
-                        int no, int nv, double *part1, double *Yvv, hipStream_t s);
+                          hipStream_t s, bool xt_f32 = false);
+// X, T: ordered blocks of double, or of float when x_f32
+void launch_small_right(const void *X, const void *T, const double *gov, const double *F, const double *U,
+                        int no, int nv, double *part1, double *Yvv, hipStream_t s, bool x_f32 = false);
 // pairing maps of the doubles blocks (mode 0 symmetrise, 1 gradient -> left vector, 2 left
 // vector -> gradient representer); outputs must not alias inputs
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,

@@ -364,7 +364,10 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, double *__restrict__ Xt,
+// OT: element type of the ordered blocks written (double, or float for the reduced-precision
+// forms of the right and left transforms and the ground residual)
+template <typename OT>
+__global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, OT *__restrict__ Xt,
                                                         const UniqueTriple *ut, int no, int nv, int covariant, int nu,
                                                         int nvec, long long xuv, long long xtv) {
   __shared__ double cube[SUB];
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
   for (int s = 0; s < 6; s++) {
     if (!((u.mask >> s) & 1)) continue;
     const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
-    double *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
+    OT *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
     // output local index w = v.s, i.e. w_n = v_{s_n}; the writer of w reads v with v_{s_n} = w_n
     const int W0 = TT * T[s0], W1 = TT * T[s1], W2 = TT * T[s2];
     for (int r = 0; r < TT; r++) {
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
       if (W0 + w[0] >= nv || W1 + w[1] >= nv || W2 + w[2] >= nv) continue;
       int v[3];
       v[s0] = w[0]; v[s1] = w[1]; v[s2] = w[2];
-      dst[(W0 + w[0]) * nv2 + (long long)(W1 + w[1]) * nv + (W2 + w[2])] = cube[v[0] * LX + v[1] * LY + v[2]];
+      dst[(W0 + w[0]) * nv2 + (long long)(W1 + w[1]) * nv + (W2 + w[2])] = (OT)cube[v[0] * LX + v[1] * LY + v[2]];
     }
   }
 }
@@ -544,7 +547,8 @@ constexpr double kCoef[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
 
 __device__ __forceinline__ int tile_code(int x, int y, int z, int nt) { return (x * nt + y) * nt + z; }
 
-__global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restrict__ Xu, double *__restrict__ Xt,
+template <typename OT>
+__global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restrict__ Xu, OT *__restrict__ Xt,
                                                          const UniqueTriple *ut, int no, int nv, int nu, int nvec,
                                                          long long xuv, long long xtv) {
   __shared__ double cube[SUB];
@@ -629,7 +633,7 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
     for (int s = 0; s < 6; s++) {
       if (!((u.mask >> s) & 1)) continue;
       const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
-      double *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
+      OT *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
       const int W0 = TT * sel3(TT3[0], TT3[1], TT3[2], s0), W1 = TT * sel3(TT3[0], TT3[1], TT3[2], s1),
                 W2 = TT * sel3(TT3[0], TT3[1], TT3[2], s2);
       // output local w = (r, lb, lc) sits at v with v_{s_n} = w_n: LDS weight of w_n is that of axis s_n
@@ -637,11 +641,11 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
       const int q0 = sel3(ax[0], ax[1], ax[2], s0), q1 = sel3(ax[0], ax[1], ax[2], s1),
                 q2 = sel3(ax[0], ax[1], ax[2], s2);
       if (W1 + lb >= nv || W2 + lc >= nv) continue;
-      double *drow = dst + (long long)(W1 + lb) * nv + (W2 + lc);
+      OT *drow = dst + (long long)(W1 + lb) * nv + (W2 + lc);
       const double *cb = cube + lb * q1 + lc * q2;
       for (int r = 0; r < TT; r++) {
         if (W0 + r >= nv) break;
-        drow[(W0 + r) * nv2] = cb[r * q0];
+        drow[(W0 + r) * nv2] = (OT)cb[r * q0];
       }
     }
   }
@@ -659,8 +663,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Each of the four waves takes every fourth row b; its lanes run over the n_o n_v pairs (r, c)
 // of the row, 64 at a time, so every pass but the last is a full wave of independent loads and
 // a row costs one cross-lane reduction.
-template <bool HAS_T>
-__global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ X, const double *__restrict__ T,
+template <bool HAS_T, typename XT_>
+__global__ __launch_bounds__(256) void k_small_right(const XT_ *__restrict__ X, const XT_ *__restrict__ T,
                                                      const double *__restrict__ gov, const double *__restrict__ F,
                                                      const double *__restrict__ U, int no, int nv,
                                                      double *__restrict__ part1, double *__restrict__ Yvv) {
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const long long off = ((long long)p * no + q) * no * nv3 + (long long)a * nv2;  // r = 0, b = 0
-  const double *x0 = X + off;
+  const XT_ *x0 = X + off;
   const double *g0 = gov + (long long)q * no * nv2;
   const int nrc = no * nv;
   const int r0 = lane / nv, c0 = lane - r0 * nv;  // (r, c) of position e = lane
@@ -682,10 +686,10 @@ __global__ __launch_bounds__(256) void k_small_right(const double *__restrict__ 
 #pragma unroll 4
     for (int e = lane; e < nrc; e += 64) {
       const long long o = (long long)r * nv3 + bo + c;
-      const double x = x0[o];
+      const double x = (double)x0[o];
       racc += x * g0[(long long)r * nv2 + bo + c];
       yb += x * F[r * nv + c];
-      if (HAS_T) yb += T[off + o] * U[r * nv + c];
+      if (HAS_T) yb += (double)T[off + o] * U[r * nv + c];
       // advance the position by 64: c += 64 with the carry into r
       c += 64;
       while (c >= nv) {
@@ -1026,10 +1030,10 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
   L1D(k_add_vo, (long long)no * nv, D, NO, N, no, nv, Y, f);
 }
 
-void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, const UniqueTriple *ut, int nu,
+void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
                           long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
-                          hipStream_t s) {
+                          hipStream_t s, bool xt_f32) {
   if (nu <= 0 || nv <= 0 || vb.nvec <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
   LocalTerms l = lt;
@@ -1043,23 +1047,43 @@ void launch_permute_denom(const double *W, double *Xu, double *Xt, double *Xc, c
     // L2).  Ragged tiles are exact: a member tile loads zeros past n_v, a permuted read of an
     // output inside n_v stays inside n_v, and writes stop at n_v.
     const int norb = nt * (nt + 1) * (nt + 2) / 6;
-    hipLaunchKernelGGL(k_contra_orbit, dim3((unsigned)((long long)vb.nvec * nu * norb)), dim3(256), 0, s, Xu, Xt, ut,
-                       no, nv, nu, vb.nvec, vb.xu, vb.xt);
+    const dim3 og((unsigned)((long long)vb.nvec * nu * norb));
+    if (xt_f32)
+      hipLaunchKernelGGL(k_contra_orbit<float>, og, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, nu, vb.nvec, vb.xu,
+                         vb.xt);
+    else
+      hipLaunchKernelGGL(k_contra_orbit<double>, og, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, nu, vb.nvec, vb.xu,
+                         vb.xt);
+  } else if (xt_f32) {
+    hipLaunchKernelGGL(k_contra_scatter<float>, grid, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, 0, nu, vb.nvec,
+                       vb.xu, vb.xt);
   } else {
-    hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xt, ut, no, nv, 0, nu, vb.nvec, vb.xu, vb.xt);
+    hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, 0, nu, vb.nvec,
+                       vb.xu, vb.xt);
   }
   if (Xc)
-    hipLaunchKernelGGL(k_contra_scatter, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu, vb.nvec, vb.xu, vb.xt);
+    hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu, vb.nvec, vb.xu,
+                       vb.w);
 }
 
-void launch_small_right(const double *X, const double *T, const double *gov, const double *F, const double *U,
-                        int no, int nv, double *part1, double *Yvv, hipStream_t s) {
+void launch_small_right(const void *X, const void *T, const double *gov, const double *F, const double *U,
+                        int no, int nv, double *part1, double *Yvv, hipStream_t s, bool x_f32) {
   if (no <= 0 || nv <= 0 || g_dry) return;
+  if (x_f32) {
+    if (T)
+      hipLaunchKernelGGL((k_small_right<true, float>), dim3(no * no * nv), dim3(256), 0, s, (const float *)X,
+                         (const float *)T, gov, F, U, no, nv, part1, Yvv);
+    else
+      hipLaunchKernelGGL((k_small_right<false, float>), dim3(no * no * nv), dim3(256), 0, s, (const float *)X,
+                         (const float *)nullptr, gov, F, U, no, nv, part1, Yvv);
+    return;
+  }
   if (T)
-    hipLaunchKernelGGL(k_small_right<true>, dim3(no * no * nv), dim3(256), 0, s, X, T, gov, F, U, no, nv, part1, Yvv);
+    hipLaunchKernelGGL((k_small_right<true, double>), dim3(no * no * nv), dim3(256), 0, s, (const double *)X,
+                       (const double *)T, gov, F, U, no, nv, part1, Yvv);
   else
-    hipLaunchKernelGGL(k_small_right<false>, dim3(no * no * nv), dim3(256), 0, s, X, T, gov, F, U, no, nv, part1,
-                       Yvv);
+    hipLaunchKernelGGL((k_small_right<false, double>), dim3(no * no * nv), dim3(256), 0, s, (const double *)X,
+                       (const double *)nullptr, gov, F, U, no, nv, part1, Yvv);
 }
 
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,

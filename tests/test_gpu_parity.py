@@ -469,3 +469,24 @@ def test_densities_wide_virtual_space(lib, ws, d):
                                 lib.vec_to_device(lam), p.t2_vVoO, p.t2_vVOo)
     ref = orc.densities(om[0], Ls[0], Rs[0], lam, p.t2_vVoO, p.t2_vVOo)
     _check_dens((got[0][0], got[1][0], got[2][0]), ref)
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("d", [I.Dims(4, 12, 6, 20, 60), I.Dims(3, 32, 4, 41, 11)], ids=str)
+def test_densities_every_permutation_pass_form(lib, ws, d, form):
+    """Densities (covariant and contravariant blocks of every ordering) with each form of the
+    contravariant pass: the oracle's results."""
+    p, orc, g = _dens_case(lib, d, 37)
+    Ls, Rs = I.left_vectors(p, 2), I.right_vectors(p, 2)
+    lam = I.lambda_vector(p)
+    om = I.omegas(False, 2)
+    ws.set_tuning({"contra_form": form})
+    try:
+        Dm0, D0m, s = lib.triples_densities(ws, g, om, [lib.vec_to_device(v) for v in Ls],
+                                            [lib.vec_to_device(v) for v in Rs], lib.vec_to_device(lam),
+                                            p.t2_vVoO, p.t2_vVOo)
+    finally:
+        ws.set_tuning(None)
+    for m in range(2):
+        ref = orc.densities(om[m], Ls[m], Rs[m], lam, p.t2_vVoO, p.t2_vVOo)
+        _check_dens((Dm0[m], D0m[m], s[m]), ref)
