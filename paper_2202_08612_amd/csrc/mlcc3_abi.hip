@@ -1628,6 +1628,15 @@ void cvs_project_out(const Dims &d, const mlcc3_out &o, hipStream_t s) {
 // vectors per group: several vectors share one launch of the d-contraction and of the
 // permutation passes; a group holds two ordered-triple buffers (W, X~) per vector, kept within
 // 45% of device memory (environment MLCC3_VEC_BATCH and the workspace tuning cap the group size)
+// The W blocks of a vector group and, once the permutation pass has read them, the group's
+// contravariant blocks (R~ or L~) share one buffer: the pass reads W into the unique-triple
+// blocks before it writes any contravariant element, so one ordered-triple buffer per vector
+// (and the shared tau~) is what a transform holds, not two.
+double *wx_buffer(mlcc3_ws ws, const Dims &d, int nb, hipStream_t s) {
+  const size_t w = (size_t)(d.nord * d.nv3 * nb), x = xcount(xpitch(d.nord * d.nv3) * nb);
+  return buf(ws, "W", std::max(w, x), s);
+}
+
 int group_size(mlcc3_ws ws, const Dims &d, int nvec) {
   int cap = kMaxVecBatch;
   if (const char *e = std::getenv("MLCC3_VEC_BATCH")) cap = std::max(1, std::min(cap, std::atoi(e)));
@@ -1637,7 +1646,8 @@ int group_size(mlcc3_ws ws, const Dims &d, int nvec) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0) total = tot;
   }
-  const double per = 2.2 * sizeof(double) * (double)(d.nord * d.nv3) + 1.0;
+  // per vector: the shared W / contravariant buffer and the unique-triple blocks
+  const double per = 1.3 * sizeof(double) * (double)(d.nord * d.nv3) + 1.0;
   const int fit = (int)std::max(1.0, std::floor(0.45 * (double)total / per));
   (void)ws;
   return std::max(1, std::min({nvec, cap, fit}));
@@ -2094,7 +2104,7 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     const RightSizes z = right_sizes(d);
     for (int m0 = 0; m0 < nvec; m0 += ng) {
       const int nb = std::min(ng, nvec - m0);
-      double *XRg = buf(ws, "XR", xcount(xpitch(d.nord * d.nv3) * nb), s);
+      double *XRg = wx_buffer(ws, d, nb, s);  // R~ of the group overwrites its W
       group_dlhat(ws, g, d, R + m0, nb, s);
       for (int v = 0; v < nb; v++) right_vector_prep(ws, g, d, R[m0 + v], v, nb, s);
       build_R3(ws, g, d, R + m0, omega + m0, nb, r, XRg, nullptr, s);
@@ -2179,7 +2189,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     const long long sLA = (long long)no * no * nv * NV;
     for (int m0 = 0; m0 < nvec; m0 += ng) {
       const int nb = std::min(ng, nvec - m0);
-      double *XLg = buf(ws, "XR", xcount(xpitch(d.nord * d.nv3) * nb), s);
+      double *XLg = wx_buffer(ws, d, nb, s);  // L~ of the group overwrites its W
       // L3 (SI transpose transformation, exact-transpose index placement):
       //   sum_D L^{aD}_{ij} g_Dbkc - sum_L L^{ab}_{iL} g_jLkc + local terms
       build_L3(ws, g, d, L + m0, omega + m0, nb, r, XLg, "LA", "LV", s);

@@ -54,9 +54,11 @@ def _fake(n):
 # I.Dims(17, 3, 18, 5, 7): more than 16 active occupied orbitals (generic occupied Gram blocks);
 # I.Dims(6, 9, 6, 140, 33): odd n_v^3 with N_V >= 96 (the wide back-contractions of the
 # reduced-precision forms read the contravariant blocks at element offsets that are not
-# multiples of 4)
+# multiples of 4); I.Dims(15, 150, 39, 263, 906): the guanine-shaped 15/150 active space (ordered-triple
+# buffers of 91 GB, element offsets far beyond 2^31)
 CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1), I.sweep_dims(5),
-                                                   I.Dims(17, 3, 18, 5, 7), I.Dims(6, 9, 6, 140, 33)]
+                                                   I.Dims(17, 3, 18, 5, 7), I.Dims(6, 9, 6, 140, 33),
+                                                   I.Dims(15, 150, 39, 263, 906)]
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x6"])
