@@ -105,7 +105,8 @@ def unit_flops(d, tb, te):
 # L with core-valence loop skipping.  Context only: real molecules, eT, precision not stated.
 PAPER_GUANINE = {(10, 100): {"right_transform": 1.72, "left_transform": 1.86, "ground_residual": 3.03,
                              "densities": 3.68 + 7.29},
-                 (13, 130): {"right_transform": 4.82, "left_transform": 5.27, "ground_residual": 10.72},
+                 (13, 130): {"right_transform": 4.82, "left_transform": 5.27, "ground_residual": 10.72,
+                             "densities": 14.76 + 29.97},
                  (15, 150): {"right_transform": 9.22, "left_transform": 9.83, "ground_residual": 24.93}}
 
 

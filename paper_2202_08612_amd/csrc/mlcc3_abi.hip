@@ -2411,7 +2411,7 @@ int mlcc3_triples_densities(mlcc3_ws ws, const mlcc3_ground *g, const double *t2
     double *lam2a = buf(ws, "lam2a", (size_t)no * no * d.nv2, s);   // lambda^{ab}_{ij}, [i][j][a][b]
     launch_pack_vvoo(lambda->x2_vVoo, no, nv, NV, 0, lam2a, s);
     double *XL = buf(ws, "XR", nbig, s);
-    double *XRt = buf(ws, "XRt", nbig, s);
+    double *XRt = buf(ws, "W", nbig, s);  // R~ of each state overwrites the W of its R3 (see wx_buffer)
     double *XRc = buf(ws, "XRc", nbig, s);
     double *tA = B(ws, "tA");
     double *V = buf(ws, "dens_V", (size_t)no * no * nv * NO, s);
