@@ -248,37 +248,3 @@ def test_wide_virtual_space_transforms(lib, ws, d):
     _check(lib.left_transform(ws, g, [0.45], [lib.vec_to_device(L)], reuse_ground=True)[0],
            orc.left_transform(0.45, L), TOL, "wide left")
 
-
-# ------------------------------------------------------------------ guanine-shaped 15/150
-def test_guanine_15_150_core_range(lib):
-    """The paper's 15/150 guanine active space (N_O=39, N_V=263, rank 906; ordered-triple buffers
-    of 91 GB, element offsets beyond 2^31) on three unique triples, (2,1,0) (2,1,1) (2,2,0):
-    ground residual, and right and left transform with core-valence separation (core orbital 0),
-    against the oracle.  Own workspace (about 195 GiB), released at the end."""
-    from oracle.oracle import Oracle
-    d = I.Dims(15, 150, 39, 263, 906)
-    rng = (3, 6)
-    assert _canon(15)[rng[0]:rng[1]] == [(2, 1, 0), (2, 1, 1), (2, 2, 0)]
-    p = I.make_problem(d, 20220217 + 200 + 15, core=True)
-    core = [1] + [0] * (d.N_O - 1)
-    w = float(I.omegas(True, 1)[0])
-    R, L = I.right_vectors(p, 1)[0], I.left_vectors(p, 1)[0]
-    ws15 = lib.Workspace(0)
-    try:
-        g = lib.Ground(p)
-        _say(f"guanine 15/150, triples {rng}")
-        om = lib.ground_residual(ws15, g, triple_range=rng)
-        rho = lib.right_transform(ws15, g, [w], [lib.vec_to_device(R)], triple_range=rng, reuse_ground=True,
-                                  cvs_core=core)[0]
-        sig = lib.left_transform(ws15, g, [w], [lib.vec_to_device(L)], triple_range=rng, reuse_ground=True,
-                                 cvs_core=core)[0]
-        got = [{k: _np(x[k]) for k in x} for x in (om, rho, sig)]
-        _say(f"  workspace {ws15.bytes() / 2**30:.1f} GiB")
-    finally:
-        ws15.close()
-    t0 = time.time()
-    _check(got[0], Oracle(p).ground_residual(*rng), TOL, "15/150 ground")
-    orc = Oracle(p, cvs_core=core)
-    _check(got[1], orc.right_transform(w, R, *rng), TOL, "15/150 right cvs")
-    _check(got[2], orc.left_transform(w, L, *rng), TOL, "15/150 left cvs")
-    _say(f"  oracle {time.time() - t0:.1f} s")
