@@ -107,7 +107,9 @@ PAPER_GUANINE = {(10, 100): {"right_transform": 1.72, "left_transform": 1.86, "g
                              "densities": 3.68 + 7.29},
                  (13, 130): {"right_transform": 4.82, "left_transform": 5.27, "ground_residual": 10.72,
                              "densities": 14.76 + 29.97},
-                 (15, 150): {"right_transform": 9.22, "left_transform": 9.83, "ground_residual": 24.93}}
+                 (15, 150): {"right_transform": 9.22, "left_transform": 9.83, "ground_residual": 24.93},
+                 (18, 180): {"right_transform": 20.90, "left_transform": 22.59, "ground_residual": 70.31},
+                 (20, 200): {"right_transform": 33.13, "left_transform": 36.58, "ground_residual": 125.74}}
 
 
 def paper_shapes(args):

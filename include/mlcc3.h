@@ -164,10 +164,17 @@ int mlcc3_ws_phase_stats(mlcc3_ws ws, int32_t phase, int64_t *launches, double *
  *   contra_form:  contravariant pass: 1 = one workgroup per 16^3 sub-cube, 2 = one per orbit
  *                 of sub-cubes under the virtual permutations (any n_v); the default takes the
  *                 orbit pass when 16 divides n_v or n_v > 64;
- *   vec_group:    cap on the vectors that share one launch in the right and left transforms.
+ *   vec_group:    cap on the vectors that share one launch in the right and left transforms;
+ *   occ_slab:     ground residual and right and left transforms in occupied slabs: the
+ *                 ordered-triple buffers hold the triples whose first index p lies in a slab
+ *                 of at most occ_slab values (the unique-triple blocks are accumulated slab by
+ *                 slab, the back-contractions take the slab's rows or sum over slabs); 0 = the
+ *                 whole occupied range in one slab when its buffers fit in the device memory,
+ *                 else the widest slab that fits (results agree with the one-slab call to
+ *                 rounding; the densities always use one slab).
  * mlcc3_ws_set_tuning(ws, NULL) restores the defaults; out-of-range values give MLCC3_EINVAL. */
 typedef struct {
-  int32_t dc_wg_per_cu, back_ksplit, narrow_tile, contra_form, vec_group;
+  int32_t dc_wg_per_cu, back_ksplit, narrow_tile, contra_form, vec_group, occ_slab;
 } mlcc3_tuning;
 int mlcc3_ws_set_tuning(mlcc3_ws ws, const mlcc3_tuning *t);
 int mlcc3_ws_get_tuning(mlcc3_ws ws, mlcc3_tuning *t);

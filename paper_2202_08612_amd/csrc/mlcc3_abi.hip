@@ -70,6 +70,9 @@ thread_local int t_prec = MLCC3_FP64;   // arithmetic of the d-contractions of t
 // the contravariant ordered-triple blocks (tau~, R~, L~) of the running call hold float elements
 // (the reduced-precision forms of the ground residual and the transforms; never in the densities)
 thread_local bool t_xf32 = false;
+// occupied slab of the running call: the ordered-triple buffers hold the triples with first
+// index t_p0 <= p < t_p0 + t_np at [p - t_p0][q][r]; t_np = 0: all of them (no slab)
+thread_local int t_p0 = 0, t_np = 0;
 // core-valence separation of the running call: on/off, active core orbitals as bits, device flags [N_O]
 thread_local int t_cvs = 0;
 thread_local unsigned long long t_cvs_bits = 0;
@@ -585,6 +588,9 @@ size_t xesz() { return t_xf32 ? sizeof(float) : sizeof(double); }
 // element pitch of the vectors of a group in the contravariant buffers: float blocks start on
 // 256-byte boundaries (the 16-byte loads of the split-bf16 staging need 16-byte aligned bases)
 long long xpitch(long long n) { return t_xf32 ? (n + 63) / 64 * 64 : n; }
+// first indices p held by the ordered-triple buffers, and the ordered triples they hold
+int snp(const Dims &d) { return t_np > 0 ? t_np : d.no; }
+long long sord(const Dims &d) { return (long long)snp(d) * d.no * d.no; }
 // the A operand of a segment reads the running call's contravariant blocks (float when t_xf32)
 void xa(Seg &sg) {
   if (!t_xf32) return;
@@ -960,20 +966,27 @@ TripleFilter triple_filter(const Dims &d, const Range &r, bool zero) {
   f.core = t_cvs ? t_cvs_bits : 0;
   f.tb = r.tb;
   f.te = r.te;
+  f.pq0 = t_p0 * d.no;
   return f;
 }
 
 // W_v[p][q][r][a][b][c] = sum_seg sum_D x_seg,v[(p,q,a)][D] G_seg,v[r][D][(b,c)] for the nb vectors
 // of a group (W_v at W + v*|W|), one persistent launch for the whole group; only the ordered
 // triples of the range r (and, under core-valence separation, with a core index) are formed
-void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, const Range &r, hipStream_t s) {
-  const long long Wv = d.nord * d.nv3;
+void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg0, int nseg, const Range &r, hipStream_t s) {
+  const long long Wv = sord(d) * d.nv3;
+  // rows (p,q,a) of the occupied slab: the x operands start at row t_p0 n_o n_v
+  DSeg seg[2];
+  for (int i = 0; i < nseg; i++) {
+    seg[i] = seg0[i];
+    seg[i].x += (long long)t_p0 * d.no * d.nv * d.NV;
+  }
   if (t_prec == MLCC3_BF16X3 || t_prec == MLCC3_BF16X6) {
     // split-bf16 products on bf16 planes of the operands (B planes transposed, K-contiguous)
     mlcc3_ws ws = t_ws;
     const int ns = t_prec == MLCC3_BF16X3 ? 2 : 3;
     BfGemm g;
-    g.M = d.no * d.no * d.nv;
+    g.M = snp(d) * d.no * d.nv;
     g.N = (int)d.nv2;
     g.nbatch = d.no;
     g.nvec = nb;
@@ -1029,7 +1042,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, const 
     // FP32 MFMA on rounded, zero-padded copies of the operands; W and all later steps stay FP64
     mlcc3_ws ws = t_ws;
     MixGemm g;
-    g.M = d.no * d.no * d.nv;
+    g.M = snp(d) * d.no * d.nv;
     g.N = (int)d.nv2;
     g.nbatch = d.no;
     g.nvec = nb;
@@ -1080,7 +1093,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg, int nseg, const 
     return;
   }
   TileGemm g;
-  g.M = d.no * d.no * d.nv;
+  g.M = snp(d) * d.no * d.nv;
   g.N = (int)d.nv2;
   g.nbatch = d.no;
   g.nvec = nb;
@@ -1127,12 +1140,14 @@ const double *occ_xT(mlcc3_ws ws, const Dims &d, const double *const *x, int nb,
 // symmetrise, divide and convert the W blocks of nb vectors (W_v at W + v*|W|) into X~_v at
 // Xt + v*pitch (pitch |W|, padded to 64 elements for float blocks; covariant X into Xc at
 // + v*|W|); one launch per pass for the whole group
+// passes: 3 both, 1 the symmetrisation only (W -> Xu, added into Xu for a later occupied slab),
+// 2 the contravariant pass only (Xu -> Xt for the slab)
 void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const double *eps_o, const double *eps_v,
              const double *omega, int nb, Range r, const LocalTerms &lt, const OccTerm &ot, hipStream_t s,
-             double *Xc = nullptr) {
+             double *Xc = nullptr, int passes = 3) {
   check(nb >= 1 && nb <= kMaxVecBatch, "vector group too large");
   // unique-triple blocks Xu[u][a][b][c] with rows of pitch occ_pitch(n_v) (whole 128-byte lines)
-  const long long Wv = d.nord * d.nv3, Xuv = (long long)ws->nu * d.nv2 * occ_pitch(d.nv);
+  const long long Wv = sord(d) * d.nv3, Xuv = (long long)ws->nu * d.nv2 * occ_pitch(d.nv);
   double *Xu = buf(ws, "Xu", (size_t)(Xuv * nb), s);
   VecBatch vb;
   vb.nvec = nb;
@@ -1142,11 +1157,18 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
   for (int v = 0; v < nb; v++) vb.omega[v] = omega[v];
   vb.cvs = t_cvs;
   vb.core_bits = t_cvs_bits;
-  check_bytes(W, sizeof(double) * Wv * nb, "W (permutation)");
-  check_bytes(Xt, xesz() * vb.xt * nb, "X~ (permutation)");
-  if (Xc) check_bytes(Xc, sizeof(double) * Wv * nb, "covariant X (permutation)");
-  launch_permute_denom(W, Xu, Xt, Xc, (const UniqueTriple *)B(ws, "utriples"), ws->nu, d.no, d.nv, eps_o, eps_v, vb,
-                       r.tb, r.te, lt, ot, tune().contra_form, s, t_xf32);
+  vb.p0 = t_p0;
+  vb.np = t_np;
+  const UniqueTriple *ut = (const UniqueTriple *)B(ws, "utriples");
+  if (passes & 1) {
+    check_bytes(W, sizeof(double) * Wv * nb, "W (permutation)");
+    launch_sym_denom(W, Xu, ut, ws->nu, d.no, d.nv, eps_o, eps_v, vb, r.tb, r.te, lt, ot, s);
+  }
+  if (passes & 2) {
+    check_bytes(Xt, xesz() * vb.xt * nb, "X~ (permutation)");
+    if (Xc) check_bytes(Xc, sizeof(double) * Wv * nb, "covariant X (permutation)");
+    launch_contra(Xu, Xt, Xc, ut, ws->nu, d.no, d.nv, vb, tune().contra_form, s, t_xf32);
+  }
   HIPRT(hipGetLastError());
 }
 
@@ -1189,9 +1211,11 @@ bool tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
 // writes one partial product per k into P[k][(i,j,a)][n] and a fixed-order sum reduces them.
 // X~ vanishes on the ordered triples outside the range r (and the all-valence ones under
 // core-valence separation): the wide GEMM writes zero partial tiles there without computing.
-void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N, double *Y, const Range &r,
+void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N, double *Y0, const Range &r,
              hipStream_t s) {
-  const long long MN = (long long)d.no * d.no * d.nv * N;
+  // rows (i,j,a) of the occupied slab
+  const long long MN = (long long)snp(d) * d.no * d.nv * N;
+  double *Y = Y0 + (long long)t_p0 * d.no * d.nv * N;
   double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
   const Idx2 xrow = split(d.nv, (long long)d.no * d.nv3, d.nv2);
   if (N >= 96 && (t_prec == MLCC3_BF16X3 || t_prec == MLCC3_BF16X6)) {
@@ -1200,7 +1224,7 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     // all column tiles, the triples block (B, FP64, split into planes while it is staged) is read
     // by ceil(N / 128) row tiles; FP32 sums over 64-deep K steps, FP64 across steps
     const int ns = t_prec == MLCC3_BF16X3 ? 2 : 3;
-    const int M2 = d.no * d.no * d.nv;
+    const int M2 = snp(d) * d.no * d.nv;
     const int Kp = ((int)d.nv2 + BF_BK - 1) / BF_BK * BF_BK, Mp = (N + BF_BM - 1) / BF_BM * BF_BM;
     const long long pa = (long long)d.no * Mp * Kp;  // one plane
     uint16_t *Am = (uint16_t *)buf(ws, "bk_A", (size_t)(pa * ns + 3) / 4, s);
@@ -1237,7 +1261,7 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     return;
   } else if (N >= 96) {
     TileGemm g;
-    g.M = d.no * d.no * d.nv;
+    g.M = snp(d) * d.no * d.nv;
     g.N = N;
     g.nbatch = d.no;
     g.C = P;
@@ -1251,7 +1275,7 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
   } else {
     // narrow N (N_O): the generic GEMM picks 32-wide tiles
     Gemm g;
-    g.M = d.no * d.no * d.nv;
+    g.M = snp(d) * d.no * d.nv;
     g.N = N;
     g.nbatch = d.no;
     g.C = P;
@@ -1291,8 +1315,8 @@ Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2
   Gemm g;
   g.M = (int)d.nv2;
   g.N = d.NO;
-  g.nbatch = d.no;
-  g.C = Y;
+  g.nbatch = snp(d);  // batches i of the occupied slab
+  g.C = Y + (long long)t_p0 * d.nv2 * d.NO;
   g.crow = plain(d.NO);
   g.ccol = plain(1);
   g.cbatch = d.nv2 * d.NO;
@@ -1312,24 +1336,28 @@ Gemm back_vO(const Dims &d, const double *X1, BMap G1, const double *X2, BMap G2
 // G stored [j][k][c][L]
 BMap bm_jkcL(const Dims &d, const double *G) { return {G, plain(d.NO), plain(1), 0}; }
 
-// Y[(q,r,c)][M] = sum_{p,(a,b)} X~[p][q][r][a][b][c] x[a][b][p][M], split over p
-void back_qrc(mlcc3_ws ws, const Dims &d, const double *X, const double *x, double *Y, hipStream_t s) {
+// Y[(q,r,c)][M] = sum_{p,(a,b)} X~[p][q][r][a][b][c] x[a][b][p][M], split over p: the partial
+// products P[p] of the occupied slab's p go to buffer pname, and (sum) the fixed-order sum over
+// all p is written to Y (an occupied-slab caller sums once after the last slab)
+void back_qrc(mlcc3_ws ws, const Dims &d, const double *X, const double *x, double *Y, hipStream_t s,
+              const char *pname = "split_part", bool sum = true) {
   const long long MN = (long long)d.no * d.no * d.nv * d.NO;
-  double *P = buf(ws, "split_part", (size_t)(MN * d.no), s);
+  double *P = buf(ws, pname, (size_t)(MN * d.no), s);
   Gemm g;
   g.M = d.no * d.no * d.nv;
   g.N = d.NO;
-  g.nbatch = d.no;
-  g.C = P;
+  g.nbatch = snp(d);
+  g.C = P + t_p0 * MN;
   g.crow = plain(d.NO);
   g.ccol = plain(1);
   g.cbatch = MN;
   g.nseg = 1;
-  g.seg[0] = seg(X, split(d.nv, d.nv3, 1), plain(d.nv), (long long)d.no * d.no * d.nv3, x,
+  g.seg[0] = seg(X, split(d.nv, d.nv3, 1), plain(d.nv), (long long)d.no * d.no * d.nv3, x + (long long)t_p0 * d.NO,
                  plain((long long)d.no * d.NO), plain(1), d.NO, (int)d.nv2);
   xa(g.seg[0]);
   narrow_tile(g);
   gemm(g, s);
+  if (!sum) return;
   launch_sum_rows(P, d.no, MN, Y, s);
   HIPRT(hipGetLastError());
 }
@@ -1531,9 +1559,9 @@ void right_vector_prep(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const 
 // R3 of the nb prepared right vectors of a group (slots 0..nb-1 of the prep buffers):
 // contravariant into the vector pitch of Xt (see permute), covariant into Xc (optional)
 void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *R, const double *omega, int nb,
-              Range r, double *Xt, double *Xc, hipStream_t s) {
+              Range r, double *Xt, double *Xc, hipStream_t s, int passes = 3) {
   const RightSizes z = right_sizes(d);
-  double *W = buf(ws, "W", (size_t)(d.nord * d.nv3 * nb), s);
+  double *W = buf(ws, "W", (size_t)(sord(d) * d.nv3 * nb), s);
   DSeg sg[2];
   sg[0].x = B(ws, "RA");
   sg[0].xv = z.RA;
@@ -1550,13 +1578,13 @@ void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   occ_add(ot, d, RBxT, xv, B(ws, "G2"), 0, nb);
   occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "Uo"), z.Uo, nb);
   (void)R;
-  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, LocalTerms{}, ot, s, Xc);
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, LocalTerms{}, ot, s, Xc, passes);
 }
 
 // L3 (transpose-transformation recipe) of nb left-type vectors into Xt (vector pitch as in permute); packs
 // LA/LV (stacked, under the given names) and the singles copy "L1s"
 void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec *L, const double *omega, int nb,
-              Range r, double *Xt, const char *laname, const char *lvname, hipStream_t s) {
+              Range r, double *Xt, const char *laname, const char *lvname, hipStream_t s, int passes = 3) {
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
   const long long sLA = (long long)no * no * nv * NV, sLV = (long long)no * no * d.nv2, sL1 = (long long)NV * NO;
   double *LA = buf(ws, laname, (size_t)(sLA * nb), s);
@@ -1570,7 +1598,7 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
       HIPRT(hipMemcpyAsync(L1 + v * sL1, L[v].x1, sizeof(double) * sL1, hipMemcpyDeviceToDevice, s));
     lb[v] = L[v].x2_vvoO;
   }
-  double *W = buf(ws, "W", (size_t)(d.nord * d.nv3 * nb), s);
+  double *W = buf(ws, "W", (size_t)(sord(d) * d.nv3 * nb), s);
   DSeg sg;
   sg.x = LA;
   sg.xv = sLA;
@@ -1584,7 +1612,7 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   lt.L1 = L1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
   lt.L1v = sL1;
   lt.LVv = sLV;
-  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, lt, ot, s);
+  permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, lt, ot, s, nullptr, passes);
 }
 
 // core-valence separation of a right or left transform: device copy of the core flags, active
@@ -1651,6 +1679,215 @@ int group_size(mlcc3_ws ws, const Dims &d, int nvec) {
   const int fit = (int)std::max(1.0, std::floor(0.45 * (double)total / per));
   (void)ws;
   return std::max(1, std::min({nvec, cap, fit}));
+}
+
+// ------------------------------------------------------ occupied slabs
+// For shapes whose ordered-triple buffers do not fit in the device memory, the ground residual
+// and the transforms run in occupied slabs: the buffers hold only the ordered triples whose
+// first index p lies in the slab ([p - p0][q][r]).  Every ordering of a unique triple
+// contributes to its symmetrised block Xu on its own, so Xu is accumulated over one pass of
+// slabs (d-contraction and symmetrisation of the slab's W); a second pass of slabs forms the
+// slab's contravariant blocks from Xu, and each back-contraction either has p among its output
+// rows (the slab's rows) or sums over p (partial products per p, summed once at the end, or a
+// GEMM that adds into its output).  A transform holds W, one contravariant slab and Xu.
+
+// first indices per occupied slab: the tuning's cap, else all of them (0: one slab) when W,
+// the contravariant blocks and Xu fit in 80% of the device memory, else the widest slab that fits
+int slab_width(mlcc3_ws ws, const Dims &d) {
+  if (ws->arena) return 0;
+  const int cap = tune().occ_slab;
+  if (cap > 0) return cap >= d.no ? 0 : cap;
+  size_t total = (size_t)256 << 30;
+  if (!g_dry) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0) total = tot;
+  }
+  const double xu = (double)ws->nu * d.nv2 * occ_pitch(d.nv) * sizeof(double);
+  const double per_p = 2.0 * sizeof(double) * (double)d.no * d.no * d.nv3;
+  const double budget = 0.8 * (double)total - xu - 4.0 * (double)(1 << 30);
+  const double fit = std::floor(budget / per_p);
+  if (fit >= d.no) return 0;
+  check(fit >= 1.0, "the unique-triple blocks leave no room for an occupied slab of one index");
+  return (int)fit;
+}
+
+struct SlabScope {  // sets the occupied slab of the running call, restores "no slab" at exit
+  SlabScope(int p0, int np) {
+    t_p0 = p0;
+    t_np = np;
+  }
+  ~SlabScope() {
+    t_p0 = 0;
+    t_np = 0;
+  }
+};
+
+// the slab's contravariant blocks from Xu, into "XS"
+double *contra_slab(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, hipStream_t s) {
+  double *X = buf(ws, "XS", xcount(xpitch(sord(d) * d.nv3)), s);
+  const double zero = 0.0;
+  permute(ws, d, nullptr, X, g->eps_o, g->eps_v, &zero, 1, r, LocalTerms{}, OccTerm{}, s, nullptr, 2);
+  return X;
+}
+
+// Xu of tau3, accumulated over the slabs of width w
+void tau_xu_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, int w, hipStream_t s) {
+  for (int p0 = 0; p0 < d.no; p0 += w) {
+    SlabScope sc(p0, std::min(w, d.no - p0));
+    double *W = buf(ws, "W", (size_t)(sord(d) * d.nv3), s);
+    DSeg sg;
+    sg.x = B(ws, "tA");
+    sg.G = B(ws, "G1");
+    w_dterm(d, W, 1, &sg, 1, r, s);
+    OccTerm ot;
+    occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1);
+    const double zero = 0.0;
+    permute(ws, d, W, nullptr, g->eps_o, g->eps_v, &zero, 1, r, LocalTerms{}, ot, s, nullptr, 1);
+  }
+}
+
+void ground_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, int w, const mlcc3_out *out,
+                  hipStream_t s) {
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+  tau_xu_slabs(ws, g, d, r, w, s);
+  log_phase("tau3");
+  double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+  double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+  double *part1 = buf(ws, "part1", (size_t)no * no * nv, s);
+  double *Yvv = buf(ws, "Yvv", (size_t)no * no * d.nv2, s);
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    double *XT = contra_slab(ws, g, d, r, s);
+    back_vV(ws, d, XT, B(ws, "Gb1"), NV, YvV, r, s);
+    gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
+    launch_small_right(XT, nullptr, B(ws, "gov"), B(ws, "F"), nullptr, no, nv, part1, Yvv, s, t_xf32, t_p0, t_np);
+  }
+  log_phase("back");
+  launch_singles_out(part1, no, nv, NO, NV, out->x1, s);
+  DoublesRaw y;
+  y.YvV = YvV; y.YvO = YvO; y.Yvv = Yvv;
+  y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
+  launch_doubles_out(y, out->x2_vVoo, out->x2_vvoO, s);
+  HIPRT(hipGetLastError());
+  log_phase("out");
+}
+
+// right transform of one vector (slot 0 of the prepared-vector buffers) in slabs of width w
+void right_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &R, double omega, const Range &r,
+                 int w, const mlcc3_out &rho, hipStream_t s) {
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+  group_dlhat(ws, g, d, &R, 1, s);
+  right_vector_prep(ws, g, d, R, 0, 1, s);
+  double *Ukc = B(ws, "Ukc"), *Xi = B(ws, "Xi");
+  double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+  double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+  double *part1 = buf(ws, "part1", (size_t)no * no * nv, s);
+  double *spare = buf(ws, "part1_tau", (size_t)no * no * nv, s);  // the tau~ pass's unused part1
+  double *Yvv = buf(ws, "Yvv", (size_t)no * no * d.nv2, s);
+  double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
+  // tau~ pass: Xtau = sum tau~ g_Lbkc; YvO = -sum tau~ Xi; Yvv = sum tau~ Upsilon_kc
+  tau_xu_slabs(ws, g, d, r, w, s);
+  log_phase("tau3");
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    double *XT = contra_slab(ws, g, d, r, s);
+    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
+    gemm(back_vO(d, XT, bm_jkcL(d, Xi), nullptr, BMap{}, YvO, -1.0), s);
+    launch_small_right(XT, nullptr, B(ws, "gov"), Ukc, nullptr, no, nv, spare, Yvv, s, t_xf32, t_p0, t_np);
+  }
+  // R~ pass
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    build_R3(ws, g, d, &R, &omega, 1, r, nullptr, nullptr, s, 1);
+  }
+  log_phase("R3");
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    double *XR = contra_slab(ws, g, d, r, s);
+    back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, r, s);
+    Gemm bo = back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0);
+    bo.beta = 1.0;
+    gemm(bo, s);
+    launch_small_right(XR, nullptr, B(ws, "gov"), B(ws, "F"), nullptr, no, nv, part1, Yvv, s, t_xf32, t_p0, t_np,
+                       true);
+  }
+  log_phase("back");
+  {  // Y^{aD}_{ij} -= sum_L Xtau[(i,j,a)][L] R^D_L
+    Gemm gg;
+    gg.M = no * no * nv;
+    gg.N = NV;
+    gg.C = YvV;
+    gg.crow = plain(NV);
+    gg.ccol = plain(1);
+    gg.alpha = -1.0;
+    gg.beta = 1.0;
+    gg.nseg = 1;
+    gg.seg[0] = seg(Xtau, plain(NO), plain(1), 0, R.x1, plain(1), plain(NO), 0, NO);
+    gemm(gg, s);
+  }
+  launch_singles_out(part1, no, nv, NO, NV, rho.x1, s);
+  DoublesRaw y;
+  y.YvV = YvV; y.YvO = YvO; y.Yvv = Yvv;
+  y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 1;
+  launch_doubles_out(y, rho.x2_vVoo, rho.x2_vvoO, s);
+  HIPRT(hipGetLastError());
+  log_phase("out");
+}
+
+// the triples contractions of the left transform of one vector in slabs of width w: QvV
+// ("YvV"), QvO ("YvO"), Bq, Aq, Qtau and Xtau as the one-slab path forms them
+void left_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec &L, double omega, const Range &r,
+                int w, hipStream_t s) {
+  const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+  double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
+  double *QvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
+  double *QvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
+  double *Bq = buf(ws, "Bq", (size_t)no * d.nv2 * NV, s);
+  double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);
+  double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);
+  // tau~ pass: Xtau, and the partial products of Qtau per p
+  tau_xu_slabs(ws, g, d, r, w, s);
+  log_phase("tau3");
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    double *XT = contra_slab(ws, g, d, r, s);
+    back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
+    back_qrc(ws, d, XT, L.x2_vvoO, Qtau, s, "qrc_tau", false);
+  }
+  // L~ pass
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    build_L3(ws, g, d, &L, &omega, 1, r, nullptr, "LA", "LV", s, 1);
+  }
+  log_phase("L3");
+  for (int p0 = 0; p0 < no; p0 += w) {
+    SlabScope sc(p0, std::min(w, no - p0));
+    double *XL = contra_slab(ws, g, d, r, s);
+    back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, r, s);
+    gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0), s);
+    // Bq[r][(b,c)][E] += sum_{(p,q,a) of the slab} L~[p][q][r][a][b][c] t^{aE}_{pq}
+    TileGemm gg;
+    gg.M = (int)d.nv2;
+    gg.N = NV;
+    gg.nbatch = no;
+    gg.ak = 0;
+    gg.C = Bq;
+    gg.cmap = plain(NV);
+    gg.cbatch = d.nv2 * NV;
+    gg.beta = p0 > 0 ? 1.0 : 0.0;
+    gg.nseg = 1;
+    gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA") + (long long)p0 * no * nv * NV,
+                     NV, 0, snp(d) * no * nv);
+    xa(gg.seg[0]);
+    tgemm(gg, s, true);
+    back_qrc(ws, d, XL, g->t2_vvoO, Aq, s, "qrc_l", false);
+  }
+  log_phase("back");
+  // the fixed-order sums over p of the partial products
+  const long long MN = (long long)no * no * nv * NO;
+  launch_sum_rows(B(ws, "qrc_l"), no, MN, Aq, s);
+  launch_sum_rows(B(ws, "qrc_tau"), no, MN, Qtau, s);
+  HIPRT(hipGetLastError());
 }
 
 // ------------------------------------------------------ density contractions
@@ -1847,6 +2084,7 @@ int mlcc3_ws_set_tuning(mlcc3_ws ws, const mlcc3_tuning *t) {
     check(t->narrow_tile == 0 || (t->narrow_tile < 100 && ok(tm) && ok(tn)), "narrow_tile must be 10*TM+TN, TM,TN in {1,2,4}");
     check(t->contra_form >= 0 && t->contra_form <= 2, "contra_form out of range");
     check(t->vec_group >= 0, "vec_group < 0");
+    check(t->occ_slab >= 0, "occ_slab < 0");
     ws->tune = *t;
   });
 }
@@ -1962,6 +2200,11 @@ void ground_residual_call(mlcc3_ws ws, const mlcc3_ground *g, const mlcc3_opts *
   }
   prepare_ground(ws, g, o.reuse_ground != 0, s);
   log_phase("prep");
+  if (const int slab = slab_width(ws, d)) {  // occupied slabs
+    ws->tau = mlcc3_ws_s::TauKey{};
+    ground_slabs(ws, g, d, r, slab, out, s);
+    return;
+  }
   tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
   log_phase("tau3");
   double *XT = B(ws, "XT");
@@ -2093,6 +2336,14 @@ int mlcc3_right_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, cons
     prepare_ground(ws, g, o.reuse_ground != 0, s);
     log_phase("prep");
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
+    if (const int slab = slab_width(ws, d)) {  // occupied slabs, vector by vector
+      ws->tau = mlcc3_ws_s::TauKey{};
+      for (int m = 0; m < nvec; m++) {
+        right_slabs(ws, g, d, R[m], omega[m], r, slab, rho[m], s);
+        cvs_project_out(d, rho[m], s);
+      }
+      return;
+    }
     // tau~ and Xtau[(i,j,a)][L] = sum tau~ g_Lbkc (shared by all vectors)
     const bool tau_kept = tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
     log_phase("tau3");
@@ -2177,12 +2428,135 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
     prepare_ground(ws, g, o.reuse_ground != 0, s);
     log_phase("prep");
     const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV, nc = d.nc;
+    double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
+    const double *gLE = gle_block(ws, g, d, s);
+    // the singles of sigma and the output gather, from the triples contractions of vector m:
+    // QvV, QvO (doubles), Bq, Aq, Qtau, Xtau
+    auto assemble = [&](int m, const double *LA, double *QvV, double *QvO, double *Bq, double *Aq, double *Qtau,
+                        const double *Xtau) {
+      double *V = buf(ws, "Vkc", (size_t)no * nv, s);  // V_kc = sum tau~ L^{ab}_{ij} = sum_q Qtau[q][k][c][q]
+      launch_diag_sum(Qtau, no, nv, NO, V, s);
+      HIPRT(hipGetLastError());
+      double *s1 = sigma[m].x1;
+      HIPRT(hipMemsetAsync(s1, 0, sizeof(double) * NV * NO, s));
+      // (i) sigma^D_L += sum_kc V_kc (2 g_kcLD - g_kDLc) = sum_J [2 s_J L_LD - sum_k L_kD u_J[k][L]]
+      {
+        double *sJ = buf(ws, "vs_J", (size_t)nc, s);
+        double *uJ = buf(ws, "vu_J", (size_t)nc * no * NO, s);
+        // s_J = sum_kc V_kc L^J_kc  (A: [J][(k,c)] from L_OV)
+        Gemm g1 = gemm_plain(nc, 1, sJ, plain(1), plain(1), 1.0, 0.0);
+        g1.nseg = 1;
+        g1.seg[0] = seg(g->L_OV, plain((long long)NO * NV), split(nv, NV, 1), 0, V, plain(1), plain(1), 0, no * nv);
+        gemm(g1, s);
+        // u_J[k][L] = sum_c L_OV[J][L][c] V[k][c]   (rows (J,L))
+        Gemm g3 = gemm_plain(nc * NO, no, uJ, split(NO, (long long)no * NO, 1), plain(NO), 1.0, 0.0);
+        g3.nseg = 1;
+        g3.seg[0] = seg(g->L_OV, plain(NV), plain(1), 0, V, plain(1), plain(nv), 0, nv);
+        gemm(g3, s);
+        // sigma[D][L] += 2 sum_J L_OV[J][L][D] s_J   (rows (L,D))
+        Gemm g4 = gemm_plain(NO * NV, 1, s1, split(NV, 1, NO), plain(0), 2.0, 1.0);
+        g4.nseg = 1;
+        g4.seg[0] = seg(g->L_OV, plain(1), plain((long long)NO * NV), 0, sJ, plain(1), plain(1), 0, nc);
+        gemm(g4, s);
+        // sigma[D][L] -= sum_{(J,k)} L_OV[J][k][D] u_J[k][L]
+        Gemm g5 = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
+        g5.nseg = 1;
+        g5.seg[0] = seg(g->L_OV, plain(1), split(no, (long long)NO * NV, NV), 0, uJ, plain(NO), plain(1), 0, nc * no);
+        gemm(g5, s);
+      }
+      // (ii) sigma^D_L -= sum L^{aD}_{ij} Xtau[(i,j,a)][L] ; (iii) -= sum g_jDkc Qtau[(j,k,c)][L]
+      {
+        Gemm gg = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
+        gg.nseg = 2;
+        gg.seg[0] = seg(LA, plain(1), plain(NV), 0, Xtau, plain(NO), plain(1), 0, no * no * nv);
+        gg.seg[1] = seg(B(ws, "gDo"), plain(1), plain(NV), 0, Qtau, plain(NO), plain(1), 0, no * no * nv);
+        gemm(gg, s);
+      }
+      // (iv) sigma^D_l += sum_{J,c} Lh_cD (Hp - H2)[l][J][c] - sum_{J,M} L_MD H3[l][J][M]
+      double *Hp = buf(ws, "Hp", (size_t)no * nc * nv, s);
+      double *H2 = buf(ws, "H2", (size_t)no * nc * nv, s);
+      double *H3 = buf(ws, "H3", (size_t)no * nc * NO, s);
+      {
+        // Hp[l][J][c] = sum_{(b,E)} Lh_bE Bq[l][b][c][E]
+        Gemm gg = gemm_plain(nc, nv, Hp, plain(nv), plain(1), 1.0, 0.0);
+        gg.nbatch = no;
+        gg.cbatch = (long long)nc * nv;
+        gg.nseg = 1;
+        gg.seg[0] = seg(LhvV, plain((long long)nv * NV), plain(1), 0, Bq, split(NV, (long long)nv * NV, 1), plain(NV),
+                        d.nv2 * NV, nv * NV);
+        gemm(gg, s);
+        // H2[l][J][c] = sum_{(j,M)} Lh_Mj Aq[j][l][c][M]
+        Gemm g2 = gemm_plain(nc, nv, H2, plain(nv), plain(1), 1.0, 0.0);
+        g2.nbatch = no;
+        g2.cbatch = (long long)nc * nv;
+        g2.nseg = 1;
+        g2.seg[0] = seg(LhOO, plain((long long)NO * NO), split(NO, 1, NO), 0, Aq,
+                        split(NO, (long long)no * nv * NO, 1), plain(NO), (long long)nv * NO, no * NO);
+        gemm(g2, s);
+        // H3[l][J][M] = sum_{(k,c)} Lh_ck Aq[l][k][c][M]
+        Gemm g3 = gemm_plain(nc, NO, H3, plain(NO), plain(1), 1.0, 0.0);
+        g3.nbatch = no;
+        g3.cbatch = (long long)nc * NO;
+        g3.nseg = 1;
+        g3.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Aq, plain(NO), plain(1),
+                        (long long)no * nv * NO, no * nv);
+        gemm(g3, s);
+        // sigma[D][l] += sum Lh_cD (Hp - H2)
+        Gemm g4 = gemm_plain(NV, no, s1, plain(NO), plain(1), 1.0, 1.0);
+        g4.nseg = 2;
+        g4.seg[0] = seg(LhvV, plain(1), plain(NV), 0, Hp, plain(1), plain((long long)nc * nv), 0, nc * nv);
+        g4.seg[1] = seg(LhvV, plain(1), plain(NV), 0, H2, plain(1), plain((long long)nc * nv), 0, nc * nv, -1.0);
+        gemm(g4, s);
+        // sigma[D][l] -= sum L_MD H3
+        Gemm g5 = gemm_plain(NV, no, s1, plain(NO), plain(1), -1.0, 1.0);
+        g5.nseg = 1;
+        g5.seg[0] = seg(g->L_OV, plain(1), plain(NV), 0, H3, plain(1), plain((long long)nc * NO), 0, nc * NO);
+        gemm(g5, s);
+      }
+      // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE sum_{(k,c)} Lh_ck Bq[k][d][c][E];
+      //     the second term is taken as sum_{(k,c,E)} Bq[k][d][c][E] ghat_ckLE (gLE, formed once
+      //     per ground state) instead of through the rank x n_v N_V intermediate
+      {
+        double *Am = buf(ws, "Am", (size_t)no * nc * no * nv, s);
+        double *Z = buf(ws, "Zl", (size_t)nc * no * nv, s);
+        // Am[j][J][(k,d)] = sum_M Lh_Mj Aq[j][k][d][M]
+        Gemm g1 = gemm_plain(nc, no * nv, Am, plain((long long)no * nv), plain(1), 1.0, 0.0);
+        g1.nbatch = no;
+        g1.cbatch = (long long)nc * no * nv;
+        g1.nseg = 1;
+        g1.seg[0] = seg(LhOO, plain((long long)NO * NO), plain(NO), 1, Aq, plain(1), plain(NO),
+                        (long long)no * nv * NO, NO);
+        gemm(g1, s);
+        launch_left_Z(Am, Hp, nc, no, nv, Z, s);
+        HIPRT(hipGetLastError());
+        // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(k,c,E)} Bq[k][d][c][E] gLE[k][c][L][E]
+        Gemm g3 = gemm_plain(nv, NO, s1, plain(NO), plain(1), 1.0, 1.0);
+        g3.nseg = 2;
+        g3.seg[0] = seg(Z, plain(1), plain(nv), 0, LhOO, split(no, (long long)NO * NO, 1), plain(NO), 0, nc * no);
+        g3.seg[1] = seg(Bq, plain((long long)nv * NV), split(nv * NV, d.nv2 * NV, 1), 0, gLE,
+                        split(NV, (long long)NO * NV, 1), plain(NV), 0, no * nv * NV, -1.0);
+        gemm(g3, s);
+      }
+      DoublesRaw y;
+      y.YvV = QvV; y.YvO = QvO; y.Yvv = nullptr;
+      y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
+      launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
+      HIPRT(hipGetLastError());
+      cvs_project_out(d, sigma[m], s);
+    };
+    const int slab = slab_width(ws, d);
+    if (slab > 0) {  // occupied slabs, vector by vector
+      ws->tau = mlcc3_ws_s::TauKey{};
+      for (int m = 0; m < nvec; m++) {
+        left_slabs(ws, g, d, L[m], omega[m], r, slab, s);
+        assemble(m, B(ws, "LA"), B(ws, "YvV"), B(ws, "YvO"), B(ws, "Bq"), B(ws, "Aq"), B(ws, "Qtau"), B(ws, "Xtau"));
+      }
+      return;
+    }
     const bool tau_kept = tau_path(ws, g, d, r, s, nullptr, o.reuse_tau != 0);
     log_phase("tau3");
     double *XT = B(ws, "XT");
     double *Xtau = xtau_block(ws, d, XT, tau_kept, r, s);
-    double *LhOO = B(ws, "LhOO"), *LhvV = B(ws, "LhvV"), *LhvO = B(ws, "LhvO");
-    const double *gLE = gle_block(ws, g, d, s);
     // vectors in groups: L3 of a whole group in one d-contraction launch and one launch per
     // permutation pass, then the back-contractions vector by vector
     const int ng = group_size(ws, d, nvec);
@@ -2228,115 +2602,7 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
         double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);
         back_qrc(ws, d, XL, g->t2_vvoO, Aq, s);
         back_qrc(ws, d, XT, L2b, Qtau, s);
-        double *V = buf(ws, "Vkc", (size_t)no * nv, s);  // V_kc = sum tau~ L^{ab}_{ij} = sum_q Qtau[q][k][c][q]
-        launch_diag_sum(Qtau, no, nv, NO, V, s);
-        HIPRT(hipGetLastError());
-        double *s1 = sigma[m].x1;
-        HIPRT(hipMemsetAsync(s1, 0, sizeof(double) * NV * NO, s));
-        // (i) sigma^D_L += sum_kc V_kc (2 g_kcLD - g_kDLc) = sum_J [2 s_J L_LD - sum_k L_kD u_J[k][L]]
-        {
-          double *sJ = buf(ws, "vs_J", (size_t)nc, s);
-          double *uJ = buf(ws, "vu_J", (size_t)nc * no * NO, s);
-          // s_J = sum_kc V_kc L^J_kc  (A: [J][(k,c)] from L_OV)
-          Gemm g1 = gemm_plain(nc, 1, sJ, plain(1), plain(1), 1.0, 0.0);
-          g1.nseg = 1;
-          g1.seg[0] = seg(g->L_OV, plain((long long)NO * NV), split(nv, NV, 1), 0, V, plain(1), plain(1), 0, no * nv);
-          gemm(g1, s);
-          // u_J[k][L] = sum_c L_OV[J][L][c] V[k][c]   (rows (J,L))
-          Gemm g3 = gemm_plain(nc * NO, no, uJ, split(NO, (long long)no * NO, 1), plain(NO), 1.0, 0.0);
-          g3.nseg = 1;
-          g3.seg[0] = seg(g->L_OV, plain(NV), plain(1), 0, V, plain(1), plain(nv), 0, nv);
-          gemm(g3, s);
-          // sigma[D][L] += 2 sum_J L_OV[J][L][D] s_J   (rows (L,D))
-          Gemm g4 = gemm_plain(NO * NV, 1, s1, split(NV, 1, NO), plain(0), 2.0, 1.0);
-          g4.nseg = 1;
-          g4.seg[0] = seg(g->L_OV, plain(1), plain((long long)NO * NV), 0, sJ, plain(1), plain(1), 0, nc);
-          gemm(g4, s);
-          // sigma[D][L] -= sum_{(J,k)} L_OV[J][k][D] u_J[k][L]
-          Gemm g5 = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
-          g5.nseg = 1;
-          g5.seg[0] = seg(g->L_OV, plain(1), split(no, (long long)NO * NV, NV), 0, uJ, plain(NO), plain(1), 0, nc * no);
-          gemm(g5, s);
-        }
-        // (ii) sigma^D_L -= sum L^{aD}_{ij} Xtau[(i,j,a)][L] ; (iii) -= sum g_jDkc Qtau[(j,k,c)][L]
-        {
-          Gemm gg = gemm_plain(NV, NO, s1, plain(NO), plain(1), -1.0, 1.0);
-          gg.nseg = 2;
-          gg.seg[0] = seg(LA, plain(1), plain(NV), 0, Xtau, plain(NO), plain(1), 0, no * no * nv);
-          gg.seg[1] = seg(B(ws, "gDo"), plain(1), plain(NV), 0, Qtau, plain(NO), plain(1), 0, no * no * nv);
-          gemm(gg, s);
-        }
-        // (iv) sigma^D_l += sum_{J,c} Lh_cD (Hp - H2)[l][J][c] - sum_{J,M} L_MD H3[l][J][M]
-        double *Hp = buf(ws, "Hp", (size_t)no * nc * nv, s);
-        double *H2 = buf(ws, "H2", (size_t)no * nc * nv, s);
-        double *H3 = buf(ws, "H3", (size_t)no * nc * NO, s);
-        {
-          // Hp[l][J][c] = sum_{(b,E)} Lh_bE Bq[l][b][c][E]
-          Gemm gg = gemm_plain(nc, nv, Hp, plain(nv), plain(1), 1.0, 0.0);
-          gg.nbatch = no;
-          gg.cbatch = (long long)nc * nv;
-          gg.nseg = 1;
-          gg.seg[0] = seg(LhvV, plain((long long)nv * NV), plain(1), 0, Bq, split(NV, (long long)nv * NV, 1), plain(NV),
-                          d.nv2 * NV, nv * NV);
-          gemm(gg, s);
-          // H2[l][J][c] = sum_{(j,M)} Lh_Mj Aq[j][l][c][M]
-          Gemm g2 = gemm_plain(nc, nv, H2, plain(nv), plain(1), 1.0, 0.0);
-          g2.nbatch = no;
-          g2.cbatch = (long long)nc * nv;
-          g2.nseg = 1;
-          g2.seg[0] = seg(LhOO, plain((long long)NO * NO), split(NO, 1, NO), 0, Aq,
-                          split(NO, (long long)no * nv * NO, 1), plain(NO), (long long)nv * NO, no * NO);
-          gemm(g2, s);
-          // H3[l][J][M] = sum_{(k,c)} Lh_ck Aq[l][k][c][M]
-          Gemm g3 = gemm_plain(nc, NO, H3, plain(NO), plain(1), 1.0, 0.0);
-          g3.nbatch = no;
-          g3.cbatch = (long long)nc * NO;
-          g3.nseg = 1;
-          g3.seg[0] = seg(LhvO, plain((long long)nv * NO), split(nv, 1, NO), 0, Aq, plain(NO), plain(1),
-                          (long long)no * nv * NO, no * nv);
-          gemm(g3, s);
-          // sigma[D][l] += sum Lh_cD (Hp - H2)
-          Gemm g4 = gemm_plain(NV, no, s1, plain(NO), plain(1), 1.0, 1.0);
-          g4.nseg = 2;
-          g4.seg[0] = seg(LhvV, plain(1), plain(NV), 0, Hp, plain(1), plain((long long)nc * nv), 0, nc * nv);
-          g4.seg[1] = seg(LhvV, plain(1), plain(NV), 0, H2, plain(1), plain((long long)nc * nv), 0, nc * nv, -1.0);
-          gemm(g4, s);
-          // sigma[D][l] -= sum L_MD H3
-          Gemm g5 = gemm_plain(NV, no, s1, plain(NO), plain(1), -1.0, 1.0);
-          g5.nseg = 1;
-          g5.seg[0] = seg(g->L_OV, plain(1), plain(NV), 0, H3, plain(1), plain((long long)nc * NO), 0, nc * NO);
-          gemm(g5, s);
-        }
-        // (v) sigma^d_L += sum_{J,k} Lh_Lk Z[J][k][d] - sum_{J,E} L_LE sum_{(k,c)} Lh_ck Bq[k][d][c][E];
-        //     the second term is taken as sum_{(k,c,E)} Bq[k][d][c][E] ghat_ckLE (gLE, formed once
-        //     per ground state) instead of through the rank x n_v N_V intermediate
-        {
-          double *Am = buf(ws, "Am", (size_t)no * nc * no * nv, s);
-          double *Z = buf(ws, "Zl", (size_t)nc * no * nv, s);
-          // Am[j][J][(k,d)] = sum_M Lh_Mj Aq[j][k][d][M]
-          Gemm g1 = gemm_plain(nc, no * nv, Am, plain((long long)no * nv), plain(1), 1.0, 0.0);
-          g1.nbatch = no;
-          g1.cbatch = (long long)nc * no * nv;
-          g1.nseg = 1;
-          g1.seg[0] = seg(LhOO, plain((long long)NO * NO), plain(NO), 1, Aq, plain(1), plain(NO),
-                          (long long)no * nv * NO, NO);
-          gemm(g1, s);
-          launch_left_Z(Am, Hp, nc, no, nv, Z, s);
-          HIPRT(hipGetLastError());
-          // sigma[d][L] += sum_{(J,k)} Z[J][k][d] Lh_Lk - sum_{(k,c,E)} Bq[k][d][c][E] gLE[k][c][L][E]
-          Gemm g3 = gemm_plain(nv, NO, s1, plain(NO), plain(1), 1.0, 1.0);
-          g3.nseg = 2;
-          g3.seg[0] = seg(Z, plain(1), plain(nv), 0, LhOO, split(no, (long long)NO * NO, 1), plain(NO), 0, nc * no);
-          g3.seg[1] = seg(Bq, plain((long long)nv * NV), split(nv * NV, d.nv2 * NV, 1), 0, gLE,
-                          split(NV, (long long)NO * NV, 1), plain(NV), 0, no * nv * NV, -1.0);
-          gemm(g3, s);
-        }
-        DoublesRaw y;
-        y.YvV = QvV; y.YvO = QvO; y.Yvv = nullptr;
-        y.no = no; y.nv = nv; y.NO = NO; y.NV = NV; y.delta = 0;
-        launch_doubles_out(y, sigma[m].x2_vVoo, sigma[m].x2_vvoO, s);
-        HIPRT(hipGetLastError());
-        cvs_project_out(d, sigma[m], s);
+        assemble(m, LA, QvV, QvO, Bq, Aq, Qtau, Xtau);
       }
     }
   });

@@ -66,6 +66,7 @@ struct TripleFilter {
   int on = 0, no = 0, nv = 0, zero = 0;
   unsigned long long core = 0;
   long long tb = 0, te = 0;
+  int pq0 = 0;  // the rows start at pair pq0 (an occupied slab: pq0 = p0 n_o)
 };
 
 __device__ __forceinline__ bool triple_needed(const TripleFilter &f, int p, int q, int r) {
@@ -78,7 +79,7 @@ __device__ __forceinline__ bool triple_needed(const TripleFilter &f, int p, int 
 
 // is any row of [m0, m1) of batch r needed?
 __device__ __forceinline__ bool tile_needed(const TripleFilter &f, int r, int m0, int m1) {
-  for (int pq = m0 / f.nv; pq <= (m1 - 1) / f.nv; pq++)
+  for (int pq = m0 / f.nv + f.pq0; pq <= (m1 - 1) / f.nv + f.pq0; pq++)
     if (triple_needed(f, pq / f.no, pq % f.no, r)) return true;
   return false;
 }

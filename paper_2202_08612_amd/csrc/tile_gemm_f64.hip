@@ -288,7 +288,7 @@ hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
     vec = vec && even_map(sg.amap) && sg.ldb % 2 == 0 && sg.abatch % 2 == 0 && sg.bbatch % 2 == 0 &&
           sg.avec % 2 == 0 && sg.bvec % 2 == 0 && abase && (uintptr_t)sg.B % 16 == 0;
   }
-  if (af && (g.dcontract || g.beta != 0.0)) return hipErrorInvalidValue;
+  if (af && g.dcontract) return hipErrorInvalidValue;
   for (int i = 0; i < g.nseg; i++) g.seg[i].amap = branchless(g.seg[i].amap);
   g.cmap = branchless(g.cmap);
   if (g.dcontract && g.beta != 0.0) return hipErrorInvalidValue;
@@ -307,7 +307,8 @@ hipError_t tile_gemm_f64(const TileGemm &g0, hipStream_t s) {
   MLCC3_TG(true, false, true, false) MLCC3_TG(false, true, false, false) MLCC3_TG(false, true, true, false)
   MLCC3_TG(false, false, false, false) MLCC3_TG(false, false, true, false)
   MLCC3_TG(true, true, false, true) MLCC3_TG(true, false, false, true) MLCC3_TG(false, true, false, true)
-  MLCC3_TG(false, false, false, true)
+  MLCC3_TG(false, false, false, true) MLCC3_TG(false, true, true, true) MLCC3_TG(false, false, true, true)
+  else return hipErrorInvalidValue;  // no instantiation for this combination
 #undef MLCC3_TG
   return hipGetLastError();
 }

@@ -77,6 +77,10 @@ struct VecBatch {
   double omega[kMaxVecBatch] = {0.0};
   int cvs = 0;
   unsigned long long core_bits = 0;
+  // occupied slab (np > 0): the ordered blocks in W and Xt are those with first index
+  // p0 <= p < p0 + np, stored at [p - p0][q][r]; the symmetrisation adds the slab's orderings
+  // into Xu (writes them when p0 == 0) and the contravariant pass writes the slab's orderings
+  int p0 = 0, np = 0;
 };
 
 // W -> Xu (covariant unique-triple blocks [u][a][b][c], rows of pitch occ_pitch(n_v)) -> Xt
@@ -85,13 +89,22 @@ struct VecBatch {
 // sub-cube (contra_form 1), per orbit of sub-cubes (2), or by the size rule (0: per orbit
 // when 16 divides n_v or n_v > 64)
 // (xt_f32: Xt holds float elements; the covariant copy Xc is always double)
+// launch_sym_denom and launch_contra are its two passes on their own (for occupied slabs)
+void launch_sym_denom(const double *W, double *Xu, const UniqueTriple *ut, int nu, int no, int nv, const double *eps_o,
+                      const double *eps_v, const VecBatch &vb, long long tb, long long te, const LocalTerms &lt,
+                      const OccTerm &ot, hipStream_t s);
+void launch_contra(const double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu, int no, int nv,
+                   const VecBatch &vb, int contra_form, hipStream_t s, bool xt_f32);
 void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
                           long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
                           hipStream_t s, bool xt_f32 = false);
-// X, T: ordered blocks of double, or of float when x_f32
+// X, T: ordered blocks of double, or of float when x_f32; with np > 0 the blocks hold the
+// occupied slab p0 <= p < p0 + np ([p - p0][q][r]) and the outputs are written for its rows
+// (part1 + p0 n_o n_v, Yvv + p0 n_o n_v^2); yacc adds into Yvv instead of writing it
 void launch_small_right(const void *X, const void *T, const double *gov, const double *F, const double *U,
-                        int no, int nv, double *part1, double *Yvv, hipStream_t s, bool x_f32 = false);
+                        int no, int nv, double *part1, double *Yvv, hipStream_t s, bool x_f32 = false, int p0 = 0,
+                        int np = 0, bool yacc = false);
 // pairing maps of the doubles blocks (mode 0 symmetrise, 1 gradient -> left vector, 2 left
 // vector -> gradient representer); outputs must not alias inputs
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,

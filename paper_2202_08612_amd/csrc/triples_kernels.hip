@@ -310,6 +310,10 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const bool keep = !vb.cvs || (((vb.core_bits >> u.i) | (vb.core_bits >> u.j) | (vb.core_bits >> u.k)) & 1ULL);
   const bool active = !(u.i == u.j && u.j == u.k) && u.canon >= tb && u.canon < te && keep;
+  // occupied slab: orderings whose first index lies outside it are left to the other slabs; a
+  // later slab (p0 > 0) adds into Xu and skips the triples none of whose orderings it holds
+  const int sp0 = vb.p0, sp1 = vb.np > 0 ? vb.p0 + vb.np : no;
+  if (sp0 > 0 && !((u.i >= sp0 && u.i < sp1) || (u.j >= sp0 && u.j < sp1) || (u.k >= sp0 && u.k < sp1))) return;
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
   double acc[TT];
 #pragma unroll
@@ -318,10 +322,11 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
     for (int s = 0; s < 6; s++) {
       const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
       const int p = sel3(u.i, u.j, u.k, s0), q = sel3(u.i, u.j, u.k, s1), rr = sel3(u.i, u.j, u.k, s2);
+      if (p < sp0 || p >= sp1) continue;  // uniform over the workgroup
       const int X0 = TT * sel3(T0, T1, T2, s0), Y0 = TT * sel3(T0, T1, T2, s1), Z0 = TT * sel3(T0, T1, T2, s2);
       {
         double v[TT];
-        cube_load(W + ((long long)(p * no + q) * no + rr) * nv3, nv, nv, X0, Y0, Z0, v);
+        cube_load(W + ((long long)((p - sp0) * no + q) * no + rr) * nv3, nv, nv, X0, Y0, Z0, v);
         __syncthreads();
         cube_store(v, cube);
       }
@@ -360,7 +365,9 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
     const int ga = TT * T0 + r;
     if (ga >= nv) break;
     const double den = eps_v[ga] + eps_v[gb] + eps_v[gc] - eocc - omega;
-    dst[((long long)ga * nv + gb) * up + gc] = active ? -acc[r] / den : 0.0;
+    const double x = active ? -acc[r] / den : 0.0;
+    if (sp0 > 0) dst[((long long)ga * nv + gb) * up + gc] += x;
+    else dst[((long long)ga * nv + gb) * up + gc] = x;
   }
 }
 
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
 template <typename OT>
 __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, OT *__restrict__ Xt,
                                                         const UniqueTriple *ut, int no, int nv, int covariant, int nu,
-                                                        int nvec, long long xuv, long long xtv) {
+                                                        int nvec, long long xuv, long long xtv, int sp0, int sp1) {
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
   int vec, tri, T[3];
@@ -377,6 +384,8 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
   Xu += vec * xuv;
   Xt += vec * xtv;
   const UniqueTriple u = ut[tri];
+  // occupied slab [sp0, sp1): only the orderings whose first index lies in it are written
+  if (!((u.i >= sp0 && u.i < sp1) || (u.j >= sp0 && u.j < sp1) || (u.k >= sp0 && u.k < sp1))) return;
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
@@ -413,7 +422,8 @@ __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict
   for (int s = 0; s < 6; s++) {
     if (!((u.mask >> s) & 1)) continue;
     const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
-    OT *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
+    if (o[s0] < sp0 || o[s0] >= sp1) continue;
+    OT *dst = Xt + ((long long)((o[s0] - sp0) * no + o[s1]) * no + o[s2]) * nv3;
     // output local index w = v.s, i.e. w_n = v_{s_n}; the writer of w reads v with v_{s_n} = w_n
     const int W0 = TT * T[s0], W1 = TT * T[s1], W2 = TT * T[s2];
     for (int r = 0; r < TT; r++) {
@@ -550,7 +560,7 @@ __device__ __forceinline__ int tile_code(int x, int y, int z, int nt) { return (
 template <typename OT>
 __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restrict__ Xu, OT *__restrict__ Xt,
                                                          const UniqueTriple *ut, int no, int nv, int nu, int nvec,
-                                                         long long xuv, long long xtv) {
+                                                         long long xuv, long long xtv, int sp0, int sp1) {
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
   const int norb = nt * (nt + 1) * (nt + 2) / 6;
@@ -580,6 +590,8 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
     nm += dup ? 0 : 1;
   }
   const UniqueTriple u = ut[tri];
+  // occupied slab [sp0, sp1): only the orderings whose first index lies in it are written
+  if (!((u.i >= sp0 && u.i < sp1) || (u.j >= sp0 && u.j < sp1) || (u.k >= sp0 && u.k < sp1))) return;
   const long long nv2 = (long long)nv * nv, nv3 = nv2 * nv;
   const int o[3] = {u.i, u.j, u.k};
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
@@ -633,7 +645,8 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
     for (int s = 0; s < 6; s++) {
       if (!((u.mask >> s) & 1)) continue;
       const int s0 = c_perm[s][0], s1 = c_perm[s][1], s2 = c_perm[s][2];
-      OT *dst = Xt + ((long long)(o[s0] * no + o[s1]) * no + o[s2]) * nv3;
+      if (o[s0] < sp0 || o[s0] >= sp1) continue;
+      OT *dst = Xt + ((long long)((o[s0] - sp0) * no + o[s1]) * no + o[s2]) * nv3;
       const int W0 = TT * sel3(TT3[0], TT3[1], TT3[2], s0), W1 = TT * sel3(TT3[0], TT3[1], TT3[2], s1),
                 W2 = TT * sel3(TT3[0], TT3[1], TT3[2], s2);
       // output local w = (r, lb, lc) sits at v with v_{s_n} = w_n: LDS weight of w_n is that of axis s_n
@@ -669,7 +682,7 @@ template <bool HAS_T, typename XT_, int SR_AG>
 __global__ __launch_bounds__(256) void k_small_right(const XT_ *__restrict__ X, const XT_ *__restrict__ T,
                                                      const double *__restrict__ gov, const double *__restrict__ F,
                                                      const double *__restrict__ U, int no, int nv,
-                                                     double *__restrict__ part1, double *__restrict__ Yvv) {
+                                                     double *__restrict__ part1, double *__restrict__ Yvv, int yacc) {
   const int nag = (nv + SR_AG - 1) / SR_AG;
   const int id = blockIdx.x;
   const int ag = id % nag, q = (id / nag) % no, p = id / (nag * no);
@@ -719,7 +732,10 @@ __global__ __launch_bounds__(256) void k_small_right(const XT_ *__restrict__ X, 
 #pragma unroll
     for (int t = 0; t < SR_AG; t++) {
       const double y = wave_sum(yb[t]);
-      if (lane == 0 && t < na) Yvv[(((long long)p * no + q) * nv + a0 + t) * nv + b] = y;
+      if (lane == 0 && t < na) {
+        double &yo = Yvv[(((long long)p * no + q) * nv + a0 + t) * nv + b];
+        yo = yacc ? yo + y : y;
+      }
     }
   }
 #pragma unroll
@@ -1057,16 +1073,23 @@ void launch_add_vo(double *D, int NO, int N, int no, int nv, const double *Y, do
   L1D(k_add_vo, (long long)no * nv, D, NO, N, no, nv, Y, f);
 }
 
-void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
-                          int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
-                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
-                          hipStream_t s, bool xt_f32) {
+void launch_sym_denom(const double *W, double *Xu, const UniqueTriple *ut, int nu, int no, int nv, const double *eps_o,
+                      const double *eps_v, const VecBatch &vb, long long tb, long long te, const LocalTerms &lt,
+                      const OccTerm &ot, hipStream_t s) {
   if (nu <= 0 || nv <= 0 || vb.nvec <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
   LocalTerms l = lt;
   if (!l.L1) l.L1v = l.LVv = 0;
   const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
   hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot, nu);
+}
+
+void launch_contra(const double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu, int no, int nv,
+                   const VecBatch &vb, int contra_form, hipStream_t s, bool xt_f32) {
+  if (nu <= 0 || nv <= 0 || vb.nvec <= 0 || g_dry) return;
+  const int nt = (nv + TT - 1) / TT;
+  const int sp0 = vb.p0, sp1 = vb.np > 0 ? vb.p0 + vb.np : no;
+  const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
   if (contra_form == 2 || (contra_form == 0 && (nv % TT == 0 || nv > 4 * TT))) {
     // one workgroup per orbit of tiles reads each sub-cube of X_u once (measured 2.3 -> 1.8 ms
     // per launch at n_v = 80, right + left transform 174.6 -> 168.3 ms at n_v = 136; at n_v = 60
@@ -1077,42 +1100,55 @@ void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, con
     const dim3 og((unsigned)((long long)vb.nvec * nu * norb));
     if (xt_f32)
       hipLaunchKernelGGL(k_contra_orbit<float>, og, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, nu, vb.nvec, vb.xu,
-                         vb.xt);
+                         vb.xt, sp0, sp1);
     else
       hipLaunchKernelGGL(k_contra_orbit<double>, og, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, nu, vb.nvec, vb.xu,
-                         vb.xt);
+                         vb.xt, sp0, sp1);
   } else if (xt_f32) {
     hipLaunchKernelGGL(k_contra_scatter<float>, grid, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, 0, nu, vb.nvec,
-                       vb.xu, vb.xt);
+                       vb.xu, vb.xt, sp0, sp1);
   } else {
     hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, 0, nu, vb.nvec,
-                       vb.xu, vb.xt);
+                       vb.xu, vb.xt, sp0, sp1);
   }
   if (Xc)
     hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu, vb.nvec, vb.xu,
-                       vb.w);
+                       vb.w, sp0, sp1);
+}
+
+void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
+                          int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
+                          long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,
+                          hipStream_t s, bool xt_f32) {
+  launch_sym_denom(W, Xu, ut, nu, no, nv, eps_o, eps_v, vb, tb, te, lt, ot, s);
+  launch_contra(Xu, Xt, Xc, ut, nu, no, nv, vb, contra_form, s, xt_f32);
 }
 
 void launch_small_right(const void *X, const void *T, const double *gov, const double *F, const double *U,
-                        int no, int nv, double *part1, double *Yvv, hipStream_t s, bool x_f32) {
+                        int no, int nv, double *part1, double *Yvv, hipStream_t s, bool x_f32, int p0, int np,
+                        bool yacc) {
   if (no <= 0 || nv <= 0 || g_dry) return;
+  if (np <= 0) np = no;
+  part1 += (long long)p0 * no * nv;  // rows of the slab (the blocks hold p - p0)
+  Yvv += (long long)p0 * no * nv * nv;
+  const int ya = yacc ? 1 : 0;
   if (x_f32) {  // one value of a per workgroup
-    const dim3 grid((unsigned)(no * no * nv));
+    const dim3 grid((unsigned)(np * no * nv));
     if (T)
       hipLaunchKernelGGL((k_small_right<true, float, 1>), grid, dim3(256), 0, s, (const float *)X, (const float *)T,
-                         gov, F, U, no, nv, part1, Yvv);
+                         gov, F, U, no, nv, part1, Yvv, ya);
     else
       hipLaunchKernelGGL((k_small_right<false, float, 1>), grid, dim3(256), 0, s, (const float *)X,
-                         (const float *)nullptr, gov, F, U, no, nv, part1, Yvv);
+                         (const float *)nullptr, gov, F, U, no, nv, part1, Yvv, ya);
     return;
   }
-  const dim3 grid((unsigned)(no * no * ((nv + 3) / 4)));  // four values of a per workgroup
+  const dim3 grid((unsigned)(np * no * ((nv + 3) / 4)));  // four values of a per workgroup
   if (T)
     hipLaunchKernelGGL((k_small_right<true, double, 4>), grid, dim3(256), 0, s, (const double *)X, (const double *)T,
-                       gov, F, U, no, nv, part1, Yvv);
+                       gov, F, U, no, nv, part1, Yvv, ya);
   else
     hipLaunchKernelGGL((k_small_right<false, double, 4>), grid, dim3(256), 0, s, (const double *)X,
-                       (const double *)nullptr, gov, F, U, no, nv, part1, Yvv);
+                       (const double *)nullptr, gov, F, U, no, nv, part1, Yvv, ya);
 }
 
 void launch_vec_map(const double *A2, const double *B2, int no, int nv, int NO, int NV, int mode, double *oA,

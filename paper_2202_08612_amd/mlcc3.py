@@ -46,7 +46,7 @@ class _Opts(ctypes.Structure):
                 ("cvs_core", ctypes.c_void_p), ("reuse_tau", ctypes.c_int32)]
 
 
-TUNING_FIELDS = ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group")
+TUNING_FIELDS = ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group", "occ_slab")
 
 
 class _Tuning(ctypes.Structure):

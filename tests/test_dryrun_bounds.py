@@ -58,7 +58,9 @@ def _fake(n):
 # buffers of 91 GB, element offsets far beyond 2^31)
 CASES = [I.CONFIGS[c]["dims"] for c in range(5)] + [I.Dims(5, 17, 7, 37, 23), I.Dims(3, 2, 3, 2, 1), I.sweep_dims(5),
                                                    I.Dims(17, 3, 18, 5, 7), I.Dims(6, 9, 6, 140, 33),
-                                                   I.Dims(15, 150, 39, 263, 906)]
+                                                   I.Dims(15, 150, 39, 263, 906), I.Dims(18, 180, 39, 263, 906),
+                                                   I.Dims(20, 200, 39, 263, 906)]
+# (18/180 and 20/200 exceed one device's memory in one occupied slab: the calls run in slabs)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x6"])
@@ -138,7 +140,8 @@ def test_cvs_launches_in_bounds(lib, d):
 
 
 class T(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int32) for k in ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group")]
+    _fields_ = [(k, ctypes.c_int32) for k in ("dc_wg_per_cu", "back_ksplit", "narrow_tile", "contra_form", "vec_group",
+                                              "occ_slab")]
 
 
 def test_tuning_validation(lib):
@@ -146,21 +149,22 @@ def test_tuning_validation(lib):
     assert lib.mlcc3_ws_create(ctypes.byref(ws), 0) == 0
     t = T()
     assert lib.mlcc3_ws_get_tuning(ws, ctypes.byref(t)) == 0
-    assert (t.dc_wg_per_cu, t.back_ksplit, t.narrow_tile, t.contra_form, t.vec_group) == (0, 0, 0, 0, 0)
+    assert (t.dc_wg_per_cu, t.back_ksplit, t.narrow_tile, t.contra_form, t.vec_group, t.occ_slab) == (0, 0, 0, 0, 0, 0)
     for bad in (T(9, 0, 0, 0, 0), T(-2, 0, 0, 0, 0), T(0, 9, 0, 0, 0), T(0, 0, 43, 0, 0), T(0, 0, 3, 0, 0),
-                T(0, 0, 0, 3, 0), T(0, 0, 0, 0, -1)):
+                T(0, 0, 0, 3, 0), T(0, 0, 0, 0, -1), T(0, 0, 0, 0, 0, -1)):
         assert lib.mlcc3_ws_set_tuning(ws, ctypes.byref(bad)) == -1
-    good = T(-1, 8, 42, 1, 2)
+    good = T(-1, 8, 42, 1, 2, 3)
     assert lib.mlcc3_ws_set_tuning(ws, ctypes.byref(good)) == 0
     assert lib.mlcc3_ws_get_tuning(ws, ctypes.byref(t)) == 0
-    assert (t.dc_wg_per_cu, t.back_ksplit, t.narrow_tile, t.contra_form, t.vec_group) == (-1, 8, 42, 1, 2)
+    assert (t.dc_wg_per_cu, t.back_ksplit, t.narrow_tile, t.contra_form, t.vec_group, t.occ_slab) == (-1, 8, 42, 1, 2, 3)
     assert lib.mlcc3_ws_set_tuning(ws, None) == 0
     assert lib.mlcc3_ws_get_tuning(ws, ctypes.byref(t)) == 0 and t.back_ksplit == 0
     assert lib.mlcc3_ws_destroy(ws) == 0
 
 
-@pytest.mark.parametrize("tune", [T(1, 1, 11, 1, 1), T(-1, 8, 44, 2, 2), T(4, 3, 14, 0, 0), T(3, 2, 41, 1, 3)],
-                         ids=["min", "max", "mixed", "odd"])
+@pytest.mark.parametrize("tune", [T(1, 1, 11, 1, 1), T(-1, 8, 44, 2, 2), T(4, 3, 14, 0, 0), T(3, 2, 41, 1, 3),
+                                  T(0, 0, 0, 0, 0, 1), T(0, 0, 0, 2, 0, 2), T(-1, 2, 41, 1, 0, 5)],
+                         ids=["min", "max", "mixed", "odd", "slab1", "slab2", "slab5"])
 @pytest.mark.parametrize("d", [I.CONFIGS[1]["dims"], I.CONFIGS[3]["dims"], I.Dims(5, 17, 7, 37, 23)], ids=str)
 def test_tuned_launches_in_bounds(lib, d, tune):
     """Every launch-shape choice keeps all launches inside their buffers (all precisions)."""

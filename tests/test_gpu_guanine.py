@@ -69,3 +69,41 @@ def test_guanine_15_150_core_range():
     _check(got[1], orc.right_transform(w, R, *rng), "15/150 right cvs")
     _check(got[2], orc.left_transform(w, L, *rng), "15/150 left cvs")
     print(f"  oracle {time.time() - t0:.1f} s", flush=True)
+
+
+def test_guanine_20_200_occupied_slabs():
+    """20/200 (512 GB per ordered-triple buffer): the calls run in occupied slabs chosen from the
+    device memory; ground residual and right transform with core-valence separation on two
+    unique triples, (2,1,0) (2,1,1), against the oracle."""
+    import torch
+    from oracle.oracle import Oracle
+    from paper_2202_08612_amd import mlcc3 as lib
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info(0)
+    if total < NEED:
+        pytest.skip(f"device memory {total / 2**30:.0f} GiB < {NEED / 2**30:.0f} GiB")
+    d = I.Dims(20, 200, 39, 263, 906)
+    rng = (3, 5)
+    assert _canon(20)[rng[0]:rng[1]] == [(2, 1, 0), (2, 1, 1)]
+    p = I.make_problem(d, 20220217 + 200 + 20, core=True)
+    core = [1] + [0] * (d.N_O - 1)
+    w = float(I.omegas(True, 1)[0])
+    R = I.right_vectors(p, 1)[0]
+    ws = lib.Workspace(0)
+    try:
+        g = lib.Ground(p)
+        print(f"guanine 20/200, triples {rng}", flush=True)
+        om = lib.ground_residual(ws, g, triple_range=rng)
+        rho = lib.right_transform(ws, g, [w], [lib.vec_to_device(R)], triple_range=rng, reuse_ground=True,
+                                  cvs_core=core)[0]
+        got = [{k: x[k].detach().cpu().numpy() for k in x} for x in (om, rho)]
+        used = ws.bytes()
+        print(f"  workspace {used / 2**30:.1f} GiB of {total / 2**30:.0f} GiB", flush=True)
+    finally:
+        ws.close()
+    assert used < 0.9 * total
+    t0 = time.time()
+    _check(got[0], Oracle(p).ground_residual(*rng), "20/200 ground")
+    _check(got[1], Oracle(p, cvs_core=core).right_transform(w, R, *rng), "20/200 right cvs")
+    print(f"  oracle {time.time() - t0:.1f} s", flush=True)
