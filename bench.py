@@ -45,7 +45,7 @@ MIXED_FORMS = {
 # HBM bytes per d-contraction launch (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, calibrated against a plain
 # copy, mean of the 5 launches of one step) measured with rocprofv3 on the kernel source whose sha256
 # starts with "src"; reported only while that source is unchanged and for that workload.
-DCONTRACT_TRAFFIC = {"src": "cf303409a47aa31f", "dims": (12, 60, 30, 250, 600), "bytes": 9.62e+09}
+DCONTRACT_TRAFFIC = {"src": "752f98f9e14d128b", "dims": (12, 60, 30, 250, 600), "bytes": 9.625e+09}
 METRIC = "GFLOP/s + % MFMA peak, MLCC3 triples Jacobian transform, FP64 vs mixed at ≤1e-6 err"
 
 

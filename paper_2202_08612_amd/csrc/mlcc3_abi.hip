@@ -17,6 +17,7 @@
 #include <mutex>
 #include <string>
 #include <vector>
+#include <array>
 
 #include "../../include/mlcc3.h"
 #include "mlcc3_internal.h"
@@ -73,6 +74,9 @@ thread_local bool t_xf32 = false;
 // occupied slab of the running call: the ordered-triple buffers hold the triples with first
 // index t_p0 <= p < t_p0 + t_np at [p - t_p0][q][r]; t_np = 0: all of them (no slab)
 thread_local int t_p0 = 0, t_np = 0;
+// the unique triples with an index in the slab (device list of t_ntl indices), NULL: all
+thread_local const int *t_tl = nullptr;
+thread_local int t_ntl = 0;
 // core-valence separation of the running call: on/off, active core orbitals as bits, device flags [N_O]
 thread_local int t_cvs = 0;
 thread_local unsigned long long t_cvs_bits = 0;
@@ -1159,6 +1163,8 @@ void permute(mlcc3_ws ws, const Dims &d, const double *W, double *Xt, const doub
   vb.core_bits = t_cvs_bits;
   vb.p0 = t_p0;
   vb.np = t_np;
+  vb.tl = t_tl;
+  vb.ntl = t_ntl;
   const UniqueTriple *ut = (const UniqueTriple *)B(ws, "utriples");
   if (passes & 1) {
     check_bytes(W, sizeof(double) * Wv * nb, "W (permutation)");
@@ -1711,16 +1717,58 @@ int slab_width(mlcc3_ws ws, const Dims &d) {
   return (int)fit;
 }
 
+// the unique triples each slab of width w visits (those with an index in the slab), as one
+// device list "slab_tl" with the slabs' lists back to back; returns the offsets (one per slab
+// and the end)
+std::vector<int> slab_lists(mlcc3_ws ws, const Dims &d, int w, hipStream_t s) {
+  std::vector<int> all, off;
+  int u = 0;
+  std::vector<std::array<int, 3>> tri;
+  for (int i = 0; i < d.no; i++)
+    for (int j = 0; j <= i; j++)
+      for (int k = 0; k <= j; k++) tri.push_back({i, j, k});  // the order of the prepared triple list
+  check((int)tri.size() == ws->nu, "internal: unique triple count");
+  for (int p0 = 0; p0 < d.no; p0 += w) {
+    off.push_back((int)all.size());
+    const int p1 = std::min(d.no, p0 + w);
+    for (u = 0; u < ws->nu; u++) {
+      const auto &t = tri[u];
+      if ((t[0] >= p0 && t[0] < p1) || (t[1] >= p0 && t[1] < p1) || (t[2] >= p0 && t[2] < p1)) all.push_back(u);
+    }
+  }
+  off.push_back((int)all.size());
+  int *dl = (int *)buf(ws, "slab_tl", (all.size() * sizeof(int) + sizeof(double) - 1) / sizeof(double) + 1, s);
+  if (!g_dry) {
+    HIPRT(hipMemcpyAsync(dl, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPRT(hipStreamSynchronize(s));  // the host list goes out of scope
+  }
+  return off;
+}
+
 struct SlabScope {  // sets the occupied slab of the running call, restores "no slab" at exit
-  SlabScope(int p0, int np) {
+  SlabScope(mlcc3_ws ws, const std::vector<int> &off, int w, int p0, int np) {
     t_p0 = p0;
     t_np = np;
+    const int sl = p0 / w;
+    t_tl = (const int *)B(ws, "slab_tl") + off[sl];
+    t_ntl = off[sl + 1] - off[sl];
   }
   ~SlabScope() {
     t_p0 = 0;
     t_np = 0;
+    t_tl = nullptr;
+    t_ntl = 0;
   }
 };
+
+// Xu = 0 before the first slab adds into it
+void zero_xu(mlcc3_ws ws, const Dims &d, hipStream_t s) {
+  const long long n = (long long)ws->nu * d.nv2 * occ_pitch(d.nv);
+  double *Xu = buf(ws, "Xu", (size_t)n, s);
+  check_bytes(Xu, sizeof(double) * n, "Xu (zero)");
+  launch_zero(Xu, n, s);
+  HIPRT(hipGetLastError());
+}
 
 // the slab's contravariant blocks from Xu, into "XS"
 double *contra_slab(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, hipStream_t s) {
@@ -1731,9 +1779,11 @@ double *contra_slab(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Ran
 }
 
 // Xu of tau3, accumulated over the slabs of width w
-void tau_xu_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, int w, hipStream_t s) {
+void tau_xu_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, int w,
+                  const std::vector<int> &off, hipStream_t s) {
+  zero_xu(ws, d, s);
   for (int p0 = 0; p0 < d.no; p0 += w) {
-    SlabScope sc(p0, std::min(w, d.no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, d.no - p0));
     double *W = buf(ws, "W", (size_t)(sord(d) * d.nv3), s);
     DSeg sg;
     sg.x = B(ws, "tA");
@@ -1749,14 +1799,15 @@ void tau_xu_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range
 void ground_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range &r, int w, const mlcc3_out *out,
                   hipStream_t s) {
   const int no = d.no, nv = d.nv, NO = d.NO, NV = d.NV;
-  tau_xu_slabs(ws, g, d, r, w, s);
+  const std::vector<int> off = slab_lists(ws, d, w, s);
+  tau_xu_slabs(ws, g, d, r, w, off, s);
   log_phase("tau3");
   double *YvV = buf(ws, "YvV", (size_t)no * no * nv * NV, s);
   double *YvO = buf(ws, "YvO", (size_t)no * d.nv2 * NO, s);
   double *part1 = buf(ws, "part1", (size_t)no * no * nv, s);
   double *Yvv = buf(ws, "Yvv", (size_t)no * no * d.nv2, s);
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     double *XT = contra_slab(ws, g, d, r, s);
     back_vV(ws, d, XT, B(ws, "Gb1"), NV, YvV, r, s);
     gemm(back_vO(d, XT, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0), s);
@@ -1786,23 +1837,25 @@ void right_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_
   double *Yvv = buf(ws, "Yvv", (size_t)no * no * d.nv2, s);
   double *Xtau = buf(ws, "Xtau", (size_t)no * no * nv * NO, s);
   // tau~ pass: Xtau = sum tau~ g_Lbkc; YvO = -sum tau~ Xi; Yvv = sum tau~ Upsilon_kc
-  tau_xu_slabs(ws, g, d, r, w, s);
+  const std::vector<int> off = slab_lists(ws, d, w, s);
+  tau_xu_slabs(ws, g, d, r, w, off, s);
   log_phase("tau3");
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     double *XT = contra_slab(ws, g, d, r, s);
     back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
     gemm(back_vO(d, XT, bm_jkcL(d, Xi), nullptr, BMap{}, YvO, -1.0), s);
     launch_small_right(XT, nullptr, B(ws, "gov"), Ukc, nullptr, no, nv, spare, Yvv, s, t_xf32, t_p0, t_np);
   }
   // R~ pass
+  zero_xu(ws, d, s);
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     build_R3(ws, g, d, &R, &omega, 1, r, nullptr, nullptr, s, 1);
   }
   log_phase("R3");
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     double *XR = contra_slab(ws, g, d, r, s);
     back_vV(ws, d, XR, B(ws, "Gb1"), NV, YvV, r, s);
     Gemm bo = back_vO(d, XR, bm_jkcL(d, B(ws, "Gb3")), nullptr, BMap{}, YvO, -1.0);
@@ -1846,22 +1899,24 @@ void left_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_v
   double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);
   double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);
   // tau~ pass: Xtau, and the partial products of Qtau per p
-  tau_xu_slabs(ws, g, d, r, w, s);
+  const std::vector<int> off = slab_lists(ws, d, w, s);
+  tau_xu_slabs(ws, g, d, r, w, off, s);
   log_phase("tau3");
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     double *XT = contra_slab(ws, g, d, r, s);
     back_vV(ws, d, XT, B(ws, "gLb"), NO, Xtau, r, s);
     back_qrc(ws, d, XT, L.x2_vvoO, Qtau, s, "qrc_tau", false);
   }
   // L~ pass
+  zero_xu(ws, d, s);
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     build_L3(ws, g, d, &L, &omega, 1, r, nullptr, "LA", "LV", s, 1);
   }
   log_phase("L3");
   for (int p0 = 0; p0 < no; p0 += w) {
-    SlabScope sc(p0, std::min(w, no - p0));
+    SlabScope sc(ws, off, w, p0, std::min(w, no - p0));
     double *XL = contra_slab(ws, g, d, r, s);
     back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, r, s);
     gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0), s);

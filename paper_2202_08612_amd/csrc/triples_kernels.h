@@ -81,6 +81,10 @@ struct VecBatch {
   // p0 <= p < p0 + np, stored at [p - p0][q][r]; the symmetrisation adds the slab's orderings
   // into Xu (writes them when p0 == 0) and the contravariant pass writes the slab's orderings
   int p0 = 0, np = 0;
+  // the unique triples the passes visit: tl[0..ntl) (indices into the triple list), NULL = all
+  // (a slab's passes visit only the triples with an index in the slab)
+  const int *tl = nullptr;
+  int ntl = 0;
 };
 
 // W -> Xu (covariant unique-triple blocks [u][a][b][c], rows of pitch occ_pitch(n_v)) -> Xt
@@ -95,6 +99,8 @@ void launch_sym_denom(const double *W, double *Xu, const UniqueTriple *ut, int n
                       const OccTerm &ot, hipStream_t s);
 void launch_contra(const double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu, int no, int nv,
                    const VecBatch &vb, int contra_form, hipStream_t s, bool xt_f32);
+// dst[0..n) = 0
+void launch_zero(double *dst, long long n, hipStream_t s);
 void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
                           int no, int nv, const double *eps_o, const double *eps_v, const VecBatch &vb,
                           long long tb, long long te, const LocalTerms &lt, const OccTerm &ot, int contra_form,

@@ -300,7 +300,8 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
   int vec, tri, T[3];
-  pass_item(vb.nvec, nu, nt, vec, tri, T);
+  pass_item(vb.nvec, vb.tl ? vb.ntl : nu, nt, vec, tri, T);
+  if (vb.tl) tri = vb.tl[tri];
   W += vec * vb.w;
   Xu += vec * vb.xu;
   const double omega = vb.omega[vec];
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
   // occupied slab: orderings whose first index lies outside it are left to the other slabs; a
   // later slab (p0 > 0) adds into Xu and skips the triples none of whose orderings it holds
   const int sp0 = vb.p0, sp1 = vb.np > 0 ? vb.p0 + vb.np : no;
-  if (sp0 > 0 && !((u.i >= sp0 && u.i < sp1) || (u.j >= sp0 && u.j < sp1) || (u.k >= sp0 && u.k < sp1))) return;
+  if (vb.np > 0 && !((u.i >= sp0 && u.i < sp1) || (u.j >= sp0 && u.j < sp1) || (u.k >= sp0 && u.k < sp1))) return;
   const int tid = threadIdx.x, lb = tid >> 4, lc = tid & 15;
   double acc[TT];
 #pragma unroll
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
     if (ga >= nv) break;
     const double den = eps_v[ga] + eps_v[gb] + eps_v[gc] - eocc - omega;
     const double x = active ? -acc[r] / den : 0.0;
-    if (sp0 > 0) dst[((long long)ga * nv + gb) * up + gc] += x;
+    if (vb.np > 0) dst[((long long)ga * nv + gb) * up + gc] += x;
     else dst[((long long)ga * nv + gb) * up + gc] = x;
   }
 }
@@ -376,11 +377,13 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
 template <typename OT>
 __global__ __launch_bounds__(256) void k_contra_scatter(const double *__restrict__ Xu, OT *__restrict__ Xt,
                                                         const UniqueTriple *ut, int no, int nv, int covariant, int nu,
-                                                        int nvec, long long xuv, long long xtv, int sp0, int sp1) {
+                                                        int nvec, long long xuv, long long xtv, int sp0, int sp1,
+                                                        const int *tl) {
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
   int vec, tri, T[3];
   pass_item(nvec, nu, nt, vec, tri, T);
+  if (tl) tri = tl[tri];
   Xu += vec * xuv;
   Xt += vec * xtv;
   const UniqueTriple u = ut[tri];
@@ -560,7 +563,8 @@ __device__ __forceinline__ int tile_code(int x, int y, int z, int nt) { return (
 template <typename OT>
 __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restrict__ Xu, OT *__restrict__ Xt,
                                                          const UniqueTriple *ut, int no, int nv, int nu, int nvec,
-                                                         long long xuv, long long xtv, int sp0, int sp1) {
+                                                         long long xuv, long long xtv, int sp0, int sp1,
+                                                         const int *tl) {
   __shared__ double cube[SUB];
   const int nt = (nv + TT - 1) / TT;
   const int norb = nt * (nt + 1) * (nt + 2) / 6;
@@ -569,7 +573,7 @@ __global__ __launch_bounds__(256, 2) void k_contra_orbit(const double *__restric
   const long long x8 = bid % 8, slot = bid / 8, q8 = n / 8, rem = n % 8;
   const long long L = x8 * q8 + (x8 < rem ? x8 : rem) + slot;
   const long long vt = L / norb;
-  const int vec = (int)(vt / nu), tri = (int)(vt - (long long)vec * nu);
+  const int vec = (int)(vt / nu), tri = tl ? tl[vt - (long long)vec * nu] : (int)(vt - (long long)vec * nu);
   int orb = (int)(L - vt * norb), A = 0, B = 0, C = 0;
   for (int a = 0, idx = 0; a < nt; a++)
     for (int b = 0; b <= a; b++)
@@ -1080,8 +1084,20 @@ void launch_sym_denom(const double *W, double *Xu, const UniqueTriple *ut, int n
   const int nt = (nv + TT - 1) / TT;
   LocalTerms l = lt;
   if (!l.L1) l.L1v = l.LVv = 0;
-  const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
+  const int nw = vb.tl ? vb.ntl : nu;  // triples visited
+  if (nw <= 0) return;
+  const dim3 grid((unsigned)((long long)vb.nvec * nw * nt * nt * nt));
   hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot, nu);
+}
+
+__global__ void k_zero(double *dst, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = 0.0;
+}
+
+void launch_zero(double *dst, long long n, hipStream_t s) {
+  if (n <= 0 || g_dry) return;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, n);
 }
 
 void launch_contra(const double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu, int no, int nv,
@@ -1089,7 +1105,9 @@ void launch_contra(const double *Xu, void *Xt, double *Xc, const UniqueTriple *u
   if (nu <= 0 || nv <= 0 || vb.nvec <= 0 || g_dry) return;
   const int nt = (nv + TT - 1) / TT;
   const int sp0 = vb.p0, sp1 = vb.np > 0 ? vb.p0 + vb.np : no;
-  const dim3 grid((unsigned)((long long)vb.nvec * nu * nt * nt * nt));
+  const int nw = vb.tl ? vb.ntl : nu;  // triples visited
+  if (nw <= 0) return;
+  const dim3 grid((unsigned)((long long)vb.nvec * nw * nt * nt * nt));
   if (contra_form == 2 || (contra_form == 0 && (nv % TT == 0 || nv > 4 * TT))) {
     // one workgroup per orbit of tiles reads each sub-cube of X_u once (measured 2.3 -> 1.8 ms
     // per launch at n_v = 80, right + left transform 174.6 -> 168.3 ms at n_v = 136; at n_v = 60
@@ -1097,23 +1115,23 @@ void launch_contra(const double *Xu, void *Xt, double *Xc, const UniqueTriple *u
     // L2).  Ragged tiles are exact: a member tile loads zeros past n_v, a permuted read of an
     // output inside n_v stays inside n_v, and writes stop at n_v.
     const int norb = nt * (nt + 1) * (nt + 2) / 6;
-    const dim3 og((unsigned)((long long)vb.nvec * nu * norb));
+    const dim3 og((unsigned)((long long)vb.nvec * nw * norb));
     if (xt_f32)
-      hipLaunchKernelGGL(k_contra_orbit<float>, og, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, nu, vb.nvec, vb.xu,
-                         vb.xt, sp0, sp1);
+      hipLaunchKernelGGL(k_contra_orbit<float>, og, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, nw, vb.nvec, vb.xu,
+                         vb.xt, sp0, sp1, vb.tl);
     else
-      hipLaunchKernelGGL(k_contra_orbit<double>, og, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, nu, vb.nvec, vb.xu,
-                         vb.xt, sp0, sp1);
+      hipLaunchKernelGGL(k_contra_orbit<double>, og, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, nw, vb.nvec, vb.xu,
+                         vb.xt, sp0, sp1, vb.tl);
   } else if (xt_f32) {
-    hipLaunchKernelGGL(k_contra_scatter<float>, grid, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, 0, nu, vb.nvec,
-                       vb.xu, vb.xt, sp0, sp1);
+    hipLaunchKernelGGL(k_contra_scatter<float>, grid, dim3(256), 0, s, Xu, (float *)Xt, ut, no, nv, 0, nw, vb.nvec,
+                       vb.xu, vb.xt, sp0, sp1, vb.tl);
   } else {
-    hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, 0, nu, vb.nvec,
-                       vb.xu, vb.xt, sp0, sp1);
+    hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, (double *)Xt, ut, no, nv, 0, nw, vb.nvec,
+                       vb.xu, vb.xt, sp0, sp1, vb.tl);
   }
   if (Xc)
-    hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nu, vb.nvec, vb.xu,
-                       vb.w, sp0, sp1);
+    hipLaunchKernelGGL(k_contra_scatter<double>, grid, dim3(256), 0, s, Xu, Xc, ut, no, nv, 1, nw, vb.nvec, vb.xu,
+                       vb.w, sp0, sp1, vb.tl);
 }
 
 void launch_permute_denom(const double *W, double *Xu, void *Xt, double *Xc, const UniqueTriple *ut, int nu,
