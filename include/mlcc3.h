@@ -77,8 +77,10 @@ enum {
    Omega^{aD}_{ij}; their triples operand is split while it is staged).  In the reduced forms
    of the ground residual and the right and left transforms, the contravariant triples blocks
    (tau~, R~, L~; formed in FP64) are stored in FP32 and widened to FP64 where they are read
-   (about 6e-8 relative per element); the densities keep them in FP64.  The occupied (N_O-sized)
-   terms, permutations, denominators, the arithmetic of the N_O-wide back-contractions and every
+   (about 6e-8 relative per element), and the occupied (N_O-sized) term of each intermediate,
+   sum_L x^{ab}_{pL} G_{Lqrc}, runs as FP32 MFMA products on FP32 copies of its operands (FP32
+   sums over the N_O values of L, added in FP64); the densities keep both in FP64.  The
+   permutations, denominators, the arithmetic of the N_O-wide back-contractions and every
    output stay FP64 in all forms.
    MLCC3_FP32:   FP32 MFMA on operands rounded to FP32, FP32 sums over 32-deep K slabs, FP64
                  across slabs (about 1e-7 relative).
@@ -104,8 +106,9 @@ typedef struct {
   int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3, MLCC3_BF16X6:
                              arithmetic of the d-contraction GEMMs (and, in the split-bf16
                              forms, of the N_V-wide back-contractions) and storage of the
-                             contravariant triples blocks (FP32 in the reduced forms, except in
-                             the densities); denominators and accumulation stay FP64 */
+                             contravariant triples blocks and of the occupied term (FP32 in
+                             the reduced forms, except in the densities); denominators and
+                             accumulation stay FP64 */
   int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
                              since the last call on this workspace; reuse its prepared blocks.
                              The call checks that: a 64-bit fingerprint of the inputs' contents

@@ -129,36 +129,45 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_bf16(const BfGemm g) {
         const int n = n0 + sr;
         brow = n < g.N ? mix_moff(sg.bmap, n) : -1;
       }
+      // offset of element k of a B row (the K map, if any)
+      auto koff = [&](int k) -> long long {
+        return sg.kd > 0 ? (long long)(k / sg.kd) * sg.ks + k % sg.kd : (long long)k;
+      };
       auto load = [&](int kt) {
         const int k = kt * BK + 8 * kc;
+        // the two halves of the 8 k values: each lies in one run of the K map when kd % 4 == 0
+        const bool full = brow >= 0 && k + 8 <= sg.K && sg.kd % 4 == 0;
+        const long long o0 = full ? brow + koff(k) : 0, o1 = full ? brow + koff(k + 4) : 0;
         if (BMODE == 1) {
-          if (brow >= 0 && k + 8 <= sg.K && ((brow + k) & 1) == 0) {  // four 16-byte loads
-            const double2 *q = (const double2 *)(B64 + brow + k);
+          if (full && ((o0 | o1) & 1) == 0) {  // four 16-byte loads
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-              const double2 v = q[e];
-              xb[2 * e] = v.x;
-              xb[2 * e + 1] = v.y;
+            for (int h = 0; h < 2; h++) {
+              const double2 *q = (const double2 *)(B64 + (h ? o1 : o0));
+#pragma unroll
+              for (int e = 0; e < 2; e++) {
+                const double2 v = q[e];
+                xb[4 * h + 2 * e] = v.x;
+                xb[4 * h + 2 * e + 1] = v.y;
+              }
             }
           } else {
 #pragma unroll
-            for (int e = 0; e < 8; e++) xb[e] = (brow >= 0 && k + e < sg.K) ? B64[brow + k + e] : 0.0;
+            for (int e = 0; e < 8; e++) xb[e] = (brow >= 0 && k + e < sg.K) ? B64[brow + koff(k + e)] : 0.0;
           }
         } else if (BMODE == 2) {
           // kept as float until the store: a conversion here would wait for the loads
-          if (brow >= 0 && k + 8 <= sg.K && ((brow + k) & 3) == 0) {  // two 16-byte loads
-            const float4 *q = (const float4 *)(B32 + brow + k);
+          if (full && ((o0 | o1) & 3) == 0) {  // two 16-byte loads
 #pragma unroll
-            for (int e = 0; e < 2; e++) {
-              const float4 v = q[e];
-              xf[4 * e] = v.x;
-              xf[4 * e + 1] = v.y;
-              xf[4 * e + 2] = v.z;
-              xf[4 * e + 3] = v.w;
+            for (int h = 0; h < 2; h++) {
+              const float4 v = *(const float4 *)(B32 + (h ? o1 : o0));
+              xf[4 * h] = v.x;
+              xf[4 * h + 1] = v.y;
+              xf[4 * h + 2] = v.z;
+              xf[4 * h + 3] = v.w;
             }
           } else {
 #pragma unroll
-            for (int e = 0; e < 8; e++) xf[e] = (brow >= 0 && k + e < sg.K) ? B32[brow + k + e] : 0.0f;
+            for (int e = 0; e < 8; e++) xf[e] = (brow >= 0 && k + e < sg.K) ? B32[brow + koff(k + e)] : 0.0f;
           }
         }
 #pragma unroll
@@ -320,6 +329,7 @@ hipError_t dcontract_bf16(const BfGemm &g0, hipStream_t s) {
       return hipErrorInvalidValue;
     // the 16-byte loads test the alignment of the element offset only
     if ((sg.B64 && (uintptr_t)sg.B64 % 16) || (sg.B32 && (uintptr_t)sg.B32 % 16)) return hipErrorInvalidValue;
+    if (sg.kd < 0 || sg.ks < 0 || (sg.kd > 0 && !sg.B64 && !sg.B32)) return hipErrorInvalidValue;
   }
   if (g.cmap.d <= 0) {
     g.cmap.d = 0x7fffffff;

@@ -66,6 +66,10 @@ struct BfSeg {
   const float *B32 = nullptr;  // instead of B64: float elements at the same offsets
   Idx2 bmap;
   int K = 0;
+  // with B64 or B32 only: kd > 0 maps k to (k / kd) ks + k % kd (element k of row n at
+  // bmap(n) + (k / kd) ks + k % kd instead of bmap(n) + k)
+  int kd = 0;
+  long long ks = 0;
 };
 
 // C[z*cbatch + cmap(m) + n] = sum_seg sum_(s,t) sum_k A_seg,s[m][k] B_seg,t[z][n][k] (bf16 MFMA,

@@ -1118,8 +1118,11 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg0, int nseg, const
 }
 
 // occupied-term operands: xT[p][a][L][b] (launch_occ_xT of an [a][b][p][L] block) and G stored
-// [L][q][r][c] (G2, Uo, Gb3L); vector v of a group at + v*xv, + v*gv (stride 0: shared)
-void occ_add(OccTerm &ot, const Dims &d, const double *xT, long long xv, const double *G, long long gv, int nb) {
+// [L][q][r][c] (G2, Uo, Gb3L); vector v of a group at + v*xv, + v*gv (stride 0: shared).  In the
+// reduced-precision forms the term is formed from FP32 copies of both operands (workspace
+// buffers of the segment, one block per vector or one shared block).
+void occ_add(mlcc3_ws ws, OccTerm &ot, const Dims &d, const double *xT, long long xv, const double *G, long long gv,
+             int nb, hipStream_t s) {
   const int sg = ot.nseg++;
   ot.NO = d.NO;
   ot.x[sg] = xT;
@@ -1127,6 +1130,18 @@ void occ_add(OccTerm &ot, const Dims &d, const double *xT, long long xv, const d
   ot.xv[sg] = xv;
   ot.gv[sg] = gv;
   for (int v = 0; v < nb; v++) reg_check_occ(d, xT + v * xv, G + v * gv);
+  if (!t_xf32) return;
+  static const char *const xname[2] = {"occ_x32_0", "occ_x32_1"}, *const gname[2] = {"occ_g32_0", "occ_g32_1"};
+  const long long nx = (long long)d.no * d.nv * d.NO * occ_pitch(d.nv), ng = (long long)d.no * d.no * d.nv * d.NO;
+  const int nxb = xv ? nb : 1, ngb = gv ? nb : 1;
+  float *xs = (float *)buf(ws, xname[sg], (size_t)((nx * nxb + 1) / 2), s);
+  float *gs = (float *)buf(ws, gname[sg], (size_t)((ng * ngb + 1) / 2), s);
+  for (int v = 0; v < nxb; v++) launch_to_f32(xT + v * xv, nx, xs + v * nx, s);
+  for (int v = 0; v < ngb; v++) launch_to_f32(G + v * gv, ng, gs + v * ng, s);
+  ot.xs[sg] = xs;
+  ot.Gs[sg] = gs;
+  ot.xsv[sg] = xv ? nx : 0;
+  ot.gsv[sg] = gv ? ng : 0;
 }
 
 // transposed occupied-term copies of nb [a][b][p][L] blocks (block v at x[v]) into workspace
@@ -1205,7 +1220,7 @@ bool tau_path(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, Range r, hipStr
   sg.G = B(ws, "G1");
   w_dterm(d, W, 1, &sg, 1, r, s);
   OccTerm ot;
-  occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1);
+  occ_add(ws, ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1, s);
   const double zero = 0.0;
   permute(ws, d, W, XT, g->eps_o, g->eps_v, &zero, 1, r, LocalTerms{}, ot, s, Xc);
   ws->tau = key;
@@ -1295,6 +1310,74 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
   }
   launch_sum_rows(P, d.no, MN, Y, s);
   HIPRT(hipGetLastError());
+}
+
+// Bq[r][(b,c)][E] = sum_{(p,q,a)} L~[p][q][r][a][b][c] t^{aE}_{pq} (intermediate of the singles
+// terms of the left transform).  FP64: tile GEMM over rows (b,c) and K = (p,q,a) of the occupied
+// slab, added into Bq after the first slab.  Split-bf16 forms: L~ is read through its pair
+// symmetry, L~[p][q][r][a][b][c] = L~[r][q][p][c][b][a], so that for each r the summed indices
+// (q,p,a) run along the ordered buffer with a contiguous; Bq^T[r][E][(b,c)] = sum_{(q,p,a)}
+// t^{aE}_{pq} L~[r][q][p][c][b][a] then takes the amplitudes as the pre-split operand (planes
+// [E][(q,p,a)]) and L~ as the operand split while staged, K mapped over the (q,p) blocks.  Each
+// slab forms its rows r whole; a transpose writes them into Bq.
+void form_Bq(mlcc3_ws ws, const Dims &d, const double *XL, double *Bq, hipStream_t s) {
+  const int no = d.no, nv = d.nv, NV = d.NV;
+  const long long cb = (long long)NV * d.nv2;  // one r of Bq
+  if (NV >= 96 && (t_prec == MLCC3_BF16X3 || t_prec == MLCC3_BF16X6)) {
+    const int ns = t_prec == MLCC3_BF16X3 ? 2 : 3;
+    const int K = no * no * nv, nr = snp(d);
+    const int Kp = (K + BF_BK - 1) / BF_BK * BF_BK, Mp = (NV + BF_BM - 1) / BF_BM * BF_BM;
+    const long long pa = (long long)Mp * Kp;  // one plane
+    const double *tA = B(ws, "tA");
+    double *tq = buf(ws, "bq_tq", (size_t)K * NV, s);
+    uint16_t *Am = (uint16_t *)buf(ws, "bq_A", (size_t)(pa * ns + 3) / 4, s);
+    double *BT = buf(ws, "bq_T", (size_t)(nr * cb), s);
+    check_bytes(tA, sizeof(double) * (size_t)K * NV, "t (Bq)");
+    launch_swap01(tA, no, (long long)nv * NV, tq, s);  // [q][p][a][E]
+    check_bytes(Am, (size_t)(pa * ns) * sizeof(uint16_t), "bf16 t planes (Bq)");
+    HIPCHK(split_bf16(tq, 1, K, NV, Am, Kp, Mp, pa, ns, 1, s));
+    BfGemm g;
+    g.M = NV;
+    g.N = (int)d.nv2;
+    g.nbatch = nr;
+    g.ns = ns;
+    g.C = BT;
+    g.cmap = plain(d.nv2);
+    g.cbatch = cb;
+    g.nseg = 1;
+    g.seg[0].A = Am;
+    g.seg[0].aplane = pa;
+    if (t_xf32) g.seg[0].B32 = (const float *)XL;
+    else g.seg[0].B64 = XL;
+    g.seg[0].bmap = split(nv, nv, d.nv2);             // row (b,c) at b n_v + c n_v^2
+    g.seg[0].bbatch = (long long)no * no * d.nv3;     // r: the first index of the ordered buffer
+    g.seg[0].K = K;
+    g.seg[0].Kp = Kp;
+    g.seg[0].kd = nv;                                 // k = (q,p,a) at (q n_o + p) n_v^3 + a
+    g.seg[0].ks = d.nv3;
+    check_range(XL, g.seg[0].bmap, (int)d.nv2, split(nv, d.nv3, 1), K, g.seg[0].bbatch, nr, "L~ (Bq)", 0, 1,
+                xesz());
+    check_range(BT, plain(d.nv2), NV, plain(1), (int)d.nv2, cb, nr, "C (Bq)");
+    HIPCHK(dcontract_bf16(g, s));
+    check_range(Bq + t_p0 * cb, plain(NV), (int)d.nv2, plain(1), NV, cb, nr, "Bq");
+    launch_transpose(BT, Bq + t_p0 * cb, nr, NV, (int)d.nv2, s);
+    HIPRT(hipGetLastError());
+    return;
+  }
+  TileGemm gg;
+  gg.M = (int)d.nv2;
+  gg.N = NV;
+  gg.nbatch = no;
+  gg.ak = 0;
+  gg.C = Bq;
+  gg.cmap = plain(NV);
+  gg.cbatch = cb;
+  gg.beta = t_p0 > 0 ? 1.0 : 0.0;
+  gg.nseg = 1;
+  gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA") + (long long)t_p0 * no * nv * NV,
+                   NV, 0, snp(d) * no * nv);
+  xa(gg.seg[0]);
+  tgemm(gg, s, t_np > 0);
 }
 
 // Xtau[(i,j,a)][L] = sum tau~ g_Lbkc, kept with the tau~ blocks it was formed from
@@ -1581,8 +1664,8 @@ void build_R3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   long long xv = 0;
   const double *RBxT = occ_xT(ws, d, rb.data(), nb, "RBxT", &xv, s);
   OccTerm ot;
-  occ_add(ot, d, RBxT, xv, B(ws, "G2"), 0, nb);
-  occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "Uo"), z.Uo, nb);
+  occ_add(ws, ot, d, RBxT, xv, B(ws, "G2"), 0, nb, s);
+  occ_add(ws, ot, d, B(ws, "t2xT"), 0, B(ws, "Uo"), z.Uo, nb, s);
   (void)R;
   permute(ws, d, W, Xt, g->eps_o, g->eps_v, omega, nb, r, LocalTerms{}, ot, s, Xc, passes);
 }
@@ -1613,7 +1696,7 @@ void build_L3(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_vec
   long long xv = 0;
   const double *LBxT = occ_xT(ws, d, lb.data(), nb, "LBxT", &xv, s);
   OccTerm ot;
-  occ_add(ot, d, LBxT, xv, B(ws, "Gb3L"), 0, nb);
+  occ_add(ws, ot, d, LBxT, xv, B(ws, "Gb3L"), 0, nb, s);
   LocalTerms lt;
   lt.L1 = L1; lt.gov = B(ws, "gov"); lt.LV = LV; lt.F = B(ws, "F"); lt.NO = NO;
   lt.L1v = sL1;
@@ -1790,7 +1873,7 @@ void tau_xu_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const Range
     sg.G = B(ws, "G1");
     w_dterm(d, W, 1, &sg, 1, r, s);
     OccTerm ot;
-    occ_add(ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1);
+    occ_add(ws, ot, d, B(ws, "t2xT"), 0, B(ws, "G2"), 0, 1, s);
     const double zero = 0.0;
     permute(ws, d, W, nullptr, g->eps_o, g->eps_v, &zero, 1, r, LocalTerms{}, ot, s, nullptr, 1);
   }
@@ -1920,21 +2003,7 @@ void left_slabs(mlcc3_ws ws, const mlcc3_ground *g, const Dims &d, const mlcc3_v
     double *XL = contra_slab(ws, g, d, r, s);
     back_vV(ws, d, XL, B(ws, "G1t"), NV, QvV, r, s);
     gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0), s);
-    // Bq[r][(b,c)][E] += sum_{(p,q,a) of the slab} L~[p][q][r][a][b][c] t^{aE}_{pq}
-    TileGemm gg;
-    gg.M = (int)d.nv2;
-    gg.N = NV;
-    gg.nbatch = no;
-    gg.ak = 0;
-    gg.C = Bq;
-    gg.cmap = plain(NV);
-    gg.cbatch = d.nv2 * NV;
-    gg.beta = p0 > 0 ? 1.0 : 0.0;
-    gg.nseg = 1;
-    gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA") + (long long)p0 * no * nv * NV,
-                     NV, 0, snp(d) * no * nv);
-    xa(gg.seg[0]);
-    tgemm(gg, s, true);
+    form_Bq(ws, d, XL, Bq, s);
     back_qrc(ws, d, XL, g->t2_vvoO, Aq, s, "qrc_l", false);
   }
   log_phase("back");
@@ -2636,22 +2705,8 @@ int mlcc3_left_transform(mlcc3_ws ws, const mlcc3_ground *g, int32_t nvec, const
         gemm(back_vO(d, XL, BMap{B(ws, "G2"), plain(1), plain((long long)no * no * nv), 0}, nullptr, BMap{}, QvO, -1.0),
              s);
         // intermediates of the singles
-        // Bq[r][(b,c)][E] = sum_{(p,q,a)} L~[p][q][r][a][b][c] t^{aE}_{pq}
         double *Bq = buf(ws, "Bq", (size_t)no * d.nv2 * NV, s);
-        {
-          TileGemm gg;
-          gg.M = (int)d.nv2;
-          gg.N = NV;
-          gg.nbatch = no;
-          gg.ak = 0;
-          gg.C = Bq;
-          gg.cmap = plain(NV);
-          gg.cbatch = d.nv2 * NV;
-          gg.nseg = 1;
-          gg.seg[0] = tseg(XL, split(nv, (long long)no * d.nv3, d.nv2), d.nv3, B(ws, "tA"), NV, 0, no * no * nv);
-          xa(gg.seg[0]);
-          tgemm(gg, s);
-        }
+        form_Bq(ws, d, XL, Bq, s);
         // Aq[(q,r,c)][M] = sum L~[p][q][r][a][b][c] t^{ab}_{pM};  Qtau likewise with tau~ and L^{ab}_{pL}
         double *Aq = buf(ws, "Aq", (size_t)no * no * nv * NO, s);
         double *Qtau = buf(ws, "Qtau", (size_t)no * no * nv * NO, s);

@@ -31,6 +31,12 @@ struct OccTerm {
   const double *G[2] = {nullptr, nullptr};
   long long xv[2] = {0, 0}, gv[2] = {0, 0};  // per-vector strides (0: shared by all vectors)
   int nseg = 0, NO = 0;
+  // reduced-precision forms: FP32 copies of every segment's x and G (same layouts, per-vector
+  // strides xsv/gsv); when set, the term is formed from them with FP32 MFMA products (FP32 sums
+  // over the N_O values of L of one segment, added into the FP64 sub-cube)
+  const float *xs[2] = {nullptr, nullptr};
+  const float *Gs[2] = {nullptr, nullptr};
+  long long xsv[2] = {0, 0}, gsv[2] = {0, 0};
 };
 
 // Raw (pre-symmetrisation) doubles blocks; delta=1 applies Delta^{-1}.
@@ -124,6 +130,10 @@ void launch_cvs_project(const double *x1, const double *x2a, const double *x2b, 
 // are whole 128-byte lines
 __host__ __device__ inline int occ_pitch(int nv) { return (nv + 15) / 16 * 16; }
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s);
+// dst[i] = FP32 of src[i] (rounded to nearest), i < n
+void launch_to_f32(const double *src, long long n, float *dst, hipStream_t s);
+// dst[q][p][x] = src[p][q][x] (p, q < n, x < inner); dst must not alias src
+void launch_swap01(const double *src, int n, long long inner, double *dst, hipStream_t s);
 // out[z][c][r] = in[z][r][c], z < batch
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s);
 // out[i] = sum_r P[r][i], r = 0..rows-1 (fixed order)

@@ -291,8 +291,70 @@ __device__ __forceinline__ void occ_term_cube(const OccTerm &ot, int vec, int no
   }
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// occ_term_cube from the FP32 copies of the operands (reduced-precision forms) with
+// v_mfma_f32_16x16x4_f32: operand lanes as in the FP64 form, result register v of lane l at row
+// 4(l/16) + v, column l%16.  Each segment's sum over its N_O values of L is formed in FP32 and
+// added in FP64.
+__device__ __forceinline__ void occ_term_cube_f32(const OccTerm &ot, int vec, int no, int nv, int p, int q, int r,
+                                                  int X0, int Y0, int Z0, double *cube) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ly = lane & 15, lk = lane >> 4;
+  const int NO = ot.NO;
+  const int gy = Y0 + ly, gz = Z0 + ly;
+  const int nvp = occ_pitch(nv);
+  constexpr int KC = 4;
+  constexpr int XS = TT / 4;
+  const long long qr = (long long)no * no * nv;
+#pragma unroll
+  for (int h = 0; h < XS; h += 2) {
+    d4v sum[2];
+    sum[0] = d4v{0.0, 0.0, 0.0, 0.0};
+    sum[1] = sum[0];
+    for (int sg = 0; sg < ot.nseg; sg++) {
+      f4v acc[2];
+      acc[0] = f4v{0.f, 0.f, 0.f, 0.f};
+      acc[1] = acc[0];
+      const float *gb = ot.Gs[sg] + vec * ot.gsv[sg] + (long long)(q * no + r) * nv + gz;
+      for (int k0 = 0; k0 < NO; k0 += 4 * KC) {
+        float a[2][KC], b[KC];
+#pragma unroll
+        for (int u = 0; u < KC; u++) {
+          const int L = k0 + 4 * u + lk;
+          b[u] = (L < NO && gz < nv) ? gb[L * qr] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+          const int gx = X0 + wave + 4 * (h + e);
+          const float *xa = ot.xs[sg] + vec * ot.xsv[sg] + ((long long)p * nv + gx) * NO * nvp + gy;
+#pragma unroll
+          for (int u = 0; u < KC; u++) {
+            const int L = k0 + 4 * u + lk;
+            a[e][u] = (L < NO && gy < nv && gx < nv) ? xa[L * nvp] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < KC; u++)
+#pragma unroll
+          for (int e = 0; e < 2; e++) acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e][u], b[u], acc[e], 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 2; e++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) sum[e][v] += (double)acc[e][v];
+    }
+#pragma unroll
+    for (int e = 0; e < 2; e++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) cube[(wave + 4 * (h + e)) * LX + (4 * lk + v) * LY + ly] -= sum[e][v];
+  }
+}
+
 __device__ __forceinline__ int sel3(int a0, int a1, int a2, int i) { return i == 0 ? a0 : (i == 1 ? a1 : a2); }
 
+// OF32: the occupied term from the FP32 operand copies (occ_term_cube_f32)
+template <bool OF32>
 __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__ W, double *__restrict__ Xu,
                                                       const UniqueTriple *ut, int no, int nv, const double *eps_o,
                                                       const double *eps_v, VecBatch vb, long long tb, long long te,
@@ -333,7 +395,8 @@ __global__ __launch_bounds__(256, 4) void k_sym_denom(const double *__restrict__
       }
       if (ot.nseg > 0) {
         __syncthreads();
-        occ_term_cube(ot, vec, no, nv, p, q, rr, X0, Y0, Z0, cube);
+        if (OF32) occ_term_cube_f32(ot, vec, no, nv, p, q, rr, X0, Y0, Z0, cube);
+        else occ_term_cube(ot, vec, no, nv, p, q, rr, X0, Y0, Z0, cube);
       }
       __syncthreads();
       // output local index v = (r, lb, lc) reads the source cube at (v_{s0}, v_{s1}, v_{s2})
@@ -1087,7 +1150,12 @@ void launch_sym_denom(const double *W, double *Xu, const UniqueTriple *ut, int n
   const int nw = vb.tl ? vb.ntl : nu;  // triples visited
   if (nw <= 0) return;
   const dim3 grid((unsigned)((long long)vb.nvec * nw * nt * nt * nt));
-  hipLaunchKernelGGL(k_sym_denom, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot, nu);
+  if (ot.nseg > 0 && ot.xs[0])
+    hipLaunchKernelGGL(k_sym_denom<true>, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot,
+                       nu);
+  else
+    hipLaunchKernelGGL(k_sym_denom<false>, grid, dim3(256), 0, s, W, Xu, ut, no, nv, eps_o, eps_v, vb, tb, te, l, ot,
+                       nu);
 }
 
 __global__ void k_zero(double *dst, long long n) {
@@ -1182,6 +1250,25 @@ void launch_cvs_project(const double *x1, const double *x2a, const double *x2b, 
 
 void launch_occ_xT(const double *x, int no, int nv, int NO, double *xT, hipStream_t s) {
   L1D(k_occ_xT, (long long)no * nv * NO * occ_pitch(nv), x, no, nv, NO, xT);
+}
+
+__global__ void k_to_f32(const double *__restrict__ src, long long n, float *__restrict__ dst) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+void launch_to_f32(const double *src, long long n, float *dst, hipStream_t s) { L1D(k_to_f32, n, src, n, dst); }
+
+__global__ void k_swap01(const double *__restrict__ src, int n, long long inner, double *__restrict__ dst) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)n * n * inner) return;
+  const long long pq = i / inner, x = i - pq * inner;
+  const int p = (int)(pq / n), q = (int)(pq - (long long)p * n);
+  dst[((long long)q * n + p) * inner + x] = src[i];
+}
+
+void launch_swap01(const double *src, int n, long long inner, double *dst, hipStream_t s) {
+  L1D(k_swap01, (long long)n * n * inner, src, n, inner, dst);
 }
 
 void launch_transpose(const double *in, double *out, int batch, int R, int C, hipStream_t s) {

@@ -1,9 +1,12 @@
 """Mixed-precision paths: the d-contractions run as FP32 MFMA on rounded copies of the FP64
 operands (precision="fp32"), or as split-bf16 MFMA products (precision="bf16x6": three bf16
-planes per operand, six products; "bf16x3": two planes, three products).  The occupied term,
-the permutations, the denominators, the back-contractions and every output stay FP64.  Every
-result is checked against the FP64 oracle, norm-wise and max-abs over max-abs, and against the
-FP64 GPU path to show that the reduced-precision path really ran.
+planes per operand, six products; "bf16x3": two planes, three products).  In the reduced forms
+the contravariant triples blocks are stored in FP32, the occupied term of each intermediate runs
+as FP32 MFMA products, and the split-bf16 forms also run the N_V-wide back-contractions (and the
+Bq intermediate of the left transform) in split-bf16 products; the permutations, the
+denominators, the N_O-wide back-contractions and every output stay FP64.  Every result is
+checked against the FP64 oracle, norm-wise and max-abs over max-abs, and against the FP64 GPU
+path to show that the reduced-precision path really ran.
 
 Tolerances: fp32 and bf16x6 at 1e-6.  bf16x3 drops the lo*lo product and the remainder beyond
 two bf16 planes: per product about 3 * 2^-18 = 1.1e-5 relative to |x y| (each plane keeps 8
@@ -21,7 +24,9 @@ pytestmark = pytest.mark.gpu
 MIXTOL = 1e-6
 TOL = {"fp32": MIXTOL, "bf16x6": MIXTOL, "bf16x3": 2e-4}
 PRECS = list(TOL)
-SHAPES = [I.CONFIGS[0]["dims"], I.Dims(5, 17, 7, 37, 23), I.Dims(6, 9, 6, 140, 33)]
+# N_V >= 96 takes the split-bf16 N_V-wide products (n_v = 9: element loads of the staged operand;
+# n_v = 12: its 16-byte loads)
+SHAPES = [I.CONFIGS[0]["dims"], I.Dims(5, 17, 7, 37, 23), I.Dims(6, 9, 6, 140, 33), I.Dims(4, 12, 5, 100, 24)]
 
 
 @pytest.fixture(scope="module")

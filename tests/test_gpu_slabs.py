@@ -38,7 +38,7 @@ def _calls(lib, ws, g, om, R, L, prec, **kw):
 
 
 CASES = [(I.Dims(4, 12, 6, 20, 60), 1), (I.Dims(4, 12, 6, 20, 60), 3), (I.Dims(5, 17, 7, 37, 23), 2),
-         (I.Dims(6, 9, 6, 140, 33), 4), (I.Dims(3, 32, 4, 41, 11), 2)]
+         (I.Dims(6, 9, 6, 140, 33), 4), (I.Dims(3, 32, 4, 41, 11), 2), (I.Dims(4, 12, 5, 100, 24), 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x6", "fp32"])
