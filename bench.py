@@ -17,7 +17,8 @@ every error is within 1e-6, its speedup over FP64 are reported in the "mixed" ob
 JSON line; "fp64_vs_oracle" holds the FP64 path's own errors.
 
 Prints ONE JSON line (rank 0).  Options: --gpus (only 1 is supported: the hot path
-runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --no-iteration, --no-per-call, --cfg;
+runs on one GPU), --steps, --warmup, --no-cpu-baseline, --no-mixed, --mixed-forms, --no-iteration,
+--no-per-call, --cfg;
 --copy-mib, --paper-shapes, --nv-sweep, --config3 and --config4 run other reports instead of the step.
 """
 from __future__ import annotations
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--cfg", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision steps (FP32 and split-bf16 MFMA)")
+    ap.add_argument("--mixed-forms", default=",".join(MIXED_FORMS),
+                    help="comma-separated reduced-precision forms to time after the FP64 step")
     ap.add_argument("--no-iteration", action="store_true",
                     help="skip the right + left iteration timing with and without kept tau~ blocks")
     ap.add_argument("--no-per-call", action="store_true",
@@ -82,7 +85,11 @@ def parse():
                     help="instead of the step: time the ground residual, right and left transforms and the "
                          "densities at a fixed active space (n_o=8, n_v=136) over six inactive-space sizes "
                          "(N_O/N_V 13/217 .. 38/652), one JSON line per size and one with linear fits in N_V")
-    return ap.parse_args()
+    args = ap.parse_args()
+    bad = set(args.mixed_forms.split(",")) - set(MIXED_FORMS)
+    if bad:
+        ap.error(f"unknown form(s) in --mixed-forms: {sorted(bad)}; known: {list(MIXED_FORMS)}")
+    return args
 
 
 def unit_flops(d, tb, te):
@@ -623,7 +630,7 @@ def main():
                "sigma": mlcc3.to_numpy(outs["sig"][0])}
     if not args.no_mixed:
         res["mixed"] = {form: mixed_report(args, d, flops_step, dt, ref, ref_kind, timed, Lh, form)
-                        for form in MIXED_FORMS}
+                        for form in MIXED_FORMS if form in args.mixed_forms.split(",")}
     print(json.dumps(res), flush=True)
 
 

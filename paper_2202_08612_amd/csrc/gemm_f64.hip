@@ -7,6 +7,8 @@
 // is (32*TM) x (32*TN).  K advances in slabs of 16 staged through LDS with a
 // register prefetch of the next slab (two LDS buffers, one barrier per slab).
 // Global loads are coalesced along whichever operand index is unit-stride.
+#include <type_traits>
+
 #include "mlcc3_internal.h"
 
 namespace mlcc3 {
@@ -15,14 +17,23 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;
 
-// AF: the A operand of every segment holds float elements (Operand::pf), widened when staged
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// AF: the A operand of every segment holds float elements (Operand::pf) (the contravariant
+// triples of the reduced-precision forms); the product then runs as v_mfma_f32_16x16x4_f32 on
+// FP32 slabs in LDS (B rounded to FP32 when staged), each 16-deep K slab summed in FP32 and
+// added into the FP64 accumulators.  Result register v of lane l: row 4(l/16) + v (FP32 MFMA)
+// or l/16 + 4v (FP64 MFMA), column l%16.
 template <int TM, int TN, bool AKF, bool BNF, bool AF>
 __device__ __forceinline__ void gemm_body(const Gemm &g) {
+  typedef typename std::conditional<AF, float, double>::type LT;
   constexpr int BM = 32 * TM, BN = 32 * TN;
-  constexpr int PA = BM + 2, PB = BN + 2;
+  // row pitches: 2 doubles, or 16 floats, of padding so that the 4 rows of a fragment read
+  // fall in different banks
+  constexpr int PA = BM + (AF ? 16 : 2), PB = BN + (AF ? 16 : 2);
   constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
-  __shared__ double As[2][BK][PA];
-  __shared__ double Bs[2][BK][PB];
+  __shared__ LT As[2][BK][PA];
+  __shared__ LT Bs[2][BK][PB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int z = blockIdx.z / g.ksplit, part = blockIdx.z % g.ksplit;
@@ -103,13 +114,13 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
 #pragma unroll
       for (int u = 0; u < NA; u++) {
         const double av = AF ? (double)raf[u] : ra[u];
-        if (AKF) As[buf][tid % BK][tid / BK + u * (256 / BK)] = av * scale;
-        else As[buf][tid / BM + u * (256 / BM)][tid % BM] = av * scale;
+        if (AKF) As[buf][tid % BK][tid / BK + u * (256 / BK)] = (LT)(av * scale);
+        else As[buf][tid / BM + u * (256 / BM)][tid % BM] = (LT)(av * scale);
       }
 #pragma unroll
       for (int u = 0; u < NB; u++) {
-        if (BNF) Bs[buf][tid / BN + u * (256 / BN)][tid % BN] = rb[u];
-        else Bs[buf][tid % BK][tid / BK + u * (256 / BK)] = rb[u];
+        if (BNF) Bs[buf][tid / BN + u * (256 / BN)][tid % BN] = (LT)rb[u];
+        else Bs[buf][tid % BK][tid / BK + u * (256 / BK)] = (LT)rb[u];
       }
     };
 
@@ -121,27 +132,57 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
     for (int kt = 0; kt < nkt; kt++) {
       const int cur = kt & 1;
       if (kt + 1 < nkt) load(kt + 1);
+      if constexpr (AF) {
+        f4 acc32[TM][TN];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double a[TM], b[TN];
+        for (int i = 0; i < TM; i++)
 #pragma unroll
-        for (int i = 0; i < TM; i++) a[i] = As[cur][kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
+          for (int j = 0; j < TN; j++) acc32[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < TN; j++) b[j] = Bs[cur][kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
+        for (int kk = 0; kk < BK; kk += 4) {
+          float a[TM], b[TN];
+#pragma unroll
+          for (int i = 0; i < TM; i++) a[i] = As[cur][kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
+#pragma unroll
+          for (int j = 0; j < TN; j++) b[j] = Bs[cur][kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
+#pragma unroll
+          for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+              acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc32[i][j], 0, 0, 0);
+        }
 #pragma unroll
         for (int i = 0; i < TM; i++)
 #pragma unroll
           for (int j = 0; j < TN; j++)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; v++) acc[i][j][v] += (double)acc32[i][j][v];
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          double a[TM], b[TN];
+#pragma unroll
+          for (int i = 0; i < TM; i++) a[i] = As[cur][kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
+#pragma unroll
+          for (int j = 0; j < TN; j++) b[j] = Bs[cur][kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
+#pragma unroll
+          for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
       }
       if (kt + 1 < nkt) store(cur ^ 1);
       __syncthreads();
     }
   }
 
-  // epilogue: on gfx950 lane l, register v of a 16x16 f64 tile holds row l/16 + 4v, column l%16.
-  // All old C values are loaded before the first store so the loads are not serialised
-  // behind stores to the same array.
+  // epilogue: lane l, register v of a 16x16 tile holds row l/16 + 4v (FP64 MFMA) or 4(l/16) + v
+  // (FP32 MFMA), column l%16.  All old C values are loaded before the first store so the loads
+  // are not serialised behind stores to the same array.
+  auto row_of = [&](int i, int v) {
+    return m0 + wm0 + 16 * i + (AF ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v);
+  };
   if (g.ksplit > 1) {
     double *Pp = g.P + ((long long)z * g.ksplit + part) * (long long)g.M * g.N;
 #pragma unroll
@@ -152,7 +193,7 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
       for (int i = 0; i < TM; i++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-          const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
+          const int m = row_of(i, v);
           if (m < g.M) Pp[(long long)m * g.N + n] = acc[i][j][v];
         }
     }
@@ -171,7 +212,7 @@ __device__ __forceinline__ void gemm_body(const Gemm &g) {
   for (int i = 0; i < TM; i++)
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      const int m = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
+      const int m = row_of(i, v);
       rok[i][v] = m < g.M;
       ro[i][v] = rok[i][v] ? ioff(g.crow, m) : 0;
     }
