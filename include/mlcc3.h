@@ -79,9 +79,10 @@ enum {
    (tau~, R~, L~; formed in FP64) are stored in FP32 and widened to FP64 where they are read
    (about 6e-8 relative per element), and the occupied (N_O-sized) term of each intermediate,
    sum_L x^{ab}_{pL} G_{Lqrc}, runs as FP32 MFMA products on FP32 copies of its operands (FP32
-   sums over the N_O values of L, added in FP64); the densities keep both in FP64.  The
-   permutations, denominators, the arithmetic of the N_O-wide back-contractions and every
-   output stay FP64 in all forms.
+   sums over the N_O values of L, added in FP64), and the N_O-wide back-contractions of the
+   FP32 blocks run as FP32 MFMA products (FP32 sums over 16-deep K slabs, added in FP64); the
+   densities keep all of these in FP64.  The permutations, denominators and every output stay
+   FP64 in all forms.
    MLCC3_FP32:   FP32 MFMA on operands rounded to FP32, FP32 sums over 32-deep K slabs, FP64
                  across slabs (about 1e-7 relative).
    MLCC3_BF16X3: split-bf16 products (Henry, Tang and Heinecke, ARITH 2019): each operand is
@@ -105,10 +106,10 @@ typedef struct { double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_out;
 typedef struct {
   int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3, MLCC3_BF16X6:
                              arithmetic of the d-contraction GEMMs (and, in the split-bf16
-                             forms, of the N_V-wide back-contractions) and storage of the
-                             contravariant triples blocks and of the occupied term (FP32 in
-                             the reduced forms, except in the densities); denominators and
-                             accumulation stay FP64 */
+                             forms, of the N_V-wide back-contractions); in the reduced forms
+                             also FP32 storage of the contravariant triples blocks and FP32
+                             MFMA for the occupied term and the N_O-wide products (not in the
+                             densities); denominators and accumulation stay FP64 */
   int32_t reuse_ground;   /* nonzero: the ground-state inputs (same pointers) are unchanged
                              since the last call on this workspace; reuse its prepared blocks.
                              The call checks that: a 64-bit fingerprint of the inputs' contents

@@ -1,10 +1,10 @@
 """Mixed-precision paths: the d-contractions run as FP32 MFMA on rounded copies of the FP64
 operands (precision="fp32"), or as split-bf16 MFMA products (precision="bf16x6": three bf16
 planes per operand, six products; "bf16x3": two planes, three products).  In the reduced forms
-the contravariant triples blocks are stored in FP32, the occupied term of each intermediate runs
-as FP32 MFMA products, and the split-bf16 forms also run the N_V-wide back-contractions (and the
-Bq intermediate of the left transform) in split-bf16 products; the permutations, the
-denominators, the N_O-wide back-contractions and every output stay FP64.  Every result is
+the contravariant triples blocks are stored in FP32, the occupied term of each intermediate and
+the N_O-wide back-contractions run as FP32 MFMA products, and the split-bf16 forms also run the
+N_V-wide back-contractions (and the Bq intermediate of the left transform) in split-bf16
+products; the permutations, the denominators and every output stay FP64.  Every result is
 checked against the FP64 oracle, norm-wise and max-abs over max-abs, and against the FP64 GPU
 path to show that the reduced-precision path really ran.
 
