@@ -72,9 +72,10 @@ enum {
 };
 
 /* Arithmetic of the O(N_V n_v^3 n_o^3) GEMMs of the Implementation section: the d-contractions
-   that build the triples intermediates in every reduced form, and in the split-bf16 forms also
-   the N_V-wide back-contractions of the contravariant triples (rho^{aD}_{ij}, sigma^{aD}_{ij},
-   Omega^{aD}_{ij}; their triples operand is split while it is staged).  In the reduced forms
+   that build the triples intermediates in every reduced form, and also the N_V-wide
+   back-contractions of the contravariant triples (rho^{aD}_{ij}, sigma^{aD}_{ij},
+   Omega^{aD}_{ij}: FP32 MFMA in the FP32 form; split-bf16 in the split-bf16 forms, which also
+   run the left transform's Bq product so, the triples operand split while it is staged).  In the reduced forms
    of the ground residual and the right and left transforms, the contravariant triples blocks
    (tau~, R~, L~; formed in FP64) are stored in FP32 and widened to FP64 where they are read
    (about 6e-8 relative per element), and the occupied (N_O-sized) term of each intermediate,
@@ -105,8 +106,8 @@ typedef struct { double *x1, *x2_vVoo, *x2_vvoO; } mlcc3_out;
 
 typedef struct {
   int32_t precision;      /* MLCC3_FP64 (default), MLCC3_FP32, MLCC3_BF16X3, MLCC3_BF16X6:
-                             arithmetic of the d-contraction GEMMs (and, in the split-bf16
-                             forms, of the N_V-wide back-contractions); in the reduced forms
+                             arithmetic of the d-contraction GEMMs and of the N_V-wide
+                             back-contractions; in the reduced forms
                              also FP32 storage of the contravariant triples blocks and FP32
                              MFMA for the occupied term and the N_O-wide products (not in the
                              densities); denominators and accumulation stay FP64 */

@@ -4,8 +4,9 @@
 // Tang and Heinecke, ARITH 2019) and the plane pairs (s, t) with s + t < ns multiplied in bf16
 // MFMA: ns = 2 is the three-product form (hi*hi + hi*lo + lo*hi), ns = 3 the six-product form.
 // Products of bf16 planes are exact in FP32; the MFMA sums them in FP32 over two 32-deep K
-// slabs, after which the FP32 tile is added into an FP64 accumulator.  W is written in FP64 and
-// everything after it stays FP64.
+// slabs, after which the FP32 tile is added into an FP64 accumulator.  W is written in FP64.
+// The same kernel runs the N_V-wide back-contractions with the triples operand split while it
+// is staged (BMODE 1, 2).
 //
 // gfx950 mapping: v_mfma_f32_16x16x32_bf16 (operand lane l: A row l%16 and B column l%16, the
 // 8 consecutive k of chunk l/16; result register v of lane l: row 4(l/16) + v, column l%16).

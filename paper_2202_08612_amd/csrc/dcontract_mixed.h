@@ -22,6 +22,11 @@ struct MixSeg {
   const float *B = nullptr;
   long long ldb = 0, bbatch = 0, bvec = 0;
   int Kp = 0, Np = 0;
+  // A read in place instead (K > 0): element (m, k) of batch z at A + v*avec + z*abatch +
+  // amap(m) + k for k < K (zero for K <= k < Kp); lda unused, no padding needed
+  Idx2 amap;
+  long long abatch = 0;
+  int K = 0;
 };
 
 // C[z*cbatch + cmap(m) + n] = sum_seg sum_k A_seg[m][k] B_seg[z][k][n]  (FP32 MFMA; FP32 sums over
@@ -34,7 +39,8 @@ struct MixGemm {
   Idx2 cmap;
   long long cbatch = 0, cvec = 0;
   int persist = 0;
-  // ordered triples the call does not need are skipped (see TileGemm)
+  // ordered triples the call does not need are skipped (see TileGemm); tf.zero writes the
+  // skipped tiles as zeros
   TripleFilter tf;
 };
 

@@ -2,9 +2,10 @@
 // 32-deep K slabs, FP64 across slabs):
 //   W[p][q][r][a][b][c] = sum_seg sum_D x_seg[(p,q,a)][D] G_seg[r][D][(b,c)]
 // The operands are FP32 copies of the FP64 blocks (rounded to nearest), padded to multiples
-// of 4 in K and N so that every staged load is a 16-byte vector; W is written in FP64 and
-// everything after it (occupied term, permutations, denominators, back-contractions) stays
-// FP64.
+// of 4 in K and N so that every staged load is a 16-byte vector; W is written in FP64.  The
+// same kernel runs the N_V-wide back-contraction of the FP32 contravariant blocks in the FP32
+// form, with A read in place through its row map (MixSeg::K > 0: loads masked at K, 16-byte
+// vectors where the offset allows).
 //
 // gfx950 mapping: v_mfma_f32_16x16x4_f32 (operand lane l: A row l%16, k l/16; B k l/16,
 // column l%16; result register v of lane l: row 4(l/16) + v, column l%16).  256 threads in a
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
     t -= grp * GM * nt;
     const int m0 = (gbase + t % gsz) * BM, n0 = (t / gsz) * BN;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 32;
-    if (g.tf.on && !tile_needed(g.tf, z, m0, min(g.M, m0 + BM))) continue;
+    const bool skip = g.tf.on && !tile_needed(g.tf, z, m0, min(g.M, m0 + BM));  // uniform per workgroup
+    if (skip && !g.tf.zero) continue;
 
     f4 acc[4][2];
     d4 acc64[4][2];
@@ -63,18 +65,33 @@ __global__ __launch_bounds__(256, 2) void k_dcontract_f32(const MixGemm g) {
     const int bq = tid & 15, br = tid >> 4;
     f4 ra[4], rb[2];
 
-    for (int s = 0; s < g.nseg; s++) {
+    for (int s = 0; s < (skip ? 0 : g.nseg); s++) {
       const MixSeg &sg = g.seg[s];
       const int Kp = sg.Kp;
-      const float *Ap = sg.A + vv * sg.avec;
+      const bool inplace = sg.K > 0;  // uniform
+      const float *Ap = sg.A + vv * sg.avec + (inplace ? (long long)z * sg.abatch : 0);
       const float *Bp = sg.B + vv * sg.bvec + (long long)z * sg.bbatch;
       const int nkt = (Kp + BK - 1) / BK;
+      long long arow[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int m = m0 + ar + 32 * u;
+        arow[u] = m >= g.M ? -1 : (inplace ? mix_moff(sg.amap, m) : (long long)m * sg.lda);
+      }
       auto load = [&](int kt) {
         const int k = kt * BK + 4 * aq;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          const int m = m0 + ar + 32 * u;
-          ra[u] = (m < g.M && k < Kp) ? *(const f4 *)(Ap + (long long)m * sg.lda + k) : f4{0.f, 0.f, 0.f, 0.f};
+          if (!inplace) {
+            ra[u] = (arow[u] >= 0 && k < Kp) ? *(const f4 *)(Ap + arow[u] + k) : f4{0.f, 0.f, 0.f, 0.f};
+          } else if (arow[u] >= 0 && k + 4 <= sg.K && ((arow[u] + k) & 3) == 0) {
+            ra[u] = *(const f4 *)(Ap + arow[u] + k);
+          } else {
+            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int e = 0; e < 4; e++) v[e] = (arow[u] >= 0 && k + e < sg.K) ? Ap[arow[u] + k + e] : 0.f;
+            ra[u] = v;
+          }
         }
         const int n = n0 + 4 * bq;
 #pragma unroll
@@ -174,7 +191,13 @@ hipError_t dcontract_f32(const MixGemm &g0, hipStream_t s) {
     if (sg.Kp % 4 || sg.Np % 4 || sg.lda % 4 || sg.ldb % 4 || sg.bbatch % 4 || sg.avec % 4 || sg.bvec % 4 ||
         sg.Np < g.N || (uintptr_t)sg.A % 16 || (uintptr_t)sg.B % 16)
       return hipErrorInvalidValue;
+    if (sg.K < 0 || sg.K > sg.Kp || sg.abatch < 0) return hipErrorInvalidValue;
   }
+  for (int i = 0; i < g.nseg; i++)
+    if (g.seg[i].K > 0 && g.seg[i].amap.d <= 0) {  // one-level map: no division in the kernel
+      g.seg[i].amap.d = 0x7fffffff;
+      g.seg[i].amap.s1 = 0;
+    }
   if (g.cmap.d <= 0) {
     g.cmap.d = 0x7fffffff;
     g.cmap.s1 = 0;

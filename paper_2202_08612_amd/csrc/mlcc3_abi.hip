@@ -1043,7 +1043,7 @@ void w_dterm(const Dims &d, double *W, int nb, const DSeg *seg0, int nseg, const
     return;
   }
   if (t_prec == MLCC3_FP32) {
-    // FP32 MFMA on rounded, zero-padded copies of the operands; W and all later steps stay FP64
+    // FP32 MFMA on rounded, zero-padded copies of the operands; W is written in FP64
     mlcc3_ws ws = t_ws;
     MixGemm g;
     g.M = snp(d) * d.no * d.nv;
@@ -1280,6 +1280,36 @@ void back_vV(mlcc3_ws ws, const Dims &d, const double *X, const double *G, int N
     launch_transpose(P, Y, 1, N, M2, s);
     HIPRT(hipGetLastError());
     return;
+  } else if (N >= 96 && t_prec == MLCC3_FP32 && t_xf32) {
+    // FP32 form: FP32 MFMA on the FP32 blocks, read in place, and an FP32 copy of the integral
+    // block ([k][(b,c)][n], rows padded to whole 32-deep K slabs); FP32 sums over each slab,
+    // FP64 across slabs
+    const int Kp = ((int)d.nv2 + 31) / 32 * 32, Np = (N + 3) / 4 * 4;
+    float *Gf = (float *)buf(ws, "bk_G32", (size_t)((long long)d.no * Kp * Np + 1) / 2, s);
+    check_range(G, plain(N), (int)d.nv2, plain(1), N, d.nv2 * N, d.no, "G (back-contraction)");
+    check_bytes(Gf, sizeof(float) * (size_t)d.no * Kp * Np, "FP32 G (back-contraction)");
+    HIPCHK(pad_to_f32(G, d.no, (int)d.nv2, N, Gf, Kp, Np, s));
+    MixGemm g;
+    g.M = snp(d) * d.no * d.nv;
+    g.N = N;
+    g.nbatch = d.no;
+    g.C = P;
+    g.cmap = plain(N);
+    g.cbatch = MN;
+    g.nseg = 1;
+    g.tf = triple_filter(d, r, true);
+    g.seg[0].A = (const float *)X;
+    g.seg[0].amap = xrow;
+    g.seg[0].abatch = d.nv3;
+    g.seg[0].K = (int)d.nv2;
+    g.seg[0].B = Gf;
+    g.seg[0].ldb = Np;
+    g.seg[0].bbatch = (long long)Kp * Np;
+    g.seg[0].Kp = Kp;
+    g.seg[0].Np = Np;
+    check_range(X, xrow, g.M, plain(1), (int)d.nv2, d.nv3, d.no, "X~ (back-contraction)", 0, 1, xesz());
+    check_range(P, plain(N), g.M, plain(1), N, MN, d.no, "C (back-contraction)");
+    HIPCHK(dcontract_f32(g, s));
   } else if (N >= 96) {
     TileGemm g;
     g.M = snp(d) * d.no * d.nv;
